@@ -1,0 +1,227 @@
+/*
+ * flp.h - filtered Lanczos procedure on MI355X (gfx950): C ABI.
+ *
+ * Computes every eigenpair of a large sparse real symmetric matrix A that
+ * lies in a closed interval [alpha, beta] (the problem stated in the
+ * paper's program summary), by Lanczos on a Chebyshev polynomial filter
+ * p(A) of the interval's indicator (Sections 2.2-2.3), following
+ * Aurentz, Kalantzis and Saad, "Cucheb: a GPU implementation of the
+ * filtered Lanczos procedure".
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Return value: 0 (FLP_OK) on success, a negative FLP_E_* code otherwise.
+ *   On failure flp_last_error() returns a message (thread-local).  No C++
+ *   exception crosses this boundary.
+ * - Device pointers are hipMalloc'd (or torch-allocated) memory on the
+ *   current HIP device; host pointers are ordinary memory.  Each argument
+ *   below says which.
+ * - Blocks of r vectors are row-major n x r: entry (i, j) at [i * ld + j],
+ *   ld >= r.  The matrix is CSR, zero-based int32 indices, columns sorted
+ *   within a row, both triangles stored (Section 3.2.1 keeps the full
+ *   symmetric matrix on the GPU without exploiting symmetry).
+ * - `stream` is a hipStream_t passed as void*; NULL means the default
+ *   stream.
+ * - The library keeps a per-device workspace that grows on demand and is
+ *   released by flp_release_workspace() or at process exit.  Calls on one
+ *   device must not overlap in time (they share that workspace).
+ */
+#ifndef FLP_H
+#define FLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+#define FLP_OK            0
+#define FLP_E_ARG        -1  /* invalid argument (NaN, alpha >= beta, r < 1, n <= 0, ...) */
+#define FLP_E_INTERVAL   -2  /* [alpha, beta] does not meet [lambda_min, lambda_max] */
+#define FLP_E_NOTSYM     -3  /* matrix failed the optional symmetry check */
+#define FLP_E_NOMEM      -4  /* device allocation failed or exceeds the limit */
+#define FLP_E_NOCONV     -5  /* basis limit reached before convergence (result still returned) */
+#define FLP_E_DEVICE     -6  /* HIP runtime error; message in flp_last_error() */
+
+/* precision of the filter recurrence (Section 2.2 applies p(A) by Clenshaw) */
+#define FLP_PREC_FP64         0  /* FP64 matrix values, vectors and accumulation */
+#define FLP_PREC_FP32_FILTER  1  /* FP32 values/vectors/accumulation in the filter only */
+
+/* ------------------------------------------------------------------ types */
+
+/* Sparse symmetric matrix in CSR form (Section 3.2.1).  All pointers are
+ * DEVICE pointers owned by the caller, who keeps them alive until every
+ * call using them has completed.  val32 is optional: an FP32 copy of val
+ * used by FLP_PREC_FP32_FILTER (the library converts val itself when it is
+ * NULL). */
+typedef struct flp_csr {
+    int32_t n;              /* order of A, > 0 */
+    int64_t nnz;            /* stored entries, < 2^31 */
+    const int32_t *rowptr;  /* device int32[n + 1], rowptr[0] = 0, non-decreasing */
+    const int32_t *colind;  /* device int32[nnz], 0 <= colind < n */
+    const double *val;      /* device float64[nnz] */
+    const float *val32;     /* device float32[nnz] or NULL */
+} flp_csr;
+
+/* A Chebyshev filter polynomial (Section 3.2.3 stores the degree, the
+ * Chebyshev coefficients and the spectrum bounds).  Opaque; host memory. */
+typedef struct flp_filter flp_filter;
+
+/* Options for flp_solve.  Fill with flp_opts_default() first. */
+typedef struct flp_opts {
+    int32_t block;        /* block size r >= 1 (Section 2.3); default 1 */
+    int32_t degree;       /* filter degree m; <= 0 selects it by eq. optimaldegree */
+    double eps;           /* tolerance of the degree rule; default 0.31227 */
+    double tol;           /* required ||Ax - lambda x|| / ||A||; default 1e-9 */
+    int32_t check_every;  /* block steps between convergence checks; default 30 */
+    int32_t prec;         /* FLP_PREC_FP64 (default) or FLP_PREC_FP32_FILTER */
+    uint64_t seed;        /* seed of the random start block and bounds start vector */
+    int64_t max_basis;    /* cap on Lanczos basis columns; <= 0 picks min(n, memory) */
+    int32_t k0;           /* Lanczos steps of the bounds estimate; default 40 */
+    const double *start;  /* HOST n x block row-major start block, or NULL (random) */
+    double lmin, lmax;    /* spectrum bounds to use if lmin < lmax; else estimated */
+    void *stream;         /* hipStream_t, NULL = default stream */
+} flp_opts;
+
+typedef struct flp_stats {
+    int32_t iters;         /* block Lanczos steps (the paper's "iters") */
+    int64_t mv;            /* products with A inside the filter: r * m * iters */
+    int32_t basis_cols;    /* Lanczos basis columns at convergence */
+    int32_t polish_sweeps; /* FP64 refinement sweeps (FP32 filter only) */
+    double t_pre;          /* seconds: spectrum bounds (the paper's PREPROC) */
+    double t_mv;           /* seconds: filter applications (the paper's MV) */
+    double t_orth;         /* seconds: reorthogonalisation + block QR (ORTH) */
+    double t_check;        /* seconds: convergence checks (host eigensolves) */
+    double t_rr;           /* seconds: Rayleigh-Ritz, residuals, polish */
+    double t_total;        /* seconds: whole call */
+    double filter_bytes;   /* algorithmic bytes moved by the filter SpMMs */
+} flp_stats;
+
+/* Result of flp_solve; owned by the library until flp_result_free(). */
+typedef struct flp_result {
+    int32_t n;
+    int32_t count;        /* eigenvalues found in [alpha, beta], with multiplicity */
+    double *evals;        /* HOST float64[count], ascending */
+    double *resid;        /* HOST float64[count]: ||A x - lambda x||_2 / ||A|| */
+    double *evecs;        /* DEVICE float64[n * count], column-major (x_j at evecs + j*n) */
+    double lmin, lmax;    /* spectrum bounds used for the affine map (eq. transf) */
+    double alpha, beta;   /* the interval as given */
+    int32_t degree;       /* filter degree used */
+    int32_t converged;    /* 1 if the stopping rule was met */
+    flp_stats stats;
+} flp_result;
+
+/* ------------------------------------------------------------------ calls */
+
+/* Fill *o with the defaults listed in flp_opts. */
+void flp_opts_default(flp_opts *o);
+
+/* Build the filter p_m = sum_{i<=m} b_i T_i for the indicator of
+ * [alpha, beta] (Section 2.2: closed-form Chebyshev coefficients of the
+ * ideal filter phi; truncation at degree m).
+ *   alpha, beta: the interval in A's units, alpha < beta.
+ *   degree: m >= 1, or <= 0 to pick the smallest m with
+ *           ||p_m - phi|| < eps ||phi|| (eq. optimaldegree, eps = 0.31227).
+ *   lmin, lmax: bounds of A's spectrum, lmin < lmax; the map
+ *           A -> (A - cI)/e of eq. transf uses c = (lmin+lmax)/2,
+ *           e = (lmax-lmin)/2.  Pass -1, 1 when alpha, beta are already
+ *           in [-1, 1].  [alpha, beta] is clamped to [lmin, lmax].
+ *   out: receives a new filter (host memory); free with flp_filter_free.
+ * Errors: FLP_E_ARG (NaN, alpha >= beta, lmin >= lmax, degree > 100000),
+ *         FLP_E_INTERVAL (empty after clamping). */
+int flp_build_filter(double alpha, double beta, int32_t degree, double lmin, double lmax,
+                     flp_filter **out);
+int flp_build_filter_eps(double alpha, double beta, int32_t degree, double lmin, double lmax,
+                         double eps, flp_filter **out);
+void flp_filter_free(flp_filter *p);
+/* Degree m of the filter. */
+int32_t flp_filter_degree(const flp_filter *p);
+/* Copy b_0..b_m into host coeffs[0..cap); returns m + 1 (or a negative error). */
+int32_t flp_filter_coeffs(const flp_filter *p, double *coeffs, int32_t cap);
+/* Spectrum bounds and mapped interval: out[0..5] = lmin, lmax, c, e, alpha', beta'. */
+int flp_filter_info(const flp_filter *p, double *out6);
+/* Evaluate p at host points z (already in [-1,1] units), host in/out. */
+int flp_filter_eval(const flp_filter *p, const double *z, double *out, int32_t count);
+
+/* W = p(Ahat) V, Ahat = (A - cI)/e (eq. transf), by Clenshaw's backward
+ * recurrence (Section 2.2) with the affine map and the three-term update
+ * fused into each sparse-matrix product: m products with A.
+ *   V: DEVICE n x r row-major (ld = r), float64.
+ *   W: DEVICE n x r row-major (ld = r), float64; must not alias V.
+ *   r: 1 <= r <= 32.
+ *   prec: FLP_PREC_FP64, or FLP_PREC_FP32_FILTER (V is rounded to FP32,
+ *         the recurrence runs in FP32, W is written in FP64).
+ * Stream-ordered and asynchronous (no host synchronisation unless the
+ * workspace must grow).  Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
+int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, double *W,
+                     int32_t r, int32_t prec, void *stream);
+
+/* Y = A X (plain CSR SpMM, Section 3.2.1).  X, Y: DEVICE n x r row-major
+ * with leading dimensions ldx, ldy >= r; 1 <= r <= 32; FP64.  Async. */
+int flp_spmm(const flp_csr *A, const double *X, int32_t ldx, double *Y, int32_t ldy,
+             int32_t r, void *stream);
+
+/* Full reorthogonalisation of a block against a basis (Section 3.2.2), two
+ * passes of classical Gram-Schmidt:
+ *   H1 = Q^T W, W -= Q H1, H2 = Q^T W, W -= Q H2, H = H1 + H2.
+ *   Q: DEVICE n x k row-major with leading dimension ldq >= k (k >= 1).
+ *   W: DEVICE n x r row-major (ld = r), updated in place, 1 <= r <= 16.
+ *   H: HOST float64[k * r] row-major (k x r) receiving H1 + H2, or NULL.
+ * Synchronises the stream when H is non-NULL. */
+int flp_block_orth(const double *Q, int64_t ldq, int32_t k, int32_t n, double *W, int32_t r,
+                   double *H, void *stream);
+
+/* Block normalisation W = Qn S (eq. lanczos: S upper triangular with a
+ * non-negative diagonal) by Cholesky QR applied twice.
+ *   W: DEVICE n x r row-major (ld = r), overwritten by Qn; 1 <= r <= 16.
+ *   S: HOST float64[r * r] row-major, receives S.
+ * Returns FLP_E_ARG if W is numerically rank deficient.  Synchronous. */
+int flp_block_qr(double *W, int32_t n, int32_t r, double *S, void *stream);
+
+/* Estimate [lambda_min, lambda_max] by k0 steps of unfiltered Lanczos with
+ * full reorthogonalisation (Section 2.2: a few Lanczos steps), widened by
+ * the Ritz residual bounds and 1e-3 of the width, clamped to the Gershgorin
+ * enclosure.  Host outputs.  Synchronous. */
+int flp_estimate_bounds(const flp_csr *A, int32_t k0, uint64_t seed, double *lmin, double *lmax,
+                        void *stream);
+
+/* Every eigenpair of A in [alpha, beta] (program summary; Sections 2-3):
+ * bounds (PREPROC) -> filter (Section 2.2) -> block Lanczos on p(A) with
+ * full reorthogonalisation (Section 2.3, eq. lanczos) -> periodic
+ * convergence checks on the Ritz values of T_k -> Rayleigh-Ritz with A
+ * (eq. rayleigh, eq. proj).  opts may be NULL (defaults).  Synchronous.
+ * On FLP_OK or FLP_E_NOCONV *out holds a result to free with
+ * flp_result_free().  Errors: FLP_E_ARG, FLP_E_INTERVAL, FLP_E_NOMEM,
+ * FLP_E_NOCONV, FLP_E_DEVICE. */
+int flp_solve(const flp_csr *A, double alpha, double beta, const flp_opts *opts,
+              flp_result **out);
+void flp_result_free(flp_result *res);
+/* Copy the result's eigenvectors (count x n doubles, column-major) into the
+ * DEVICE buffer dst; stream-ordered (NULL = default stream). */
+int flp_result_copy_evecs(const flp_result *res, double *dst, void *stream);
+
+/* Dense symmetric eigensolver used for the projected problems (Section
+ * 3.2.2 solves T_k's eigenproblem on the CPU with a banded symmetric
+ * eigensolver).  Host only; no GPU needed.
+ *   M: HOST float64[N * N] row-major symmetric with semi-bandwidth bw
+ *      (bw = N - 1 for dense), not modified.
+ *   evals: HOST float64[N], ascending.
+ *   evecs: HOST float64[N * N] row-major (column j = eigenvector j), or NULL.
+ * Returns FLP_OK or FLP_E_ARG. */
+int flp_host_sym_eig(int32_t N, int32_t bw, const double *M, double *evals, double *evecs);
+
+/* Free the calling device's workspace. */
+void flp_release_workspace(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *flp_last_error(void);
+
+/* Library version string. */
+const char *flp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLP_H */

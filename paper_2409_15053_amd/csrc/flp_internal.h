@@ -1,0 +1,92 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/flp.h"
+
+namespace flp {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+#define FLP_HIP(call)                                                            \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            ::flp::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+            return FLP_E_DEVICE;                                                 \
+        }                                                                        \
+    } while (0)
+
+// ---------------------------------------------------------------- host eigensolver
+// Eigenvalues (ascending) of the symmetric N x N row-major M with
+// semi-bandwidth bw; rows[0..nrows) of the eigenvector matrix (columns =
+// eigenvectors, same order as evals) are written to Z (nrows x N row-major).
+// Returns 0 on success.
+int sym_eig(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Z);
+
+// ---------------------------------------------------------------- kernel launchers
+// All take a stream and return hipError_t from the launch.
+
+// out = alpha * (A X) + beta * X + gamma * V + delta * Y, row-major blocks of
+// r columns with leading dimensions; V / Y may be NULL (their terms skipped).
+// T = float or double selects the matrix values and the vector type; the
+// output type is Tout.
+template <typename T, typename Tout>
+hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val,
+                            int r, const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy,
+                            Tout *out, int ldo, T alpha, T beta, T gamma, T delta,
+                            hipStream_t s);
+
+// Partial sums for C = A^T B over row chunks: A n x K (lda), B n x c (ldb).
+// partials[chunk][K * c] (row-major K x c).  Returns the number of chunks
+// used via *nchunks (caller sizes partials with plan_tn()).
+struct TnPlan {
+    int chunk_rows;
+    int nchunks;
+    size_t partial_elems;  // nchunks * K * c
+};
+TnPlan plan_tn(int n, int K, int c);
+hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, const double *A, int64_t lda,
+                                  const double *B, int64_t ldb, double *partials, hipStream_t s);
+// C (K x c, ldc) = sum over chunks of partials (deterministic order).
+hipError_t launch_reduce_partials(const TnPlan &pl, int K, int c, const double *partials, double *C,
+                                  int ldc, hipStream_t s);
+
+// C (n x c, ldc) = beta * C + alpha * A (n x K, lda) B (K x c, ldb); B on device.
+hipError_t launch_gemm_nn(int n, int K, int c, double alpha, const double *A, int64_t lda,
+                          const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                          hipStream_t s);
+
+// Gershgorin: lo/hi per block into part (2 * nblocks doubles), then reduced
+// to out[0] = min(a_ii - R_i), out[1] = max(a_ii + R_i).
+hipError_t launch_gershgorin(int n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                             double *part, int part_cap, double *out, hipStream_t s);
+int gershgorin_blocks(int n);
+
+// N(0,1) entries from a counter-based generator: out[i] for i < count, with
+// leading-dimension layout rows x cols (ld).
+hipError_t launch_randn(int rows, int cols, double *out, int64_t ld, uint64_t seed, uint64_t stream_id,
+                        hipStream_t s);
+
+// dst (rows x cols, ldd) = scale * src (rows x cols, lds); optional FP32 copy dst32.
+hipError_t launch_copy_block(int rows, int cols, double scale, const double *src, int64_t lds, double *dst,
+                             int64_t ldd, float *dst32, int64_t ldd32, hipStream_t s);
+hipError_t launch_to_float(int64_t count, const double *src, float *dst, hipStream_t s);
+hipError_t launch_scale(int64_t count, double a, const double *src, double *dst, hipStream_t s);
+
+// resid[j] = || AX[:, j] - lam[j] X[:, j] ||_2 for row-major n x c blocks
+// (partials of squares per block, reduced in a second pass).
+hipError_t launch_resid_norms(int n, int c, const double *AX, int64_t ldax, const double *X,
+                              int64_t ldx, const double *lam, double *part, int nchunks,
+                              double *out, hipStream_t s);
+int resid_chunks(int n);
+
+// dst (column-major n x c, ld n) = src (row-major n x c, lds)
+hipError_t launch_transpose_out(int n, int c, const double *src, int64_t lds, double *dst,
+                                hipStream_t s);
+
+}  // namespace flp

@@ -1,0 +1,660 @@
+// Device kernels of the filtered Lanczos procedure for gfx950 (CDNA4).
+//
+// * cheb_step: one Clenshaw step of the filter (Section 2.2) as a CSR SpMM
+//   over a row-major block of r vectors with the affine map and the
+//   three-term update fused into the epilogue.
+// * gemm_tn / gemm_nn: the tall-skinny products of the full
+//   reorthogonalisation (Section 3.2.2) on FP64 MFMA (16x16x4).
+// * small helpers: Gershgorin bounds, counter-based normal generator,
+//   block copies, residual norms.
+#include "flp_internal.h"
+
+#include <algorithm>
+
+namespace flp {
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int NXCD = 8;
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Renumber so that each XCD receives one contiguous range of tiles:
+// neighbouring rows of the matrix then share that XCD's L2 for the gathered
+// vector entries.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    int q = G / NXCD, rem = G % NXCD;
+    int x = b % NXCD, s = b / NXCD;
+    return (x < rem) ? x * (q + 1) + s : rem * (q + 1) + (x - rem) * q + s;
+}
+
+template <typename T, int VEC>
+struct Vec;
+template <>
+struct Vec<double, 1> {
+    using type = double;
+};
+template <>
+struct Vec<double, 2> {
+    using type = double2;
+};
+template <>
+struct Vec<float, 1> {
+    using type = float;
+};
+template <>
+struct Vec<float, 2> {
+    using type = float2;
+};
+template <>
+struct Vec<float, 4> {
+    using type = float4;
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T *p, T (&v)[VEC]) {
+    using V = typename Vec<T, VEC>::type;
+    V x = *reinterpret_cast<const V *>(p);
+    if constexpr (VEC == 1) {
+        v[0] = x;
+    } else if constexpr (VEC == 2) {
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec(T *p, const T (&v)[VEC]) {
+    using V = typename Vec<T, VEC>::type;
+    V x;
+    if constexpr (VEC == 1) {
+        x = v[0];
+    } else if constexpr (VEC == 2) {
+        x.x = v[0];
+        x.y = v[1];
+    } else {
+        x.x = v[0];
+        x.y = v[1];
+        x.z = v[2];
+        x.w = v[3];
+    }
+    *reinterpret_cast<V *>(p) = x;
+}
+
+// ------------------------------------------------------------------ filter step
+//
+// LPR lanes share one matrix row; lane `sub` owns columns
+// [sub*VEC, sub*VEC + VEC) of the block.  All lanes of a row walk the row's
+// nonzeros together (the column index and value loads of a row coalesce to
+// one request), and each gathers its VEC contiguous entries of X[col, :].
+template <typename T, typename Tout, int LPR, int VEC>
+__global__ __launch_bounds__(256) void cheb_step_kernel(
+    int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+    const T *__restrict__ val, int r, const T *__restrict__ X, int ldx, const T *__restrict__ V,
+    int ldv, const T *__restrict__ Y, int ldy, Tout *__restrict__ out, int ldo, T alpha, T beta,
+    T gamma, T delta) {
+    constexpr int RPB = 256 / LPR;  // rows per block
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int row = tile * RPB + threadIdx.x / LPR;
+    const int sub = threadIdx.x % LPR;
+    const int c0 = sub * VEC;
+    if (row >= n || c0 >= r) return;
+    const int p0 = rowptr[row], p1 = rowptr[row + 1];
+    T acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = T(0);
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        int cc[4];
+        T aa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            cc[u] = colind[p + u];
+            aa[u] = val[p + u];
+        }
+        T xv[4][VEC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) load_vec<T, VEC>(X + (int64_t)cc[u] * ldx + c0, xv[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], xv[u][v], acc[v]);
+    }
+    for (; p < p1; ++p) {
+        int cc = colind[p];
+        T aa = val[p];
+        T xv[VEC];
+        load_vec<T, VEC>(X + (int64_t)cc * ldx + c0, xv);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = fma(aa, xv[v], acc[v]);
+    }
+    T xr[VEC];
+    load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
+    T res[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) res[v] = alpha * acc[v] + beta * xr[v];
+    if (V) {
+        T vv[VEC];
+        load_vec<T, VEC>(V + (int64_t)row * ldv + c0, vv);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(gamma, vv[v], res[v]);
+    }
+    if (Y) {
+        T yy[VEC];
+        load_vec<T, VEC>(Y + (int64_t)row * ldy + c0, yy);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(delta, yy[v], res[v]);
+    }
+    if constexpr (sizeof(Tout) == sizeof(T)) {
+        store_vec<Tout, VEC>(out + (int64_t)row * ldo + c0, res);
+    } else {
+        Tout o[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) o[v] = (Tout)res[v];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) out[(int64_t)row * ldo + c0 + v] = o[v];
+    }
+}
+
+template <typename T, typename Tout, int LPR, int VEC>
+hipError_t cheb_launch(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
+                       const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
+                       int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s) {
+    constexpr int RPB = 256 / LPR;
+    int grid = (n + RPB - 1) / RPB;
+    hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC>), dim3(grid), dim3(256), 0, s, n, rowptr,
+                       colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T, typename Tout>
+hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
+                            const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
+                            int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    // vector width: 16-byte loads when every leading dimension allows it
+    constexpr int V16 = 16 / (int)sizeof(T);
+    auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    bool aligned16 = (ldx % V16 == 0) && (!V || ldv % V16 == 0) && (!Y || ldy % V16 == 0) &&
+                     (ldo % V16 == 0) && (sizeof(Tout) == sizeof(T)) && al(X) && al(V) && al(Y) && al(out);
+#define FLP_CHEB(LPR, VEC) \
+    return cheb_launch<T, Tout, LPR, VEC>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s)
+    if (aligned16 && r % V16 == 0) {
+        int lpr = r / V16;
+        if constexpr (sizeof(T) == 8) {
+            if (lpr == 1) FLP_CHEB(1, 2);
+            if (lpr == 2) FLP_CHEB(2, 2);
+            if (lpr == 4) FLP_CHEB(4, 2);
+            if (lpr == 8) FLP_CHEB(8, 2);
+            if (lpr == 16) FLP_CHEB(16, 2);
+        } else {
+            if (lpr == 1) FLP_CHEB(1, 4);
+            if (lpr == 2) FLP_CHEB(2, 4);
+            if (lpr == 4) FLP_CHEB(4, 4);
+            if (lpr == 8) FLP_CHEB(8, 4);
+        }
+    }
+    if (r == 1) FLP_CHEB(1, 1);
+    if (r == 2) FLP_CHEB(2, 1);
+    if (r <= 4) FLP_CHEB(4, 1);
+    if (r <= 8) FLP_CHEB(8, 1);
+    if (r <= 16) FLP_CHEB(16, 1);
+    if (r <= 32) FLP_CHEB(32, 1);
+#undef FLP_CHEB
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_cheb_step<double, double>(int, const int32_t *, const int32_t *, const double *, int,
+                                                     const double *, int, const double *, int, const double *,
+                                                     int, double *, int, double, double, double, double,
+                                                     hipStream_t);
+template hipError_t launch_cheb_step<float, float>(int, const int32_t *, const int32_t *, const float *, int,
+                                                   const float *, int, const float *, int, const float *, int,
+                                                   float *, int, float, float, float, float, hipStream_t);
+template hipError_t launch_cheb_step<float, double>(int, const int32_t *, const int32_t *, const float *, int,
+                                                    const float *, int, const float *, int, const float *, int,
+                                                    double *, int, float, float, float, float, hipStream_t);
+
+// ------------------------------------------------------------------ MFMA helpers
+//
+// v_mfma_f64_16x16x4f64: D(16x16) = A(16x4) B(4x16) + C.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; it holds D[l/16 + 4 v][l % 16]
+// for v = 0..3 (rows interleaved across the four lane groups; checked on
+// gfx950 with a one-hot probe).
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// C partial (K x c) over one chunk of rows: each wave owns NT output tiles
+// of 16 A-columns x 16 B-columns; the block's 4 waves split the chunk's
+// rows and combine through LDS.
+template <int NT>
+__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int c, int chunk_rows,
+                                                              const double *__restrict__ A, int64_t lda,
+                                                              const double *__restrict__ B, int64_t ldb,
+                                                              double *__restrict__ partials) {
+    __shared__ double red[4][4][WAVE];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int ntb = (c + 15) / 16;            // B tiles
+    const int chunk = blockIdx.x;
+    const int tg = blockIdx.y / ntb;          // group of NT A tiles
+    const int tb = blockIdx.y % ntb;          // B tile
+    const int r0 = chunk * chunk_rows;
+    const int r1 = min(n, r0 + chunk_rows);
+    const int kr = lane / 16, mc = lane % 16;
+    const int bcol = tb * 16 + mc;
+    const bool bok = bcol < c;
+    int acol[NT];
+    bool aok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        acol[t] = (tg * NT + t) * 16 + mc;
+        aok[t] = acol[t] < K;
+    }
+    dbl4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // the 4 waves interleave 4-row groups (2 groups per wave and iteration)
+    for (int g = r0 + wave * 4; g < r1; g += 4 * 4 * 2) {
+        double bv[2], av[2][NT];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int row = g + u * 16 + kr;
+            bool rok = row < r1;
+            bv[u] = (rok && bok) ? B[(int64_t)row * ldb + bcol] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) av[u][t] = (rok && aok[t]) ? A[(int64_t)row * lda + acol[t]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(av[u][t], bv[u], acc[t]);
+    }
+    // combine the 4 waves one output tile at a time through LDS
+    double *dst = partials + (size_t)chunk * K * c;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave][v][lane] = acc[t][v];
+        __syncthreads();
+        {
+            const int v = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+            double s = red[0][v][l] + red[1][v][l] + red[2][v][l] + red[3][v][l];
+            int i = (tg * NT + t) * 16 + (l / 16) + 4 * v;
+            int j = tb * 16 + (l % 16);
+            if (i < K && j < c) dst[(size_t)i * c + j] = s;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reduce_partials_kernel(int nchunks, int K, int c, const double *__restrict__ partials,
+                                       double *__restrict__ C, int ldc) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    int total = K * c;
+    if (idx >= total) return;
+    double s = 0.0;
+    for (int q = 0; q < nchunks; ++q) s += partials[(size_t)q * total + idx];
+    C[(size_t)(idx / c) * ldc + idx % c] = s;
+}
+
+// C = beta C + alpha A B: each wave computes MT row tiles (16 rows each) x
+// NT column tiles (16 columns each).  The k index inside a group of 16 is
+// permuted (k = 4 * (l/16) + step) so each lane reads 4 contiguous A
+// entries with two 16-byte loads.
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, double alpha,
+                                                      const double *A, int64_t lda,
+                                                      const double *__restrict__ B, int64_t ldb, double beta,
+                                                      double *C, int64_t ldc, bool vec_a) {
+    // A and C may be the same block (in-place C = A B): each wave reads all
+    // of its rows of A before it writes those rows of C.
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int nct = (c + 16 * NT - 1) / (16 * NT);
+    const int wg = xcd_tile(blockIdx.x, gridDim.x);
+    const int rblk = wg / nct, cblk = wg % nct;
+    const int row0 = (rblk * 4 + wave) * (16 * MT);
+    if (row0 >= n) return;
+    const int kq = lane / 16, m = lane % 16;
+    dbl4 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    int col[NT];
+    bool cok[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        col[j] = (cblk * NT + j) * 16 + m;
+        cok[j] = col[j] < c;
+    }
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const int kb = k0 + 4 * kq;  // this lane's 4 contiguous k values
+        double a[MT][4];
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            int row = row0 + i * 16 + m;
+            const double *ap = A + (int64_t)row * lda + kb;
+            if (row < n && vec_a && kb + 4 <= K) {
+                double2 x0 = *reinterpret_cast<const double2 *>(ap);
+                double2 x1 = *reinterpret_cast<const double2 *>(ap + 2);
+                a[i][0] = x0.x;
+                a[i][1] = x0.y;
+                a[i][2] = x1.x;
+                a[i][3] = x1.y;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[i][q] = (row < n && kb + q < K) ? ap[q] : 0.0;
+            }
+        }
+        double b[4][NT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                b[q][j] = (kb + q < K && cok[j]) ? B[(int64_t)(kb + q) * ldb + col[j]] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[i][j] = mfma16x16x4(a[i][q], b[q][j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            if (!cok[j]) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int row = row0 + i * 16 + kq + 4 * v;
+                if (row < n) {
+                    double *cp = C + (int64_t)row * ldc + col[j];
+                    double prev = (beta != 0.0) ? beta * *cp : 0.0;
+                    *cp = prev + alpha * acc[i][j][v];
+                }
+            }
+        }
+}
+
+}  // namespace
+
+TnPlan plan_tn(int n, int K, int c) {
+    TnPlan p;
+    const int ntiles = ((K + 127) / 128) * ((c + 15) / 16);
+    // aim for ~2048 blocks in total, at least 128 rows per block, and keep
+    // the partial buffer near 32M doubles at most
+    int nch = std::max(1, 2048 / std::max(1, ntiles));
+    int rows = (n + nch - 1) / nch;
+    rows = std::max(rows, 128);
+    size_t per = (size_t)K * c;
+    while ((size_t)((n + rows - 1) / rows) * per > (size_t)(32u << 20)) rows *= 2;
+    rows = (rows + 127) / 128 * 128;
+    p.chunk_rows = rows;
+    p.nchunks = (n + rows - 1) / rows;
+    p.partial_elems = (size_t)p.nchunks * per;
+    return p;
+}
+
+hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, const double *A, int64_t lda,
+                                  const double *B, int64_t ldb, double *partials, hipStream_t s) {
+    constexpr int NT = 8;
+    dim3 grid(pl.nchunks, ((K + 16 * NT - 1) / (16 * NT)) * ((c + 15) / 16));
+    hipLaunchKernelGGL((gemm_tn_partial_kernel<NT>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, lda, B,
+                       ldb, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const TnPlan &pl, int K, int c, const double *partials, double *C, int ldc,
+                                  hipStream_t s) {
+    int total = K * c;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((total + 255) / 256), dim3(256), 0, s, pl.nchunks, K, c,
+                       partials, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn(int n, int K, int c, double alpha, const double *A, int64_t lda, const double *B,
+                          int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t s) {
+    if (n <= 0 || c <= 0) return hipSuccess;
+    bool vec_a = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    if (c <= 16) {
+        constexpr int MT = 4, NT = 1;
+        int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);
+        hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks), dim3(256), 0, s, n, K, c, alpha, A, lda, B,
+                           ldb, beta, C, ldc, vec_a);
+    } else {
+        constexpr int MT = 2, NT = 4;
+        int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);
+        int nct = (c + 16 * NT - 1) / (16 * NT);
+        hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks * nct), dim3(256), 0, s, n, K, c, alpha, A,
+                           lda, B, ldb, beta, C, ldc, vec_a);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ helpers
+
+namespace {
+
+__global__ void gershgorin_kernel(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                                  const double *__restrict__ val, double *__restrict__ part) {
+    __shared__ double slo[256], shi[256];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double lo = 1e308, hi = -1e308;
+    if (i < n) {
+        double d = 0.0, rad = 0.0;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (colind[p] == i)
+                d += val[p];
+            else
+                rad += fabs(val[p]);
+        }
+        lo = d - rad;
+        hi = d + rad;
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + w]);
+            shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = slo[0];
+        part[2 * blockIdx.x + 1] = shi[0];
+    }
+}
+
+__global__ void minmax_kernel(int m, const double *__restrict__ part, double *__restrict__ out) {
+    __shared__ double slo[256], shi[256];
+    double lo = 1e308, hi = -1e308;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        lo = fmin(lo, part[2 * i]);
+        hi = fmax(hi, part[2 * i + 1]);
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + w]);
+            shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = slo[0];
+        out[1] = shi[0];
+    }
+}
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the output function applied
+// to a Weyl sequence; used here as a counter-based generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ void randn_kernel(int rows, int cols, double *__restrict__ out, int64_t ld, uint64_t seed,
+                             uint64_t sid) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)rows * cols;
+    if (idx >= total) return;
+    uint64_t key = splitmix64(seed ^ splitmix64(sid));
+    uint64_t u1 = splitmix64(key + 2 * (uint64_t)idx);
+    uint64_t u2 = splitmix64(key + 2 * (uint64_t)idx + 1);
+    // 53-bit uniforms in (0, 1] and [0, 1); Box-Muller
+    double a = ((u1 >> 11) + 1) * (1.0 / 9007199254740992.0);
+    double b = (u2 >> 11) * (1.0 / 9007199254740992.0);
+    double z = sqrt(-2.0 * log(a)) * cospi(2.0 * b);
+    out[(idx / cols) * ld + idx % cols] = z;
+}
+
+__global__ void copy_block_kernel(int rows, int cols, double scale, const double *__restrict__ src,
+                                  int64_t lds, double *__restrict__ dst, int64_t ldd, float *__restrict__ dst32,
+                                  int64_t ldd32) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)rows * cols) return;
+    int64_t i = idx / cols, j = idx % cols;
+    double v = scale * src[i * lds + j];
+    if (dst) dst[i * ldd + j] = v;
+    if (dst32) dst32[i * ldd32 + j] = (float)v;
+}
+
+__global__ void to_float_kernel(int64_t count, const double *__restrict__ src, float *__restrict__ dst) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = (float)src[i];
+}
+
+__global__ void scale_kernel(int64_t count, double a, const double *__restrict__ src, double *__restrict__ dst) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = a * src[i];
+}
+
+// per (chunk, column): sum of squares of AX - lam X over the chunk's rows
+__global__ void resid_partial_kernel(int n, int c, const double *__restrict__ AX, int64_t ldax,
+                                     const double *__restrict__ X, int64_t ldx, const double *__restrict__ lam,
+                                     int rows_per_chunk, double *__restrict__ part) {
+    __shared__ double red[256];
+    const int chunk = blockIdx.x, j0 = blockIdx.y * 64;
+    const int j = j0 + threadIdx.x % 64, rsub = threadIdx.x / 64;
+    double s = 0.0;
+    if (j < c) {
+        double l = lam[j];
+        int r0 = chunk * rows_per_chunk, r1 = min(n, r0 + rows_per_chunk);
+        for (int i = r0 + rsub; i < r1; i += 4) {
+            double d = AX[(int64_t)i * ldax + j] - l * X[(int64_t)i * ldx + j];
+            s = fma(d, d, s);
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 64 && j < c) {
+        double t = red[threadIdx.x] + red[threadIdx.x + 64] + red[threadIdx.x + 128] + red[threadIdx.x + 192];
+        part[(size_t)chunk * c + j] = t;
+    }
+}
+
+__global__ void resid_final_kernel(int nchunks, int c, const double *__restrict__ part, double *__restrict__ out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= c) return;
+    double s = 0.0;
+    for (int q = 0; q < nchunks; ++q) s += part[(size_t)q * c + j];
+    out[j] = sqrt(s);
+}
+
+__global__ void transpose_out_kernel(int n, int c, const double *__restrict__ src, int64_t lds,
+                                     double *__restrict__ dst) {
+    __shared__ double t[32][33];
+    int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // bx: rows of src, by: columns
+    int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 256 threads: ty 0..7
+    for (int k = ty; k < 32; k += 8) {
+        int i = bx + k, j = by + tx;
+        t[k][tx] = (i < n && j < c) ? src[(int64_t)i * lds + j] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        int j = by + k, i = bx + tx;
+        if (i < n && j < c) dst[(int64_t)j * n + i] = t[tx][k];
+    }
+}
+
+}  // namespace
+
+int gershgorin_blocks(int n) { return (n + 255) / 256; }
+
+hipError_t launch_gershgorin(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double *part,
+                             int part_cap, double *out, hipStream_t s) {
+    int nb = gershgorin_blocks(n);
+    if (nb > part_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gershgorin_kernel, dim3(nb), dim3(256), 0, s, n, rowptr, colind, val, part);
+    hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(256), 0, s, nb, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_randn(int rows, int cols, double *out, int64_t ld, uint64_t seed, uint64_t sid, hipStream_t s) {
+    int64_t total = (int64_t)rows * cols;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(randn_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rows, cols, out, ld,
+                       seed, sid);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_block(int rows, int cols, double scale, const double *src, int64_t lds, double *dst,
+                             int64_t ldd, float *dst32, int64_t ldd32, hipStream_t s) {
+    int64_t total = (int64_t)rows * cols;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rows, cols, scale,
+                       src, lds, dst, ldd, dst32, ldd32);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_float(int64_t count, const double *src, float *dst, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(int64_t count, double a, const double *src, double *dst, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, a, src, dst);
+    return hipGetLastError();
+}
+
+int resid_chunks(int n) { return std::max(1, std::min(512, (n + 1023) / 1024)); }
+
+hipError_t launch_resid_norms(int n, int c, const double *AX, int64_t ldax, const double *X, int64_t ldx,
+                              const double *lam, double *part, int nchunks, double *out, hipStream_t s) {
+    if (c <= 0) return hipSuccess;
+    int rpc = (n + nchunks - 1) / nchunks;
+    hipLaunchKernelGGL(resid_partial_kernel, dim3(nchunks, (c + 63) / 64), dim3(256), 0, s, n, c, AX, ldax, X, ldx,
+                       lam, rpc, part);
+    hipLaunchKernelGGL(resid_final_kernel, dim3((c + 255) / 256), dim3(256), 0, s, nchunks, c, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_out(int n, int c, const double *src, int64_t lds, double *dst, hipStream_t s) {
+    if (n <= 0 || c <= 0) return hipSuccess;
+    dim3 grid((n + 31) / 32, (c + 31) / 32);
+    hipLaunchKernelGGL(transpose_out_kernel, grid, dim3(256), 0, s, n, c, src, lds, dst);
+    return hipGetLastError();
+}
+
+}  // namespace flp

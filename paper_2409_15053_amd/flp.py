@@ -1,0 +1,309 @@
+"""ctypes binding of the C ABI in include/flp.h (argument marshalling only).
+
+Every function here forwards to the HIP library ``libflp.so``; nothing is
+computed in Python.  Device buffers are torch CUDA (HIP) tensors; streams
+are torch streams.  If the library is not built, the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflp.so")
+
+FLP_OK = 0
+FLP_E_ARG = -1
+FLP_E_INTERVAL = -2
+FLP_E_NOTSYM = -3
+FLP_E_NOMEM = -4
+FLP_E_NOCONV = -5
+FLP_E_DEVICE = -6
+FLP_PREC_FP64 = 0
+FLP_PREC_FP32_FILTER = 1
+
+EXPORTS = [
+    "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
+    "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval",
+    "flp_filter_apply", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
+    "flp_solve", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
+    "flp_release_workspace", "flp_last_error", "flp_version",
+]
+
+
+class FlpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"flp error {code}: {msg}")
+        self.code = code
+
+
+class FlpCsrC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val32", ctypes.c_void_p)]
+
+
+class FlpOptsC(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("degree", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("max_basis", ctypes.c_int64), ("k0", ctypes.c_int32),
+                ("start", ctypes.c_void_p), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class FlpStatsC(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("mv", ctypes.c_int64), ("basis_cols", ctypes.c_int32),
+                ("polish_sweeps", ctypes.c_int32), ("t_pre", ctypes.c_double), ("t_mv", ctypes.c_double),
+                ("t_orth", ctypes.c_double), ("t_check", ctypes.c_double), ("t_rr", ctypes.c_double),
+                ("t_total", ctypes.c_double), ("filter_bytes", ctypes.c_double)]
+
+
+class FlpResultC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("count", ctypes.c_int32), ("evals", ctypes.POINTER(ctypes.c_double)),
+                ("resid", ctypes.POINTER(ctypes.c_double)), ("evecs", ctypes.c_void_p),
+                ("lmin", ctypes.c_double), ("lmax", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("degree", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("stats", FlpStatsC)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libflp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run python -m paper_2409_15053_amd.build)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, F64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "flp_opts_default": (None, [ctypes.POINTER(FlpOptsC)]),
+        "flp_build_filter": (ctypes.c_int, [F64, F64, I32, F64, F64, PP]),
+        "flp_build_filter_eps": (ctypes.c_int, [F64, F64, I32, F64, F64, F64, PP]),
+        "flp_filter_free": (None, [P]),
+        "flp_filter_degree": (I32, [P]),
+        "flp_filter_coeffs": (I32, [P, P, I32]),
+        "flp_filter_info": (ctypes.c_int, [P, P]),
+        "flp_filter_eval": (ctypes.c_int, [P, P, P, I32]),
+        "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, P, I32, I32, P]),
+        "flp_spmm": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), P, I32, P, I32, I32, P]),
+        "flp_block_orth": (ctypes.c_int, [P, I64, I32, I32, P, I32, P, P]),
+        "flp_block_qr": (ctypes.c_int, [P, I32, I32, P, P]),
+        "flp_estimate_bounds": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, U64, P, P, P]),
+        "flp_solve": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), F64, F64, ctypes.POINTER(FlpOptsC),
+                                     ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
+        "flp_result_free": (None, [ctypes.POINTER(FlpResultC)]),
+        "flp_result_copy_evecs": (ctypes.c_int, [ctypes.POINTER(FlpResultC), P, P]),
+        "flp_host_sym_eig": (ctypes.c_int, [I32, I32, P, P, P]),
+        "flp_release_workspace": (None, []),
+        "flp_last_error": (ctypes.c_char_p, []),
+        "flp_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow=()):
+    if rc != FLP_OK and rc not in allow:
+        raise FlpError(rc, load().flp_last_error().decode())
+    return rc
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ matrices
+
+class DeviceCsr:
+    """A CSR matrix resident in device memory (torch tensors kept alive here)."""
+
+    def __init__(self, n, rowptr, colind, val, val32=None):
+        self.n = int(n)
+        self.rowptr, self.colind, self.val, self.val32 = rowptr, colind, val, val32
+        self.nnz = int(colind.numel())
+        self.c = FlpCsrC(self.n, self.nnz, rowptr.data_ptr(), colind.data_ptr(), val.data_ptr(),
+                         val32.data_ptr() if val32 is not None else None)
+
+    @classmethod
+    def from_host(cls, A, device="cuda:0", with_fp32: bool = False):
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(A.rowptr, dtype=np.int32)).to(device)
+        ci = torch.from_numpy(np.ascontiguousarray(A.colind, dtype=np.int32)).to(device)
+        va = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device)
+        v32 = va.float() if with_fp32 else None
+        return cls(A.n, rp, ci, va, v32)
+
+
+# ------------------------------------------------------------------ filter
+
+class Filter:
+    """Owner of an flp_filter handle."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.flp_filter_free(self.h)
+            self.h = None
+
+    @property
+    def degree(self) -> int:
+        return int(load().flp_filter_degree(self.h))
+
+    def coeffs(self) -> np.ndarray:
+        m1 = load().flp_filter_coeffs(self.h, None, 0)
+        out = np.zeros(m1)
+        _check(0 if load().flp_filter_coeffs(self.h, _np_ptr(out), m1) == m1 else -1)
+        return out
+
+    def info(self) -> dict:
+        o = np.zeros(6)
+        _check(load().flp_filter_info(self.h, _np_ptr(o)))
+        return dict(lmin=o[0], lmax=o[1], c=o[2], e=o[3], alpha=o[4], beta=o[5])
+
+    def eval(self, z) -> np.ndarray:
+        z = np.ascontiguousarray(np.atleast_1d(z), dtype=np.float64)
+        out = np.zeros_like(z)
+        _check(load().flp_filter_eval(self.h, _np_ptr(z), _np_ptr(out), z.size))
+        return out
+
+
+def flp_build_filter(alpha: float, beta: float, degree: int, lmin: float, lmax: float,
+                     eps: float | None = None) -> Filter:
+    lib = load()
+    h = ctypes.c_void_p()
+    if eps is None:
+        _check(lib.flp_build_filter(alpha, beta, degree, lmin, lmax, ctypes.byref(h)))
+    else:
+        _check(lib.flp_build_filter_eps(alpha, beta, degree, lmin, lmax, eps, ctypes.byref(h)))
+    return Filter(h)
+
+
+def flp_filter_apply(filt: Filter, A: DeviceCsr, V, W, prec: int = FLP_PREC_FP64, stream=None):
+    """W = p(Ahat) V on the device (V, W: contiguous float64 n x r tensors)."""
+    assert V.is_contiguous() and W.is_contiguous() and V.dtype == W.dtype
+    r = 1 if V.dim() == 1 else V.shape[1]
+    _check(load().flp_filter_apply(filt.h, ctypes.byref(A.c), V.data_ptr(), W.data_ptr(), r, prec,
+                                   _stream_ptr(stream)))
+
+
+def flp_spmm(A: DeviceCsr, X, Y, stream=None):
+    r = 1 if X.dim() == 1 else X.shape[1]
+    ldx = r if X.dim() == 1 else X.stride(0)
+    ldy = r if Y.dim() == 1 else Y.stride(0)
+    _check(load().flp_spmm(ctypes.byref(A.c), X.data_ptr(), ldx, Y.data_ptr(), ldy, r, _stream_ptr(stream)))
+
+
+def flp_block_orth(Q, k: int, W, stream=None) -> np.ndarray:
+    """CGS2 of W (n x r) against the first k columns of Q (n x ldq); returns H (k x r)."""
+    n, r = W.shape
+    H = np.zeros((k, r))
+    _check(load().flp_block_orth(Q.data_ptr(), Q.stride(0), k, n, W.data_ptr(), r, _np_ptr(H),
+                                 _stream_ptr(stream)))
+    return H
+
+
+def flp_block_qr(W, stream=None) -> np.ndarray:
+    n, r = W.shape
+    S = np.zeros((r, r))
+    _check(load().flp_block_qr(W.data_ptr(), n, r, _np_ptr(S), _stream_ptr(stream)))
+    return S
+
+
+def flp_estimate_bounds(A: DeviceCsr, k0: int = 40, seed: int = 0, stream=None):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(load().flp_estimate_bounds(ctypes.byref(A.c), k0, seed, ctypes.byref(lo), ctypes.byref(hi),
+                                      _stream_ptr(stream)))
+    return lo.value, hi.value
+
+
+def flp_host_sym_eig(M: np.ndarray, bw: int | None = None, vectors: bool = True):
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    N = M.shape[0]
+    ev = np.zeros(N)
+    Z = np.zeros((N, N)) if vectors else None
+    _check(load().flp_host_sym_eig(N, N - 1 if bw is None else bw, _np_ptr(M), _np_ptr(ev),
+                                   _np_ptr(Z) if vectors else None))
+    return (ev, Z) if vectors else ev
+
+
+def default_opts() -> FlpOptsC:
+    o = FlpOptsC()
+    load().flp_opts_default(ctypes.byref(o))
+    return o
+
+
+def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: int = 0, seed: int = 0,
+              prec: int = FLP_PREC_FP64, start: np.ndarray | None = None, bounds=None, max_basis: int = 0,
+              check_every: int = 0, eps: float = 0.0, k0: int = 0, want_vectors: bool = True,
+              stream=None) -> dict:
+    """Every eigenpair of A in [alpha, beta].  Returns a dict with numpy
+    ``evals``/``resid``, a torch ``evecs`` (n x count, float64, on A's
+    device) and the solve statistics."""
+    import torch
+    lib = load()
+    o = default_opts()
+    o.block = block
+    o.degree = degree
+    o.seed = seed
+    o.prec = prec
+    o.max_basis = max_basis
+    if check_every:
+        o.check_every = check_every
+    if eps:
+        o.eps = eps
+    if k0:
+        o.k0 = k0
+    keep = None
+    if start is not None:
+        keep = np.ascontiguousarray(start, dtype=np.float64)
+        o.start = _np_ptr(keep)
+    if bounds is not None:
+        o.lmin, o.lmax = bounds
+    o.stream = _stream_ptr(stream)
+    res = ctypes.POINTER(FlpResultC)()
+    rc = lib.flp_solve(ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(res))
+    _check(rc, allow=(FLP_E_NOCONV,))
+    try:
+        r = res.contents
+        cnt = r.count
+        evals = np.array([r.evals[i] for i in range(cnt)], dtype=np.float64)
+        resid = np.array([r.resid[i] for i in range(cnt)], dtype=np.float64)
+        evecs = None
+        if want_vectors:
+            evecs_t = torch.empty((cnt, A.n), dtype=torch.float64, device=A.val.device)
+            if cnt:
+                _check(lib.flp_result_copy_evecs(res, evecs_t.data_ptr(), _stream_ptr(stream)))
+            evecs = evecs_t.t()
+        st = r.stats
+        stats = {f: getattr(st, f) for f, _ in FlpStatsC._fields_}
+        out = dict(evals=evals, resid=resid, evecs=evecs, count=cnt, lmin=r.lmin, lmax=r.lmax,
+                   degree=r.degree, converged=bool(r.converged), rc=rc, stats=stats)
+    finally:
+        lib.flp_result_free(res)
+    return out
+
+
+def flp_release_workspace():
+    load().flp_release_workspace()
+
+
+def flp_version() -> str:
+    return load().flp_version().decode()

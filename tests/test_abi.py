@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol declared in include/flp.h, validates arguments, and its host-side
+arithmetic (filter coefficients, degree rule, banded eigensolver) matches
+the oracle and LAPACK."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import flp_oracle as O
+from paper_2409_15053_amd import flp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "flp.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(flp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = flp.load()
+    names = declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(flp.EXPORTS)
+
+
+def test_version():
+    assert flp.flp_version().startswith("flp-mi355x")
+
+
+@pytest.mark.parametrize("alpha,beta,lmin,lmax,m", [
+    (0.5, 1.0, 0.0, 8.0, 50), (-0.645, -0.0053, -1.21, 32.8, 0), (-1.0, -0.5, -1.0, 1.0, 80),
+    (0.1, 0.3, -1.0, 1.0, 0), (-5.0, 0.2, -1.0, 1.0, 10)])
+def test_filter_matches_oracle(alpha, beta, lmin, lmax, m):
+    f = flp.flp_build_filter(alpha, beta, m, lmin, lmax)
+    info = f.info()
+    c, e = O.affine_map(lmin, lmax)
+    a1 = min(max((max(alpha, lmin) - c) / e, -1), 1)
+    b1 = min(max((min(beta, lmax) - c) / e, -1), 1)
+    assert abs(info["alpha"] - a1) < 1e-15 and abs(info["beta"] - b1) < 1e-15
+    want_m = m if m > 0 else O.filter_degree(a1, b1)
+    assert f.degree == want_m
+    b = O.cheb_coeffs(a1, b1, want_m)
+    assert np.max(np.abs(f.coeffs() - b)) < 1e-14
+    z = np.linspace(-1, 1, 41)
+    assert np.max(np.abs(f.eval(z) - O.cheb_eval(b, z))) < 1e-12
+
+
+def test_filter_table2_auto_degrees_through_abi():
+    rows = [(-1.21, 32.8, -0.645, -0.0053, 49), (-1.23, 32.7, -0.650, -0.0096, 49),
+            (-1.21, 49.8, -0.640, -0.0028, 61), (-1.20, 43.1, -0.660, -0.3300, 98),
+            (-1.25, 1300.0, -0.640, 0.0, 308)]
+    for lo, hi, a, b, m in rows:
+        assert flp.flp_build_filter(a, b, 0, lo, hi).degree == m
+
+
+@pytest.mark.parametrize("args,code", [
+    ((1.0, 0.5, 10, -1.0, 1.0), flp.FLP_E_ARG),           # alpha >= beta
+    ((float("nan"), 0.5, 10, -1.0, 1.0), flp.FLP_E_ARG),  # NaN
+    ((0.0, 0.5, 10, 1.0, -1.0), flp.FLP_E_ARG),           # lmin >= lmax
+    ((2.0, 3.0, 10, -1.0, 1.0), flp.FLP_E_INTERVAL),      # outside the spectrum
+    ((0.0, 0.5, 200000, -1.0, 1.0), flp.FLP_E_ARG),       # degree too large
+])
+def test_filter_argument_errors(args, code):
+    with pytest.raises(flp.FlpError) as ei:
+        flp.flp_build_filter(*args)
+    assert ei.value.code == code
+
+
+def test_solve_rejects_bad_csr_without_gpu():
+    lib = flp.load()
+    A = flp.FlpCsrC(0, 0, None, None, None, None)
+    res = ctypes.POINTER(flp.FlpResultC)()
+    assert lib.flp_solve(ctypes.byref(A), 0.0, 1.0, None, ctypes.byref(res)) == flp.FLP_E_ARG
+    assert b"n must be positive" in lib.flp_last_error()
+    A = flp.FlpCsrC(10, 1 << 31, 1, 1, 1, None)
+    assert lib.flp_solve(ctypes.byref(A), 0.0, 1.0, None, ctypes.byref(res)) == flp.FLP_E_ARG
+
+
+@pytest.mark.parametrize("N,bw", [(1, 0), (2, 1), (7, 1), (60, 1), (60, 3), (97, 8), (120, 16), (80, 79)])
+def test_host_banded_eigensolver_against_lapack(N, bw):
+    g = np.random.Generator(np.random.PCG64(N * 100 + bw))
+    M = g.standard_normal((N, N))
+    M = M + M.T
+    i, j = np.indices((N, N))
+    M[np.abs(i - j) > bw] = 0.0
+    ev, Z = flp.flp_host_sym_eig(M, bw)
+    w = np.linalg.eigvalsh(M)
+    scale = max(1.0, np.max(np.abs(w)))
+    assert np.max(np.abs(ev - w)) < 1e-13 * scale * max(1, N) ** 0.5
+    assert np.max(np.abs(M @ Z - Z * ev)) < 1e-12 * scale * max(1, N) ** 0.5
+    assert np.max(np.abs(Z.T @ Z - np.eye(N))) < 1e-12 * max(1, N) ** 0.5
+
+
+def test_host_eigensolver_degenerate_and_clustered():
+    # block-tridiagonal with exact multiplicities and a tight cluster
+    d = np.array([1.0, 1.0, 1.0, 2.0, 2.0 + 1e-13, 3.0, -1.0, -1.0])
+    g = np.random.Generator(np.random.PCG64(5))
+    Qr, _ = np.linalg.qr(g.standard_normal((8, 8)))
+    M = (Qr * d) @ Qr.T
+    M = 0.5 * (M + M.T)
+    ev, Z = flp.flp_host_sym_eig(M)
+    assert np.max(np.abs(ev - np.sort(d))) < 1e-14 * 8
+    assert np.max(np.abs(Z.T @ Z - np.eye(8))) < 1e-13
+    assert np.max(np.abs(M @ Z - Z * ev)) < 1e-13

@@ -1,0 +1,228 @@
+"""GPU parity of the individual hot-path calls against the CPU oracle.
+
+Every call goes through the C ABI (libflp.so) and is compared element by
+element with the oracle on the same seeded inputs.
+
+Tolerances (derived from the arithmetic, stated per test):
+* SpMM: each output sums at most k = max nnz/row products, so
+  |err| <= k u sum_j |a_ij x_j| (u = 2^-53), for both sides together 2k u.
+* filter (Clenshaw on the GPU vs the forward recurrence in the oracle):
+  each of the m steps rounds an SpMM plus a three-term update, and the
+  rounding errors of step k reach the result through the recurrence with
+  a gain of at most m (Chebyshev polynomials of the second kind are
+  bounded by their degree on [-1, 1]); hence
+  |err| <= 2 m^2 (k + 4) u sum_i |b_i| max|V| for both sides together.
+  FP32 filter: the same bound with u = 2^-24 and m in place of m^2 (the
+  FP64 oracle's own error is negligible; the FP32 error is dominated by
+  the rounding of V, A and each step, which the filter sums with gain
+  sum_i |b_i|).
+* Gram-Schmidt / QR: backward stable, 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import flp_oracle as O
+from paper_2409_15053_amd import flp
+from paper_2409_15053_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible MI355X"
+    flp.load()
+    return t
+
+
+def dev(t, a):
+    return t.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def max_row_nnz(A):
+    return int(np.max(np.diff(A.rowptr)))
+
+
+MATRICES = {
+    "lap2d_13": lambda: I.laplacian_2d(13),
+    "rand_97": lambda: I.random_sym(97, 0.08, seed=3),
+    "lap3d7_9_U": lambda: I.laplacian_3d(9, I.uniform_potential(9, 4)),
+    "lap3d13_8_wells": lambda: I.laplacian_3d_13pt(8, I.gaussian_wells(8, 5)),
+    "diag_31": lambda: I.diagonal_csr(np.linspace(-2, 3, 31)),
+}
+
+
+@pytest.mark.parametrize("name", list(MATRICES))
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 8, 16, 32])
+def test_spmm_parity(torch, name, r):
+    A = MATRICES[name]()
+    X = I.random_block(A.n, r, seed=r)
+    dA = flp.DeviceCsr.from_host(A)
+    Y = torch.zeros((A.n, r), dtype=torch.float64, device="cuda:0")
+    flp.flp_spmm(dA, dev(torch, X), Y)
+    torch.cuda.synchronize()
+    want = O.spmm(A, X)
+    bound = 2 * max_row_nnz(A) * U64 * (np.abs(A.to_scipy()) @ np.abs(X))
+    assert np.all(np.abs(Y.cpu().numpy() - want) <= bound + 1e-300)
+
+
+def test_spmm_strided_block(torch):
+    A = I.laplacian_3d(7)
+    X = I.random_block(A.n, 20, seed=1)
+    dA = flp.DeviceCsr.from_host(A)
+    Xd = dev(torch, X)
+    Y = torch.zeros((A.n, 20), dtype=torch.float64, device="cuda:0")
+    flp.flp_spmm(dA, Xd[:, 4:12], Y[:, 2:10])
+    torch.cuda.synchronize()
+    got = Y.cpu().numpy()
+    assert np.allclose(got[:, 2:10], O.spmm(A, X[:, 4:12]), rtol=0, atol=1e-12)
+    assert np.all(got[:, :2] == 0) and np.all(got[:, 10:] == 0)
+
+
+def filter_case(A, alpha, beta, m, r, seed):
+    lmin, lmax = O.gershgorin(A)
+    f = flp.flp_build_filter(alpha, beta, m, lmin, lmax)
+    b = f.coeffs()
+    V = I.random_block(A.n, r, seed=seed)
+    return f, b, V, lmin, lmax
+
+
+@pytest.mark.parametrize("name", list(MATRICES))
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 17, 60])
+@pytest.mark.parametrize("r", [1, 3, 8, 16])
+def test_filter_apply_fp64_parity(torch, name, m, r):
+    A = MATRICES[name]()
+    lmin, lmax = O.gershgorin(A)
+    width = lmax - lmin
+    alpha, beta = lmin + 0.3 * width, lmin + 0.45 * width
+    f, b, V, lmin, lmax = filter_case(A, alpha, beta, m, r, seed=m * 7 + r)
+    dA = flp.DeviceCsr.from_host(A)
+    W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+    flp.flp_filter_apply(f, dA, dev(torch, V), W)
+    torch.cuda.synchronize()
+    want = O.filter_apply(A, lmin, lmax, b, V)
+    k = max_row_nnz(A)
+    tol = 2 * m * m * (k + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    err = np.max(np.abs(W.cpu().numpy() - want))
+    assert err <= tol, (err, tol)
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 40])
+@pytest.mark.parametrize("r", [1, 4, 8, 16])
+def test_filter_apply_fp32_parity(torch, m, r):
+    A = I.laplacian_3d(10, I.uniform_potential(10, 9))
+    lmin, lmax = O.gershgorin(A)
+    f, b, V, lmin, lmax = filter_case(A, 6.0, 7.5, m, r, seed=m + r)
+    dA = flp.DeviceCsr.from_host(A)
+    W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+    flp.flp_filter_apply(f, dA, dev(torch, V), W, prec=flp.FLP_PREC_FP32_FILTER)
+    torch.cuda.synchronize()
+    want = O.filter_apply(A, lmin, lmax, b, V)
+    k = max_row_nnz(A)
+    tol = 2 * m * (k + 4) * U32 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    err = np.max(np.abs(W.cpu().numpy() - want))
+    assert err <= tol, (err, tol)
+
+
+def test_filter_apply_ragged_large_grid(torch):
+    """Several thousand tiles with a ragged tail (n not a multiple of any tile)."""
+    A = I.laplacian_3d_13pt(37, I.gaussian_wells(37, 11))   # n = 50653
+    lmin, lmax = O.gershgorin(A)
+    f = flp.flp_build_filter(-2.0, -0.5, 30, lmin, lmax)
+    b = f.coeffs()
+    V = I.random_block(A.n, 16, seed=2)
+    dA = flp.DeviceCsr.from_host(A)
+    W = torch.empty((A.n, 16), dtype=torch.float64, device="cuda:0")
+    flp.flp_filter_apply(f, dA, dev(torch, V), W)
+    torch.cuda.synchronize()
+    want = O.filter_apply(A, lmin, lmax, b, V)
+    tol = 2 * 30 * 30 * (13 + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    assert np.max(np.abs(W.cpu().numpy() - want)) <= tol
+
+
+def test_filter_apply_errors(torch):
+    A = I.laplacian_2d(5)
+    dA = flp.DeviceCsr.from_host(A)
+    f = flp.flp_build_filter(1.0, 2.0, 5, 0.0, 8.0)
+    V = torch.zeros((A.n, 2), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(flp.FlpError):
+        flp.flp_filter_apply(f, dA, V, V)  # aliasing
+    W = torch.zeros((A.n, 40), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(flp.FlpError):
+        flp.flp_filter_apply(f, dA, torch.zeros_like(W), W)  # r > 32
+
+
+@pytest.mark.parametrize("n,k,r", [(1000, 1, 1), (1000, 7, 3), (5003, 48, 8), (20011, 160, 16), (777, 16, 16)])
+def test_block_orth_parity(torch, n, k, r):
+    g = np.random.Generator(np.random.PCG64(n + k))
+    Q, _ = np.linalg.qr(g.standard_normal((n, k)))
+    ldq = k + 5
+    Qp = np.zeros((n, ldq))
+    Qp[:, :k] = Q
+    W = g.standard_normal((n, r))
+    Qd = dev(torch, Qp)
+    Wd = dev(torch, W)
+    H = flp.flp_block_orth(Qd, k, Wd)
+    # the definition: two passes of classical Gram-Schmidt
+    H1 = Q.T @ W
+    W1 = W - Q @ H1
+    H2 = Q.T @ W1
+    W2 = W1 - Q @ H2
+    assert np.max(np.abs(H - (H1 + H2))) < 1e-12 * np.max(np.abs(W)) * np.sqrt(n)
+    got = Wd.cpu().numpy()
+    assert np.max(np.abs(got - W2)) < 1e-12 * np.max(np.abs(W))
+    assert np.max(np.abs(Q.T @ got)) < 1e-13 * np.sqrt(n) * np.max(np.abs(W))
+
+
+@pytest.mark.parametrize("n,r", [(100, 1), (1000, 3), (4099, 8), (30000, 16)])
+def test_block_qr_parity(torch, n, r):
+    g = np.random.Generator(np.random.PCG64(n * r))
+    W = g.standard_normal((n, r)) @ np.triu(g.standard_normal((r, r)) + 3 * np.eye(r))
+    Wd = dev(torch, W)
+    S = flp.flp_block_qr(Wd)
+    Qn = Wd.cpu().numpy()
+    # unique QR with a positive diagonal (eq. lanczos: S upper triangular)
+    Qr, R = np.linalg.qr(W)
+    sg = np.sign(np.diag(R))
+    R = sg[:, None] * R
+    assert np.allclose(np.tril(S, -1), 0)
+    assert np.all(np.diag(S) > 0)
+    assert np.max(np.abs(S - R)) < 1e-11 * np.max(np.abs(R))
+    assert np.max(np.abs(Qn.T @ Qn - np.eye(r))) < 1e-13
+    assert np.max(np.abs(Qn @ S - W)) < 1e-12 * np.max(np.abs(W))
+
+
+def test_block_qr_rank_deficient_is_reported(torch):
+    g = np.random.Generator(np.random.PCG64(1))
+    W = g.standard_normal((500, 4))
+    W[:, 3] = W[:, 0] - 2 * W[:, 1]
+    with pytest.raises(flp.FlpError):
+        flp.flp_block_qr(dev(torch, W))
+
+
+def lap1d(N):
+    j = np.arange(1, N + 1)
+    return 4 * np.sin(j * np.pi / (2 * (N + 1))) ** 2
+
+
+@pytest.mark.parametrize("case", ["2d40", "3d20", "3d13pt16"])
+def test_bounds_enclose_spectrum(torch, case):
+    if case == "2d40":
+        A, lo, hi = I.laplacian_2d(40), 2 * lap1d(40)[0], 2 * lap1d(40)[-1]
+    elif case == "3d20":
+        A, lo, hi = I.laplacian_3d(20), 3 * lap1d(20)[0], 3 * lap1d(20)[-1]
+    else:
+        A = I.laplacian_3d_13pt(16)
+        w = np.linalg.eigvalsh(np.diag(np.full(16, 2.5)) + np.diag(np.full(15, -4 / 3), 1) +
+                               np.diag(np.full(15, -4 / 3), -1) + np.diag(np.full(14, 1 / 12), 2) +
+                               np.diag(np.full(14, 1 / 12), -2))
+        lo, hi = 3 * w[0], 3 * w[-1]
+    dA = flp.DeviceCsr.from_host(A)
+    lmin, lmax = flp.flp_estimate_bounds(dA, 40, 7)
+    glo, ghi = O.gershgorin(A)
+    assert lmin <= lo and lmax >= hi
+    assert glo <= lmin and lmax <= ghi

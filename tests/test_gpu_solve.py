@@ -1,0 +1,184 @@
+"""End-to-end parity of flp_solve (GPU, through the C ABI) against the
+oracle and against closed forms.
+
+Contract (stated for every result): the eigenvalue count in [alpha, beta]
+is exact, eigenvalues agree within 1e-10 relative, and every residual
+||A x - lambda x|| / ||A|| is at most 1e-9.  Eigenvectors are compared by
+principal angles inside each cluster (eigenvalues closer than 1e-8 ||A||),
+||sin Theta|| <= 1e-7.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import flp_oracle as O
+from paper_2409_15053_amd import flp
+from paper_2409_15053_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible MI355X"
+    flp.load()
+    return t
+
+
+def lap1d(N):
+    j = np.arange(1, N + 1)
+    return 4 * np.sin(j * np.pi / (2 * (N + 1))) ** 2
+
+
+def check_against(res, want_vals, want_vecs=None, anorm=None):
+    got = np.sort(res["evals"])
+    assert res["count"] == len(want_vals), (res["count"], len(want_vals))
+    if len(want_vals) == 0:
+        return
+    rel = np.abs(got - want_vals) / np.maximum(np.abs(want_vals), 1e-300)
+    assert np.max(rel) <= 1e-10, np.max(rel)
+    assert np.max(res["resid"]) <= 1e-9, np.max(res["resid"])
+    X = res["evecs"].cpu().numpy()
+    assert np.max(np.abs(X.T @ X - np.eye(X.shape[1]))) < 1e-10
+    if want_vecs is not None:
+        # principal angles per cluster
+        gap = 1e-8 * anorm
+        i = 0
+        while i < len(want_vals):
+            j = i + 1
+            while j < len(want_vals) and want_vals[j] - want_vals[j - 1] < gap:
+                j += 1
+            Ug = X[:, i:j]
+            Uw = want_vecs[:, i:j]
+            s = np.linalg.svd(Uw.T @ Ug, compute_uv=False)
+            sin_max = math.sqrt(max(0.0, 1.0 - float(np.min(s)) ** 2))
+            assert sin_max <= 1e-7, (i, j, sin_max)
+            i = j
+
+
+def test_c1_laplacian_2d(torch):
+    """2D 5-point Laplacian on 40 x 40, [0.5, 1.0], degree 50, r = 1: the 69
+    eigenvalues 4 sin^2(j pi/82) + 4 sin^2(k pi/82) (33 of them double)."""
+    w = I.workload_c1()
+    A = w["A"]
+    mu = lap1d(40)
+    exact = np.sort((mu[:, None] + mu[None, :]).ravel())
+    exact = exact[(exact >= 0.5) & (exact <= 1.0)]
+    dA = flp.DeviceCsr.from_host(A)
+    res = flp.flp_solve(dA, 0.5, 1.0, block=1, degree=50, seed=w["seed"])
+    assert res["converged"]
+    lam, V = O.dense_eigs_in_interval(A, 0.5, 1.0)
+    check_against(res, exact, V, anorm=8.0)
+    assert res["stats"]["mv"] == 1 * 50 * res["stats"]["iters"]
+    # the oracle on the same problem finds the same set
+    ores = O.flp_solve(A, 0.5, 1.0, block=1, degree=50, seed=w["seed"])
+    assert len(ores.evals) == res["count"]
+    assert np.max(np.abs(np.sort(ores.evals) - np.sort(res["evals"])) / exact) <= 1e-10
+
+
+@pytest.mark.parametrize("block", [1, 2, 3, 4])
+def test_random_sparse_interior(torch, block):
+    A = I.random_sym(600, 0.015, seed=40 + block)
+    lam_all = np.linalg.eigvalsh(A.to_dense())
+    i0, i1 = 250, 289
+    alpha = 0.5 * (lam_all[i0 - 1] + lam_all[i0])
+    beta = 0.5 * (lam_all[i1] + lam_all[i1 + 1])
+    dA = flp.DeviceCsr.from_host(A)
+    res = flp.flp_solve(dA, alpha, beta, block=block, seed=3)
+    want, V = O.dense_eigs_in_interval(A, alpha, beta)
+    check_against(res, want, V, anorm=np.max(np.abs(lam_all)))
+
+
+@pytest.mark.parametrize("kind,N,block", [("7pt", 16, 8), ("13pt", 13, 16), ("7pt", 20, 4)])
+def test_kronecker_separable_3d(torch, kind, N, block):
+    field, vx, vy, vz = I.separable_potential(N, seed=17 + N)
+    if kind == "7pt":
+        A = I.laplacian_3d(N, field)
+        st = {0: 2.0, 1: -1.0}
+    else:
+        A = I.laplacian_3d_13pt(N, field)
+        st = {0: I.FOURTH_ORDER_1D[0], 1: I.FOURTH_ORDER_1D[1], 2: I.FOURTH_ORDER_1D[2]}
+
+    def one_d(v):
+        T = np.zeros((N, N))
+        for d, cf in st.items():
+            idx = np.arange(N - d)
+            T[idx, idx + d] = cf
+            T[idx + d, idx] = cf
+        np.fill_diagonal(T, st[0] + v)
+        return np.linalg.eigvalsh(T)
+
+    a, b, c = one_d(vx), one_d(vy), one_d(vz)
+    spec = np.sort((a[:, None, None] + b[None, :, None] + c[None, None, :]).ravel())
+    i0, i1 = 5, 84
+    alpha = 0.5 * (spec[i0 - 1] + spec[i0])
+    beta = 0.5 * (spec[i1] + spec[i1 + 1])
+    dA = flp.DeviceCsr.from_host(A)
+    res = flp.flp_solve(dA, alpha, beta, block=block, seed=N)
+    check_against(res, spec[i0:i1 + 1])
+
+
+def test_hamiltonian_wells_dense(torch):
+    N = 15
+    A = I.laplacian_3d_13pt(N, I.gaussian_wells(N, I.BASE_SEED + 3))
+    lam_all = np.linalg.eigvalsh(A.to_dense())
+    i0, i1 = 10, 69
+    alpha = 0.5 * (lam_all[i0 - 1] + lam_all[i0])
+    beta = 0.5 * (lam_all[i1] + lam_all[i1 + 1])
+    dA = flp.DeviceCsr.from_host(A)
+    res = flp.flp_solve(dA, alpha, beta, block=16, seed=1)
+    want, V = O.dense_eigs_in_interval(A, alpha, beta)
+    check_against(res, want, V, anorm=np.max(np.abs(lam_all)))
+
+
+def test_uniform_potential_lowest_block8(torch):
+    N = 16
+    A = I.laplacian_3d(N, I.uniform_potential(N, I.BASE_SEED + 2))
+    lam_all = np.linalg.eigvalsh(A.to_dense())
+    i1 = 49
+    alpha = lam_all[0] - 1.0
+    beta = 0.5 * (lam_all[i1] + lam_all[i1 + 1])
+    dA = flp.DeviceCsr.from_host(A)
+    res = flp.flp_solve(dA, alpha, beta, block=8, seed=2)
+    want, V = O.dense_eigs_in_interval(A, alpha, beta)
+    check_against(res, want, V, anorm=np.max(np.abs(lam_all)))
+
+
+def test_empty_interval_in_gap(torch):
+    A = I.diagonal_csr(np.array([0.0, 1.0, 2.0, 3.0, 4.0] * 20))
+    dA = flp.DeviceCsr.from_host(A)
+    res = flp.flp_solve(dA, 1.2, 1.8, block=1, seed=1)
+    assert res["count"] == 0
+
+
+def test_interval_outside_spectrum_errors(torch):
+    A = I.laplacian_2d(10)
+    dA = flp.DeviceCsr.from_host(A)
+    with pytest.raises(flp.FlpError) as ei:
+        flp.flp_solve(dA, 100.0, 200.0, block=1)
+    assert ei.value.code == flp.FLP_E_INTERVAL
+
+
+def test_multiplicity_with_blocks(torch):
+    """A diagonal matrix with a 5-fold eigenvalue inside the interval; block
+    Lanczos (Section 2.3) recovers every copy through breakdown repair."""
+    d = np.concatenate([np.linspace(-3, -1, 150), np.full(5, 0.5), np.linspace(1, 4, 150)])
+    A = I.diagonal_csr(d)
+    dA = flp.DeviceCsr.from_host(A)
+    res = flp.flp_solve(dA, 0.0, 0.9, block=2, seed=4)
+    assert res["count"] == 5
+    assert np.max(np.abs(res["evals"] - 0.5)) < 1e-12
+    assert np.max(res["resid"]) <= 1e-9
+
+
+def test_start_block_given(torch):
+    A = I.laplacian_2d(30)
+    mu = lap1d(30)
+    exact = np.sort((mu[:, None] + mu[None, :]).ravel())
+    exact = exact[(exact >= 1.0) & (exact <= 1.6)]
+    dA = flp.DeviceCsr.from_host(A)
+    start = I.random_block(A.n, 4, seed=9)
+    res = flp.flp_solve(dA, 1.0, 1.6, block=4, start=start)
+    check_against(res, exact)
