@@ -30,6 +30,9 @@ DEVICE = [
     "--offload-arch=" + ARCH,
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # keep MFMA accumulators in VGPRs (avoids AGPR<->VGPR copies every
+    # iteration in the tall-skinny GEMM loops)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

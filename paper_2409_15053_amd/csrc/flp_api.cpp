@@ -278,25 +278,50 @@ int ensure_val32(const flp_csr *A, const float **out, hipStream_t s) {
     return FLP_OK;
 }
 
-// W = p(Ahat) V with the workspace's Clenshaw buffers.
-int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, double *W, int r, int prec,
-                      hipStream_t s) {
+// Width of the column groups the filter runs on.  The Clenshaw recurrence
+// acts on each column independently, so a block of r columns can be
+// filtered as several narrower groups, each through all m steps.  A group
+// whose per-step working set (matrix + V + three recurrence vectors) fits
+// in the 256 MB Infinity Cache streams from that cache instead of HBM for
+// steps 2..m; this costs one extra matrix read per extra group and pays off
+// only when the narrower set fits and the full block does not.
+int filter_group_width(int n, int64_t nnz, int r, int prec) {
+    const double budget = 232e6;
+    const double wv = prec == FLP_PREC_FP32_FILTER ? 4.0 : 8.0;
+    const int vec = prec == FLP_PREC_FP32_FILTER ? 4 : 2;  // 16-byte loads
+    auto footprint = [&](int w) { return (double)nnz * (wv + 4.0) + 4.0 * (n + 1) + 4.0 * n * w * wv; };
+    if (footprint(r) <= budget) return r;
+    for (int w = r / 2; w >= vec; w /= 2) {
+        if (r % w != 0 || w % vec != 0) continue;
+        if (footprint(w) <= budget) return w;
+    }
+    return r;
+}
+
+// W = p(Ahat) V with the workspace's Clenshaw buffers (V, W: n x r with
+// leading dimensions ldv, ldw), filtered in column groups.
+int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, int ldv, double *W, int ldw, int r,
+                      int prec, hipStream_t s) {
     Workspace &w = ws();
     const int n = A->n;
+    const int gw = filter_group_width(n, A->nnz, r, prec);
     if (prec == FLP_PREC_FP32_FILTER) {
         const float *v32 = nullptr;
         CKR(ensure_val32(A, &v32, s));
         size_t vb = sizeof(float) * (size_t)n * r;
-        for (auto &u : w.U) CK(ensure(u, vb));
+        for (auto &u : w.U) CK(ensure(u, sizeof(float) * (size_t)n * gw));
         CK(ensure(w.V32, vb));
-        CK(launch_to_float((int64_t)n * r, V, (float *)w.V32.p, s));
-        return clenshaw<float>(p, n, A->rowptr, A->colind, v32, r, (const float *)w.V32.p, r, W, r,
-                               (float *)w.U[0].p, (float *)w.U[1].p, (float *)w.U[2].p, s);
+        CK(launch_copy_block(n, r, 1.0, V, ldv, DMat{nullptr, 0, 0, 0}, 0, (float *)w.V32.p, r, s));
+        for (int j0 = 0; j0 < r; j0 += gw)
+            CKR(clenshaw<float>(p, n, A->rowptr, A->colind, v32, gw, (const float *)w.V32.p + j0, r, W + j0, ldw,
+                                (float *)w.U[0].p, (float *)w.U[1].p, (float *)w.U[2].p, s));
+        return FLP_OK;
     }
-    size_t vb = sizeof(double) * (size_t)n * r;
-    for (auto &u : w.U) CK(ensure(u, vb));
-    return clenshaw<double>(p, n, A->rowptr, A->colind, A->val, r, V, r, W, r, (double *)w.U[0].p,
-                            (double *)w.U[1].p, (double *)w.U[2].p, s);
+    for (auto &u : w.U) CK(ensure(u, sizeof(double) * (size_t)n * gw));
+    for (int j0 = 0; j0 < r; j0 += gw)
+        CKR(clenshaw<double>(p, n, A->rowptr, A->colind, A->val, gw, V + j0, ldv, W + j0, ldw, (double *)w.U[0].p,
+                             (double *)w.U[1].p, (double *)w.U[2].p, s));
+    return FLP_OK;
 }
 
 // ------------------------------------------------------------------ small dense helpers (host)
@@ -365,12 +390,12 @@ int small_dev(size_t elems, double **out) {
 // C (K x c, host or device) = A^T B with A n x K (lda), B n x c (ldb).
 // dev_out: device K x c row-major; host_out (optional) receives a copy
 // (synchronises the stream).
-int gram_tn(int n, int K, int c, const double *A, int64_t lda, const double *B, int64_t ldb, double *dev_out,
+int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *dev_out,
             double *host_out, hipStream_t s) {
     Workspace &w = ws();
     TnPlan pl = plan_tn(n, K, c);
     CK(ensure(w.partials, pl.partial_elems * sizeof(double)));
-    CK(launch_gemm_tn_partial(pl, n, K, c, A, lda, B, ldb, (double *)w.partials.p, s));
+    CK(launch_gemm_tn_partial(pl, n, K, c, A, B, ldb, (double *)w.partials.p, s));
     CK(launch_reduce_partials(pl, K, c, (double *)w.partials.p, dev_out, c, s));
     if (host_out) {
         CK(hipMemcpyAsync(host_out, dev_out, sizeof(double) * (size_t)K * c, hipMemcpyDeviceToHost, s));
@@ -380,12 +405,12 @@ int gram_tn(int n, int K, int c, const double *A, int64_t lda, const double *B, 
 }
 
 // Two passes of classical Gram-Schmidt of W (n x r, ld r) against
-// Q (n x k, ldq).  H1, H2 (k x r each) stay on the device in hdev[0..2kr).
-int cgs2(const double *Q, int64_t ldq, int k, int n, double *W, int r, double *hdev, hipStream_t s) {
+// the first k columns of Q.  H1, H2 (k x r each) stay on the device in hdev[0..2kr).
+int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s) {
     for (int pass = 0; pass < 2; ++pass) {
         double *H = hdev + (size_t)pass * k * r;
-        CKR(gram_tn(n, k, r, Q, ldq, W, r, H, nullptr, s));
-        CK(launch_gemm_nn(n, k, r, -1.0, Q, ldq, H, r, 1.0, W, r, s));
+        CKR(gram_tn(n, k, r, Q, W, r, H, nullptr, s));
+        CK(launch_gemm_nn(n, k, r, -1.0, Q, H, r, 1.0, W, r, s));
     }
     return FLP_OK;
 }
@@ -398,7 +423,7 @@ int cgs2(const double *Q, int64_t ldq, int k, int n, double *W, int r, double *h
 // Cholesky pivot sqrt(d_i) is only resolved down to ~1e-8 ||W||_F: a column
 // counts as dependent when sqrt(d_i) < 1e-7 ||W||_F.  S: host r x r
 // row-major.
-int block_qr_impl(double *W, int n, int r, const double *Q, int64_t ldq, int k, std::vector<double> &S,
+int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<double> &S,
                   uint64_t seed, uint64_t sid, hipStream_t s, bool *replaced, int depth = 0) {
     if (depth > 3) return fail(FLP_E_DEVICE, "block QR: could not repair a rank-deficient block");
     double *dev = nullptr;
@@ -407,7 +432,7 @@ int block_qr_impl(double *W, int n, int r, const double *Q, int64_t ldq, int k, 
     std::vector<double> G((size_t)r * r), R1, R2, Ri;
     std::vector<int> bad, bad2;
     // pass 1
-    CKR(gram_tn(n, r, r, W, r, W, r, gdev, G.data(), s));
+    CKR(gram_tn(n, r, r, plain_mat(W, r), W, r, gdev, G.data(), s));
     double fro2 = 0.0;
     for (int i = 0; i < r; ++i) fro2 += std::max(G[i * r + i], 0.0);
     const double thr = 1e-7 * std::sqrt(fro2);
@@ -416,16 +441,16 @@ int block_qr_impl(double *W, int n, int r, const double *Q, int64_t ldq, int k, 
     for (int i = 0; i < r; ++i) nbad += bad[i];
     upper_inverse(r, R1, Ri);
     CK(h2d(rdev, Ri.data(), sizeof(double) * r * r, s));
-    CK(launch_gemm_nn(n, r, r, 1.0, W, r, rdev, r, 0.0, W, r, s));
+    CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(W, r), rdev, r, 0.0, W, r, s));
     if (nbad == 0) {
         // pass 2 on the (nearly) orthonormal block
-        CKR(gram_tn(n, r, r, W, r, W, r, gdev, G.data(), s));
+        CKR(gram_tn(n, r, r, plain_mat(W, r), W, r, gdev, G.data(), s));
         cholesky_flag(r, G.data(), 1e-300, R2, bad2);
         for (int i = 0; i < r; ++i)
             if (bad2[i]) return fail(FLP_E_DEVICE, "block QR: second Cholesky pass broke down");
         upper_inverse(r, R2, Ri);
         CK(h2d(rdev, Ri.data(), sizeof(double) * r * r, s));
-        CK(launch_gemm_nn(n, r, r, 1.0, W, r, rdev, r, 0.0, W, r, s));
+        CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(W, r), rdev, r, 0.0, W, r, s));
         matmul_upper(r, R2, R1, S);
         CK(hipStreamSynchronize(s));
         return FLP_OK;
@@ -440,9 +465,9 @@ int block_qr_impl(double *W, int n, int r, const double *Q, int64_t ldq, int k, 
             for (int j = 0; j < r; ++j) S1[i * r + j] = 0.0;
     for (int i = 0; i < r; ++i)
         if (bad[i]) CK(launch_randn(n, 1, W + i, r, seed, sid * 131 + depth * 17 + i + 1, s));
-    if (Q && k > 0) CKR(cgs2(Q, ldq, k, n, W, r, hdev, s));
+    if (Q && k > 0) CKR(cgs2(*Q, k, n, W, r, hdev, s));
     std::vector<double> S2;
-    CKR(block_qr_impl(W, n, r, Q, ldq, k, S2, seed, sid + 7777, s, nullptr, depth + 1));
+    CKR(block_qr_impl(W, n, r, Q, k, S2, seed, sid + 7777, s, nullptr, depth + 1));
     matmul_upper(r, S2, S1, S);
     return FLP_OK;
 }
@@ -462,9 +487,9 @@ int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, 
     // start vector
     CK(launch_randn(n, 1, wv, 1, seed, 0xB0B0, s));
     double g = 0.0;
-    CKR(gram_tn(n, 1, 1, wv, 1, wv, 1, dev, &g, s));
+    CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, dev, &g, s));
     if (!(g > 0.0)) return fail(FLP_E_DEVICE, "bounds: zero start vector");
-    CK(launch_copy_block(n, 1, 1.0 / std::sqrt(g), wv, 1, Qb, ldb, nullptr, 0, s));
+    CK(launch_copy_block(n, 1, 1.0 / std::sqrt(g), wv, 1, plain_mat(Qb, ldb), 0, nullptr, 0, s));
     std::vector<double> al, be;
     std::vector<double> h1(k), h2(k);
     double beta_k = 0.0;
@@ -473,17 +498,17 @@ int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, 
         // w = A q_j
         CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, 1, Qb + j, ldb, nullptr, 0, nullptr,
                                             0, wv, 1, 1.0, 0.0, 0.0, 0.0, s));
-        CKR(cgs2(Qb, ldb, j + 1, n, wv, 1, dev, s));
+        CKR(cgs2(plain_mat(Qb, ldb), j + 1, n, wv, 1, dev, s));
         CK(hipMemcpyAsync(h1.data(), dev, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
         CK(hipMemcpyAsync(h2.data(), dev + (j + 1), sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-        CKR(gram_tn(n, 1, 1, wv, 1, wv, 1, dev + 2 * ldb, &g, s));
+        CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, dev + 2 * ldb, &g, s));
         al.push_back(h1[j] + h2[j]);
         double bj = std::sqrt(std::max(g, 0.0));
         be.push_back(bj);
         steps = j + 1;
         beta_k = bj;
         if (bj == 0.0 || j == k - 1) break;
-        CK(launch_copy_block(n, 1, 1.0 / bj, wv, 1, Qb + j + 1, ldb, nullptr, 0, s));
+        CK(launch_copy_block(n, 1, 1.0 / bj, wv, 1, plain_mat(Qb, ldb), j + 1, nullptr, 0, s));
     }
     // Ritz values of the tridiagonal and the last eigenvector row
     std::vector<double> T((size_t)steps * steps, 0.0);
@@ -524,6 +549,65 @@ int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, 
 
 // ------------------------------------------------------------------ solve
 
+// Y (n x c, ld ldc) <- Y R^{-1} with Y^T Y = R^T R (one Cholesky QR pass);
+// tmp is an n x c work block.
+int orthonormalize_cols(int n, int c, double *&Y, double *&tmp, int ldc, double *sdev, hipStream_t s) {
+    std::vector<double> G((size_t)c * c), R, Ri;
+    std::vector<int> bad;
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), Y, ldc, sdev, G.data(), s));
+    cholesky_flag(c, G.data(), 1e-300, R, bad);
+    for (int i = 0; i < c; ++i)
+        if (bad[i]) return fail(FLP_E_DEVICE, "Ritz block lost rank");
+    upper_inverse(c, R, Ri);
+    std::vector<double> Rp((size_t)c * ldc, 0.0);
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) Rp[(size_t)i * ldc + j] = Ri[(size_t)i * c + j];
+    CK(h2d(sdev, Rp.data(), sizeof(double) * Rp.size(), s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(Y, ldc), sdev, ldc, 0.0, tmp, ldc, s));
+    std::swap(Y, tmp);
+    return FLP_OK;
+}
+
+// Rayleigh-Ritz with A on the orthonormal block Y (eq. rayleigh, eq. proj):
+// G = Y^T A Y = Z diag(lam) Z^T, X = Y Z, AX = (A Y) Z and the residual
+// norms ||A x_j - lam_j x_j|| (host, unscaled).  lam ascending.
+int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
+                  double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s) {
+    Workspace &w = ws();
+    for (int j0 = 0; j0 < c; j0 += 16) {
+        int cw = std::min(16, c - j0);
+        CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, cw, Y + j0, ldc, nullptr, 0, nullptr,
+                                            0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
+    }
+    std::vector<double> G((size_t)c * c);
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), AY, ldc, sdev, G.data(), s));
+    std::vector<double> Gs((size_t)c * c);
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) Gs[(size_t)i * c + j] = 0.5 * (G[(size_t)i * c + j] + G[(size_t)j * c + i]);
+    lam.assign(c, 0.0);
+    std::vector<double> ZG((size_t)c * c);
+    std::vector<int> rows(c);
+    for (int i = 0; i < c; ++i) rows[i] = i;
+    if (sym_eig(c, c - 1, Gs.data(), lam.data(), rows.data(), c, ZG.data()) != 0)
+        return fail(FLP_E_DEVICE, "eigensolver for the Rayleigh-Ritz matrix did not converge");
+    std::vector<double> Zp((size_t)c * ldc, 0.0);
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) Zp[(size_t)i * ldc + j] = ZG[(size_t)i * c + j];
+    CK(h2d(sdev, Zp.data(), sizeof(double) * Zp.size(), s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(Y, ldc), sdev, ldc, 0.0, X, ldc, s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(AY, ldc), sdev, ldc, 0.0, AX, ldc, s));
+    double *lamd = sdev + (size_t)c * ldc;
+    double *rdev = lamd + ldc;
+    CK(h2d(lamd, lam.data(), sizeof(double) * c, s));
+    int nch = resid_chunks(n);
+    CK(ensure(w.resid_part, sizeof(double) * (size_t)nch * c));
+    CK(launch_resid_norms(n, c, AX, ldc, X, ldc, lamd, (double *)w.resid_part.p, nch, rdev, s));
+    res.assign(c, 0.0);
+    CK(hipMemcpyAsync(res.data(), rdev, sizeof(double) * c, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return FLP_OK;
+}
+
 int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out) {
     const double t_start = now();
     hipStream_t s = (hipStream_t)o.stream;
@@ -558,14 +642,17 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     int64_t maxb = o.max_basis > 0 ? o.max_basis : kDefaultMaxBasis;
     maxb = std::min<int64_t>(maxb, n);
     const int max_steps = std::max<int>(1, (int)(maxb / r));
-    const int64_t ldq = ((int64_t)max_steps * r + 1) & ~int64_t(1);
-
-    CK(ensure(w.Q, sizeof(double) * (size_t)n * ldq));
+    // Lanczos basis: column panels of 128 columns, each a contiguous
+    // row-major n x 128 block (the reorthogonalisation streams whole panels)
+    const int lpw = 7;
+    const int64_t npanels = ((int64_t)max_steps * r + (1 << lpw) - 1) >> lpw;
+    CK(ensure(w.Q, sizeof(double) * (size_t)n * (size_t)(npanels << lpw)));
     CK(ensure(w.W, sizeof(double) * (size_t)n * r));
     CK(ensure(w.Vin, sizeof(double) * (size_t)n * r));
-    double *Q = (double *)w.Q.p, *W = (double *)w.W.p, *Vin = (double *)w.Vin.p;
+    double *W = (double *)w.W.p, *Vin = (double *)w.Vin.p;
+    const DMat Q = panel_mat((double *)w.Q.p, n, lpw);
     double *hdev = nullptr;
-    CKR(small_dev((size_t)2 * ldq * r + 4 * r * r + 64, &hdev));
+    CKR(small_dev((size_t)2 * (npanels << lpw) * r + 4 * r * r + 64, &hdev));
 
     // start block
     if (o.start) {
@@ -574,9 +661,9 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         CK(launch_randn(n, r, W, r, o.seed, 0x51A7, s));
     }
     std::vector<double> Sj;
-    CKR(block_qr_impl(W, n, r, nullptr, 0, 0, Sj, o.seed, 1, s, nullptr));
-    CK(launch_copy_block(n, r, 1.0, W, r, Q, ldq, nullptr, 0, s));
-    CK(launch_copy_block(n, r, 1.0, W, r, Vin, r, nullptr, 0, s));
+    CKR(block_qr_impl(W, n, r, nullptr, 0, Sj, o.seed, 1, s, nullptr));
+    CK(launch_copy_block(n, r, 1.0, W, r, Q, 0, nullptr, 0, s));
+    CK(launch_copy_block(n, r, 1.0, W, r, plain_mat(Vin, r), 0, nullptr, 0, s));
 
     hipEvent_t ev[4];
     for (auto &e : ev) CK(hipEventCreate(&e));
@@ -598,11 +685,11 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     while (steps < max_steps) {
         const int k = (steps + 1) * r;  // basis columns so far
         CK(hipEventRecord(ev[0], s));
-        CKR(filter_apply_impl(filt.get(), A, Vin, W, r, o.prec, s));
+        CKR(filter_apply_impl(filt.get(), A, Vin, r, W, r, r, o.prec, s));
         CK(hipEventRecord(ev[1], s));
         st.filter_bytes += step_bytes * filt->m;
         st.mv += (int64_t)r * filt->m;
-        CKR(cgs2(Q, ldq, k, n, W, r, hdev, s));
+        CKR(cgs2(Q, k, n, W, r, hdev, s));
         CK(hipMemcpyAsync(h1.data(), hdev + (size_t)(k - r) * r, sizeof(double) * r * r, hipMemcpyDeviceToHost, s));
         CK(hipMemcpyAsync(h2.data(), hdev + (size_t)k * r + (size_t)(k - r) * r, sizeof(double) * r * r,
                           hipMemcpyDeviceToHost, s));
@@ -612,7 +699,7 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
                 double a = h1[i * r + j] + h2[i * r + j], b = h1[j * r + i] + h2[j * r + i];
                 D_all.push_back(0.5 * (a + b));
             }
-        CKR(block_qr_impl(W, n, r, Q, ldq, k, Sj, o.seed, 1000 + steps, s, nullptr));
+        CKR(block_qr_impl(W, n, r, &Q, k, Sj, o.seed, 1000 + steps, s, nullptr));
         S_all.insert(S_all.end(), Sj.begin(), Sj.end());
         CK(hipEventRecord(ev[2], s));
         CK(hipEventSynchronize(ev[2]));
@@ -668,8 +755,8 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
             }
             prev_count = (int)cand.size();
         }
-        CK(launch_copy_block(n, r, 1.0, W, r, Q + (size_t)k, ldq, nullptr, 0, s));
-        CK(launch_copy_block(n, r, 1.0, W, r, Vin, r, nullptr, 0, s));
+        CK(launch_copy_block(n, r, 1.0, W, r, Q, k, nullptr, 0, s));
+        CK(launch_copy_block(n, r, 1.0, W, r, plain_mat(Vin, r), 0, nullptr, 0, s));
     }
     st.iters = steps;
     st.basis_cols = kfinal;
@@ -721,67 +808,51 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         double *sdev = nullptr;
         CKR(small_dev((size_t)std::max(K, c) * ldc * 2 + 4 * (size_t)ldc + 64, &sdev));
         CK(h2d(sdev, Wc.data(), sizeof(double) * Wc.size(), s));
-        // Y = Q_k W_C
-        CK(launch_gemm_nn(n, K, c, 1.0, Q, ldq, sdev, ldc, 0.0, Y, ldc, s));
-        // orthonormalise Y (one Cholesky QR pass; Y is orthonormal to rounding)
-        std::vector<double> G((size_t)c * c), R, Ri;
-        std::vector<int> bad;
-        CKR(gram_tn(n, c, c, Y, ldc, Y, ldc, sdev, G.data(), s));
-        cholesky_flag(c, G.data(), 1e-300, R, bad);
-        upper_inverse(c, R, Ri);
-        {
-            std::vector<double> Rp((size_t)c * ldc, 0.0);
-            for (int i = 0; i < c; ++i)
-                for (int j = 0; j < c; ++j) Rp[(size_t)i * ldc + j] = Ri[(size_t)i * c + j];
-            CK(h2d(sdev, Rp.data(), sizeof(double) * Rp.size(), s));
-            CK(launch_gemm_nn(n, c, c, 1.0, Y, ldc, sdev, ldc, 0.0, X, ldc, s));
-            std::swap(Y, X);
+        // Ritz vectors of p(A): Y = Q_k W_C (eq. proj)
+        CK(launch_gemm_nn(n, K, c, 1.0, Q, sdev, ldc, 0.0, Y, ldc, s));
+        CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
+        std::vector<double> lam, rres;
+        CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+        // FP32 filter: FP64 polish sweeps (X <- p(A) X, orthonormalise, RR
+        // with A) until the in-interval residuals meet the tolerance
+        auto worst = [&](int &i0, int &i1) {
+            i0 = 0;
+            while (i0 < c && lam[i0] < alpha) ++i0;
+            i1 = i0;
+            while (i1 < c && lam[i1] <= beta) ++i1;
+            double m = 0.0;
+            for (int j = i0; j < i1; ++j) m = std::max(m, rres[j] / anorm);
+            return m;
+        };
+        const double tol = o.tol > 0 ? o.tol : kDefaultTol;
+        int i0 = 0, i1 = 0;
+        if (o.prec == FLP_PREC_FP32_FILTER) {
+            while (worst(i0, i1) > tol && st.polish_sweeps < 3) {
+                for (auto &u : w.U) CK(ensure(u, sizeof(double) * (size_t)n * 16));
+                for (int j0 = 0; j0 < c; j0 += 16) {
+                    int cw = std::min(16, c - j0);
+                    CKR(filter_apply_impl(filt.get(), A, X + j0, ldc, Y + j0, ldc, cw, FLP_PREC_FP64, s));
+                }
+                st.filter_bytes += filter_step_bytes(n, A->nnz, 16, FLP_PREC_FP64) * filt->m * ((c + 15) / 16);
+                CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
+                CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
+                CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+                ++st.polish_sweeps;
+            }
         }
-        // AY = A Y in chunks of up to 16 columns
-        for (int j0 = 0; j0 < c; j0 += 16) {
-            int cw = std::min(16, c - j0);
-            CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, cw, Y + j0, ldc, nullptr, 0,
-                                                nullptr, 0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
-        }
-        // G = Y^T A Y
-        CKR(gram_tn(n, c, c, Y, ldc, AY, ldc, sdev, G.data(), s));
-        std::vector<double> Gs((size_t)c * c);
-        for (int i = 0; i < c; ++i)
-            for (int j = 0; j < c; ++j) Gs[(size_t)i * c + j] = 0.5 * (G[(size_t)i * c + j] + G[(size_t)j * c + i]);
-        std::vector<double> lam(c), ZG((size_t)c * c);
-        std::vector<int> allrows(c);
-        for (int i = 0; i < c; ++i) allrows[i] = i;
-        if (sym_eig(c, c - 1, Gs.data(), lam.data(), allrows.data(), c, ZG.data()) != 0)
-            return fail(FLP_E_DEVICE, "eigensolver for the Rayleigh-Ritz matrix did not converge");
-        // keep lambda in [alpha, beta]: a contiguous range of the sorted values
-        int i0 = 0;
-        while (i0 < c && lam[i0] < alpha) ++i0;
-        int i1 = i0;
-        while (i1 < c && lam[i1] <= beta) ++i1;
+        worst(i0, i1);
         const int cnt = i1 - i0;
         res->count = cnt;
         if (cnt > 0) {
-            const int ldz = (cnt + 1) & ~1;
-            std::vector<double> Zk((size_t)c * ldz, 0.0);
-            for (int i = 0; i < c; ++i)
-                for (int j = 0; j < cnt; ++j) Zk[(size_t)i * ldz + j] = ZG[(size_t)i * c + i0 + j];
-            CK(h2d(sdev, Zk.data(), sizeof(double) * Zk.size(), s));
-            CK(launch_gemm_nn(n, c, cnt, 1.0, Y, ldc, sdev, ldz, 0.0, X, ldz, s));
-            CK(launch_gemm_nn(n, c, cnt, 1.0, AY, ldc, sdev, ldz, 0.0, AX, ldz, s));
-            double *lamd = sdev + (size_t)c * ldz;
-            double *rdev = lamd + ldz;
-            CK(h2d(lamd, lam.data() + i0, sizeof(double) * cnt, s));
-            int nch = resid_chunks(n);
-            CK(ensure(w.resid_part, sizeof(double) * (size_t)nch * cnt));
-            CK(launch_resid_norms(n, cnt, AX, ldz, X, ldz, lamd, (double *)w.resid_part.p, nch, rdev, s));
             res->evals = new double[cnt];
             res->resid = new double[cnt];
-            std::memcpy(res->evals, lam.data() + i0, sizeof(double) * cnt);
-            CK(hipMemcpyAsync(res->resid, rdev, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+            for (int j = 0; j < cnt; ++j) {
+                res->evals[j] = lam[i0 + j];
+                res->resid[j] = rres[i0 + j] / anorm;
+            }
             CK(hipMalloc(&res->evecs, sizeof(double) * (size_t)n * cnt));
-            CK(launch_transpose_out(n, cnt, X, ldz, res->evecs, s));
+            CK(launch_transpose_out(n, cnt, X + i0, ldc, res->evecs, s));
             CK(hipStreamSynchronize(s));
-            for (int j = 0; j < cnt; ++j) res->resid[j] /= anorm;
         }
     }
     st.t_rr = now() - tr;
@@ -866,7 +937,7 @@ int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, dou
     if (!V || !W) return fail(FLP_E_ARG, "V and W must be non-NULL");
     if (V == W) return fail(FLP_E_ARG, "W must not alias V");
     if (prec != FLP_PREC_FP64 && prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
-    return filter_apply_impl(p, A, V, W, r, prec, (hipStream_t)stream);
+    return filter_apply_impl(p, A, V, r, W, r, r, prec, (hipStream_t)stream);
 }
 
 int flp_spmm(const flp_csr *A, const double *X, int32_t ldx, double *Y, int32_t ldy, int32_t r, void *stream) {
@@ -883,7 +954,7 @@ int flp_block_orth(const double *Q, int64_t ldq, int32_t k, int32_t n, double *W
     hipStream_t s = (hipStream_t)stream;
     double *hdev = nullptr;
     CKR(small_dev((size_t)2 * k * r + 64, &hdev));
-    CKR(cgs2(Q, ldq, k, n, W, r, hdev, s));
+    CKR(cgs2(plain_mat(Q, ldq), k, n, W, r, hdev, s));
     if (H) {
         std::vector<double> h((size_t)2 * k * r);
         CK(hipMemcpyAsync(h.data(), hdev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
@@ -897,7 +968,7 @@ int flp_block_qr(double *W, int32_t n, int32_t r, double *S, void *stream) {
     if (!W || !S || n < 1 || r < 1 || r > 16 || r > n) return fail(FLP_E_ARG, "bad arguments");
     std::vector<double> Sv;
     bool replaced = false;
-    CKR(block_qr_impl(W, n, r, nullptr, 0, 0, Sv, 12345, 1, (hipStream_t)stream, &replaced));
+    CKR(block_qr_impl(W, n, r, nullptr, 0, Sv, 12345, 1, (hipStream_t)stream, &replaced));
     if (replaced) return fail(FLP_E_ARG, "block is numerically rank deficient");
     std::memcpy(S, Sv.data(), sizeof(double) * r * r);
     return FLP_OK;

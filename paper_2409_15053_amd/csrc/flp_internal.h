@@ -28,6 +28,22 @@ void set_error(const std::string &msg);
 // Returns 0 on success.
 int sym_eig(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Z);
 
+// ---------------------------------------------------------------- tall matrices
+// A tall n x K matrix stored plainly (row-major, leading dimension ld) or
+// as column panels of 2^lpw columns, each panel a row-major n x 2^lpw block
+// placed ps elements after the previous one.  Element (i, q) lives at
+// p[(q >> lpw) * ps + i * ld + (q & (2^lpw - 1))].
+struct DMat {
+    double *p;
+    int64_t ld;
+    int64_t ps;
+    int lpw;
+};
+inline DMat plain_mat(const double *p, int64_t ld) { return DMat{const_cast<double *>(p), ld, 0, 30}; }
+inline DMat panel_mat(const double *p, int64_t n, int lpw) {
+    return DMat{const_cast<double *>(p), int64_t(1) << lpw, n << lpw, lpw};
+}
+
 // ---------------------------------------------------------------- kernel launchers
 // All take a stream and return hipError_t from the launch.
 
@@ -50,16 +66,15 @@ struct TnPlan {
     size_t partial_elems;  // nchunks * K * c
 };
 TnPlan plan_tn(int n, int K, int c);
-hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, const double *A, int64_t lda,
-                                  const double *B, int64_t ldb, double *partials, hipStream_t s);
+hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A, const double *B, int64_t ldb,
+                                  double *partials, hipStream_t s);
 // C (K x c, ldc) = sum over chunks of partials (deterministic order).
 hipError_t launch_reduce_partials(const TnPlan &pl, int K, int c, const double *partials, double *C,
                                   int ldc, hipStream_t s);
 
 // C (n x c, ldc) = beta * C + alpha * A (n x K, lda) B (K x c, ldb); B on device.
-hipError_t launch_gemm_nn(int n, int K, int c, double alpha, const double *A, int64_t lda,
-                          const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
-                          hipStream_t s);
+hipError_t launch_gemm_nn(int n, int K, int c, double alpha, DMat A, const double *B, int64_t ldb, double beta,
+                          double *C, int64_t ldc, hipStream_t s);
 
 // Gershgorin: lo/hi per block into part (2 * nblocks doubles), then reduced
 // to out[0] = min(a_ii - R_i), out[1] = max(a_ii + R_i).
@@ -72,9 +87,10 @@ int gershgorin_blocks(int n);
 hipError_t launch_randn(int rows, int cols, double *out, int64_t ld, uint64_t seed, uint64_t stream_id,
                         hipStream_t s);
 
-// dst (rows x cols, ldd) = scale * src (rows x cols, lds); optional FP32 copy dst32.
-hipError_t launch_copy_block(int rows, int cols, double scale, const double *src, int64_t lds, double *dst,
-                             int64_t ldd, float *dst32, int64_t ldd32, hipStream_t s);
+// dst columns [dcol0, dcol0 + cols) = scale * src (rows x cols, lds) when
+// dst.p is non-NULL; optional FP32 copy dst32 (rows x cols, ldd32).
+hipError_t launch_copy_block(int rows, int cols, double scale, const double *src, int64_t lds, DMat dst, int dcol0,
+                             float *dst32, int64_t ldd32, hipStream_t s);
 hipError_t launch_to_float(int64_t count, const double *src, float *dst, hipStream_t s);
 hipError_t launch_scale(int64_t count, double a, const double *src, double *dst, hipStream_t s);
 

@@ -237,14 +237,65 @@ __device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// C partial (K x c) over one chunk of rows: each wave owns NT output tiles
-// of 16 A-columns x 16 B-columns; the block's 4 waves split the chunk's
-// rows and combine through LDS.
+__device__ __forceinline__ const double *col_base(const DMat &m, int q) {
+    return m.p + (int64_t)(q >> m.lpw) * m.ps + (q & ((1 << m.lpw) - 1));
+}
+
+// C partial (K x c) over one chunk of rows.  Each wave owns NT output
+// tiles of 16 A-columns x 16 B-columns, taken in pairs: the pair (2p, 2p+1)
+// covers 32 consecutive A columns, lane (k, m) reads columns 2m and 2m+1 of
+// the pair with one 16-byte load and feeds the first to tile 2p and the
+// second to tile 2p+1 (tile 2p's row i is column 2i of the pair).  The
+// block's 4 waves split the chunk's rows and combine through LDS.  A group
+// of NT tiles never straddles a panel (16 NT divides the panel width).
+// Loads are unconditional: in a group that runs past K the A columns are
+// clamped to valid addresses (they only feed discarded output rows), and B
+// rows past the chunk are zeroed.
+template <int NT, bool VEC, bool CLAMP>
+__device__ __forceinline__ void tn_rows(int g0, int r1, int K, int q0, const double *abase, int64_t lda,
+                                        const double *__restrict__ B, int64_t ldb, int bcol, int kr, int mc,
+                                        dbl4 (&acc)[NT]) {
+    constexpr int NP = NT / 2;
+    int aoff[NP][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        aoff[p][0] = CLAMP ? min(p * 32 + 2 * mc, K - 1 - q0) : p * 32 + 2 * mc;
+        aoff[p][1] = CLAMP ? min(p * 32 + 2 * mc + 1, K - 1 - q0) : p * 32 + 2 * mc + 1;
+    }
+    for (int g = g0; g < r1; g += 4 * 4 * 2) {
+        double bv[2];
+        double2 av[2][NP];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int row = g + u * 16 + kr;
+            const int rc = min(row, r1 - 1);
+            const double x = B[(int64_t)rc * ldb + bcol];
+            bv[u] = row < r1 ? x : 0.0;
+            const double *ar = abase + (int64_t)rc * lda;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                if constexpr (VEC) {
+                    av[u][p] = *reinterpret_cast<const double2 *>(ar + aoff[p][0]);
+                } else {
+                    av[u][p].x = ar[aoff[p][0]];
+                    av[u][p].y = ar[aoff[p][1]];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                acc[2 * p] = mfma16x16x4(av[u][p].x, bv[u], acc[2 * p]);
+                acc[2 * p + 1] = mfma16x16x4(av[u][p].y, bv[u], acc[2 * p + 1]);
+            }
+    }
+}
+
 template <int NT>
-__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int c, int chunk_rows,
-                                                              const double *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int c, int chunk_rows, DMat A,
                                                               const double *__restrict__ B, int64_t ldb,
-                                                              double *__restrict__ partials) {
+                                                              double *__restrict__ partials, bool aligned) {
     __shared__ double red[4][4][WAVE];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int ntb = (c + 15) / 16;            // B tiles
@@ -254,45 +305,30 @@ __global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int 
     const int r0 = chunk * chunk_rows;
     const int r1 = min(n, r0 + chunk_rows);
     const int kr = lane / 16, mc = lane % 16;
-    const int bcol = tb * 16 + mc;
-    const bool bok = bcol < c;
-    int acol[NT];
-    bool aok[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        acol[t] = (tg * NT + t) * 16 + mc;
-        aok[t] = acol[t] < K;
-    }
+    const int q0 = tg * NT * 16;
+    const double *abase = col_base(A, q0);
+    const int bcol = min(tb * 16 + mc, c - 1);
     dbl4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // the 4 waves interleave 4-row groups (2 groups per wave and iteration)
-    for (int g = r0 + wave * 4; g < r1; g += 4 * 4 * 2) {
-        double bv[2], av[2][NT];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            int row = g + u * 16 + kr;
-            bool rok = row < r1;
-            bv[u] = (rok && bok) ? B[(int64_t)row * ldb + bcol] : 0.0;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) av[u][t] = (rok && aok[t]) ? A[(int64_t)row * lda + acol[t]] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(av[u][t], bv[u], acc[t]);
-    }
+    if (q0 + 16 * NT > K)
+        tn_rows<NT, false, true>(r0 + wave * 4, r1, K, q0, abase, A.ld, B, ldb, bcol, kr, mc, acc);
+    else if (aligned)
+        tn_rows<NT, true, false>(r0 + wave * 4, r1, K, q0, abase, A.ld, B, ldb, bcol, kr, mc, acc);
+    else
+        tn_rows<NT, false, false>(r0 + wave * 4, r1, K, q0, abase, A.ld, B, ldb, bcol, kr, mc, acc);
     // combine the 4 waves one output tile at a time through LDS
     double *dst = partials + (size_t)chunk * K * c;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
+        if (q0 + (t & ~1) * 16 >= K) break;  // uniform
 #pragma unroll
         for (int v = 0; v < 4; ++v) red[wave][v][lane] = acc[t][v];
         __syncthreads();
         {
             const int v = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
             double s = red[0][v][l] + red[1][v][l] + red[2][v][l] + red[3][v][l];
-            int i = (tg * NT + t) * 16 + (l / 16) + 4 * v;
+            int i = q0 + (t / 2) * 32 + 2 * ((l / 16) + 4 * v) + (t & 1);
             int j = tb * 16 + (l % 16);
             if (i < K && j < c) dst[(size_t)i * c + j] = s;
         }
@@ -300,27 +336,44 @@ __global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int 
     }
 }
 
-__global__ void reduce_partials_kernel(int nchunks, int K, int c, const double *__restrict__ partials,
-                                       double *__restrict__ C, int ldc) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    int total = K * c;
-    if (idx >= total) return;
-    double s = 0.0;
-    for (int q = 0; q < nchunks; ++q) s += partials[(size_t)q * total + idx];
-    C[(size_t)(idx / c) * ldc + idx % c] = s;
+// Sum of the per-chunk partials in a fixed order (deterministic): each
+// block owns 64 outputs; its 4 thread rows split the chunks and combine
+// through LDS.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(int nchunks, int total, int c,
+                                                              const double *__restrict__ partials,
+                                                              double *__restrict__ C, int ldc) {
+    __shared__ double red[4][64];
+    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+    const int o = blockIdx.x * 64 + tx;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (o < total) {
+        const double *p = partials + o;
+        int q = ty;
+        for (; q + 12 < nchunks; q += 16) {
+            s0 += p[(size_t)q * total];
+            s1 += p[(size_t)(q + 4) * total];
+            s2 += p[(size_t)(q + 8) * total];
+            s3 += p[(size_t)(q + 12) * total];
+        }
+        for (; q < nchunks; q += 4) s0 += p[(size_t)q * total];
+    }
+    red[ty][tx] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (ty == 0 && o < total) C[(size_t)(o / c) * ldc + o % c] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
 }
 
 // C = beta C + alpha A B: each wave computes MT row tiles (16 rows each) x
 // NT column tiles (16 columns each).  The k index inside a group of 16 is
 // permuted (k = 4 * (l/16) + step) so each lane reads 4 contiguous A
-// entries with two 16-byte loads.
+// entries with two 16-byte loads.  A group of 16 k values never straddles a
+// panel.  Loads are unconditional: rows past n and columns past c are
+// clamped (they only feed outputs that are not written) and B rows past K
+// are zeroed.  A and C may be the same block (in-place C = A B): each wave
+// reads all of its rows of A before it writes those rows of C.
 template <int MT, int NT>
-__global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, double alpha,
-                                                      const double *A, int64_t lda,
+__global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, double alpha, DMat A,
                                                       const double *__restrict__ B, int64_t ldb, double beta,
                                                       double *C, int64_t ldc, bool vec_a) {
-    // A and C may be the same block (in-place C = A B): each wave reads all
-    // of its rows of A before it writes those rows of C.
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int nct = (c + 16 * NT - 1) / (16 * NT);
     const int wg = xcd_tile(blockIdx.x, gridDim.x);
@@ -334,37 +387,54 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, doubl
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
     int col[NT];
-    bool cok[NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        col[j] = (cblk * NT + j) * 16 + m;
-        cok[j] = col[j] < c;
-    }
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int j = 0; j < NT; ++j) col[j] = min((cblk * NT + j) * 16 + m, c - 1);
+    int64_t roff[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) roff[i] = (int64_t)min(row0 + i * 16 + m, n - 1) * A.ld;
+    const int kfull = vec_a ? (K & ~15) : 0;
+    int k0 = 0;
+    for (; k0 < kfull; k0 += 16) {
         const int kb = k0 + 4 * kq;  // this lane's 4 contiguous k values
+        const double *abase = col_base(A, kb);
         double a[MT][4];
 #pragma unroll
         for (int i = 0; i < MT; ++i) {
-            int row = row0 + i * 16 + m;
-            const double *ap = A + (int64_t)row * lda + kb;
-            if (row < n && vec_a && kb + 4 <= K) {
-                double2 x0 = *reinterpret_cast<const double2 *>(ap);
-                double2 x1 = *reinterpret_cast<const double2 *>(ap + 2);
-                a[i][0] = x0.x;
-                a[i][1] = x0.y;
-                a[i][2] = x1.x;
-                a[i][3] = x1.y;
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a[i][q] = (row < n && kb + q < K) ? ap[q] : 0.0;
-            }
+            const double *ap = abase + roff[i];
+            double2 x0 = *reinterpret_cast<const double2 *>(ap);
+            double2 x1 = *reinterpret_cast<const double2 *>(ap + 2);
+            a[i][0] = x0.x;
+            a[i][1] = x0.y;
+            a[i][2] = x1.x;
+            a[i][3] = x1.y;
         }
         double b[4][NT];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
-                b[q][j] = (kb + q < K && cok[j]) ? B[(int64_t)(kb + q) * ldb + col[j]] : 0.0;
+            for (int j = 0; j < NT; ++j) b[q][j] = B[(int64_t)(kb + q) * ldb + col[j]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[i][j] = mfma16x16x4(a[i][q], b[q][j], acc[i][j]);
+    }
+    for (; k0 < K; k0 += 16) {  // ragged tail (or unaligned A): scalar loads
+        const int kb = k0 + 4 * kq;
+        double a[MT][4], b[4][NT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = min(kb + q, K - 1);
+            const double *ap = col_base(A, kk);
+#pragma unroll
+            for (int i = 0; i < MT; ++i) a[i][q] = ap[roff[i]];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const double x = B[(int64_t)kk * ldb + col[j]];
+                b[q][j] = (kb + q < K) ? x : 0.0;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -376,12 +446,13 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, doubl
     for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            if (!cok[j]) continue;
+            const int cj = (cblk * NT + j) * 16 + m;
+            if (cj >= c) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int row = row0 + i * 16 + kq + 4 * v;
                 if (row < n) {
-                    double *cp = C + (int64_t)row * ldc + col[j];
+                    double *cp = C + (int64_t)row * ldc + cj;
                     double prev = (beta != 0.0) ? beta * *cp : 0.0;
                     *cp = prev + alpha * acc[i][j][v];
                 }
@@ -396,7 +467,7 @@ TnPlan plan_tn(int n, int K, int c) {
     const int ntiles = ((K + 127) / 128) * ((c + 15) / 16);
     // aim for ~2048 blocks in total, at least 128 rows per block, and keep
     // the partial buffer near 32M doubles at most
-    int nch = std::max(1, 2048 / std::max(1, ntiles));
+    int nch = std::min(512, std::max(1, 2048 / std::max(1, ntiles)));
     int rows = (n + nch - 1) / nch;
     rows = std::max(rows, 128);
     size_t per = (size_t)K * c;
@@ -408,38 +479,48 @@ TnPlan plan_tn(int n, int K, int c) {
     return p;
 }
 
-hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, const double *A, int64_t lda,
-                                  const double *B, int64_t ldb, double *partials, hipStream_t s) {
-    constexpr int NT = 8;
-    dim3 grid(pl.nchunks, ((K + 16 * NT - 1) / (16 * NT)) * ((c + 15) / 16));
-    hipLaunchKernelGGL((gemm_tn_partial_kernel<NT>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, lda, B,
-                       ldb, partials);
+hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A, const double *B, int64_t ldb,
+                                  double *partials, hipStream_t s) {
+    // 16-byte A loads need an even leading dimension and panel stride
+    const bool aligned = !(A.ld & 1) && !(A.ps & 1) && !(reinterpret_cast<uintptr_t>(A.p) & 15);
+    const int nt = K <= 32 ? 2 : (K <= 64 ? 4 : 8);
+    dim3 grid(pl.nchunks, ((K + 16 * nt - 1) / (16 * nt)) * ((c + 15) / 16));
+#define FLP_TN(NT) \
+    hipLaunchKernelGGL((gemm_tn_partial_kernel<NT>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B, ldb, partials, \
+                       aligned)
+    if (nt == 2)
+        FLP_TN(2);
+    else if (nt == 4)
+        FLP_TN(4);
+    else
+        FLP_TN(8);
+#undef FLP_TN
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const TnPlan &pl, int K, int c, const double *partials, double *C, int ldc,
                                   hipStream_t s) {
     int total = K * c;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((total + 255) / 256), dim3(256), 0, s, pl.nchunks, K, c,
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((total + 63) / 64), dim3(256), 0, s, pl.nchunks, total, c,
                        partials, C, ldc);
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_nn(int n, int K, int c, double alpha, const double *A, int64_t lda, const double *B,
-                          int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t s) {
+hipError_t launch_gemm_nn(int n, int K, int c, double alpha, DMat A, const double *B, int64_t ldb, double beta,
+                          double *C, int64_t ldc, hipStream_t s) {
     if (n <= 0 || c <= 0) return hipSuccess;
-    bool vec_a = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    bool vec_a = (A.ld % 2 == 0) && (A.ps % 2 == 0) && ((reinterpret_cast<uintptr_t>(A.p) & 15) == 0);
     if (c <= 16) {
         constexpr int MT = 4, NT = 1;
         int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);
-        hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks), dim3(256), 0, s, n, K, c, alpha, A, lda, B,
-                           ldb, beta, C, ldc, vec_a);
+        hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks), dim3(256), 0, s, n, K, c, alpha, A, B, ldb, beta,
+                           C, ldc, vec_a);
     } else {
         constexpr int MT = 2, NT = 4;
         int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);
         int nct = (c + 16 * NT - 1) / (16 * NT);
-        hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks * nct), dim3(256), 0, s, n, K, c, alpha, A,
-                           lda, B, ldb, beta, C, ldc, vec_a);
+        hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks * nct), dim3(256), 0, s, n, K, c, alpha, A, B,
+                           ldb, beta, C, ldc, vec_a);
     }
     return hipGetLastError();
 }
@@ -527,14 +608,17 @@ __global__ void randn_kernel(int rows, int cols, double *__restrict__ out, int64
     out[(idx / cols) * ld + idx % cols] = z;
 }
 
-__global__ void copy_block_kernel(int rows, int cols, double scale, const double *__restrict__ src,
-                                  int64_t lds, double *__restrict__ dst, int64_t ldd, float *__restrict__ dst32,
-                                  int64_t ldd32) {
+__global__ void copy_block_kernel(int rows, int cols, double scale, const double *__restrict__ src, int64_t lds,
+                                  DMat dst, int dcol0, float *__restrict__ dst32, int64_t ldd32) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)rows * cols) return;
-    int64_t i = idx / cols, j = idx % cols;
+    int64_t i = idx / cols;
+    int j = (int)(idx % cols);
     double v = scale * src[i * lds + j];
-    if (dst) dst[i * ldd + j] = v;
+    if (dst.p) {
+        int q = dcol0 + j;
+        dst.p[(int64_t)(q >> dst.lpw) * dst.ps + i * dst.ld + (q & ((1 << dst.lpw) - 1))] = v;
+    }
     if (dst32) dst32[i * ldd32 + j] = (float)v;
 }
 
@@ -617,12 +701,12 @@ hipError_t launch_randn(int rows, int cols, double *out, int64_t ld, uint64_t se
     return hipGetLastError();
 }
 
-hipError_t launch_copy_block(int rows, int cols, double scale, const double *src, int64_t lds, double *dst,
-                             int64_t ldd, float *dst32, int64_t ldd32, hipStream_t s) {
+hipError_t launch_copy_block(int rows, int cols, double scale, const double *src, int64_t lds, DMat dst, int dcol0,
+                             float *dst32, int64_t ldd32, hipStream_t s) {
     int64_t total = (int64_t)rows * cols;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rows, cols, scale,
-                       src, lds, dst, ldd, dst32, ldd32);
+                       src, lds, dst, dcol0, dst32, ldd32);
     return hipGetLastError();
 }
 

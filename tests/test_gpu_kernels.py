@@ -226,3 +226,49 @@ def test_bounds_enclose_spectrum(torch, case):
     glo, ghi = O.gershgorin(A)
     assert lmin <= lo and lmax >= hi
     assert glo <= lmin and lmax <= ghi
+
+
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER])
+def test_filter_apply_full_size_lap3d7_100(torch, prec):
+    """Full-size filter parity at the benchmark's launch configuration:
+    7-point Laplacian on 100^3 + U[0,1) potential (n = 1e6), block 8,
+    degree 100.  Runs the column-grouped (cache-resident) FP64 path."""
+    w = I.workload_c2(100)
+    A = w["A"]
+    lmin, lmax = O.gershgorin(A)
+    m = 100
+    f = flp.flp_build_filter(0.0, 0.51, m, lmin, lmax)
+    b = f.coeffs()
+    V = I.random_block(A.n, 8, seed=123)
+    dA = flp.DeviceCsr.from_host(A, with_fp32=(prec == flp.FLP_PREC_FP32_FILTER))
+    W = torch.empty((A.n, 8), dtype=torch.float64, device="cuda:0")
+    flp.flp_filter_apply(f, dA, dev(torch, V), W, prec=prec)
+    torch.cuda.synchronize()
+    want = O.filter_apply(A, lmin, lmax, b, V)
+    k = max_row_nnz(A)
+    if prec == flp.FLP_PREC_FP64:
+        tol = 2 * m * m * (k + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    else:
+        tol = 2 * m * (k + 4) * U32 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    err = np.max(np.abs(W.cpu().numpy() - want))
+    assert err <= tol, (err, tol)
+
+
+def test_filter_apply_full_size_lap3d13_120(torch):
+    """Full-size filter parity on the 13-point 120^3 Hamiltonian with 16
+    Gaussian wells (n = 1.728e6, nnz = 2.2e7), block 16, FP64."""
+    w = I.workload_c3(120)
+    A = w["A"]
+    lmin, lmax = O.gershgorin(A)
+    m = 30
+    f = flp.flp_build_filter(-2.0, -1.0, m, lmin, lmax)
+    b = f.coeffs()
+    V = I.random_block(A.n, 16, seed=7)
+    dA = flp.DeviceCsr.from_host(A)
+    W = torch.empty((A.n, 16), dtype=torch.float64, device="cuda:0")
+    flp.flp_filter_apply(f, dA, dev(torch, V), W)
+    torch.cuda.synchronize()
+    want = O.filter_apply(A, lmin, lmax, b, V)
+    tol = 2 * m * m * (13 + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    err = np.max(np.abs(W.cpu().numpy() - want))
+    assert err <= tol, (err, tol)

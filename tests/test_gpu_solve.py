@@ -182,3 +182,40 @@ def test_start_block_given(torch):
     start = I.random_block(A.n, 4, seed=9)
     res = flp.flp_solve(dA, 1.0, 1.6, block=4, start=start)
     check_against(res, exact)
+
+
+@pytest.mark.parametrize("case", ["wells13", "uniform7"])
+def test_fp32_filter_with_fp64_polish(torch, case):
+    """FP32 filter recurrence, FP64 Lanczos/Rayleigh-Ritz and FP64 polish
+    sweeps: same contract as the FP64 path (exact count, 1e-10 relative
+    eigenvalues, residuals <= 1e-9)."""
+    if case == "wells13":
+        N = 15
+        A = I.laplacian_3d_13pt(N, I.gaussian_wells(N, I.BASE_SEED + 3))
+        block, i0, i1 = 16, 10, 69
+    else:
+        N = 16
+        A = I.laplacian_3d(N, I.uniform_potential(N, I.BASE_SEED + 2))
+        block, i0, i1 = 8, 0, 49
+    lam_all = np.linalg.eigvalsh(A.to_dense())
+    alpha = lam_all[0] - 1.0 if i0 == 0 else 0.5 * (lam_all[i0 - 1] + lam_all[i0])
+    beta = 0.5 * (lam_all[i1] + lam_all[i1 + 1])
+    dA = flp.DeviceCsr.from_host(A, with_fp32=True)
+    res = flp.flp_solve(dA, alpha, beta, block=block, seed=5, prec=flp.FLP_PREC_FP32_FILTER)
+    want, V = O.dense_eigs_in_interval(A, alpha, beta)
+    check_against(res, want, V, anorm=np.max(np.abs(lam_all)))
+    assert res["stats"]["polish_sweeps"] >= 1
+
+
+def test_fp32_and_fp64_agree(torch):
+    N = 14
+    A = I.laplacian_3d(N, I.uniform_potential(N, 77))
+    lam_all = np.linalg.eigvalsh(A.to_dense())
+    alpha = 0.5 * (lam_all[29] + lam_all[30])
+    beta = 0.5 * (lam_all[79] + lam_all[80])
+    dA = flp.DeviceCsr.from_host(A)
+    r64 = flp.flp_solve(dA, alpha, beta, block=8, seed=1)
+    r32 = flp.flp_solve(dA, alpha, beta, block=8, seed=1, prec=flp.FLP_PREC_FP32_FILTER)
+    assert r64["count"] == r32["count"] == 50
+    assert np.max(np.abs(r64["evals"] - r32["evals"]) / np.abs(r64["evals"])) <= 1e-10
+    assert max(np.max(r64["resid"]), np.max(r32["resid"])) <= 1e-9
