@@ -201,6 +201,42 @@ void flp_result_free(flp_result *res);
  * DEVICE buffer dst; stream-ordered (NULL = default stream). */
 int flp_result_copy_evecs(const flp_result *res, double *dst, void *stream);
 
+/* Statistics of a batched solve. */
+typedef struct flp_batch_stats {
+    int32_t solves;           /* problems in the batch */
+    int32_t block_steps;      /* lockstep block Lanczos steps */
+    int32_t filter_launches;  /* segmented filter launches */
+    int32_t graph_captures;   /* HIP graphs captured (one per change of the active set) */
+    int32_t graph_replays;    /* block steps replayed from a graph */
+    double t_total;           /* seconds: whole call */
+    double t_setup;           /* seconds: bounds, filters, start blocks */
+    double t_filter;          /* seconds: segmented filter launches (event-timed) */
+    double t_orth_check;      /* seconds: Gram-Schmidt, block QR, checks, finishing */
+    double t_finish;          /* seconds: Rayleigh-Ritz and polish of finished solves */
+    double filter_bytes;      /* algorithmic bytes of all filter steps */
+} flp_batch_stats;
+
+/* Every eigenpair in [alpha[i], beta[i]] of each A[i], for count independent
+ * problems solved together (the batched form of flp_solve): one segmented
+ * launch per Clenshaw step carries the current filter step of every active
+ * solve; solves leave the batch as they converge.
+ *   A: HOST array of count pointers to CSR matrices (device data).
+ *   alpha, beta: HOST arrays of count doubles.
+ *   opts: HOST array of count options or NULL (defaults).  All entries must
+ *         have the same block size and precision; opts[0].stream is the
+ *         caller's stream (synchronised at entry and exit).
+ *   use_graph: 1 to replay each block step's filter launches from a HIP graph.
+ *   results: HOST array of count result pointers (filled; free each with
+ *            flp_result_free); t_total of each result is its completion time
+ *            inside the batch.
+ *   codes: HOST array of count per-solve return codes.
+ *   stats: optional.
+ * Returns FLP_OK if every solve returned FLP_OK or FLP_E_NOCONV, else the
+ * first other error.  Synchronous. */
+int flp_solve_batch(int32_t count, const flp_csr *const *A, const double *alpha, const double *beta,
+                    const flp_opts *opts, int32_t use_graph, flp_result **results, int32_t *codes,
+                    flp_batch_stats *stats);
+
 /* Dense symmetric eigensolver used for the projected problems (Section
  * 3.2.2 solves T_k's eigenproblem on the CPU with a banded symmetric
  * eigensolver).  Host only; no GPU needed.

@@ -1,0 +1,580 @@
+// Host-side helpers of the filtered Lanczos procedure: workspace, filter
+// construction and the Clenshaw launch plan (Section 2.2), two-pass
+// Gram-Schmidt and block QR (Sections 2.3, 3.2.2), spectrum bounds, and
+// Rayleigh-Ritz with A (eq. rayleigh, eq. proj).  The device work runs in
+// the kernels of flp_kernels.hip; the small projected problems are solved on
+// the host with the banded eigensolver of flp_eigen.cpp, as in the paper.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "flp_host.h"
+
+namespace flp {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ workspace
+
+Buf::~Buf() { release(); }
+
+void Buf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+hipError_t ensure(Buf &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return e;
+    }
+    b.bytes = want;
+    return hipSuccess;
+}
+
+void Workspace::release_all() {
+    Buf *all[] = {&U[0], &U[1], &U[2], &V32, &val32, &partials, &small, &W, &Vin, &Q, &Y, &AY, &X, &AX, &resid_part};
+    for (Buf *b : all) b->release();
+    val32_src = nullptr;
+    val32_nnz = 0;
+}
+
+Workspace &ws() {
+    static Workspace w[64];
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return w[dev & 63];
+}
+
+// ------------------------------------------------------------------ CSR checks
+
+int check_csr(const flp_csr *A) {
+    if (!A) return fail(FLP_E_ARG, "A is NULL");
+    if (A->n <= 0) return fail(FLP_E_ARG, "n must be positive");
+    if (A->nnz < 0 || A->nnz >= (int64_t(1) << 31)) return fail(FLP_E_ARG, "nnz must be in [0, 2^31)");
+    if (!A->rowptr || (A->nnz > 0 && (!A->colind || !A->val)))
+        return fail(FLP_E_ARG, "CSR pointers must be non-NULL");
+    return FLP_OK;
+}
+
+
+// p(z) = sum b_i T_i(z), Clenshaw (Section 2.2) on a scalar.
+double cheb_scalar(const std::vector<double> &b, double z) {
+    double u1 = 0.0, u2 = 0.0;
+    for (int k = (int)b.size() - 1; k >= 1; --k) {
+        double u = b[k] + 2.0 * z * u1 - u2;
+        u2 = u1;
+        u1 = u;
+    }
+    return b[0] + z * u1 - u2;
+}
+
+// b_0..b_m of the indicator of [a, b] in [-1, 1] (closed form of Section 2.2).
+static void indicator_coeffs(double a1, double b1, int m, std::vector<double> &out) {
+    double ta = std::acos(a1), tb = std::acos(b1);
+    out.assign(m + 1, 0.0);
+    out[0] = (ta - tb) / M_PI;
+    for (int i = 1; i <= m; ++i) out[i] = 2.0 * (std::sin(i * ta) - std::sin(i * tb)) / (i * M_PI);
+}
+
+// Smallest m >= 1 with ||p_m - phi||_mu < eps ||phi||_mu (eq. optimaldegree);
+// the squared error falls by (pi/2) b_m^2 per degree from
+// ||phi||^2 - pi b_0^2, with ||phi||^2 = acos(a) - acos(b).
+static int auto_degree(double a1, double b1, double eps) {
+    double ta = std::acos(a1), tb = std::acos(b1);
+    double phi2 = ta - tb;
+    double b0 = phi2 / M_PI;
+    double err2 = phi2 - M_PI * b0 * b0;
+    const double lim = eps * std::sqrt(phi2);
+    for (int m = 1; m <= 2000; ++m) {
+        double bm = 2.0 * (std::sin(m * ta) - std::sin(m * tb)) / (m * M_PI);
+        err2 -= 0.5 * M_PI * bm * bm;
+        if (std::sqrt(std::max(err2, 0.0)) < lim) return m;
+    }
+    return 2000;
+}
+
+int make_filter(double alpha, double beta, int degree, double lmin, double lmax, double eps, flp_filter **out) {
+    if (!out) return fail(FLP_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!(std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(lmin) && std::isfinite(lmax)))
+        return fail(FLP_E_ARG, "non-finite interval or bounds");
+    if (!(alpha < beta)) return fail(FLP_E_ARG, "alpha must be < beta");
+    if (!(lmin < lmax)) return fail(FLP_E_ARG, "lmin must be < lmax");
+    if (degree > kMaxDegree) return fail(FLP_E_ARG, "degree too large");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(FLP_E_ARG, "eps must be in (0, 1)");
+    double lo = std::max(alpha, lmin), hi = std::min(beta, lmax);
+    if (!(lo <= hi)) return fail(FLP_E_INTERVAL, "[alpha, beta] does not meet [lmin, lmax]");
+    auto *f = new flp_filter;
+    f->alpha = alpha;
+    f->beta = beta;
+    f->lmin = lmin;
+    f->lmax = lmax;
+    f->c = 0.5 * (lmin + lmax);
+    f->e = 0.5 * (lmax - lmin);
+    f->a1 = std::min(std::max((lo - f->c) / f->e, -1.0), 1.0);
+    f->b1 = std::min(std::max((hi - f->c) / f->e, -1.0), 1.0);
+    f->m = degree > 0 ? degree : auto_degree(f->a1, f->b1, eps);
+    indicator_coeffs(f->a1, f->b1, f->m, f->b);
+    *out = f;
+    return FLP_OK;
+}
+
+// ------------------------------------------------------------------ filter apply
+//
+// Clenshaw's backward recurrence for W = p(Ahat) V (Section 2.2):
+//   U_{m+1} = U_{m+2} = 0,  U_k = b_k V + 2 Ahat U_{k+1} - U_{k+2},
+//   W = b_0 V + Ahat U_1 - U_2,   Ahat X = (A X - c X) / e.
+// U_m = b_m V is folded into the first product, so there are exactly m
+// products with A, each one launch with the update fused in.
+std::vector<ClenshawStep> clenshaw_plan(const flp_filter *p, int r, const void *V, int ldv, double *W, int ldw,
+                                        void *U0, void *U1, void *U2, bool fp32) {
+    const int m = p->m;
+    const std::vector<double> &b = p->b;
+    const double c = p->c, e = p->e;
+    const int ld = r;
+    std::vector<ClenshawStep> out;
+    auto step = [&](const void *X, int ldx, const void *Vv, const void *Y, void *o, int ldo, bool f64, double al,
+                    double be, double ga, double de) {
+        out.push_back(ClenshawStep{X, ldx, Vv, ldv, Y, ld, o, ldo, f64, al, be, ga, de});
+    };
+    const bool last_f64 = true;  // W is FP64 in both precisions
+    if (m == 1) {
+        step(V, ldv, nullptr, nullptr, W, ldw, last_f64, b[1] / e, b[0] - c * b[1] / e, 0.0, 0.0);
+        return out;
+    }
+    void *ring[3] = {U0, U1, U2};
+    // U_{m-1} = b_{m-1} V + (2 b_m / e) (A V - c V)
+    void *u_k1 = ring[0];
+    step(V, ldv, nullptr, nullptr, u_k1, ld, !fp32, 2.0 * b[m] / e, b[m - 1] - 2.0 * c * b[m] / e, 0.0, 0.0);
+    void *u_k2 = nullptr;  // U_{k+2}; U_m = b_m V is folded into the V coefficient
+    int slot = 1;
+    for (int k = m - 2; k >= 1; --k) {
+        void *o = ring[slot];
+        slot = (slot + 1) % 3;
+        if (k == m - 2)
+            step(u_k1, ld, V, nullptr, o, ld, !fp32, 2.0 / e, -2.0 * c / e, b[k] - b[m], 0.0);
+        else
+            step(u_k1, ld, V, u_k2, o, ld, !fp32, 2.0 / e, -2.0 * c / e, b[k], -1.0);
+        u_k2 = u_k1;
+        u_k1 = o;
+    }
+    // W = b_0 V + Ahat U_1 - U_2
+    if (m == 2)
+        step(u_k1, ld, V, nullptr, W, ldw, last_f64, 1.0 / e, -c / e, b[0] - b[2], 0.0);
+    else
+        step(u_k1, ld, V, u_k2, W, ldw, last_f64, 1.0 / e, -c / e, b[0], -1.0);
+    return out;
+}
+
+// Launch one planned step with the direct (single-matrix) kernel.
+int launch_plan_step(const flp_csr *A, const float *val32, int r, const ClenshawStep &st, bool fp32,
+                     hipStream_t s) {
+    const int n = A->n;
+    if (!fp32) {
+        CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, r, (const double *)st.X, st.ldx,
+                                            (const double *)st.V, st.ldv, (const double *)st.Y, st.ldy,
+                                            (double *)st.out, st.ldo, st.alpha, st.beta, st.gamma, st.delta, s));
+    } else if (st.out_f64) {
+        CK(launch_cheb_step<float, double>(n, A->rowptr, A->colind, val32, r, (const float *)st.X, st.ldx,
+                                           (const float *)st.V, st.ldv, (const float *)st.Y, st.ldy,
+                                           (double *)st.out, st.ldo, (float)st.alpha, (float)st.beta,
+                                           (float)st.gamma, (float)st.delta, s));
+    } else {
+        CK(launch_cheb_step<float, float>(n, A->rowptr, A->colind, val32, r, (const float *)st.X, st.ldx,
+                                          (const float *)st.V, st.ldv, (const float *)st.Y, st.ldy,
+                                          (float *)st.out, st.ldo, (float)st.alpha, (float)st.beta,
+                                          (float)st.gamma, (float)st.delta, s));
+    }
+    return FLP_OK;
+}
+
+// Filter bytes per SpMM step: matrix once, gathered input once, V, U_{k+2}
+// and the output once each.
+double filter_step_bytes(int n, int64_t nnz, int r, int prec) {
+    double wv = prec == FLP_PREC_FP32_FILTER ? 4.0 : 8.0;
+    return (double)nnz * (wv + 4.0) + 4.0 * (n + 1) + 4.0 * n * r * wv;
+}
+
+int ensure_val32(const flp_csr *A, Buf &buf, const double **src_cache, int64_t *nnz_cache, const float **out,
+                 hipStream_t s) {
+    if (A->val32) {
+        *out = A->val32;
+        return FLP_OK;
+    }
+    if (*src_cache != A->val || *nnz_cache != A->nnz || !buf.p) {
+        CK(ensure(buf, sizeof(float) * std::max<int64_t>(A->nnz, 1)));
+        CK(launch_to_float(A->nnz, A->val, (float *)buf.p, s));
+        *src_cache = A->val;
+        *nnz_cache = A->nnz;
+    }
+    *out = (const float *)buf.p;
+    return FLP_OK;
+}
+
+// Width of the column groups the filter runs on.  The Clenshaw recurrence
+// acts on each column independently, so a block of r columns can be
+// filtered as several narrower groups, each through all m steps.  A group
+// whose per-step working set (matrix + V + three recurrence vectors) fits
+// in the 256 MB Infinity Cache streams from that cache instead of HBM for
+// steps 2..m; this costs one extra matrix read per extra group and pays off
+// only when the narrower set fits and the full block does not.
+int filter_group_width(int n, int64_t nnz, int r, int prec) {
+    const double budget = 232e6;
+    const double wv = prec == FLP_PREC_FP32_FILTER ? 4.0 : 8.0;
+    const int vec = prec == FLP_PREC_FP32_FILTER ? 4 : 2;  // 16-byte loads
+    auto footprint = [&](int w) { return (double)nnz * (wv + 4.0) + 4.0 * (n + 1) + 4.0 * n * w * wv; };
+    if (footprint(r) <= budget) return r;
+    for (int w = r / 2; w >= vec; w /= 2) {
+        if (r % w != 0 || w % vec != 0) continue;
+        if (footprint(w) <= budget) return w;
+    }
+    return r;
+}
+
+// W = p(Ahat) V with the workspace's Clenshaw buffers (V, W: n x r with
+// leading dimensions ldv, ldw), filtered in column groups.
+int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, int ldv, double *W, int ldw, int r,
+                      int prec, hipStream_t s) {
+    Workspace &w = ws();
+    const int n = A->n;
+    const bool fp32 = prec == FLP_PREC_FP32_FILTER;
+    const int gw = filter_group_width(n, A->nnz, r, prec);
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    for (auto &u : w.U) CK(ensure(u, es * (size_t)n * gw));
+    const float *v32 = nullptr;
+    const void *vin = V;
+    int ldin = ldv;
+    if (fp32) {
+        CKR(ensure_val32(A, w.val32, &w.val32_src, &w.val32_nnz, &v32, s));
+        CK(ensure(w.V32, sizeof(float) * (size_t)n * r));
+        CK(launch_copy_block(n, r, 1.0, V, ldv, DMat{nullptr, 0, 0, 0}, 0, (float *)w.V32.p, r, s));
+        vin = w.V32.p;
+        ldin = r;
+    }
+    for (int j0 = 0; j0 < r; j0 += gw) {
+        const void *vg = fp32 ? (const void *)((const float *)vin + j0) : (const void *)((const double *)vin + j0);
+        auto plan = clenshaw_plan(p, gw, vg, ldin, W + j0, ldw, w.U[0].p, w.U[1].p, w.U[2].p, fp32);
+        for (const auto &st : plan) CKR(launch_plan_step(A, v32, gw, st, fp32, s));
+    }
+    return FLP_OK;
+}
+
+// ------------------------------------------------------------------ small dense helpers (host)
+
+// Upper Cholesky G = R^T R (r x r row-major).  Columns whose pivot falls
+// below thr^2 are flagged bad: their row of R becomes e_i (placeholder) and
+// later columns ignore them.
+void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, std::vector<int> &bad) {
+    R.assign((size_t)r * r, 0.0);
+    bad.assign(r, 0);
+    for (int i = 0; i < r; ++i) {
+        double d = G[i * r + i];
+        for (int k = 0; k < i; ++k) d -= R[k * r + i] * R[k * r + i];
+        if (!(d > thr2)) {
+            bad[i] = 1;
+            R[i * r + i] = 1.0;
+            continue;
+        }
+        double rii = std::sqrt(d);
+        R[i * r + i] = rii;
+        for (int j = i + 1; j < r; ++j) {
+            double t = G[i * r + j];
+            for (int k = 0; k < i; ++k) t -= R[k * r + i] * R[k * r + j];
+            R[i * r + j] = t / rii;
+        }
+    }
+}
+
+// inverse of an upper-triangular r x r
+void upper_inverse(int r, const std::vector<double> &R, std::vector<double> &Ri) {
+    Ri.assign((size_t)r * r, 0.0);
+    for (int j = 0; j < r; ++j) {
+        Ri[j * r + j] = 1.0 / R[j * r + j];
+        for (int i = j - 1; i >= 0; --i) {
+            double t = 0.0;
+            for (int k = i + 1; k <= j; ++k) t += R[i * r + k] * Ri[k * r + j];
+            Ri[i * r + j] = -t / R[i * r + i];
+        }
+    }
+}
+
+void matmul_upper(int r, const std::vector<double> &A, const std::vector<double> &B, std::vector<double> &C) {
+    C.assign((size_t)r * r, 0.0);
+    for (int i = 0; i < r; ++i)
+        for (int k = 0; k < r; ++k)
+            for (int j = 0; j < r; ++j) C[i * r + j] += A[i * r + k] * B[k * r + j];
+}
+
+// ------------------------------------------------------------------ device helpers
+
+// Host -> device copy that is complete when it returns (the source may be a
+// temporary host vector).
+hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+int small_dev(size_t elems, double **out) {
+    Workspace &w = ws();
+    CK(ensure(w.small, elems * sizeof(double)));
+    *out = (double *)w.small.p;
+    return FLP_OK;
+}
+
+// C (K x c, host or device) = A^T B with A n x K (lda), B n x c (ldb).
+// dev_out: device K x c row-major; host_out (optional) receives a copy
+// (synchronises the stream).
+int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *dev_out,
+            double *host_out, hipStream_t s) {
+    Workspace &w = ws();
+    TnPlan pl = plan_tn(n, K, c);
+    CK(ensure(w.partials, pl.partial_elems * sizeof(double)));
+    CK(launch_gemm_tn_partial(pl, n, K, c, A, B, ldb, (double *)w.partials.p, s));
+    CK(launch_reduce_partials(pl, K, c, (double *)w.partials.p, dev_out, c, s));
+    if (host_out) {
+        CK(hipMemcpyAsync(host_out, dev_out, sizeof(double) * (size_t)K * c, hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+    }
+    return FLP_OK;
+}
+
+// Two passes of classical Gram-Schmidt of W (n x r, ld r) against
+// the first k columns of Q.  H1, H2 (k x r each) stay on the device in hdev[0..2kr).
+int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s) {
+    for (int pass = 0; pass < 2; ++pass) {
+        double *H = hdev + (size_t)pass * k * r;
+        CKR(gram_tn(n, k, r, Q, W, r, H, nullptr, s));
+        CK(launch_gemm_nn(n, k, r, -1.0, Q, H, r, 1.0, W, r, s));
+    }
+    return FLP_OK;
+}
+
+// Block normalisation W = Qn S by Cholesky QR twice (eq. lanczos: S upper
+// triangular, non-negative diagonal).  Columns that are numerically
+// dependent are replaced by random vectors orthogonalised against Q (when
+// given) and the rest of the block; their rows of S are zero.  The Gram
+// matrix carries an absolute rounding error of about u ||W||_F^2, so a
+// Cholesky pivot sqrt(d_i) is only resolved down to ~1e-8 ||W||_F: a column
+// counts as dependent when sqrt(d_i) < 1e-7 ||W||_F.  S: host r x r
+// row-major.
+int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<double> &S,
+                  uint64_t seed, uint64_t sid, hipStream_t s, bool *replaced, int depth) {
+    if (depth > 3) return fail(FLP_E_DEVICE, "block QR: could not repair a rank-deficient block");
+    double *dev = nullptr;
+    CKR(small_dev((size_t)2 * std::max<int64_t>(k, r) * r + 4 * (size_t)r * r + 64, &dev));
+    double *gdev = dev, *rdev = dev + r * r, *hdev = dev + 2 * r * r;
+    std::vector<double> G((size_t)r * r), R1, R2, Ri;
+    std::vector<int> bad, bad2;
+    // pass 1
+    CKR(gram_tn(n, r, r, plain_mat(W, r), W, r, gdev, G.data(), s));
+    double fro2 = 0.0;
+    for (int i = 0; i < r; ++i) fro2 += std::max(G[i * r + i], 0.0);
+    const double thr = 1e-7 * std::sqrt(fro2);
+    cholesky_flag(r, G.data(), std::max(thr * thr, 1e-300), R1, bad);
+    int nbad = 0;
+    for (int i = 0; i < r; ++i) nbad += bad[i];
+    upper_inverse(r, R1, Ri);
+    CK(h2d(rdev, Ri.data(), sizeof(double) * r * r, s));
+    CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(W, r), rdev, r, 0.0, W, r, s));
+    if (nbad == 0) {
+        // pass 2 on the (nearly) orthonormal block
+        CKR(gram_tn(n, r, r, plain_mat(W, r), W, r, gdev, G.data(), s));
+        cholesky_flag(r, G.data(), 1e-300, R2, bad2);
+        for (int i = 0; i < r; ++i)
+            if (bad2[i]) return fail(FLP_E_DEVICE, "block QR: second Cholesky pass broke down");
+        upper_inverse(r, R2, Ri);
+        CK(h2d(rdev, Ri.data(), sizeof(double) * r * r, s));
+        CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(W, r), rdev, r, 0.0, W, r, s));
+        matmul_upper(r, R2, R1, S);
+        CK(hipStreamSynchronize(s));
+        return FLP_OK;
+    }
+    // repair: the good columns of W are now orthonormal; dependent ones are
+    // replaced by random vectors, the block is re-orthogonalised against Q and
+    // normalised again: W_orig ~= Qn (S2 S1) with S1 = R1 minus its bad rows.
+    if (replaced) *replaced = true;
+    std::vector<double> S1 = R1;
+    for (int i = 0; i < r; ++i)
+        if (bad[i])
+            for (int j = 0; j < r; ++j) S1[i * r + j] = 0.0;
+    for (int i = 0; i < r; ++i)
+        if (bad[i]) CK(launch_randn(n, 1, W + i, r, seed, sid * 131 + depth * 17 + i + 1, s));
+    if (Q && k > 0) CKR(cgs2(*Q, k, n, W, r, hdev, s));
+    std::vector<double> S2;
+    CKR(block_qr_impl(W, n, r, Q, k, S2, seed, sid + 7777, s, nullptr, depth + 1));
+    matmul_upper(r, S2, S1, S);
+    return FLP_OK;
+}
+
+// ------------------------------------------------------------------ bounds
+
+int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s) {
+    Workspace &w = ws();
+    const int n = A->n;
+    int k = std::max(1, std::min(k0, n));
+    const int ldb = (k + 2) & ~1;
+    CK(ensure(w.Q, sizeof(double) * (size_t)n * ldb));
+    CK(ensure(w.W, sizeof(double) * (size_t)n * 2));
+    double *Qb = (double *)w.Q.p, *wv = (double *)w.W.p;
+    double *dev = nullptr;
+    CKR(small_dev((size_t)4 * ldb + 64, &dev));
+    // start vector
+    CK(launch_randn(n, 1, wv, 1, seed, 0xB0B0, s));
+    double g = 0.0;
+    CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, dev, &g, s));
+    if (!(g > 0.0)) return fail(FLP_E_DEVICE, "bounds: zero start vector");
+    CK(launch_copy_block(n, 1, 1.0 / std::sqrt(g), wv, 1, plain_mat(Qb, ldb), 0, nullptr, 0, s));
+    std::vector<double> al, be;
+    std::vector<double> h1(k), h2(k);
+    double beta_k = 0.0;
+    int steps = 0;
+    for (int j = 0; j < k; ++j) {
+        // w = A q_j
+        CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, 1, Qb + j, ldb, nullptr, 0, nullptr,
+                                            0, wv, 1, 1.0, 0.0, 0.0, 0.0, s));
+        CKR(cgs2(plain_mat(Qb, ldb), j + 1, n, wv, 1, dev, s));
+        CK(hipMemcpyAsync(h1.data(), dev, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(h2.data(), dev + (j + 1), sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+        CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, dev + 2 * ldb, &g, s));
+        al.push_back(h1[j] + h2[j]);
+        double bj = std::sqrt(std::max(g, 0.0));
+        be.push_back(bj);
+        steps = j + 1;
+        beta_k = bj;
+        if (bj == 0.0 || j == k - 1) break;
+        CK(launch_copy_block(n, 1, 1.0 / bj, wv, 1, plain_mat(Qb, ldb), j + 1, nullptr, 0, s));
+    }
+    // Ritz values of the tridiagonal and the last eigenvector row
+    std::vector<double> T((size_t)steps * steps, 0.0);
+    for (int i = 0; i < steps; ++i) {
+        T[(size_t)i * steps + i] = al[i];
+        if (i + 1 < steps) {
+            T[(size_t)i * steps + i + 1] = be[i];
+            T[(size_t)(i + 1) * steps + i] = be[i];
+        }
+    }
+    std::vector<double> theta(steps), last(steps);
+    int row = steps - 1;
+    if (sym_eig(steps, 1, T.data(), theta.data(), &row, 1, last.data()) != 0)
+        return fail(FLP_E_DEVICE, "bounds: tridiagonal eigensolver did not converge");
+    double rho_lo = std::fabs(beta_k * last[0]);
+    double rho_hi = std::fabs(beta_k * last[steps - 1]);
+    double delta = 1e-3 * (theta[steps - 1] - theta[0]);
+    double lo = theta[0] - rho_lo - delta;
+    double hi = theta[steps - 1] + rho_hi + delta;
+    // Gershgorin enclosure
+    int nb = gershgorin_blocks(n);
+    CK(ensure(w.partials, sizeof(double) * (2 * (size_t)nb + 8)));
+    CKR(small_dev((size_t)4 * ldb + 64, &dev));
+    CK(launch_gershgorin(n, A->rowptr, A->colind, A->val, (double *)w.partials.p, nb, dev, s));
+    double gg[2];
+    CK(hipMemcpyAsync(gg, dev, sizeof(gg), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    *lmin = std::max(lo, gg[0]);
+    *lmax = std::min(hi, gg[1]);
+    if (!(*lmin < *lmax)) {
+        // a matrix with a single distinct eigenvalue: widen symmetrically
+        double mid = 0.5 * (*lmin + *lmax), rad = std::max(1e-12, 1e-8 * std::fabs(mid));
+        *lmin = mid - rad;
+        *lmax = mid + rad;
+    }
+    return FLP_OK;
+}
+
+// ------------------------------------------------------------------ solve
+
+// Y (n x c, ld ldc) <- Y R^{-1} with Y^T Y = R^T R (one Cholesky QR pass);
+// tmp is an n x c work block.
+int orthonormalize_cols(int n, int c, double *&Y, double *&tmp, int ldc, double *sdev, hipStream_t s) {
+    std::vector<double> G((size_t)c * c), R, Ri;
+    std::vector<int> bad;
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), Y, ldc, sdev, G.data(), s));
+    cholesky_flag(c, G.data(), 1e-300, R, bad);
+    for (int i = 0; i < c; ++i)
+        if (bad[i]) return fail(FLP_E_DEVICE, "Ritz block lost rank");
+    upper_inverse(c, R, Ri);
+    std::vector<double> Rp((size_t)c * ldc, 0.0);
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) Rp[(size_t)i * ldc + j] = Ri[(size_t)i * c + j];
+    CK(h2d(sdev, Rp.data(), sizeof(double) * Rp.size(), s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(Y, ldc), sdev, ldc, 0.0, tmp, ldc, s));
+    std::swap(Y, tmp);
+    return FLP_OK;
+}
+
+// Rayleigh-Ritz with A on the orthonormal block Y (eq. rayleigh, eq. proj):
+// G = Y^T A Y = Z diag(lam) Z^T, X = Y Z, AX = (A Y) Z and the residual
+// norms ||A x_j - lam_j x_j|| (host, unscaled).  lam ascending.
+int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
+                  double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s) {
+    Workspace &w = ws();
+    for (int j0 = 0; j0 < c; j0 += 16) {
+        int cw = std::min(16, c - j0);
+        CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, cw, Y + j0, ldc, nullptr, 0, nullptr,
+                                            0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
+    }
+    std::vector<double> G((size_t)c * c);
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), AY, ldc, sdev, G.data(), s));
+    std::vector<double> Gs((size_t)c * c);
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) Gs[(size_t)i * c + j] = 0.5 * (G[(size_t)i * c + j] + G[(size_t)j * c + i]);
+    lam.assign(c, 0.0);
+    std::vector<double> ZG((size_t)c * c);
+    std::vector<int> rows(c);
+    for (int i = 0; i < c; ++i) rows[i] = i;
+    if (sym_eig(c, c - 1, Gs.data(), lam.data(), rows.data(), c, ZG.data()) != 0)
+        return fail(FLP_E_DEVICE, "eigensolver for the Rayleigh-Ritz matrix did not converge");
+    std::vector<double> Zp((size_t)c * ldc, 0.0);
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) Zp[(size_t)i * ldc + j] = ZG[(size_t)i * c + j];
+    CK(h2d(sdev, Zp.data(), sizeof(double) * Zp.size(), s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(Y, ldc), sdev, ldc, 0.0, X, ldc, s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(AY, ldc), sdev, ldc, 0.0, AX, ldc, s));
+    double *lamd = sdev + (size_t)c * ldc;
+    double *rdev = lamd + ldc;
+    CK(h2d(lamd, lam.data(), sizeof(double) * c, s));
+    int nch = resid_chunks(n);
+    CK(ensure(w.resid_part, sizeof(double) * (size_t)nch * c));
+    CK(launch_resid_norms(n, c, AX, ldc, X, ldc, lamd, (double *)w.resid_part.p, nch, rdev, s));
+    res.assign(c, 0.0);
+    CK(hipMemcpyAsync(res.data(), rdev, sizeof(double) * c, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return FLP_OK;
+}
+
+}  // namespace flp

@@ -57,6 +57,27 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
                             Tout *out, int ldo, T alpha, T beta, T gamma, T delta,
                             hipStream_t s);
 
+// One segment of a segmented filter step: the current Clenshaw launch of
+// one solve in a batch (out = alpha AX + beta X + gamma V + delta Y).
+struct SegEntry {
+    const int32_t *rowptr;
+    const int32_t *colind;
+    const void *val;  // double or float, as the launch's type
+    const void *X;
+    const void *V;    // may be null
+    const void *Y;    // may be null
+    void *out;
+    int n, tile0;     // rows; first tile of this segment in the launch
+    int ldx, ldv, ldy, ldo;
+    int out_f64;      // 1: output in FP64 (last step of an FP32 filter)
+    int pad;
+    double alpha, beta, gamma, delta;
+};
+// rows per tile of the segmented kernel for block width r and value type
+int seg_rows_per_tile(int r, bool fp32);
+// One launch over nseg segments (tab: device array sorted by tile0).
+hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s);
+
 // Partial sums for C = A^T B over row chunks: A n x K (lda), B n x c (ldb).
 // partials[chunk][K * c] (row-major K x c).  Returns the number of chunks
 // used via *nchunks (caller sizes partials with plan_tn()).

@@ -222,6 +222,151 @@ template hipError_t launch_cheb_step<float, double>(int, const int32_t *, const 
                                                     const float *, int, const float *, int, const float *, int,
                                                     double *, int, float, float, float, float, hipStream_t);
 
+// ------------------------------------------------------------------ segmented filter step
+//
+// One launch advances the filters of many independent solves by one
+// Clenshaw step: the launch's tiles are split into segments (one per solve,
+// each with its own matrix, vectors and coefficients) by a prefix sum of
+// tile counts; a block finds its segment by binary search and then runs the
+// same row mapping and fused epilogue as cheb_step_kernel.
+
+namespace {
+
+template <typename T, int LPR, int VEC>
+__global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg) {
+    constexpr int RPB = 256 / LPR;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].tile0 <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SegEntry &e = tab[lo];
+    const int n = e.n;
+    const int row = (tile - e.tile0) * RPB + threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * VEC;
+    if (row >= n) return;
+    const int32_t *__restrict__ rowptr = e.rowptr;
+    const int32_t *__restrict__ colind = e.colind;
+    const T *__restrict__ val = (const T *)e.val;
+    const T *__restrict__ X = (const T *)e.X;
+    const int ldx = e.ldx;
+    const int p0 = rowptr[row], p1 = rowptr[row + 1];
+    T acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = T(0);
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        int cc[4];
+        T aa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            cc[u] = colind[p + u];
+            aa[u] = val[p + u];
+        }
+        T xv[4][VEC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) load_vec<T, VEC>(X + (int64_t)cc[u] * ldx + c0, xv[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], xv[u][v], acc[v]);
+    }
+    for (; p < p1; ++p) {
+        const int cc = colind[p];
+        const T aa = val[p];
+        T xv[VEC];
+        load_vec<T, VEC>(X + (int64_t)cc * ldx + c0, xv);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = fma(aa, xv[v], acc[v]);
+    }
+    T xr[VEC];
+    load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
+    const T alpha = (T)e.alpha, beta = (T)e.beta, gamma = (T)e.gamma, delta = (T)e.delta;
+    T res[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) res[v] = alpha * acc[v] + beta * xr[v];
+    if (e.V) {
+        T vv[VEC];
+        load_vec<T, VEC>((const T *)e.V + (int64_t)row * e.ldv + c0, vv);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(gamma, vv[v], res[v]);
+    }
+    if (e.Y) {
+        T yy[VEC];
+        load_vec<T, VEC>((const T *)e.Y + (int64_t)row * e.ldy + c0, yy);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(delta, yy[v], res[v]);
+    }
+    if (e.out_f64) {
+        double *o = (double *)e.out + (int64_t)row * e.ldo + c0;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) o[v] = (double)res[v];
+    } else {
+        store_vec<T, VEC>((T *)e.out + (int64_t)row * e.ldo + c0, res);
+    }
+}
+
+}  // namespace
+
+// lanes per row of the segmented kernel; must match launch_cheb_seg
+static int seg_lpr(int r, bool fp32) {
+    const int v16 = fp32 ? 4 : 2;
+    if (r % v16 == 0) {
+        const int l = r / v16;
+        if (l == 1 || l == 2 || l == 4 || l == 8 || (!fp32 && l == 16)) return l;
+    }
+    return r == 1 ? 1 : (r == 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32))));
+}
+
+int seg_rows_per_tile(int r, bool fp32) { return 256 / seg_lpr(r, fp32); }
+
+hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s) {
+    if (nseg <= 0 || total_tiles <= 0) return hipSuccess;
+#define FLP_SEG(T, LPR, VEC) \
+    hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC>), dim3(total_tiles), dim3(256), 0, s, tab, nseg); \
+    return hipGetLastError()
+    if (!fp32) {
+        if (r % 2 == 0) {
+            switch (r / 2) {
+                case 1: FLP_SEG(double, 1, 2);
+                case 2: FLP_SEG(double, 2, 2);
+                case 4: FLP_SEG(double, 4, 2);
+                case 8: FLP_SEG(double, 8, 2);
+                case 16: FLP_SEG(double, 16, 2);
+                default: break;
+            }
+        }
+        if (r == 1) { FLP_SEG(double, 1, 1); }
+        if (r == 2) { FLP_SEG(double, 2, 1); }
+        if (r <= 4) { FLP_SEG(double, 4, 1); }
+        if (r <= 8) { FLP_SEG(double, 8, 1); }
+        if (r <= 16) { FLP_SEG(double, 16, 1); }
+        if (r <= 32) { FLP_SEG(double, 32, 1); }
+    } else {
+        if (r % 4 == 0) {
+            switch (r / 4) {
+                case 1: FLP_SEG(float, 1, 4);
+                case 2: FLP_SEG(float, 2, 4);
+                case 4: FLP_SEG(float, 4, 4);
+                case 8: FLP_SEG(float, 8, 4);
+                default: break;
+            }
+        }
+        if (r == 1) { FLP_SEG(float, 1, 1); }
+        if (r == 2) { FLP_SEG(float, 2, 1); }
+        if (r <= 4) { FLP_SEG(float, 4, 1); }
+        if (r <= 8) { FLP_SEG(float, 8, 1); }
+        if (r <= 16) { FLP_SEG(float, 16, 1); }
+        if (r <= 32) { FLP_SEG(float, 32, 1); }
+    }
+#undef FLP_SEG
+    return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------------------------ MFMA helpers
 //
 // v_mfma_f64_16x16x4f64: D(16x16) = A(16x4) B(4x16) + C.  Lane l supplies

@@ -1,0 +1,340 @@
+// The filtered Lanczos procedure as a per-solve state machine (Sections 2.3
+// and 3.2.2): set-up (bounds, filter, start block), one block step after
+// each filter application (two-pass Gram-Schmidt, D_j, block QR, periodic
+// convergence check), and the final Rayleigh-Ritz with A.  The single-solve
+// driver runs one state machine; the batched driver advances many in
+// lockstep with one segmented filter launch per Clenshaw step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "flp_host.h"
+
+namespace flp {
+
+namespace {
+
+// T_k (K x K, row-major dense, semi-bandwidth r) from D_1..D_k and S_1..S_{k-1}
+// (eq. lanczos).
+void assemble_T(const Solve &S, int steps, std::vector<double> &T) {
+    const int r = S.r, K = steps * r;
+    T.assign((size_t)K * K, 0.0);
+    for (int b = 0; b < steps; ++b)
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) {
+                T[(size_t)(b * r + i) * K + b * r + j] = S.D_all[(size_t)b * r * r + i * r + j];
+                if (b + 1 < steps) {
+                    const double sv = S.S_all[(size_t)b * r * r + i * r + j];  // S_b(i, j)
+                    T[(size_t)((b + 1) * r + i) * K + b * r + j] = sv;
+                    T[(size_t)(b * r + j) * K + (b + 1) * r + i] = sv;
+                }
+            }
+}
+
+}  // namespace
+
+int solve_setup(Solve &S) {
+    S.t_start = now();
+    const flp_csr *A = S.A;
+    const flp_opts &o = S.o;
+    hipStream_t s = S.s;
+    S.n = A->n;
+    S.r = o.block;
+    const int n = S.n, r = S.r;
+    if (r < 1 || r > 16) return fail(FLP_E_ARG, "block size must be in [1, 16]");
+    if (r > n) return fail(FLP_E_ARG, "block size exceeds n");
+    if (!(std::isfinite(S.alpha) && std::isfinite(S.beta)) || !(S.alpha < S.beta))
+        return fail(FLP_E_ARG, "need finite alpha < beta");
+    if (o.prec != FLP_PREC_FP64 && o.prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
+    const bool fp32 = o.prec == FLP_PREC_FP32_FILTER;
+
+    // PREPROC: spectrum bounds
+    double t0 = now();
+    if (o.lmin < o.lmax) {
+        S.lmin = o.lmin;
+        S.lmax = o.lmax;
+    } else {
+        CKR(estimate_bounds_impl(A, o.k0 > 0 ? o.k0 : kDefaultK0, o.seed, &S.lmin, &S.lmax, s));
+    }
+    S.st.t_pre = now() - t0;
+
+    flp_filter *pf = nullptr;
+    CKR(make_filter(S.alpha, S.beta, o.degree, S.lmin, S.lmax, o.eps > 0 ? o.eps : kDefaultEps, &pf));
+    S.filt.reset(pf);
+    S.tau = 0.5 * std::min(cheb_scalar(S.filt->b, S.filt->a1), cheb_scalar(S.filt->b, S.filt->b1));
+    S.tol_p = fp32 ? 1e-5 : 1e-10;
+    S.check_every = o.check_every > 0 ? o.check_every : kDefaultCheck;
+
+    int64_t maxb = o.max_basis > 0 ? o.max_basis : kDefaultMaxBasis;
+    maxb = std::min<int64_t>(maxb, n);
+    S.max_steps = std::max<int>(1, (int)(maxb / r));
+    // Lanczos basis: column panels of 128 columns, each a contiguous
+    // row-major n x 128 block (the reorthogonalisation streams whole panels)
+    S.npanels = ((int64_t)S.max_steps * r + (1 << kPanelLog2) - 1) >> kPanelLog2;
+    SolveBufs &B = *S.B;
+    CK(ensure(B.Q, sizeof(double) * (size_t)n * (size_t)(S.npanels << kPanelLog2)));
+    CK(ensure(B.W, sizeof(double) * (size_t)n * r));
+    CK(ensure(B.Vin, sizeof(double) * (size_t)n * r));
+    CK(ensure(B.hdev, sizeof(double) * ((size_t)2 * (S.npanels << kPanelLog2) * r + 4 * r * r + 64)));
+    S.W = (double *)B.W.p;
+    S.Vin = (double *)B.Vin.p;
+    S.hdev = (double *)B.hdev.p;
+    S.Q = panel_mat((double *)B.Q.p, n, kPanelLog2);
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    for (auto &u : B.U) CK(ensure(u, es * (size_t)n * r));
+    for (int i = 0; i < 3; ++i) S.U[i] = B.U[i].p;
+    if (fp32) {
+        CKR(ensure_val32(A, B.val32, &B.val32_src, &B.val32_nnz, &S.val32, s));
+        CK(ensure(B.V32, sizeof(float) * (size_t)n * r));
+        S.V32 = (float *)B.V32.p;
+    }
+    S.plan = clenshaw_plan(S.filt.get(), r, fp32 ? (const void *)S.V32 : (const void *)S.Vin, r, S.W, r, S.U[0],
+                           S.U[1], S.U[2], fp32);
+
+    // start block: orthonormal random (or given) n x r
+    if (o.start) {
+        CK(h2d(S.W, o.start, sizeof(double) * (size_t)n * r, s));
+    } else {
+        CK(launch_randn(n, r, S.W, r, o.seed, 0x51A7, s));
+    }
+    std::vector<double> S0;
+    CKR(block_qr_impl(S.W, n, r, nullptr, 0, S0, o.seed, 1, s, nullptr));
+    CK(launch_copy_block(n, r, 1.0, S.W, r, S.Q, 0, nullptr, 0, s));
+    CK(launch_copy_block(n, r, 1.0, S.W, r, plain_mat(S.Vin, r), 0, S.V32, r, s));
+    return FLP_OK;
+}
+
+int solve_after_filter(Solve &S) {
+    const int n = S.n, r = S.r;
+    hipStream_t s = S.s;
+    const double t0 = now();
+    const int k = (S.steps + 1) * r;  // basis columns so far
+    S.st.filter_bytes += filter_step_bytes(n, S.A->nnz, r, S.o.prec) * S.filt->m;
+    S.st.mv += (int64_t)r * S.filt->m;
+    // full reorthogonalisation (Section 3.2.2): two passes of classical Gram-Schmidt
+    CKR(cgs2(S.Q, k, n, S.W, r, S.hdev, s));
+    std::vector<double> h1((size_t)r * r), h2((size_t)r * r);
+    CK(hipMemcpyAsync(h1.data(), S.hdev + (size_t)(k - r) * r, sizeof(double) * r * r, hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(h2.data(), S.hdev + (size_t)k * r + (size_t)(k - r) * r, sizeof(double) * r * r,
+                      hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+            const double a = h1[i * r + j] + h2[i * r + j], b = h1[j * r + i] + h2[j * r + i];
+            S.D_all.push_back(0.5 * (a + b));
+        }
+    // W = Q_{j+1} S_j (eq. lanczos)
+    CKR(block_qr_impl(S.W, n, r, &S.Q, k, S.Sj, S.o.seed, 1000 + S.steps, s, nullptr));
+    S.S_all.insert(S.S_all.end(), S.Sj.begin(), S.Sj.end());
+    S.st.t_orth += now() - t0;
+    ++S.steps;
+    const bool last = S.steps == S.max_steps || (int64_t)(S.steps + 1) * r > n;
+    if (S.steps % S.check_every == 0 || last) {
+        // convergence check on the Ritz values of T_k (Section 3.2.2)
+        const double tc = now();
+        const int K = k;
+        std::vector<double> T;
+        assemble_T(S, S.steps, T);
+        std::vector<double> theta(K);
+        std::vector<int> rows(r);
+        for (int i = 0; i < r; ++i) rows[i] = K - r + i;
+        std::vector<double> Zl((size_t)r * K);
+        if (sym_eig(K, r, T.data(), theta.data(), rows.data(), r, Zl.data()) != 0)
+            return fail(FLP_E_DEVICE, "eigensolver for T_k did not converge");
+        // rho_i = || S_k E_k^T w_i ||
+        double big = 1e-300;
+        for (double t : theta) big = std::max(big, std::fabs(t));
+        S.cand.clear();
+        bool ok = true;
+        for (int i = 0; i < K; ++i) {
+            if (theta[i] < S.tau) continue;
+            S.cand.push_back(i);
+            double rho2 = 0.0;
+            for (int a = 0; a < r; ++a) {
+                double t = 0.0;
+                for (int b = 0; b < r; ++b) t += S.Sj[a * r + b] * Zl[(size_t)b * K + i];
+                rho2 += t * t;
+            }
+            if (std::sqrt(rho2) > S.tol_p * big) ok = false;
+        }
+        S.st.t_check += now() - tc;
+        if ((ok && (int)S.cand.size() == S.prev_count) || last) {
+            S.converged = ok && (int)S.cand.size() == S.prev_count;
+            S.kfinal = K;
+            S.done = true;
+            return FLP_OK;
+        }
+        S.prev_count = (int)S.cand.size();
+    }
+    // the new block joins the basis and is the next filter input
+    CK(launch_copy_block(n, r, 1.0, S.W, r, S.Q, k, nullptr, 0, s));
+    CK(launch_copy_block(n, r, 1.0, S.W, r, plain_mat(S.Vin, r), 0, S.V32, r, s));
+    return FLP_OK;
+}
+
+int solve_finish(Solve &S, flp_result **out) {
+    const double tr = now();
+    Workspace &w = ws();
+    hipStream_t s = S.s;
+    const int n = S.n, r = S.r;
+    const flp_csr *A = S.A;
+    const double anorm = std::max(std::fabs(S.lmin), std::fabs(S.lmax));
+    auto *res = new flp_result;
+    std::memset(res, 0, sizeof(*res));
+    res->n = n;
+    res->lmin = S.lmin;
+    res->lmax = S.lmax;
+    res->alpha = S.alpha;
+    res->beta = S.beta;
+    res->degree = S.filt->m;
+    res->converged = S.converged ? 1 : 0;
+    std::unique_ptr<flp_result, void (*)(flp_result *)> guard(res, flp_result_free);
+    S.st.iters = S.steps;
+    S.st.basis_cols = S.kfinal;
+    const int c = (int)S.cand.size();
+    if (c > 0) {
+        const int K = S.kfinal;
+        // eigenvectors of T_k for the candidates (eq. proj)
+        std::vector<double> T;
+        assemble_T(S, S.steps, T);
+        std::vector<int> rows(K);
+        for (int i = 0; i < K; ++i) rows[i] = i;
+        std::vector<double> Z((size_t)K * K), th(K);
+        const double tc = now();
+        if (sym_eig(K, r, T.data(), th.data(), rows.data(), K, Z.data()) != 0)
+            return fail(FLP_E_DEVICE, "eigensolver for T_k did not converge");
+        S.st.t_check += now() - tc;
+        const int ldc = (c + 1) & ~1;
+        std::vector<double> Wc((size_t)K * ldc, 0.0);
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < c; ++j) Wc[(size_t)i * ldc + j] = Z[(size_t)i * K + S.cand[j]];
+        CK(ensure(w.Y, sizeof(double) * (size_t)n * ldc));
+        CK(ensure(w.AY, sizeof(double) * (size_t)n * ldc));
+        CK(ensure(w.X, sizeof(double) * (size_t)n * ldc));
+        CK(ensure(w.AX, sizeof(double) * (size_t)n * ldc));
+        double *Y = (double *)w.Y.p, *AY = (double *)w.AY.p, *X = (double *)w.X.p, *AX = (double *)w.AX.p;
+        double *sdev = nullptr;
+        CKR(small_dev((size_t)std::max(K, c) * ldc * 2 + 4 * (size_t)ldc + 64, &sdev));
+        CK(h2d(sdev, Wc.data(), sizeof(double) * Wc.size(), s));
+        // Ritz vectors of p(A): Y = Q_k W_C
+        CK(launch_gemm_nn(n, K, c, 1.0, S.Q, sdev, ldc, 0.0, Y, ldc, s));
+        CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
+        std::vector<double> lam, rres;
+        CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+        const double alpha = S.alpha, beta = S.beta;
+        auto worst = [&](int &i0, int &i1) {
+            i0 = 0;
+            while (i0 < c && lam[i0] < alpha) ++i0;
+            i1 = i0;
+            while (i1 < c && lam[i1] <= beta) ++i1;
+            double m = 0.0;
+            for (int j = i0; j < i1; ++j) m = std::max(m, rres[j] / anorm);
+            return m;
+        };
+        const double tol = S.o.tol > 0 ? S.o.tol : kDefaultTol;
+        int i0 = 0, i1 = 0;
+        if (S.o.prec == FLP_PREC_FP32_FILTER) {
+            // FP64 polish: X <- p(A) X, orthonormalise, Rayleigh-Ritz with A
+            while (worst(i0, i1) > tol && S.st.polish_sweeps < 3) {
+                for (int j0 = 0; j0 < c; j0 += 16) {
+                    const int cw = std::min(16, c - j0);
+                    CKR(filter_apply_impl(S.filt.get(), A, X + j0, ldc, Y + j0, ldc, cw, FLP_PREC_FP64, s));
+                }
+                S.st.filter_bytes +=
+                    filter_step_bytes(n, A->nnz, 16, FLP_PREC_FP64) * S.filt->m * ((c + 15) / 16);
+                CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
+                CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
+                CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+                ++S.st.polish_sweeps;
+            }
+        }
+        worst(i0, i1);
+        const int cnt = i1 - i0;
+        res->count = cnt;
+        if (cnt > 0) {
+            res->evals = new double[cnt];
+            res->resid = new double[cnt];
+            for (int j = 0; j < cnt; ++j) {
+                res->evals[j] = lam[i0 + j];
+                res->resid[j] = rres[i0 + j] / anorm;
+            }
+            CK(hipMalloc(&res->evecs, sizeof(double) * (size_t)n * cnt));
+            CK(launch_transpose_out(n, cnt, X + i0, ldc, res->evecs, s));
+            CK(hipStreamSynchronize(s));
+        }
+    }
+    S.st.t_rr = now() - tr;
+    S.st.t_total = now() - S.t_start;
+    res->stats = S.st;
+    *out = guard.release();
+    return S.converged ? FLP_OK : FLP_E_NOCONV;
+}
+
+// ------------------------------------------------------------------ single solve
+
+namespace {
+SolveBufs &single_bufs() {
+    static SolveBufs b[64];
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return b[dev & 63];
+}
+}  // namespace
+
+void release_single_bufs() {
+    SolveBufs &B = single_bufs();
+    Buf *all[] = {&B.Q, &B.W, &B.Vin, &B.U[0], &B.U[1], &B.U[2], &B.V32, &B.val32, &B.hdev};
+    for (Buf *b : all) b->release();
+    B.val32_src = nullptr;
+    B.val32_nnz = 0;
+}
+
+int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out) {
+    Solve S;
+    S.A = A;
+    S.alpha = alpha;
+    S.beta = beta;
+    S.o = o;
+    S.s = (hipStream_t)o.stream;
+    S.B = &single_bufs();
+    CKR(solve_setup(S));
+    const bool fp32 = o.prec == FLP_PREC_FP32_FILTER;
+    // filter in cache-sized column groups (the plan is rebuilt for the group width)
+    const int gw = filter_group_width(S.n, A->nnz, S.r, o.prec);
+    std::vector<ClenshawStep> plan;
+    for (int j0 = 0; j0 < S.r; j0 += gw) {
+        const void *vg = fp32 ? (const void *)(S.V32 + j0) : (const void *)(S.Vin + j0);
+        if (gw != S.r) {
+            // group scratch: the U buffers hold n x r, enough for n x gw
+            auto g = clenshaw_plan(S.filt.get(), gw, vg, S.r, S.W + j0, S.r, S.U[0], S.U[1], S.U[2], fp32);
+            plan.insert(plan.end(), g.begin(), g.end());
+        }
+    }
+    if (gw == S.r) plan = S.plan;
+    hipEvent_t ev[2];
+    for (auto &e : ev) CK(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ev};
+    while (!S.done) {
+        CK(hipEventRecord(ev[0], S.s));
+        for (const auto &st : plan) CKR(launch_plan_step(A, S.val32, gw, st, fp32, S.s));
+        CK(hipEventRecord(ev[1], S.s));
+        CK(hipEventSynchronize(ev[1]));
+        float ms = 0;
+        CK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        S.st.t_mv += ms * 1e-3;
+        CKR(solve_after_filter(S));
+    }
+    return solve_finish(S, out);
+}
+
+}  // namespace flp

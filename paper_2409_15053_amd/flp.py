@@ -28,7 +28,7 @@ EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
     "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval",
     "flp_filter_apply", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
-    "flp_solve", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
+    "flp_solve", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_last_error", "flp_version",
 ]
 
@@ -57,6 +57,14 @@ class FlpStatsC(ctypes.Structure):
                 ("polish_sweeps", ctypes.c_int32), ("t_pre", ctypes.c_double), ("t_mv", ctypes.c_double),
                 ("t_orth", ctypes.c_double), ("t_check", ctypes.c_double), ("t_rr", ctypes.c_double),
                 ("t_total", ctypes.c_double), ("filter_bytes", ctypes.c_double)]
+
+
+class FlpBatchStatsC(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_int32), ("block_steps", ctypes.c_int32), ("filter_launches", ctypes.c_int32),
+                ("graph_captures", ctypes.c_int32), ("graph_replays", ctypes.c_int32),
+                ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_filter", ctypes.c_double),
+                ("t_orth_check", ctypes.c_double), ("t_finish", ctypes.c_double),
+                ("filter_bytes", ctypes.c_double)]
 
 
 class FlpResultC(ctypes.Structure):
@@ -96,6 +104,7 @@ def load(path: str = LIB_PATH):
         "flp_estimate_bounds": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, U64, P, P, P]),
         "flp_solve": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), F64, F64, ctypes.POINTER(FlpOptsC),
                                      ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
+        "flp_solve_batch": (ctypes.c_int, [I32, P, P, P, P, I32, P, P, ctypes.POINTER(FlpBatchStatsC)]),
         "flp_result_free": (None, [ctypes.POINTER(FlpResultC)]),
         "flp_result_copy_evecs": (ctypes.c_int, [ctypes.POINTER(FlpResultC), P, P]),
         "flp_host_sym_eig": (ctypes.c_int, [I32, I32, P, P, P]),
@@ -299,6 +308,82 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
     finally:
         lib.flp_result_free(res)
     return out
+
+
+def _make_opts(block, degree, seed, prec, max_basis, check_every, eps, k0, bounds, stream, start=None):
+    o = default_opts()
+    o.block = block
+    o.degree = degree
+    o.seed = seed
+    o.prec = prec
+    o.max_basis = max_basis
+    if check_every:
+        o.check_every = check_every
+    if eps:
+        o.eps = eps
+    if k0:
+        o.k0 = k0
+    if bounds is not None:
+        o.lmin, o.lmax = bounds
+    o.stream = _stream_ptr(stream)
+    return o
+
+
+def _collect(res_ptr, n, device, want_vectors, stream):
+    import torch
+    lib = load()
+    r = res_ptr.contents
+    cnt = r.count
+    evals = np.array([r.evals[i] for i in range(cnt)], dtype=np.float64)
+    resid = np.array([r.resid[i] for i in range(cnt)], dtype=np.float64)
+    evecs = None
+    if want_vectors:
+        evecs_t = torch.empty((cnt, n), dtype=torch.float64, device=device)
+        if cnt:
+            _check(lib.flp_result_copy_evecs(res_ptr, evecs_t.data_ptr(), _stream_ptr(stream)))
+        evecs = evecs_t.t()
+    st = r.stats
+    stats = {f: getattr(st, f) for f, _ in FlpStatsC._fields_}
+    return dict(evals=evals, resid=resid, evecs=evecs, count=cnt, lmin=r.lmin, lmax=r.lmax,
+                degree=r.degree, converged=bool(r.converged), stats=stats)
+
+
+def flp_solve_batch(As, alphas, betas, block: int = 8, degree=0, seeds=None, prec: int = FLP_PREC_FP64,
+                    use_graph: bool = True, max_basis: int = 0, check_every: int = 0, eps: float = 0.0,
+                    k0: int = 0, want_vectors: bool = True, stream=None):
+    """Solve len(As) independent problems together (segmented filter
+    launches).  Returns (list of per-solve dicts like flp_solve, batch stats)."""
+    import torch
+    lib = load()
+    cnt = len(As)
+    if seeds is None:
+        seeds = list(range(cnt))
+    degrees = degree if isinstance(degree, (list, tuple)) else [degree] * cnt
+    opts = (FlpOptsC * cnt)()
+    for i in range(cnt):
+        opts[i] = _make_opts(block, degrees[i], seeds[i], prec, max_basis, check_every, eps, k0, None, stream)
+    arr = (ctypes.POINTER(FlpCsrC) * cnt)(*[ctypes.pointer(A.c) for A in As])
+    al = np.ascontiguousarray(alphas, dtype=np.float64)
+    be = np.ascontiguousarray(betas, dtype=np.float64)
+    res = (ctypes.POINTER(FlpResultC) * cnt)()
+    codes = np.zeros(cnt, dtype=np.int32)
+    bst = FlpBatchStatsC()
+    rc = lib.flp_solve_batch(cnt, ctypes.cast(arr, ctypes.c_void_p), _np_ptr(al), _np_ptr(be),
+                             ctypes.cast(opts, ctypes.c_void_p), 1 if use_graph else 0,
+                             ctypes.cast(res, ctypes.c_void_p), _np_ptr(codes), ctypes.byref(bst))
+    out = []
+    try:
+        _check(rc, allow=(FLP_E_NOCONV,))
+        for i in range(cnt):
+            _check(int(codes[i]), allow=(FLP_E_NOCONV,))
+            d = _collect(res[i], As[i].n, As[i].val.device, want_vectors, stream)
+            d["rc"] = int(codes[i])
+            out.append(d)
+    finally:
+        for i in range(cnt):
+            if res[i]:
+                lib.flp_result_free(res[i])
+    return out, {f: getattr(bst, f) for f, _ in FlpBatchStatsC._fields_}
 
 
 def flp_release_workspace():
