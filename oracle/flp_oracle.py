@@ -311,28 +311,50 @@ def assemble_T(D: list, S: list) -> np.ndarray:
     return T
 
 
-def lanczos_step(A, lmin, lmax, coeffs, Q: list, g: np.random.Generator):
+def lanczos_step(A, lmin, lmax, coeffs, Qk: np.ndarray, r: int, g: np.random.Generator):
     """One block step of FLP (Section 2.3, eq. lanczos; Section 3.2.2).
 
-    W = p(A) Q_j; full reorthogonalisation of W against every panel of Q
+    Qk (n x k) holds the basis so far; its last r columns are Q_j.
+    W = p(A) Q_j; full reorthogonalisation of W against every column of Qk
     (classical Gram-Schmidt, two passes); D_j = symmetric part of the
     Q_j^T p(A) Q_j block of the projection; W = Q_{j+1} S_j.
     Returns (D_j, S_j, Q_{j+1}, seconds in the filter, seconds in ORTH).
     """
-    r = Q[-1].shape[1]
     t1 = time.perf_counter()
-    W = filter_apply(A, lmin, lmax, coeffs, Q[-1])
+    W = filter_apply(A, lmin, lmax, coeffs, Qk[:, -r:])
     t_mv = time.perf_counter() - t1
     t1 = time.perf_counter()
-    Qb = np.concatenate(Q, axis=1)
-    H1 = Qb.T @ W
-    W = W - Qb @ H1
-    H2 = Qb.T @ W
-    W = W - Qb @ H2
+    H1 = Qk.T @ W
+    W = W - Qk @ H1
+    H2 = Qk.T @ W
+    W = W - Qk @ H2
     Hj = (H1 + H2)[-r:, :]
     Dj = 0.5 * (Hj + Hj.T)
-    Qn, Sj = _block_qr(W, Qb, g)
+    Qn, Sj = _block_qr(W, Qk, g)
     return Dj, Sj, Qn, t_mv, time.perf_counter() - t1
+
+
+class _Basis:
+    """Lanczos basis kept as one column-major array (columns contiguous) that
+    grows by doubling, so Qk = basis[:, :k] is a view."""
+
+    def __init__(self, n: int, first: np.ndarray):
+        self.n = n
+        self.buf = np.empty((n, max(256, first.shape[1])), order="F")
+        self.k = 0
+        self.append(first)
+
+    def append(self, block: np.ndarray):
+        r = block.shape[1]
+        if self.k + r > self.buf.shape[1]:
+            nb = np.empty((self.n, 2 * self.buf.shape[1] + r), order="F")
+            nb[:, :self.k] = self.buf[:, :self.k]
+            self.buf = nb
+        self.buf[:, self.k:self.k + r] = block
+        self.k += r
+
+    def view(self) -> np.ndarray:
+        return self.buf[:, :self.k]
 
 
 def flp_solve(A, alpha: float, beta: float, block: int = 1, degree: int = 0,
@@ -380,7 +402,7 @@ def flp_solve(A, alpha: float, beta: float, block: int = 1, degree: int = 0,
         max_basis = n
     max_steps = max(1, min(max_basis, n) // r)
 
-    Q = [orthonormal_start(np.asarray(start, dtype=np.float64).reshape(n, r))]
+    basis = _Basis(n, orthonormal_start(np.asarray(start, dtype=np.float64).reshape(n, r)))
     D, S = [], []
     t_mv = t_orth = 0.0
     prev_count = -1
@@ -388,7 +410,7 @@ def flp_solve(A, alpha: float, beta: float, block: int = 1, degree: int = 0,
     steps = 0
     sel = None
     while steps < max_steps:
-        Dj, Sj, Qn, dt_mv, dt_orth = lanczos_step(A, lmin, lmax, coeffs, Q, g)
+        Dj, Sj, Qn, dt_mv, dt_orth = lanczos_step(A, lmin, lmax, coeffs, basis.view(), r, g)
         D.append(Dj)
         S.append(Sj)
         t_mv += dt_mv
@@ -407,13 +429,13 @@ def flp_solve(A, alpha: float, beta: float, block: int = 1, degree: int = 0,
                 sel = (cand, Wt)
                 break
             prev_count = len(cand)
-        Q.append(Qn)
+        basis.append(Qn)
     times["mv"] = t_mv
     times["orth"] = t_orth
 
     t1 = time.perf_counter()
     cand, Wt = sel
-    Qb = np.concatenate(Q, axis=1)
+    Qb = basis.view()
     anorm = max(abs(lmin), abs(lmax))
     if len(cand) == 0:
         evals = np.zeros(0)

@@ -309,7 +309,7 @@ def lanczos_relation_errors(step_fn, steps=6, r=3):
     Q = [O.orthonormal_start(g.standard_normal((A.n, r)))]
     D, S = [], []
     for _ in range(steps):
-        Dj, Sj, Qn, _, _ = step_fn(A, lmin, lmax, coeffs, Q, g)
+        Dj, Sj, Qn, _, _ = step_fn(A, lmin, lmax, coeffs, np.concatenate(Q, axis=1), r, g)
         D.append(Dj)
         S.append(Sj)
         Q.append(Qn)
@@ -330,11 +330,12 @@ def test_lanczos_relation_and_orthogonality():
 
 
 def test_planted_single_pass_gram_schmidt_dropped_block_is_caught():
-    def wrong(A, lmin, lmax, coeffs, Q, g):
+    def wrong(A, lmin, lmax, coeffs, Qk, r, g):
         # reorthogonalise against the last panel only and skip the second pass
-        W = O.filter_apply(A, lmin, lmax, coeffs, Q[-1])
-        H = Q[-1].T @ W
-        W = W - Q[-1] @ H.T  # transposed coefficient block
+        Qj = Qk[:, -r:]
+        W = O.filter_apply(A, lmin, lmax, coeffs, Qj)
+        H = Qj.T @ W
+        W = W - Qj @ H.T  # transposed coefficient block
         Qn, S = np.linalg.qr(W)
         return 0.5 * (H + H.T), S, Qn, 0.0, 0.0
     orth, rel = lanczos_relation_errors(wrong)
