@@ -43,6 +43,7 @@ extern "C" {
 #define FLP_E_NOMEM      -4  /* device allocation failed or exceeds the limit */
 #define FLP_E_NOCONV     -5  /* basis limit reached before convergence (result still returned) */
 #define FLP_E_DEVICE     -6  /* HIP runtime error; message in flp_last_error() */
+#define FLP_E_PENDING    -7  /* serving: the request has not finished yet (flp_server_poll) */
 
 /* precision of the filter recurrence (Section 2.2 applies p(A) by Clenshaw) */
 #define FLP_PREC_FP64         0  /* FP64 matrix values, vectors and accumulation */
@@ -211,9 +212,9 @@ typedef struct flp_batch_stats {
     double t_total;           /* seconds: whole call */
     double t_setup;           /* seconds: bounds, filters, start blocks */
     double t_filter;          /* seconds: segmented filter launches (event-timed) */
-    double t_orth_check;      /* seconds: Gram-Schmidt, block QR, checks, finishing */
+    double t_orth_check;      /* seconds: Gram-Schmidt, block QR, convergence checks */
     double t_finish;          /* seconds: Rayleigh-Ritz and polish of finished solves */
-    double filter_bytes;      /* algorithmic bytes of all filter steps */
+    double filter_bytes;      /* algorithmic bytes of the segmented filter launches */
 } flp_batch_stats;
 
 /* Every eigenpair in [alpha[i], beta[i]] of each A[i], for count independent
@@ -236,6 +237,46 @@ typedef struct flp_batch_stats {
 int flp_solve_batch(int32_t count, const flp_csr *const *A, const double *alpha, const double *beta,
                     const flp_opts *opts, int32_t use_graph, flp_result **results, int32_t *codes,
                     flp_batch_stats *stats);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A server runs a worker thread that owns the device: requests submitted
+ * from any thread are admitted while engine slots and device memory allow
+ * (each request's footprint -- Lanczos basis of max_basis columns,
+ * recurrence vectors, FP32 copies -- is reserved against mem_budget), join
+ * the active set at the next block-step boundary, share its segmented
+ * filter launches, and leave it when they converge (continuous batching).
+ * While a server runs, other flp_* calls must not use the same device. */
+typedef struct flp_server flp_server;
+
+typedef struct flp_server_opts {
+    int32_t block;       /* block size of every request (default 8) */
+    int32_t prec;        /* precision of every request (default FLP_PREC_FP32_FILTER) */
+    int32_t max_active;  /* requests advanced together (default 64) */
+    int64_t max_basis;   /* default basis cap per request (default 1024 columns) */
+    double mem_budget;   /* device bytes for active requests; <= 0: 70% of free memory */
+    int32_t use_graph;   /* replay filter launches from HIP graphs (default 1) */
+} flp_server_opts;
+
+void flp_server_opts_default(flp_server_opts *o);
+/* Start a server on the current device.  Errors: FLP_E_ARG, FLP_E_DEVICE. */
+int flp_server_create(const flp_server_opts *opts, flp_server **out);
+/* Queue a request: every eigenpair of A in [alpha, beta].  A's device
+ * arrays must stay valid until the result has been retrieved.  opts may be
+ * NULL; its block and prec are replaced by the server's.  *ticket names the
+ * request.  Thread-safe.  Errors: FLP_E_ARG, or the server's device error. */
+int flp_server_submit(flp_server *sv, const flp_csr *A, double alpha, double beta, const flp_opts *opts,
+                      uint64_t *ticket);
+/* FLP_E_PENDING if the request is still queued or running; otherwise its
+ * return code (as flp_solve's) with *out set.  result->stats.t_total is the
+ * request's latency (submission to completion).  Thread-safe. */
+int flp_server_poll(flp_server *sv, uint64_t ticket, flp_result **out);
+/* As flp_server_poll, but blocks until the request has finished. */
+int flp_server_wait(flp_server *sv, uint64_t ticket, flp_result **out);
+/* Engine statistics so far (solves = requests submitted). */
+int flp_server_stats(flp_server *sv, flp_batch_stats *out);
+/* Finish every queued request, stop the worker, free unretrieved results. */
+int flp_server_destroy(flp_server *sv);
 
 /* Dense symmetric eigensolver used for the projected problems (Section
  * 3.2.2 solves T_k's eigenproblem on the CPU with a banded symmetric

@@ -175,12 +175,12 @@ int flp_solve_batch(int32_t count, const flp_csr *const *A, const double *alpha,
 int flp_host_sym_eig(int32_t N, int32_t bw, const double *M, double *evals, double *evecs) {
     if (N < 1 || !M || !evals || bw < 0) return fail(FLP_E_ARG, "bad arguments");
     try {
-        std::vector<int> rows;
+        std::vector<int> cols;
         if (evecs) {
-            rows.resize(N);
-            for (int i = 0; i < N; ++i) rows[i] = i;
+            cols.resize(N);
+            for (int i = 0; i < N; ++i) cols[i] = i;
         }
-        int rc = sym_eig(N, bw, M, evals, evecs ? rows.data() : nullptr, evecs ? N : 0, evecs);
+        int rc = sym_eig(N, bw, M, evals, nullptr, 0, nullptr, evecs ? cols.data() : nullptr, evecs ? N : 0, evecs);
         if (rc != 0) return fail(FLP_E_ARG, "eigensolver did not converge");
     } catch (const std::bad_alloc &) {
         return fail(FLP_E_NOMEM, "host allocation failed");

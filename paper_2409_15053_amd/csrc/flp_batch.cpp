@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "flp_host.h"
@@ -23,43 +25,6 @@
 namespace flp {
 
 namespace {
-
-struct Graph {
-    hipGraph_t g = nullptr;
-    hipGraphExec_t x = nullptr;
-    void reset() {
-        if (x) (void)hipGraphExecDestroy(x);
-        if (g) (void)hipGraphDestroy(g);
-        x = nullptr;
-        g = nullptr;
-    }
-    ~Graph() { reset(); }
-};
-
-struct StreamGuard {
-    hipStream_t s = nullptr;
-    ~StreamGuard() {
-        if (s) (void)hipStreamDestroy(s);
-    }
-};
-
-struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-    ~EventPair() {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-    }
-};
-
-// Segment tables of one block step for the active solves: table t lists
-// the solves taking part in launch t, in order, with tile offsets.
-struct Tables {
-    int M = 0, cap = 0, r = 0;
-    bool fp32 = false;
-    std::vector<SegEntry> host;    // M x cap
-    std::vector<int> nseg, tiles;  // per launch
-    Buf dev;
-};
 
 int build_tables(const std::vector<Solve *> &act, Tables &T, hipStream_t s) {
     T.M = 0;
@@ -115,126 +80,198 @@ int launch_tables(const Tables &T, hipStream_t s) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ engine
+
+int Engine::init(int r_, int prec_, bool graph_) {
+    r = r_;
+    prec = prec_;
+    use_graph = graph_;
+    T.r = r;
+    T.fp32 = prec == FLP_PREC_FP32_FILTER;
+    CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    CK(hipEventCreate(&ev_a));
+    CK(hipEventCreate(&ev_b));
+    return FLP_OK;
+}
+
+Engine::~Engine() {
+    graph_reset();
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    if (s) (void)hipStreamDestroy(s);
+}
+
+void Engine::graph_reset() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+}
+
+void Engine::add(Job *j) {
+    active.push_back(j);
+    tables_valid = false;
+}
+
+int Engine::step(std::vector<Job *> &finished) {
+    if (active.empty()) return FLP_OK;
+    std::vector<Solve *> act;
+    for (Job *j : active) act.push_back(j->S.get());
+    if (!tables_valid) {
+        graph_reset();
+        CKR(build_tables(act, T, s));
+        if (use_graph) {
+            CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            const int rc = launch_tables(T, s);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &g);
+            if (rc != FLP_OK) return rc;
+            CK(e);
+            graph = g;
+            CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            ++stats.graph_captures;
+        }
+        tables_valid = true;
+    }
+    // filter phase: one segmented launch per Clenshaw step
+    CK(hipEventRecord(ev_a, s));
+    if (use_graph) {
+        CK(hipGraphLaunch(gexec, s));
+        ++stats.graph_replays;
+    } else {
+        CKR(launch_tables(T, s));
+    }
+    CK(hipEventRecord(ev_b, s));
+    CK(hipEventSynchronize(ev_b));
+    float ms = 0;
+    CK(hipEventElapsedTime(&ms, ev_a, ev_b));
+    stats.t_filter += ms * 1e-3;
+    stats.filter_launches += T.M;
+    ++stats.block_steps;
+    for (Solve *S : act) stats.filter_bytes += filter_step_bytes(S->n, S->A->nnz, S->r, S->o.prec) * S->filt->m;
+    // block step of every active solve, phase by phase with one shared
+    // synchronisation between phases
+    const double t1 = now();
+    auto run_phase = [&](int (*phase)(Solve &)) {
+        for (Job *j : active) {
+            if (j->code != FLP_OK) continue;
+            j->code = phase(*j->S);
+            if (j->code != FLP_OK) j->msg = last_error_cstr();
+        }
+    };
+    for (Solve *S : act) S->st.t_mv += ms * 1e-3;
+    run_phase(step_orth_launch);
+    CK(hipStreamSynchronize(s));
+    run_phase(step_qr1);
+    CK(hipStreamSynchronize(s));
+    run_phase(step_qr2);
+    // convergence checks are host eigensolves: run them in parallel
+    {
+        std::vector<Job *> todo;
+        for (Job *j : active)
+            if (j->code == FLP_OK) todo.push_back(j);
+        const int nt = (int)std::min<size_t>(todo.size(), 16);
+        std::vector<std::thread> th;
+        for (int w = 0; w < nt; ++w)
+            th.emplace_back([&, w]() {
+                for (size_t q = w; q < todo.size(); q += nt) {
+                    todo[q]->code = step_check_host(*todo[q]->S);
+                    if (todo[q]->code != FLP_OK) todo[q]->msg = last_error_cstr();
+                }
+            });
+        for (auto &t : th) t.join();
+        for (Job *j : todo)
+            if (j->code == FLP_OK) {
+                j->code = step_check(*j->S);
+                if (j->code != FLP_OK) j->msg = last_error_cstr();
+            }
+    }
+    double t_fin = 0.0;
+    std::vector<Job *> keep;
+    for (Job *j : active) {
+        if (j->code == FLP_OK && !j->S->done) {
+            keep.push_back(j);
+            continue;
+        }
+        if (j->code == FLP_OK) {
+            const double tf = now();
+            j->code = solve_finish(*j->S, &j->res);
+            if (j->code != FLP_OK && j->code != FLP_E_NOCONV) j->msg = last_error_cstr();
+            t_fin += now() - tf;
+        }
+        j->t_done = now();
+        j->B.reset();  // release this solve's device memory
+        finished.push_back(j);
+    }
+    if (keep.size() != active.size()) tables_valid = false;
+    active.swap(keep);
+    stats.t_finish += t_fin;
+    stats.t_orth_check += now() - t1 - t_fin;
+    return FLP_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
 int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, const double *beta,
                      const flp_opts *opts, int use_graph, flp_result **results, int *codes, flp_batch_stats *bs) {
     const double t0 = now();
-    flp_batch_stats stats{};
-    stats.solves = count;
-    hipStream_t user = nullptr;
+    hipStream_t user = opts ? (hipStream_t)opts[0].stream : nullptr;
     flp_opts o0;
     flp_opts_default(&o0);
-    if (opts) user = (hipStream_t)opts[0].stream;
     for (int i = 0; i < count; ++i) {
         results[i] = nullptr;
         codes[i] = FLP_OK;
     }
-    CK(hipStreamSynchronize(user));
-    StreamGuard sg;
-    CK(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
-    hipStream_t s = sg.s;
-
-    std::vector<std::unique_ptr<Solve>> solves(count);
-    std::vector<std::unique_ptr<SolveBufs>> bufs(count);
-    int r = -1, prec = -1;
+    const int r = opts ? opts[0].block : o0.block;
+    const int prec = opts ? opts[0].prec : o0.prec;
     for (int i = 0; i < count; ++i) {
-        auto S = std::make_unique<Solve>();
-        S->A = A[i];
-        S->alpha = alpha[i];
-        S->beta = beta[i];
-        S->o = opts ? opts[i] : o0;
-        S->o.stream = nullptr;
-        S->s = s;
-        if (r < 0) {
-            r = S->o.block;
-            prec = S->o.prec;
-        }
-        if (S->o.block != r || S->o.prec != prec)
+        const flp_opts &o = opts ? opts[i] : o0;
+        if (o.block != r || o.prec != prec)
             return fail(FLP_E_ARG, "all solves of a batch need the same block size and precision");
-        int rc = check_csr(A[i]);
-        if (rc == FLP_OK) {
-            bufs[i] = std::make_unique<SolveBufs>();
-            S->B = bufs[i].get();
-            rc = solve_setup(*S);
-        }
-        codes[i] = rc;
-        solves[i] = std::move(S);
     }
-    stats.t_setup = now() - t0;
-
-    Tables T;
-    T.r = r;
-    T.fp32 = prec == FLP_PREC_FP32_FILTER;
-    Graph graph;
-    bool tables_valid = false;
-    EventPair ev;
-    CK(hipEventCreate(&ev.a));
-    CK(hipEventCreate(&ev.b));
-    for (;;) {
-        std::vector<Solve *> act;
-        for (int i = 0; i < count; ++i)
-            if (codes[i] == FLP_OK && !solves[i]->done) act.push_back(solves[i].get());
-        if (act.empty()) break;
-        if (!tables_valid) {
-            graph.reset();
-            CKR(build_tables(act, T, s));
-            if (use_graph) {
-                CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                int rc = launch_tables(T, s);
-                hipGraph_t g = nullptr;
-                hipError_t e = hipStreamEndCapture(s, &g);
-                if (rc != FLP_OK) return rc;
-                CK(e);
-                graph.g = g;
-                CK(hipGraphInstantiate(&graph.x, graph.g, nullptr, nullptr, 0));
-                ++stats.graph_captures;
-            }
-            tables_valid = true;
+    CK(hipStreamSynchronize(user));
+    Engine E;
+    CKR(E.init(r, prec, use_graph != 0));
+    E.stats.solves = count;
+    std::vector<std::unique_ptr<Job>> jobs(count);
+    std::vector<Job *> finished;
+    for (int i = 0; i < count; ++i) {
+        auto j = std::make_unique<Job>();
+        j->id = (uint64_t)i;
+        j->t_submit = t0;
+        j->S = std::make_unique<Solve>();
+        Solve &S = *j->S;
+        S.A = A[i];
+        S.alpha = alpha[i];
+        S.beta = beta[i];
+        S.o = opts ? opts[i] : o0;
+        S.o.stream = nullptr;
+        S.s = E.s;
+        j->code = check_csr(A[i]);
+        if (j->code == FLP_OK) {
+            j->B = std::make_unique<SolveBufs>();
+            S.B = j->B.get();
+            j->code = solve_setup(S);
         }
-        // filter phase: one segmented launch per Clenshaw step
-        CK(hipEventRecord(ev.a, s));
-        if (use_graph) {
-            CK(hipGraphLaunch(graph.x, s));
-            ++stats.graph_replays;
-        } else {
-            CKR(launch_tables(T, s));
-        }
-        CK(hipEventRecord(ev.b, s));
-        CK(hipEventSynchronize(ev.b));
-        float ms = 0;
-        CK(hipEventElapsedTime(&ms, ev.a, ev.b));
-        stats.t_filter += ms * 1e-3;
-        stats.filter_launches += T.M;
-        ++stats.block_steps;
-        // per-solve block step; finished solves leave the batch
-        const double t1 = now();
-        for (Solve *S : act) {
-            S->st.t_mv += ms * 1e-3;
-            const int i = (int)(std::find_if(solves.begin(), solves.end(),
-                                             [&](const std::unique_ptr<Solve> &p) { return p.get() == S; }) -
-                                solves.begin());
-            int rc = solve_after_filter(*S);
-            if (rc != FLP_OK) {
-                codes[i] = rc;
-                tables_valid = false;
-                continue;
-            }
-            if (S->done) {
-                tables_valid = false;
-                const double tf = now();
-                codes[i] = solve_finish(*S, &results[i]);
-                stats.t_finish += now() - tf;
-                if (results[i]) results[i]->stats.t_total = now() - t0;  // completion time inside the batch
-                stats.filter_bytes += S->st.filter_bytes;
-                bufs[i].reset();  // release this solve's device memory
-            }
-        }
-        stats.t_orth_check += now() - t1;
+        if (j->code != FLP_OK) j->msg = last_error_cstr();
+        if (j->code == FLP_OK)
+            E.add(j.get());
+        else
+            j->B.reset();
+        jobs[i] = std::move(j);
     }
-    CK(hipStreamSynchronize(s));
-    stats.t_total = now() - t0;
-    if (bs) *bs = stats;
+    E.stats.t_setup = now() - t0;
+    while (!E.active.empty()) CKR(E.step(finished));
+    CK(hipStreamSynchronize(E.s));
+    for (int i = 0; i < count; ++i) {
+        results[i] = jobs[i]->res;
+        codes[i] = jobs[i]->code;
+        if (results[i]) results[i]->stats.t_total = jobs[i]->t_done - t0;  // completion time inside the batch
+    }
+    E.stats.t_total = now() - t0;
+    if (bs) *bs = E.stats;
     for (int i = 0; i < count; ++i)
-        if (codes[i] != FLP_OK && codes[i] != FLP_E_NOCONV) return codes[i];
+        if (codes[i] != FLP_OK && codes[i] != FLP_E_NOCONV) return fail(codes[i], jobs[i]->msg);
     return FLP_OK;
 }
 

@@ -6,14 +6,18 @@
 // rotations:
 //   1. band -> tridiagonal: the outermost diagonal is annihilated one entry
 //      at a time and the bulge each rotation creates is chased down the band
-//      (Rutishauser/Schwarz band reduction), bandwidth b -> b-1 -> ... -> 1;
+//      (Rutishauser/Schwarz band reduction), bandwidth b -> b-1 -> ... -> 1,
+//      on compact band storage (each column keeps its b+2 lower entries);
 //   2. implicit symmetric QR with the Wilkinson shift on the tridiagonal
 //      (Golub & Van Loan, "Matrix Computations", Sec. 8.3).
-// Every rotation is logged.  Eigenvector rows are obtained by replaying the
-// log on selected rows of the identity: the convergence check only needs
-// the last r rows of the eigenvector matrix (for the Ritz residual bounds),
-// so it replays on r rows; the final Ritz vectors replay on all rows, in
-// parallel over row tiles.
+// Every rotation is logged, so eigenvectors are built only where needed:
+//   * selected ROWS of the eigenvector matrix Z = J_1 J_2 ... J_t by
+//     replaying the log forwards on rows of the identity (the convergence
+//     check needs the last r rows, for the Ritz residual bounds);
+//   * selected COLUMNS of Z by replaying the log backwards on columns of the
+//     identity, Z e_j = J_1 (J_2 (... (J_t e_j))) (the Ritz vectors need
+//     only the candidates' columns).
+// Both replays cost O(#rotations x #selected) and run in parallel threads.
 #include "flp_internal.h"
 
 #include <algorithm>
@@ -28,46 +32,81 @@ namespace flp {
 
 namespace {
 
-struct Rot {
-    int32_t p;  // plane (p, p+1)
-    double c, s;
+using Rot = EigRot;
+
+// Symmetric band matrix, lower half of half-width w, column-compact:
+// entry (i, j), i >= j, i - j <= w, at B[j * (w + 1) + (i - j)].
+struct Band {
+    int N, w;
+    std::vector<double> B;
+    double get(int i, int j) const {
+        if (i < j) std::swap(i, j);
+        const int d = i - j;
+        return d > w ? 0.0 : B[(size_t)j * (w + 1) + d];
+    }
+    void set(int i, int j, double v) {
+        if (i < j) std::swap(i, j);
+        const int d = i - j;
+        if (d <= w) B[(size_t)j * (w + 1) + d] = v;
+    }
 };
 
-// M' = J^T M J on rows/columns (p, p+1) restricted to [lo, hi], where
-// J[:,p] = c e_p + s e_q and J[:,q] = -s e_p + c e_q.
-inline void rotate_dense(double *M, int N, int p, double c, double s, int lo, int hi) {
-    const int q = p + 1;
-    double *rp = M + (size_t)p * N, *rq = M + (size_t)q * N;
-    for (int x = lo; x <= hi; ++x) {
-        double a = rp[x], b = rq[x];
-        rp[x] = c * a + s * b;
-        rq[x] = -s * a + c * b;
+// M' = J^T M J on the plane (p, q = p + 1), J[:,p] = c e_p + s e_q,
+// J[:,q] = -s e_p + c e_q, touching only entries within the band.  Entries
+// one step outside the band are structurally zero before and after (the
+// bulge always sits within w = b + 1 of the diagonal), so they are neither
+// read nor written.
+inline void rotate_band(Band &M, int p, double c, double s) {
+    const int q = p + 1, w = M.w, N = M.N, W1 = w + 1;
+    double *B = M.B.data();
+    // rows x < p: column x holds (p, x) at distance d = p - x and (q, x) at d + 1
+    for (int x = std::max(0, p - w); x < p; ++x) {
+        double *col = B + (size_t)x * W1;
+        const int d = p - x;
+        const double a = col[d];
+        if (d + 1 <= w) {
+            const double b = col[d + 1];
+            col[d] = c * a + s * b;
+            col[d + 1] = -s * a + c * b;
+        } else {
+            col[d] = c * a;
+        }
     }
-    for (int x = lo; x <= hi; ++x) {
-        double *row = M + (size_t)x * N;
-        double a = row[p], b = row[q];
-        row[p] = c * a + s * b;
-        row[q] = -s * a + c * b;
+    // rows x > q: column p holds (x, p) at x - p, column q holds (x, q) at x - q
+    double *cp = B + (size_t)p * W1, *cq = B + (size_t)q * W1;
+    const int xhi = std::min(N - 1, q + w);
+    for (int x = q + 1; x <= xhi; ++x) {
+        const int dp = x - p, dq = x - q;
+        const double b = cq[dq];
+        if (dp <= w) {
+            const double a = cp[dp];
+            cp[dp] = c * a + s * b;
+            cq[dq] = -s * a + c * b;
+        } else {
+            cq[dq] = c * b;
+        }
     }
+    const double app = cp[0], apq = cp[1], aqq = cq[0];
+    cp[0] = c * c * app + 2.0 * c * s * apq + s * s * aqq;
+    cq[0] = s * s * app - 2.0 * c * s * apq + c * c * aqq;
+    cp[1] = c * s * (aqq - app) + (c * c - s * s) * apq;
 }
 
-// Reduce the symmetric matrix M (N x N row-major, semi-bandwidth b) to
-// tridiagonal form in place, logging the rotations.
-void band_to_tridiag(double *M, int N, int b, std::vector<Rot> &log) {
+// Reduce a symmetric band matrix of semi-bandwidth b (stored with w = b + 1
+// so the bulge fits) to tridiagonal form in place, logging the rotations.
+void band_to_tridiag(Band &M, int b, std::vector<Rot> &log) {
+    const int N = M.N;
     for (int bw = b; bw >= 2; --bw) {
         for (int j = 0; j + bw < N; ++j) {
             int k = j, i = j + bw;
             while (i < N) {
-                double x = M[(size_t)(i - 1) * N + k];
-                double y = M[(size_t)i * N + k];
+                const double x = M.get(i - 1, k);
+                const double y = M.get(i, k);
                 if (y == 0.0) break;
-                double r = std::hypot(x, y);
-                double c = x / r, s = y / r;
-                int lo = std::max(0, i - 1 - bw - 1);
-                int hi = std::min(N - 1, i + bw + 1);
-                rotate_dense(M, N, i - 1, c, s, lo, hi);
-                M[(size_t)i * N + k] = 0.0;
-                M[(size_t)k * N + i] = 0.0;
+                const double r = std::hypot(x, y);
+                const double c = x / r, s = y / r;
+                rotate_band(M, i - 1, c, s);
+                M.set(i, k, 0.0);
                 log.push_back({i - 1, c, s});
                 // the rotation fills (i-1+bw+1, i-1); chase it with plane (i-1+bw, i+bw)
                 k = i - 1;
@@ -131,22 +170,43 @@ bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot>
     return true;
 }
 
-// Rows R of (I J_1 J_2 ... J_t): start from the identity rows and replay the
-// log.  Z is nrows x N row-major; rows[i] is the identity row for Z row i.
-void replay(const std::vector<Rot> &log, int N, const int *rows, int nrows, double *Z) {
+int nthreads_for(long work, int units) {
+    int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    nt = std::min(nt, units);
+    if (work < 4000000L) nt = 1;
+    return std::max(nt, 1);
+}
+
+template <typename F>
+void parallel_for(int units, int nt, F f) {
+    if (nt <= 1) {
+        f(0, units);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int w = 0; w < nt; ++w) {
+        const int u0 = (int)((long)units * w / nt), u1 = (int)((long)units * (w + 1) / nt);
+        th.emplace_back(f, u0, u1);
+    }
+    for (auto &t : th) t.join();
+}
+
+// Rows R of (I J_1 J_2 ... J_t): identity rows, log replayed forwards.
+// Z is nrows x N row-major; rows[i] is the identity row for Z row i.
+void replay_rows(const std::vector<Rot> &log, int N, const int *rows, int nrows, double *Z) {
     constexpr int TILE = 8;
     const int ntiles = (nrows + TILE - 1) / TILE;
     auto work = [&](int t0, int t1) {
         std::vector<double> tile((size_t)N * TILE);
         for (int t = t0; t < t1; ++t) {
-            int r0 = t * TILE, nr = std::min(TILE, nrows - r0);
+            const int r0 = t * TILE, nr = std::min(TILE, nrows - r0);
             std::fill(tile.begin(), tile.end(), 0.0);
             for (int i = 0; i < nr; ++i) tile[(size_t)rows[r0 + i] * TILE + i] = 1.0;
             for (const Rot &g : log) {
                 double *a = &tile[(size_t)g.p * TILE];
                 double *b = a + TILE;
                 for (int i = 0; i < TILE; ++i) {
-                    double u = a[i], v = b[i];
+                    const double u = a[i], v = b[i];
                     a[i] = g.c * u + g.s * v;
                     b[i] = -g.s * u + g.c * v;
                 }
@@ -155,45 +215,94 @@ void replay(const std::vector<Rot> &log, int N, const int *rows, int nrows, doub
                 for (int j = 0; j < N; ++j) Z[(size_t)(r0 + i) * N + j] = tile[(size_t)j * TILE + i];
         }
     };
-    int nthreads = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
-    nthreads = std::min(nthreads, ntiles);
-    if (nthreads <= 1 || (long)log.size() * nrows < 2000000L) {
-        work(0, ntiles);
-        return;
-    }
-    std::vector<std::thread> th;
-    for (int w = 0; w < nthreads; ++w) {
-        int t0 = (int)((long)ntiles * w / nthreads), t1 = (int)((long)ntiles * (w + 1) / nthreads);
-        th.emplace_back(work, t0, t1);
-    }
-    for (auto &t : th) t.join();
+    parallel_for(ntiles, nthreads_for((long)log.size() * nrows, ntiles), work);
+}
+
+// Columns of J_1 J_2 ... J_t selected by ids (unsorted eigen-indices):
+// identity columns, log replayed backwards.  Z is N x ncols row-major.
+void replay_cols(const std::vector<Rot> &log, int N, const int *ids, int ncols, double *Z) {
+    constexpr int TILE = 8;
+    const int ntiles = (ncols + TILE - 1) / TILE;
+    auto work = [&](int t0, int t1) {
+        std::vector<double> tile((size_t)N * TILE);
+        for (int t = t0; t < t1; ++t) {
+            const int c0 = t * TILE, nc = std::min(TILE, ncols - c0);
+            std::fill(tile.begin(), tile.end(), 0.0);
+            for (int j = 0; j < nc; ++j) tile[(size_t)ids[c0 + j] * TILE + j] = 1.0;
+            for (auto it = log.rbegin(); it != log.rend(); ++it) {
+                const Rot &g = *it;
+                double *a = &tile[(size_t)g.p * TILE];
+                double *b = a + TILE;
+                for (int j = 0; j < TILE; ++j) {
+                    const double u = a[j], v = b[j];
+                    a[j] = g.c * u - g.s * v;
+                    b[j] = g.s * u + g.c * v;
+                }
+            }
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < nc; ++j) Z[(size_t)i * ncols + c0 + j] = tile[(size_t)i * TILE + j];
+        }
+    };
+    parallel_for(ntiles, nthreads_for((long)log.size() * ncols, ntiles), work);
 }
 
 }  // namespace
 
-int sym_eig(int N, int bw, const double *M, double *evals, const int *rows, int nrows,
-            double *Z) {
+int sym_eig_keep(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Zrows,
+                 EigLog *keep) {
     if (N <= 0) return -1;
     bw = std::max(0, std::min(bw, N - 1));
-    std::vector<double> W(M, M + (size_t)N * N);
-    std::vector<Rot> log;
+    Band Bd;
+    Bd.N = N;
+    Bd.w = bw + 1;
+    Bd.B.assign((size_t)N * (Bd.w + 1), 0.0);
+    for (int j = 0; j < N; ++j)
+        for (int d = 0; d <= bw && j + d < N; ++d) {
+            const int i = j + d;
+            Bd.B[(size_t)j * (Bd.w + 1) + d] = 0.5 * (M[(size_t)i * N + j] + M[(size_t)j * N + i]);
+        }
+    std::vector<Rot> local;
+    std::vector<Rot> &log = keep ? keep->rot : local;
+    log.clear();
     log.reserve((size_t)N * 4);
-    if (bw >= 2) band_to_tridiag(W.data(), N, bw, log);
+    if (bw >= 2) band_to_tridiag(Bd, bw, log);
     std::vector<double> d(N), e(std::max(N - 1, 0));
-    for (int i = 0; i < N; ++i) d[i] = W[(size_t)i * N + i];
-    for (int i = 0; i + 1 < N; ++i) e[i] = 0.5 * (W[(size_t)i * N + i + 1] + W[(size_t)(i + 1) * N + i]);
+    for (int i = 0; i < N; ++i) d[i] = Bd.get(i, i);
+    for (int i = 0; i + 1 < N; ++i) e[i] = Bd.get(i + 1, i);
     if (!tridiag_qr(d, e, log)) return -2;
     std::vector<int> perm(N);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] < d[b]; });
     for (int i = 0; i < N; ++i) evals[i] = d[perm[i]];
-    if (nrows > 0 && Z) {
+    if (nrows > 0 && Zrows) {
         std::vector<double> tmp((size_t)nrows * N);
-        replay(log, N, rows, nrows, tmp.data());
+        replay_rows(log, N, rows, nrows, tmp.data());
         for (int i = 0; i < nrows; ++i)
-            for (int j = 0; j < N; ++j) Z[(size_t)i * N + j] = tmp[(size_t)i * N + perm[j]];
+            for (int j = 0; j < N; ++j) Zrows[(size_t)i * N + j] = tmp[(size_t)i * N + perm[j]];
+    }
+    if (keep) {
+        keep->N = N;
+        keep->perm = perm;
     }
     return 0;
+}
+
+void eig_log_cols(const EigLog &L, const int *cols, int ncols, double *Zcols) {
+    std::vector<int> ids(ncols);
+    for (int j = 0; j < ncols; ++j) ids[j] = L.perm[cols[j]];
+    replay_cols(L.rot, L.N, ids.data(), ncols, Zcols);
+}
+
+int sym_eig(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Zrows,
+            const int *cols, int ncols, double *Zcols) {
+    if (ncols > 0 && Zcols) {
+        EigLog L;
+        const int rc = sym_eig_keep(N, bw, M, evals, rows, nrows, Zrows, &L);
+        if (rc != 0) return rc;
+        eig_log_cols(L, cols, ncols, Zcols);
+        return 0;
+    }
+    return sym_eig_keep(N, bw, M, evals, rows, nrows, Zrows, nullptr);
 }
 
 }  // namespace flp

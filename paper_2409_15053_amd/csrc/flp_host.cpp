@@ -555,9 +555,9 @@ int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, d
         for (int j = 0; j < c; ++j) Gs[(size_t)i * c + j] = 0.5 * (G[(size_t)i * c + j] + G[(size_t)j * c + i]);
     lam.assign(c, 0.0);
     std::vector<double> ZG((size_t)c * c);
-    std::vector<int> rows(c);
-    for (int i = 0; i < c; ++i) rows[i] = i;
-    if (sym_eig(c, c - 1, Gs.data(), lam.data(), rows.data(), c, ZG.data()) != 0)
+    std::vector<int> cols(c);
+    for (int i = 0; i < c; ++i) cols[i] = i;
+    if (sym_eig(c, c - 1, Gs.data(), lam.data(), nullptr, 0, nullptr, cols.data(), c, ZG.data()) != 0)
         return fail(FLP_E_DEVICE, "eigensolver for the Rayleigh-Ritz matrix did not converge");
     std::vector<double> Zp((size_t)c * ldc, 0.0);
     for (int i = 0; i < c; ++i)

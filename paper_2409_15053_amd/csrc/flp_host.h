@@ -171,15 +171,93 @@ struct Solve {
     flp_stats st{};
     double t_start = 0;
     int code = FLP_OK;  // first error
+    // block-step staging: pinned host h1, h2, G, R^{-1} (r x r each) and the
+    // device Gram / R^{-1} blocks behind the projection coefficients
+    double *pin = nullptr;
+    double *gdev = nullptr, *rdev = nullptr;
+    std::vector<double> R1;
+    bool slow = false;      // this step's block needed the rank repair path
+    int checked_step = -1;  // block step whose convergence check has run
+    EigLog eig;             // rotation log of the last check's T_k
+    double t_step0 = 0.0;   // host time the current block step started
+    Solve() = default;
+    Solve(const Solve &) = delete;
+    Solve &operator=(const Solve &) = delete;
+    ~Solve();
 };
 
 // bounds, filter, buffers, start block (PREPROC and set-up)
 int solve_setup(Solve &S);
-// after the filter has produced W: CGS2, D_j, block QR, convergence check,
-// next filter input; sets S.done
+// One block step after the filter has produced W, in phases separated by a
+// stream synchronisation (the batched driver runs each phase for all solves
+// before one shared synchronisation):
+//   step_orth_launch: CGS2 against the basis, Gram matrix of W (async);
+//   step_qr1:         D_j; first Cholesky factor; apply it; second Gram (async);
+//   step_qr2:         second Cholesky factor; apply it; S_j;
+//   step_check:       convergence check at the cadence (host only), else the
+//                     new block joins the basis and becomes the next input.
+int step_orth_launch(Solve &S);
+int step_qr1(Solve &S);
+int step_qr2(Solve &S);
+int step_check(Solve &S);
+// the host part of step_check (thread-safe per solve): runs the check when
+// this block step is at the cadence and has not been checked yet
+int step_check_host(Solve &S);
+// all four phases with synchronisations (single solve)
 int solve_after_filter(Solve &S);
 // Ritz vectors, Rayleigh-Ritz with A, FP32 polish, result
 int solve_finish(Solve &S, flp_result **out);
+
+// ---------------------------------------------------------------- engine
+// Segment tables of one block step for the active solves: table t lists
+// the solves taking part in filter launch t, in order, with tile offsets.
+struct Tables {
+    int M = 0, cap = 0, r = 0;
+    bool fp32 = false;
+    std::vector<SegEntry> host;    // M x cap
+    std::vector<int> nseg, tiles;  // per launch
+    Buf dev;
+};
+
+// One request of the batched / serving engine.
+struct Job {
+    uint64_t id = 0;
+    std::unique_ptr<Solve> S;
+    std::unique_ptr<SolveBufs> B;
+    flp_result *res = nullptr;
+    int code = FLP_OK;
+    double t_submit = 0, t_done = 0;
+    size_t footprint = 0;   // device bytes reserved at admission
+    flp_csr A{};            // the caller's matrix descriptor
+    std::string msg;        // error message of a failed request
+};
+
+// Advances a set of active solves in lockstep: per block step, one
+// segmented filter launch per Clenshaw step (replayed from a HIP graph while
+// the set is unchanged), then each solve's Gram-Schmidt, block QR and
+// convergence check, then Rayleigh-Ritz for the solves that finished.
+struct Engine {
+    hipStream_t s = nullptr;
+    int r = 0, prec = 0;
+    bool use_graph = true;
+    std::vector<Job *> active;
+    Tables T;
+    bool tables_valid = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    flp_batch_stats stats{};
+    Engine() = default;
+    Engine(const Engine &) = delete;
+    Engine &operator=(const Engine &) = delete;
+    ~Engine();
+    int init(int r, int prec, bool use_graph);
+    void add(Job *j);
+    // one block step of every active solve; jobs that completed (result or
+    // error) leave the active set and are appended to finished
+    int step(std::vector<Job *> &finished);
+    void graph_reset();
+};
 
 // drivers
 int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out);

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/flp.h"
 
@@ -23,10 +24,36 @@ void set_error(const std::string &msg);
 
 // ---------------------------------------------------------------- host eigensolver
 // Eigenvalues (ascending) of the symmetric N x N row-major M with
-// semi-bandwidth bw; rows[0..nrows) of the eigenvector matrix (columns =
-// eigenvectors, same order as evals) are written to Z (nrows x N row-major).
+// semi-bandwidth bw.  Of the eigenvector matrix (columns = eigenvectors, in
+// the order of evals): rows[0..nrows) are written to Zrows (nrows x N
+// row-major) and columns cols[0..ncols) to Zcols (N x ncols row-major).
 // Returns 0 on success.
-int sym_eig(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Z);
+int sym_eig(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Zrows,
+            const int *cols = nullptr, int ncols = 0, double *Zcols = nullptr);
+
+// The rotation log of one sym_eig call, kept so eigenvector columns can be
+// produced later without repeating the reduction.
+struct EigRot {
+    int32_t p;  // plane (p, p+1)
+    double c, s;
+};
+struct EigLog {
+    int N = 0;
+    std::vector<EigRot> rot;
+    std::vector<int> perm;  // sorted position -> unsorted index
+    void clear() {
+        N = 0;
+        rot.clear();
+        rot.shrink_to_fit();
+        perm.clear();
+    }
+};
+// sym_eig that also returns its rotation log in *keep
+int sym_eig_keep(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Zrows,
+                 EigLog *keep);
+// columns cols[0..ncols) (sorted order) of the eigenvector matrix of a kept
+// log, written to Zcols (N x ncols row-major)
+void eig_log_cols(const EigLog &L, const int *cols, int ncols, double *Zcols);
 
 // ---------------------------------------------------------------- tall matrices
 // A tall n x K matrix stored plainly (row-major, leading dimension ld) or

@@ -79,10 +79,14 @@ int solve_setup(Solve &S) {
     CK(ensure(B.Q, sizeof(double) * (size_t)n * (size_t)(S.npanels << kPanelLog2)));
     CK(ensure(B.W, sizeof(double) * (size_t)n * r));
     CK(ensure(B.Vin, sizeof(double) * (size_t)n * r));
-    CK(ensure(B.hdev, sizeof(double) * ((size_t)2 * (S.npanels << kPanelLog2) * r + 4 * r * r + 64)));
+    const size_t hcols = (size_t)(S.npanels << kPanelLog2);
+    CK(ensure(B.hdev, sizeof(double) * (2 * hcols * r + 4 * (size_t)r * r + 64)));
     S.W = (double *)B.W.p;
     S.Vin = (double *)B.Vin.p;
     S.hdev = (double *)B.hdev.p;
+    S.gdev = S.hdev + 2 * hcols * r;
+    S.rdev = S.gdev + (size_t)r * r;
+    if (!S.pin) CK(hipHostMalloc((void **)&S.pin, sizeof(double) * 4 * (size_t)r * r, hipHostMallocDefault));
     S.Q = panel_mat((double *)B.Q.p, n, kPanelLog2);
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
     for (auto &u : B.U) CK(ensure(u, es * (size_t)n * r));
@@ -108,72 +112,149 @@ int solve_setup(Solve &S) {
     return FLP_OK;
 }
 
-int solve_after_filter(Solve &S) {
+Solve::~Solve() {
+    if (pin) (void)hipHostFree(pin);
+}
+
+int step_orth_launch(Solve &S) {
     const int n = S.n, r = S.r;
     hipStream_t s = S.s;
-    const double t0 = now();
+    S.t_step0 = now();
     const int k = (S.steps + 1) * r;  // basis columns so far
     S.st.filter_bytes += filter_step_bytes(n, S.A->nnz, r, S.o.prec) * S.filt->m;
     S.st.mv += (int64_t)r * S.filt->m;
     // full reorthogonalisation (Section 3.2.2): two passes of classical Gram-Schmidt
     CKR(cgs2(S.Q, k, n, S.W, r, S.hdev, s));
-    std::vector<double> h1((size_t)r * r), h2((size_t)r * r);
-    CK(hipMemcpyAsync(h1.data(), S.hdev + (size_t)(k - r) * r, sizeof(double) * r * r, hipMemcpyDeviceToHost, s));
-    CK(hipMemcpyAsync(h2.data(), S.hdev + (size_t)k * r + (size_t)(k - r) * r, sizeof(double) * r * r,
+    const size_t rr = (size_t)r * r;
+    CK(hipMemcpyAsync(S.pin, S.hdev + (size_t)(k - r) * r, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(S.pin + rr, S.hdev + (size_t)k * r + (size_t)(k - r) * r, sizeof(double) * rr,
                       hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
+    // Gram matrix of the projected block (first Cholesky QR pass)
+    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s));
+    CK(hipMemcpyAsync(S.pin + 2 * rr, S.gdev, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
+    return FLP_OK;
+}
+
+int step_qr1(Solve &S) {
+    const int n = S.n, r = S.r;
+    hipStream_t s = S.s;
+    const size_t rr = (size_t)r * r;
+    const double *h1 = S.pin, *h2 = S.pin + rr, *G = S.pin + 2 * rr;
     for (int i = 0; i < r; ++i)
         for (int j = 0; j < r; ++j) {
             const double a = h1[i * r + j] + h2[i * r + j], b = h1[j * r + i] + h2[j * r + i];
             S.D_all.push_back(0.5 * (a + b));
         }
-    // W = Q_{j+1} S_j (eq. lanczos)
-    CKR(block_qr_impl(S.W, n, r, &S.Q, k, S.Sj, S.o.seed, 1000 + S.steps, s, nullptr));
-    S.S_all.insert(S.S_all.end(), S.Sj.begin(), S.Sj.end());
-    S.st.t_orth += now() - t0;
-    ++S.steps;
-    const bool last = S.steps == S.max_steps || (int64_t)(S.steps + 1) * r > n;
-    if (S.steps % S.check_every == 0 || last) {
-        // convergence check on the Ritz values of T_k (Section 3.2.2)
-        const double tc = now();
-        const int K = k;
-        std::vector<double> T;
-        assemble_T(S, S.steps, T);
-        std::vector<double> theta(K);
-        std::vector<int> rows(r);
-        for (int i = 0; i < r; ++i) rows[i] = K - r + i;
-        std::vector<double> Zl((size_t)r * K);
-        if (sym_eig(K, r, T.data(), theta.data(), rows.data(), r, Zl.data()) != 0)
-            return fail(FLP_E_DEVICE, "eigensolver for T_k did not converge");
-        // rho_i = || S_k E_k^T w_i ||
-        double big = 1e-300;
-        for (double t : theta) big = std::max(big, std::fabs(t));
-        S.cand.clear();
-        bool ok = true;
-        for (int i = 0; i < K; ++i) {
-            if (theta[i] < S.tau) continue;
-            S.cand.push_back(i);
-            double rho2 = 0.0;
-            for (int a = 0; a < r; ++a) {
-                double t = 0.0;
-                for (int b = 0; b < r; ++b) t += S.Sj[a * r + b] * Zl[(size_t)b * K + i];
-                rho2 += t * t;
-            }
-            if (std::sqrt(rho2) > S.tol_p * big) ok = false;
-        }
-        S.st.t_check += now() - tc;
-        if ((ok && (int)S.cand.size() == S.prev_count) || last) {
-            S.converged = ok && (int)S.cand.size() == S.prev_count;
-            S.kfinal = K;
-            S.done = true;
-            return FLP_OK;
-        }
-        S.prev_count = (int)S.cand.size();
+    // W = Q_{j+1} S_j (eq. lanczos) by Cholesky QR twice
+    double fro2 = 0.0;
+    for (int i = 0; i < r; ++i) fro2 += std::max(G[i * r + i], 0.0);
+    const double thr = 1e-7 * std::sqrt(fro2);
+    std::vector<int> bad;
+    cholesky_flag(r, G, std::max(thr * thr, 1e-300), S.R1, bad);
+    S.slow = false;
+    for (int i = 0; i < r; ++i) S.slow = S.slow || bad[i];
+    if (S.slow) {
+        // numerically dependent columns: the synchronous repair path
+        const int k = (S.steps + 1) * r;
+        return block_qr_impl(S.W, n, r, &S.Q, k, S.Sj, S.o.seed, 1000 + S.steps, s, nullptr);
     }
-    // the new block joins the basis and is the next filter input
-    CK(launch_copy_block(n, r, 1.0, S.W, r, S.Q, k, nullptr, 0, s));
-    CK(launch_copy_block(n, r, 1.0, S.W, r, plain_mat(S.Vin, r), 0, S.V32, r, s));
+    std::vector<double> Ri;
+    upper_inverse(r, S.R1, Ri);
+    std::memcpy(S.pin + 3 * rr, Ri.data(), sizeof(double) * rr);
+    CK(hipMemcpyAsync(S.rdev, S.pin + 3 * rr, sizeof(double) * rr, hipMemcpyHostToDevice, s));
+    CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(S.W, r), S.rdev, r, 0.0, S.W, r, s));
+    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s));
+    CK(hipMemcpyAsync(S.pin + 2 * rr, S.gdev, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
     return FLP_OK;
+}
+
+int step_qr2(Solve &S) {
+    const int n = S.n, r = S.r;
+    hipStream_t s = S.s;
+    const size_t rr = (size_t)r * r;
+    if (!S.slow) {
+        std::vector<double> R2, Ri;
+        std::vector<int> bad;
+        cholesky_flag(r, S.pin + 2 * rr, 1e-300, R2, bad);
+        for (int i = 0; i < r; ++i)
+            if (bad[i]) return fail(FLP_E_DEVICE, "block QR: second Cholesky pass broke down");
+        upper_inverse(r, R2, Ri);
+        std::memcpy(S.pin + 3 * rr, Ri.data(), sizeof(double) * rr);
+        CK(hipMemcpyAsync(S.rdev, S.pin + 3 * rr, sizeof(double) * rr, hipMemcpyHostToDevice, s));
+        CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(S.W, r), S.rdev, r, 0.0, S.W, r, s));
+        matmul_upper(r, R2, S.R1, S.Sj);
+    }
+    S.S_all.insert(S.S_all.end(), S.Sj.begin(), S.Sj.end());
+    ++S.steps;
+    S.st.t_orth += now() - S.t_step0;
+    return FLP_OK;
+}
+
+bool at_check(const Solve &S) {
+    return S.steps % S.check_every == 0 || S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n;
+}
+
+int step_check_host(Solve &S) {
+    if (!at_check(S) || S.checked_step == S.steps) return FLP_OK;
+    S.checked_step = S.steps;
+    const int r = S.r;
+    const bool last = S.steps == S.max_steps || (int64_t)(S.steps + 1) * r > S.n;
+    // convergence check on the Ritz values of T_k (Section 3.2.2)
+    const double tc = now();
+    const int K = S.steps * r;
+    std::vector<double> T;
+    assemble_T(S, S.steps, T);
+    std::vector<double> theta(K);
+    std::vector<int> rows(r);
+    for (int i = 0; i < r; ++i) rows[i] = K - r + i;
+    std::vector<double> Zl((size_t)r * K);
+    if (sym_eig_keep(K, r, T.data(), theta.data(), rows.data(), r, Zl.data(), &S.eig) != 0)
+        return fail(FLP_E_DEVICE, "eigensolver for T_k did not converge");
+    // rho_i = || S_k E_k^T w_i ||
+    double big = 1e-300;
+    for (double t : theta) big = std::max(big, std::fabs(t));
+    S.cand.clear();
+    bool ok = true;
+    for (int i = 0; i < K; ++i) {
+        if (theta[i] < S.tau) continue;
+        S.cand.push_back(i);
+        double rho2 = 0.0;
+        for (int a = 0; a < r; ++a) {
+            double t = 0.0;
+            for (int b = 0; b < r; ++b) t += S.Sj[a * r + b] * Zl[(size_t)b * K + i];
+            rho2 += t * t;
+        }
+        if (std::sqrt(rho2) > S.tol_p * big) ok = false;
+    }
+    S.st.t_check += now() - tc;
+    if ((ok && (int)S.cand.size() == S.prev_count) || last) {
+        S.converged = ok && (int)S.cand.size() == S.prev_count;
+        S.kfinal = K;
+        S.done = true;
+        return FLP_OK;
+    }
+    S.prev_count = (int)S.cand.size();
+    S.eig.clear();
+    return FLP_OK;
+}
+
+int step_check(Solve &S) {
+    CKR(step_check_host(S));
+    if (S.done) return FLP_OK;
+    // the new block joins the basis and is the next filter input
+    const int n = S.n, r = S.r, k = S.steps * r;
+    CK(launch_copy_block(n, r, 1.0, S.W, r, S.Q, k, nullptr, 0, S.s));
+    CK(launch_copy_block(n, r, 1.0, S.W, r, plain_mat(S.Vin, r), 0, S.V32, r, S.s));
+    return FLP_OK;
+}
+
+int solve_after_filter(Solve &S) {
+    CKR(step_orth_launch(S));
+    CK(hipStreamSynchronize(S.s));
+    CKR(step_qr1(S));
+    CK(hipStreamSynchronize(S.s));
+    CKR(step_qr2(S));
+    return step_check(S);
 }
 
 int solve_finish(Solve &S, flp_result **out) {
@@ -198,20 +279,18 @@ int solve_finish(Solve &S, flp_result **out) {
     const int c = (int)S.cand.size();
     if (c > 0) {
         const int K = S.kfinal;
-        // eigenvectors of T_k for the candidates (eq. proj)
-        std::vector<double> T;
-        assemble_T(S, S.steps, T);
-        std::vector<int> rows(K);
-        for (int i = 0; i < K; ++i) rows[i] = i;
-        std::vector<double> Z((size_t)K * K), th(K);
+        // eigenvectors of T_k for the candidates (eq. proj), from the rotation
+        // log the last convergence check kept
+        std::vector<double> Zc((size_t)K * c);
         const double tc = now();
-        if (sym_eig(K, r, T.data(), th.data(), rows.data(), K, Z.data()) != 0)
-            return fail(FLP_E_DEVICE, "eigensolver for T_k did not converge");
+        if (S.eig.N != K) return fail(FLP_E_DEVICE, "internal: no eigen-decomposition of the final T_k");
+        eig_log_cols(S.eig, S.cand.data(), c, Zc.data());
+        S.eig.clear();
         S.st.t_check += now() - tc;
         const int ldc = (c + 1) & ~1;
         std::vector<double> Wc((size_t)K * ldc, 0.0);
         for (int i = 0; i < K; ++i)
-            for (int j = 0; j < c; ++j) Wc[(size_t)i * ldc + j] = Z[(size_t)i * K + S.cand[j]];
+            for (int j = 0; j < c; ++j) Wc[(size_t)i * ldc + j] = Zc[(size_t)i * c + j];
         CK(ensure(w.Y, sizeof(double) * (size_t)n * ldc));
         CK(ensure(w.AY, sizeof(double) * (size_t)n * ldc));
         CK(ensure(w.X, sizeof(double) * (size_t)n * ldc));

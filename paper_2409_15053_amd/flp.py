@@ -21,6 +21,7 @@ FLP_E_NOTSYM = -3
 FLP_E_NOMEM = -4
 FLP_E_NOCONV = -5
 FLP_E_DEVICE = -6
+FLP_E_PENDING = -7
 FLP_PREC_FP64 = 0
 FLP_PREC_FP32_FILTER = 1
 
@@ -30,6 +31,8 @@ EXPORTS = [
     "flp_filter_apply", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_last_error", "flp_version",
+    "flp_server_opts_default", "flp_server_create", "flp_server_submit", "flp_server_poll",
+    "flp_server_wait", "flp_server_stats", "flp_server_destroy",
 ]
 
 
@@ -65,6 +68,11 @@ class FlpBatchStatsC(ctypes.Structure):
                 ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_filter", ctypes.c_double),
                 ("t_orth_check", ctypes.c_double), ("t_finish", ctypes.c_double),
                 ("filter_bytes", ctypes.c_double)]
+
+
+class FlpServerOptsC(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("max_basis", ctypes.c_int64), ("mem_budget", ctypes.c_double), ("use_graph", ctypes.c_int32)]
 
 
 class FlpResultC(ctypes.Structure):
@@ -109,6 +117,14 @@ def load(path: str = LIB_PATH):
         "flp_result_copy_evecs": (ctypes.c_int, [ctypes.POINTER(FlpResultC), P, P]),
         "flp_host_sym_eig": (ctypes.c_int, [I32, I32, P, P, P]),
         "flp_release_workspace": (None, []),
+        "flp_server_opts_default": (None, [ctypes.POINTER(FlpServerOptsC)]),
+        "flp_server_create": (ctypes.c_int, [ctypes.POINTER(FlpServerOptsC), PP]),
+        "flp_server_submit": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), F64, F64, ctypes.POINTER(FlpOptsC),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+        "flp_server_poll": (ctypes.c_int, [P, U64, ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
+        "flp_server_wait": (ctypes.c_int, [P, U64, ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
+        "flp_server_stats": (ctypes.c_int, [P, ctypes.POINTER(FlpBatchStatsC)]),
+        "flp_server_destroy": (ctypes.c_int, [P]),
         "flp_last_error": (ctypes.c_char_p, []),
         "flp_version": (ctypes.c_char_p, []),
     }
@@ -384,6 +400,72 @@ def flp_solve_batch(As, alphas, betas, block: int = 8, degree=0, seeds=None, pre
             if res[i]:
                 lib.flp_result_free(res[i])
     return out, {f: getattr(bst, f) for f, _ in FlpBatchStatsC._fields_}
+
+
+class Server:
+    """Continuous-batching server (flp_server_*): submit requests from any
+    thread, collect results with poll/wait."""
+
+    def __init__(self, block: int = 8, prec: int = FLP_PREC_FP32_FILTER, max_active: int = 64,
+                 max_basis: int = 1024, mem_budget: float = 0.0, use_graph: bool = True):
+        lib = load()
+        o = FlpServerOptsC()
+        lib.flp_server_opts_default(ctypes.byref(o))
+        o.block, o.prec, o.max_active, o.max_basis = block, prec, max_active, max_basis
+        o.mem_budget, o.use_graph = mem_budget, 1 if use_graph else 0
+        h = ctypes.c_void_p()
+        _check(lib.flp_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, A: DeviceCsr, alpha: float, beta: float, seed: int = 0, degree: int = 0,
+               max_basis: int = 0, check_every: int = 0) -> int:
+        o = _make_opts(1, degree, seed, 0, max_basis, check_every, 0.0, 0, None, None)
+        o.stream = None
+        t = ctypes.c_uint64()
+        _check(load().flp_server_submit(self.h, ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(t)))
+        self._keep[t.value] = A  # the matrix must outlive the request
+        return t.value
+
+    def _finish(self, ticket, rc, res, want_vectors):
+        try:
+            _check(rc, allow=(FLP_E_NOCONV,))
+            A = self._keep.pop(ticket)
+            d = _collect(res, A.n, A.val.device, want_vectors, None)
+            d["rc"] = rc
+            return d
+        finally:
+            if res:
+                load().flp_result_free(res)
+
+    def poll(self, ticket: int, want_vectors: bool = False):
+        res = ctypes.POINTER(FlpResultC)()
+        rc = load().flp_server_poll(self.h, ticket, ctypes.byref(res))
+        if rc == FLP_E_PENDING:
+            return None
+        return self._finish(ticket, rc, res, want_vectors)
+
+    def wait(self, ticket: int, want_vectors: bool = False):
+        res = ctypes.POINTER(FlpResultC)()
+        rc = load().flp_server_wait(self.h, ticket, ctypes.byref(res))
+        return self._finish(ticket, rc, res, want_vectors)
+
+    def stats(self) -> dict:
+        st = FlpBatchStatsC()
+        _check(load().flp_server_stats(self.h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in FlpBatchStatsC._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            rc = load().flp_server_destroy(self.h)
+            self.h = None
+            _check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def flp_release_workspace():

@@ -222,3 +222,81 @@ def workload_c3(N: int = 120) -> dict:
     V = gaussian_wells(N, BASE_SEED + 3)
     return dict(name=f"lap3d13_{N}_wells16", A=laplacian_3d_13pt(N, V), block=16,
                 seed=BASE_SEED + 3)
+
+
+def lap1d_eigenvalues(N: int) -> np.ndarray:
+    """Eigenvalues 4 sin^2(j pi / (2(N+1))) of the 1D Dirichlet second difference
+    (used only to place synthetic intervals, not as a reference)."""
+    j = np.arange(1, N + 1)
+    return 4.0 * np.sin(j * np.pi / (2 * (N + 1))) ** 2
+
+
+def batch_family(count: int = 64, seed: int = BASE_SEED + 4, gmin: int = 20, gmax: int = 60,
+                 tmin: int = 10, tmax: int = 60) -> list:
+    """Independent problems for the batched form: 3D 7-point Laplacian on a
+    g^3 grid plus a U[0,1) potential, g = round(exp(U[ln gmin, ln gmax]))
+    (n log-uniform), and a low-end interval [0, beta] meant to hold about t
+    eigenvalues, t ~ U{tmin..tmax}: beta is the t-th smallest eigenvalue of
+    the potential-free Laplacian plus the potential's mean 0.5, plus a
+    seeded offset of at most one local level spacing."""
+    g = rng(seed)
+    out = []
+    for i in range(count):
+        N = int(round(float(np.exp(g.uniform(np.log(gmin), np.log(gmax))))))
+        t = int(g.integers(tmin, tmax + 1))
+        pseed = int(g.integers(0, 2 ** 31))
+        jitter = float(g.uniform(0.0, 1.0))
+        mu = lap1d_eigenvalues(N)
+        k = min(N, 12)
+        lap = np.sort((mu[:k, None, None] + mu[None, :k, None] + mu[None, None, :k]).ravel())
+        base = lap[t - 1] + 0.5
+        spacing = lap[t] - lap[t - 1] if lap[t] > lap[t - 1] else 1e-3
+        out.append(dict(name=f"lap3d7_{N}_U01_s{pseed}", N=N, potential_seed=pseed, alpha=0.0,
+                        beta=float(base + jitter * spacing), target=t))
+    return out
+
+
+def build_batch_matrix(spec: dict) -> Csr:
+    return laplacian_3d(spec["N"], uniform_potential(spec["N"], spec["potential_seed"]))
+
+
+def serve_family(count: int = 512, seed: int = BASE_SEED + 5, gmin: int = 30, gmax: int = 100,
+                 dmin: float = 4.5, dmax: float = 5.5, wells: int = 16) -> list:
+    """Requests for the serving form: 4th-order 13-point Laplacian on a g^3
+    grid plus 16 Gaussian wells (as the 120^3 Hamiltonian), g =
+    round(exp(U[ln gmin, ln gmax])), and a low-end interval [g_lo - 1, g_lo +
+    d], d ~ U[dmin, dmax], where g_lo is the matrix's Gershgorin lower bound
+    (a property of the input, computed when the matrix is built); it holds
+    tens to a few hundred bound states."""
+    g = rng(seed)
+    out = []
+    for i in range(count):
+        N = int(round(float(np.exp(g.uniform(np.log(gmin), np.log(gmax))))))
+        pseed = int(g.integers(0, 2 ** 31))
+        d = float(g.uniform(dmin, dmax))
+        out.append(dict(name=f"lap3d13_{N}_wells{wells}_s{pseed}", N=N, potential_seed=pseed, wells=wells,
+                        delta=d))
+    return out
+
+
+def gershgorin_lower(A: Csr) -> float:
+    """min_i (a_ii - sum_{j != i} |a_ij|) of a CSR matrix."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    on = rows == A.colind
+    diag = np.zeros(A.n)
+    rad = np.zeros(A.n)
+    np.add.at(diag, rows[on], A.val[on])
+    np.add.at(rad, rows[~on], np.abs(A.val[~on]))
+    return float(np.min(diag - rad))
+
+
+def build_serve_problem(spec: dict):
+    """(A, alpha, beta) of one serving request."""
+    A = laplacian_3d_13pt(spec["N"], gaussian_wells(spec["N"], spec["potential_seed"], spec["wells"]))
+    lo = gershgorin_lower(A)
+    return A, lo - 1.0, lo + spec["delta"]
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    return np.cumsum(rng(seed).exponential(1.0 / rate, size=count))

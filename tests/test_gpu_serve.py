@@ -1,0 +1,85 @@
+"""Serving form (continuous batching): requests submitted while others run
+are admitted into the active set, and each result is the same alone and
+in the mix (same count; eigenvalues within 1e-10 relative; residuals
+<= 1e-9 against the dense definition)."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import flp_oracle as O
+from paper_2409_15053_amd import flp
+from paper_2409_15053_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible MI355X"
+    flp.load()
+    return t
+
+
+def family(grids, seed0, counts):
+    out = []
+    for i, (N, cnt) in enumerate(zip(grids, counts)):
+        A = I.laplacian_3d(N, I.uniform_potential(N, seed0 + i))
+        lam = np.linalg.eigvalsh(A.to_dense())
+        out.append((A, lam[0] - 0.5, 0.5 * (lam[cnt - 1] + lam[cnt])))
+    return out
+
+
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP32_FILTER, flp.FLP_PREC_FP64])
+def test_server_staggered_arrivals_match_alone(torch, prec):
+    cases = family([8, 9, 10, 11, 12, 13, 9, 10], 4000, [10, 12, 14, 16, 18, 20, 22, 24])
+    dAs = [flp.DeviceCsr.from_host(A, with_fp32=True) for A, *_ in cases]
+    sv = flp.Server(block=8, prec=prec, max_active=4)
+    tickets = []
+    try:
+        # first wave, then more requests while the first ones run
+        for i in range(4):
+            tickets.append(sv.submit(dAs[i], cases[i][1], cases[i][2], seed=100 + i))
+        time.sleep(0.05)
+        for i in range(4, 8):
+            tickets.append(sv.submit(dAs[i], cases[i][1], cases[i][2], seed=100 + i))
+        got = [sv.wait(t) for t in tickets]
+        st = sv.stats()
+    finally:
+        sv.close()
+    assert st["solves"] == 8 and st["block_steps"] > 0
+    assert st["graph_captures"] >= 2  # the active set changed while running
+    for i, (A, alpha, beta) in enumerate(cases):
+        want, _ = O.dense_eigs_in_interval(A, alpha, beta)
+        r = got[i]
+        assert r["count"] == len(want)
+        assert np.max(np.abs(np.sort(r["evals"]) - want) / np.abs(want)) <= 1e-10
+        assert np.max(r["resid"]) <= 1e-9
+        assert r["stats"]["t_total"] > 0  # latency recorded
+        alone = flp.flp_solve(dAs[i], alpha, beta, block=8, seed=100 + i, prec=prec, max_basis=1024)
+        assert alone["count"] == r["count"]
+        assert np.max(np.abs(alone["evals"] - r["evals"]) / np.abs(r["evals"])) <= 1e-10
+
+
+def test_server_poll_pending_and_errors(torch):
+    A = I.laplacian_3d(10, I.uniform_potential(10, 1))
+    lam = np.linalg.eigvalsh(A.to_dense())
+    dA = flp.DeviceCsr.from_host(A)
+    sv = flp.Server(block=4, prec=flp.FLP_PREC_FP64, max_active=2)
+    try:
+        t = sv.submit(dA, lam[0] - 0.1, 0.5 * (lam[11] + lam[12]), seed=1)
+        r = None
+        for _ in range(2000):
+            r = sv.poll(t)
+            if r is not None:
+                break
+            time.sleep(0.005)
+        assert r is not None and r["count"] == 12
+        bad = sv.submit(dA, 50.0, 60.0, seed=2)  # outside the spectrum
+        with pytest.raises(flp.FlpError) as ei:
+            sv.wait(bad)
+        assert ei.value.code == flp.FLP_E_INTERVAL
+        assert "does not meet" in flp.load().flp_last_error().decode()
+    finally:
+        sv.close()

@@ -219,3 +219,23 @@ def test_fp32_and_fp64_agree(torch):
     assert r64["count"] == r32["count"] == 50
     assert np.max(np.abs(r64["evals"] - r32["evals"]) / np.abs(r64["evals"])) <= 1e-10
     assert max(np.max(r64["resid"]), np.max(r32["resid"])) <= 1e-9
+
+
+def test_full_size_lap3d7_100_against_oracle_reference(torch):
+    """The benchmark's solve at full size (n = 1e6, block 8, degree 100):
+    the 104 eigenvalues the oracle found in [0, beta] (tests/golden, made by
+    the oracle only), exact count, 1e-10 relative, residuals <= 1e-9."""
+    import json
+    import os
+    from .conftest import GOLDEN
+    with open(os.path.join(GOLDEN, "c2_lap3d7_100_U01.json")) as f:
+        ref = json.load(f)
+    w = I.workload_c2(100)
+    dA = flp.DeviceCsr.from_host(w["A"])
+    for prec in (flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER):
+        res = flp.flp_solve(dA, ref["alpha"], ref["beta"], block=8, degree=100, seed=7, prec=prec,
+                            want_vectors=False)
+        want = np.asarray(ref["evals"])
+        assert res["count"] == ref["count"] == len(want)
+        assert np.max(np.abs(np.sort(res["evals"]) - want) / want) <= 1e-10
+        assert np.max(res["resid"]) <= 1e-9
