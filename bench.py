@@ -18,8 +18,10 @@ the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 counter summary of the dominant kernel on the benchmark workload
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cheb_step_lap3d7_100_fp64_traffic.md")
+KERNEL_SOURCES = ["paper_2409_15053_amd/csrc/flp_kernels.hip", "paper_2409_15053_amd/csrc/flp_internal.h"]
 METRIC = "filter SpMM GB/s (% HBM roofline); eigenpairs/s; p50/p99 solve latency"
 
 WORKLOADS = {
@@ -55,9 +60,40 @@ def parse():
     ap.add_argument("--requests", type=int, default=32, help="serving form: number of requests")
     ap.add_argument("--gmin", type=int, default=30, help="serving form: smallest grid edge")
     ap.add_argument("--gmax", type=int, default=60, help="serving form: largest grid edge")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration for HBM traffic)")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving form: Poisson arrival rate as a fraction of the closed-loop throughput")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, prec, tuned):
+    """HBM bytes per launch of the filter kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a
+    plain copy of known size gives), or None when the kernel sources or the
+    launch configuration differ from the ones the counters were taken with."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None, "no counter summary"
+    kv = dict(re.findall(r"^- (\w+): (.+?)\s*$", text, re.M))
+    if kv.get("workload") != f"{workload} {prec}":
+        return None, "counters were taken on another workload"
+    if kv.get("kernel_sources_sha256") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    cfg = f"gw={tuned['group_width']} lpr={tuned['lanes_per_row']} vec={tuned['cols_per_lane']}"
+    if kv.get("launch_config") != cfg:
+        return None, f"launch configuration {cfg} differs from the profiled {kv.get('launch_config')}"
+    return float(kv["traffic_bytes_per_launch"]), TRAFFIC_PROFILE[len(ROOT) + 1:]
 
 
 def group_width(A, r, prec):
@@ -263,6 +299,11 @@ def bench_serve(args):
             while tickets[i] is None:
                 time.sleep(0.001)
             res.append(sv.wait(tickets[i]))
+            r = res[-1]
+            print(f"#   request {i + 1}/{len(dAs)} done at {time.perf_counter() - t0:.1f} s: g={fam[i]['N']} "
+                  f"d={fam[i]['delta']:.2f} count={r['count']} iters={r['stats']['iters']} "
+                  f"polish={r['stats']['polish_sweeps']} max_resid="
+                  f"{float(np.max(r['resid'])) if r['count'] else 0.0:.1e}", file=sys.stderr, flush=True)
         th.join()
         makespan = time.perf_counter() - t0
         st = sv.stats()
@@ -283,6 +324,12 @@ def bench_serve(args):
     def passing(res):
         return sum(r["count"] for r in res if r["count"] and float(np.max(r["resid"])) <= 1e-9)
 
+    for i, (f, r) in enumerate(zip(fam, opened)):
+        st = r["stats"]
+        print(f"# req {i:3d} g={f['N']:3d} d={f['delta']:.3f} count={r['count']:4d} deg={r['degree']} conv={int(r['converged'])} "
+              f"max_resid={float(np.max(r['resid'])) if r['count'] else 0.0:.2e} iters={st['iters']} "
+              f"basis={st['basis_cols']} polish={st['polish_sweeps']} t_check={st['t_check']:.3f} "
+              f"t_rr={st['t_rr']:.3f} latency={st['t_total']:.2f}s", file=sys.stderr, flush=True)
     lat = np.array([r["stats"]["t_total"] * 1e3 for r in opened])
     lat_c = np.array([r["stats"]["t_total"] * 1e3 for r in closed])
     pairs_o = passing(opened)
@@ -329,6 +376,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 1 << 30,
+                          "bytes_written_per_launch": 1 << 30, "launches": 5}), flush=True)
+        return
     flp.load()
     if WORKLOADS[args.workload]["kind"] == "batch":
         return bench_batch(args)
@@ -376,6 +433,7 @@ def main():
                 good = good and rel <= 1e-10
         ok_pairs += res["count"] if good else 0
 
+    tuned = flp.flp_tune_filter(dA, w["block"], prec)  # the cached choice the solves used
     st = [r["stats"] for r in results]
     fbytes = sum(s["filter_bytes"] for s in st)
     t_mv = sum(s["t_mv"] for s in st)
@@ -408,7 +466,8 @@ def main():
                      "pairs_passing": ok_pairs},
         "filter": {"GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS, "bytes_per_step": per_launch_bytes,
                    "avg_step_us": t_mv / launches * 1e6 if launches else None, "steps": launches,
-                   "kernel_launches_per_step": w["block"] // group_width(A, w["block"], args.prec),
+                   "kernel_launches_per_step": w["block"] // tuned["group_width"],
+                   "tuned": tuned,
                    "what": "one step = one Clenshaw step of the 8-column block (matrix read once in the "
                            "algorithmic bytes); it runs as kernel_launches_per_step launches of the "
                            "column-grouped kernel"},
@@ -417,8 +476,15 @@ def main():
         "iters": [s["iters"] for s in st],
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "cheb_step_kernel (CSR SpMM + fused Clenshaw update)"},
+                     "kernel": "cheb_step_kernel (CSR SpMM + fused Clenshaw update)",
+                     "algorithmic_bytes_per_launch": per_launch_bytes * tuned["group_width"] / w["block"],
+                     "avg_launch_us": (t_mv / launches * 1e6 * tuned["group_width"] / w["block"]
+                                       if launches else None)},
     }
+    traffic, src = measured_traffic(args.workload, args.prec, tuned)
+    out["roofline"]["traffic"] = traffic
+    out["roofline"]["traffic_unit"] = "bytes per launch"
+    out["roofline"]["traffic_source"] = src
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, alpha, beta, args.degree, results[-1], args.cpu_budget_s)

@@ -22,9 +22,12 @@
  *   symmetric matrix on the GPU without exploiting symmetry).
  * - `stream` is a hipStream_t passed as void*; NULL means the default
  *   stream.
- * - The library keeps a per-device workspace that grows on demand and is
- *   released by flp_release_workspace() or at process exit.  Calls on one
- *   device must not overlap in time (they share that workspace).
+ * - The library keeps a workspace per calling thread and device that grows
+ *   on demand and is released by flp_release_workspace() (the calling
+ *   thread's) or when the thread ends.  Calls from one thread share its
+ *   workspace, so asynchronous calls from one thread on different streams
+ *   must not overlap in time; calls from different threads do not share
+ *   it.
  */
 #ifndef FLP_H
 #define FLP_H
@@ -154,9 +157,45 @@ int flp_filter_eval(const flp_filter *p, const double *z, double *out, int32_t c
  *   prec: FLP_PREC_FP64, or FLP_PREC_FP32_FILTER (V is rounded to FP32,
  *         the recurrence runs in FP32, W is written in FP64).
  * Stream-ordered and asynchronous (no host synchronisation unless the
- * workspace must grow).  Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
+ * workspace must grow, or the launch configuration for this precision, r
+ * and matrix size is being tuned; see flp_tune_filter).
+ * Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
 int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, double *W,
                      int32_t r, int32_t prec, void *stream);
+
+/* Launch configuration of the filter's sparse-matrix step (the Clenshaw
+ * step of Section 2.2 as a CSR SpMM over r columns). */
+typedef struct flp_tune_info {
+    int32_t group_width;   /* columns per filter launch (r / group_width launches per step) */
+    int32_t lanes_per_row; /* lanes sharing one matrix row */
+    int32_t cols_per_lane; /* consecutive block columns owned by one lane */
+    int32_t rows_per_wave; /* matrix rows per 64-lane wavefront (64 / lanes_per_row) */
+    int32_t candidates;    /* configurations timed (0: default or forced, not timed) */
+    double us_per_step;    /* measured microseconds of one step over all r columns (0 if not timed) */
+} flp_tune_info;
+
+/* Autotuner.  The first time a (device, precision, r, n, nnz) combination
+ * is filtered, every supported launch shape (rows per wavefront, columns per
+ * lane) and column-group width is timed on the caller's matrix over a short
+ * ring of filter steps and the fastest is kept for the process; the batched
+ * and serving engines tune the shape of their segmented launches on the
+ * largest active matrix.  All configurations compute every output element
+ * with the same operations in the same order, so results are bit-identical.
+ * flp_tune_filter runs (or looks up) that tuning for r columns of A and
+ * reports the choice.  A: as for flp_solve (val32 may be NULL).  Synchronises
+ * the stream.  Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
+int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp_tune_info *out);
+
+/* on = 1: tune on first use (the default); on = 0: fixed default
+ * configuration (16-byte pieces per lane, column groups sized for the
+ * 256 MB Infinity Cache). */
+void flp_set_autotune(int32_t on);
+
+/* Forces one configuration for every later filter launch (testing and
+ * measurement); lanes_per_row = 0 and group_width = 0 restore tuning.  A
+ * shape with no kernel for a given width falls back to the default shape;
+ * a group width that does not divide r is ignored. */
+void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width);
 
 /* Y = A X (plain CSR SpMM, Section 3.2.1).  X, Y: DEVICE n x r row-major
  * with leading dimensions ldx, ldy >= r; 1 <= r <= 32; FP64.  Async. */
@@ -288,7 +327,7 @@ int flp_server_destroy(flp_server *sv);
  * Returns FLP_OK or FLP_E_ARG. */
 int flp_host_sym_eig(int32_t N, int32_t bw, const double *M, double *evals, double *evecs);
 
-/* Free the calling device's workspace. */
+/* Free the calling thread's workspace on the current device. */
 void flp_release_workspace(void);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -87,6 +87,46 @@ int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, dou
     return filter_apply_impl(p, A, V, r, W, r, r, prec, (hipStream_t)stream);
 }
 
+int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp_tune_info *out) {
+    if (!out) return fail(FLP_E_ARG, "out is NULL");
+    CKR(check_csr(A));
+    if (r < 1 || r > 32) return fail(FLP_E_ARG, "r must be in [1, 32]");
+    if (prec != FLP_PREC_FP64 && prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        Workspace &w = ws();
+        const bool fp32 = prec == FLP_PREC_FP32_FILTER;
+        const size_t es = fp32 ? sizeof(float) : sizeof(double);
+        const int n = A->n;
+        for (auto &u : w.U) CK(ensure(u, es * (size_t)n * r));
+        CK(ensure(w.Vg, es * (size_t)n * r));
+        CK(hipMemsetAsync(w.Vg.p, 0, es * (size_t)n * r, s));
+        const float *v32 = nullptr;
+        if (fp32) CKR(ensure_val32(A, w.val32, &w.val32_src, &w.val32_nnz, &v32, s));
+        void *U[3] = {w.U[0].p, w.U[1].p, w.U[2].p};
+        FilterTune tn;
+        CKR(tune_filter(A, v32, r, fp32, true, U, w.Vg.p, r, s, &tn));
+        CK(hipStreamSynchronize(s));
+        StepShape sh = step_shape_ok(tn.gw, fp32, tn.sh) ? tn.sh : default_step_shape(tn.gw, fp32);
+        out->group_width = tn.gw;
+        out->lanes_per_row = sh.lpr > 0 ? sh.lpr : tn.gw;
+        out->cols_per_lane = sh.lpr > 0 ? sh.vec : 1;
+        out->rows_per_wave = 64 / out->lanes_per_row;
+        out->candidates = tn.candidates;
+        out->us_per_step = tn.candidates > 0 ? tn.us_per_step : 0.0;
+        return FLP_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FLP_E_NOMEM, "host allocation failed");
+    }
+}
+
+void flp_set_autotune(int32_t on) { set_autotune(on); }
+
+void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width) {
+    force_filter_shape(StepShape{std::max(0, (int)lanes_per_row), std::max(0, (int)cols_per_lane)},
+                       std::max(0, (int)group_width));
+}
+
 int flp_spmm(const flp_csr *A, const double *X, int32_t ldx, double *Y, int32_t ldy, int32_t r, void *stream) {
     CKR(check_csr(A));
     if (r < 1 || r > 32 || ldx < r || ldy < r || !X || !Y) return fail(FLP_E_ARG, "bad block arguments");

@@ -33,7 +33,7 @@ int build_tables(const std::vector<Solve *> &act, Tables &T, hipStream_t s) {
     T.host.assign((size_t)T.M * T.cap, SegEntry{});
     T.nseg.assign(T.M, 0);
     T.tiles.assign(T.M, 0);
-    const int rpt = seg_rows_per_tile(T.r, T.fp32);
+    const int rpt = seg_rows_per_tile(T.r, T.fp32, T.sh);
     for (int t = 0; t < T.M; ++t) {
         int ns = 0, tiles = 0;
         for (Solve *S : act) {
@@ -74,7 +74,7 @@ int build_tables(const std::vector<Solve *> &act, Tables &T, hipStream_t s) {
 int launch_tables(const Tables &T, hipStream_t s) {
     const SegEntry *base = (const SegEntry *)T.dev.p;
     for (int t = 0; t < T.M; ++t)
-        CK(launch_cheb_seg(T.fp32, T.r, base + (size_t)t * T.cap, T.nseg[t], T.tiles[t], s));
+        CK(launch_cheb_seg(T.fp32, T.r, base + (size_t)t * T.cap, T.nseg[t], T.tiles[t], s, T.sh));
     return FLP_OK;
 }
 
@@ -88,17 +88,76 @@ int Engine::init(int r_, int prec_, bool graph_) {
     use_graph = graph_;
     T.r = r;
     T.fp32 = prec == FLP_PREC_FP32_FILTER;
+    CK(hipGetDevice(&device));
     CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    CK(hipStreamCreateWithFlags(&fs, hipStreamNonBlocking));
     CK(hipEventCreate(&ev_a));
     CK(hipEventCreate(&ev_b));
+    fin = std::thread([this]() { finisher_main(); });
     return FLP_OK;
 }
 
 Engine::~Engine() {
+    if (fin.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(fmu);
+            fstop = true;
+        }
+        fcv.notify_all();
+        fin.join();  // the queue is drained first
+    }
     graph_reset();
     if (ev_a) (void)hipEventDestroy(ev_a);
     if (ev_b) (void)hipEventDestroy(ev_b);
+    if (fs) (void)hipStreamDestroy(fs);
     if (s) (void)hipStreamDestroy(s);
+}
+
+void Engine::complete(Job *j) {
+    if (on_done) on_done(j);
+}
+
+void Engine::finisher_main() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        Job *j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(fmu);
+            fcv.wait(lk, [&] { return fstop || !fq.empty(); });
+            if (fq.empty()) return;
+            j = fq.front();
+            fq.pop_front();
+            ++fbusy;
+        }
+        const double t0 = now();
+        j->S->s = fs;
+        j->code = solve_finish(*j->S, &j->res);
+        if (j->code != FLP_OK && j->code != FLP_E_NOCONV) j->msg = last_error_cstr();
+        j->t_done = now();
+        j->B.reset();  // release this solve's device memory
+        {
+            std::lock_guard<std::mutex> lk(fmu);
+            t_finish += now() - t0;
+        }
+        complete(j);
+        {
+            std::lock_guard<std::mutex> lk(fmu);
+            --fbusy;
+        }
+        fdone.notify_all();
+    }
+}
+
+void Engine::wait_finisher() {
+    std::unique_lock<std::mutex> lk(fmu);
+    fdone.wait(lk, [&] { return fq.empty() && fbusy == 0; });
+}
+
+flp_batch_stats Engine::snapshot() {
+    std::lock_guard<std::mutex> lk(fmu);
+    flp_batch_stats st = stats;
+    st.t_finish = t_finish;
+    return st;
 }
 
 void Engine::graph_reset() {
@@ -113,12 +172,22 @@ void Engine::add(Job *j) {
     tables_valid = false;
 }
 
-int Engine::step(std::vector<Job *> &finished) {
+int Engine::step() {
     if (active.empty()) return FLP_OK;
     std::vector<Solve *> act;
     for (Job *j : active) act.push_back(j->S.get());
     if (!tables_valid) {
         graph_reset();
+        // launch shape of the segmented steps, tuned on the largest active
+        // matrix (its recurrence buffers are scratch between block steps)
+        Solve *big = act[0];
+        for (Solve *S : act)
+            if (S->A->nnz > big->A->nnz) big = S;
+        FilterTune tn;
+        void *U[3] = {big->U[0], big->U[1], big->U[2]};
+        CKR(tune_filter(big->A, big->val32, r, T.fp32, false, U,
+                        T.fp32 ? (const void *)big->V32 : (const void *)big->Vin, r, s, &tn));
+        T.sh = tn.sh;
         CKR(build_tables(act, T, s));
         if (use_graph) {
             CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -165,48 +234,37 @@ int Engine::step(std::vector<Job *> &finished) {
     run_phase(step_qr1);
     CK(hipStreamSynchronize(s));
     run_phase(step_qr2);
-    // convergence checks are host eigensolves: run them in parallel
-    {
-        std::vector<Job *> todo;
-        for (Job *j : active)
-            if (j->code == FLP_OK) todo.push_back(j);
-        const int nt = (int)std::min<size_t>(todo.size(), 16);
-        std::vector<std::thread> th;
-        for (int w = 0; w < nt; ++w)
-            th.emplace_back([&, w]() {
-                for (size_t q = w; q < todo.size(); q += nt) {
-                    todo[q]->code = step_check_host(*todo[q]->S);
-                    if (todo[q]->code != FLP_OK) todo[q]->msg = last_error_cstr();
-                }
-            });
-        for (auto &t : th) t.join();
-        for (Job *j : todo)
-            if (j->code == FLP_OK) {
-                j->code = step_check(*j->S);
-                if (j->code != FLP_OK) j->msg = last_error_cstr();
-            }
-    }
-    double t_fin = 0.0;
-    std::vector<Job *> keep;
+    // convergence checks: applied when their pool task has finished, started
+    // at the cadence (the solves keep stepping meanwhile)
+    run_phase([](Solve &S) { return step_check(S, true); });
+    std::vector<Job *> keep, done;
     for (Job *j : active) {
-        if (j->code == FLP_OK && !j->S->done) {
+        if (j->code == FLP_OK && !j->S->done)
             keep.push_back(j);
-            continue;
-        }
-        if (j->code == FLP_OK) {
-            const double tf = now();
-            j->code = solve_finish(*j->S, &j->res);
-            if (j->code != FLP_OK && j->code != FLP_E_NOCONV) j->msg = last_error_cstr();
-            t_fin += now() - tf;
-        }
-        j->t_done = now();
-        j->B.reset();  // release this solve's device memory
-        finished.push_back(j);
+        else
+            done.push_back(j);
     }
-    if (keep.size() != active.size()) tables_valid = false;
+    if (!done.empty()) {
+        // the finisher reads what this stream wrote (the basis)
+        CK(hipStreamSynchronize(s));
+        for (Job *j : done) {
+            if (j->code == FLP_OK) {
+                {
+                    std::lock_guard<std::mutex> lk(fmu);
+                    fq.push_back(j);
+                }
+                fcv.notify_one();
+            } else {
+                j->S->st.t_total = now() - j->S->t_start;
+                j->t_done = now();
+                j->B.reset();
+                complete(j);
+            }
+        }
+        tables_valid = false;
+    }
     active.swap(keep);
-    stats.t_finish += t_fin;
-    stats.t_orth_check += now() - t1 - t_fin;
+    stats.t_orth_check += now() - t1;
     return FLP_OK;
 }
 
@@ -234,7 +292,6 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
     CKR(E.init(r, prec, use_graph != 0));
     E.stats.solves = count;
     std::vector<std::unique_ptr<Job>> jobs(count);
-    std::vector<Job *> finished;
     for (int i = 0; i < count; ++i) {
         auto j = std::make_unique<Job>();
         j->id = (uint64_t)i;
@@ -261,13 +318,19 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
         jobs[i] = std::move(j);
     }
     E.stats.t_setup = now() - t0;
-    while (!E.active.empty()) CKR(E.step(finished));
+    int rc = FLP_OK;
+    while (!E.active.empty() && rc == FLP_OK) rc = E.step();
+    E.wait_finisher();
+    CKR(rc);
     CK(hipStreamSynchronize(E.s));
     for (int i = 0; i < count; ++i) {
         results[i] = jobs[i]->res;
         codes[i] = jobs[i]->code;
         if (results[i]) results[i]->stats.t_total = jobs[i]->t_done - t0;  // completion time inside the batch
     }
+    const double t_setup = E.stats.t_setup;
+    E.stats = E.snapshot();
+    E.stats.t_setup = t_setup;
     E.stats.t_total = now() - t0;
     if (bs) *bs = E.stats;
     for (int i = 0; i < count; ++i)

@@ -18,6 +18,13 @@
 //     identity, Z e_j = J_1 (J_2 (... (J_t e_j))) (the Ritz vectors need
 //     only the candidates' columns).
 // Both replays cost O(#rotations x #selected) and run in parallel threads.
+//
+// Dense matrices (the Rayleigh-Ritz projections, whose bandwidth is the full
+// order) take a different first phase: Householder reduction to tridiagonal
+// form (Golub & Van Loan, Alg. 8.3.1), whose cost is O(N^3) with unit-stride
+// inner loops, instead of O(N^2 log b) rotations each touching O(b) strided
+// entries.  Their eigenvectors are the logged QR rotations replayed on
+// identity columns followed by the reflectors.
 #include "flp_internal.h"
 
 #include <algorithm>
@@ -103,7 +110,7 @@ void band_to_tridiag(Band &M, int b, std::vector<Rot> &log) {
                 const double x = M.get(i - 1, k);
                 const double y = M.get(i, k);
                 if (y == 0.0) break;
-                const double r = std::hypot(x, y);
+                const double r = std::sqrt(x * x + y * y);
                 const double c = x / r, s = y / r;
                 rotate_band(M, i - 1, c, s);
                 M.set(i, k, 0.0);
@@ -148,7 +155,7 @@ bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot>
         double mu = d[hi] - ee * ee / den;
         double x = d[lo] - mu, z = e[lo];
         for (int k = lo; k < hi; ++k) {
-            double r = std::hypot(x, z);
+            double r = std::sqrt(x * x + z * z);
             double c = 1.0, s = 0.0;
             if (r != 0.0) {
                 c = x / r;
@@ -170,8 +177,11 @@ bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot>
     return true;
 }
 
+thread_local int tl_eig_threads = 16;  // inner-thread cap of the calling thread
+
 int nthreads_for(long work, int units) {
     int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    nt = std::min(nt, std::max(1, tl_eig_threads));
     nt = std::min(nt, units);
     if (work < 4000000L) nt = 1;
     return std::max(nt, 1);
@@ -246,7 +256,129 @@ void replay_cols(const std::vector<Rot> &log, int N, const int *ids, int ncols, 
     parallel_for(ntiles, nthreads_for((long)log.size() * ncols, ntiles), work);
 }
 
+// Householder reduction of a dense symmetric N x N matrix (row-major, full
+// storage, overwritten) to tridiagonal (d, e).  Step k maps row k's entries
+// k+1..N-1 to mu e_1 with H_k = I - beta_k v_k v_k^T (v_k(0) = 1), applied
+// to the trailing block as B -= v w^T + w v^T, w = p - (beta p^T v / 2) v,
+// p = beta B v.  v_k is left in row k, beta_k in beta[k].
+void householder_tridiag(int N, double *A, std::vector<double> &d, std::vector<double> &e,
+                         std::vector<double> &beta) {
+    d.assign(N, 0.0);
+    e.assign(std::max(N - 1, 0), 0.0);
+    beta.assign(std::max(N - 2, 0), 0.0);
+    std::vector<double> p(N), w(N);
+    for (int k = 0; k + 2 < N; ++k) {
+        const int len = N - k - 1;
+        double *x = A + (size_t)k * N + k + 1;
+        double sigma = 0.0;
+        for (int i = 1; i < len; ++i) sigma += x[i] * x[i];
+        const double x0 = x[0];
+        if (sigma == 0.0) {
+            e[k] = x0;
+            beta[k] = 0.0;
+            for (int i = 1; i < len; ++i) x[i] = 0.0;
+            x[0] = 1.0;
+            continue;
+        }
+        const double mu = std::sqrt(x0 * x0 + sigma);
+        const double v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+        const double bt = 2.0 * v0 * v0 / (sigma + v0 * v0);
+        const double inv = 1.0 / v0;
+        x[0] = 1.0;
+        for (int i = 1; i < len; ++i) x[i] *= inv;
+        e[k] = mu;
+        beta[k] = bt;
+        // p = beta B v over the trailing block B = A[k+1:, k+1:]
+        double pv = 0.0;
+        for (int i = 0; i < len; ++i) {
+            const double *row = A + (size_t)(k + 1 + i) * N + k + 1;
+            double t = 0.0;
+            for (int j = 0; j < len; ++j) t += row[j] * x[j];
+            p[i] = bt * t;
+            pv += p[i] * x[i];
+        }
+        const double K = 0.5 * bt * pv;
+        for (int i = 0; i < len; ++i) w[i] = p[i] - K * x[i];
+        for (int i = 0; i < len; ++i) {
+            double *row = A + (size_t)(k + 1 + i) * N + k + 1;
+            const double xi = x[i], wi = w[i];
+            for (int j = 0; j < len; ++j) row[j] -= xi * w[j] + wi * x[j];
+        }
+    }
+    for (int k = 0; k < N; ++k) d[k] = A[(size_t)k * N + k];
+    if (N >= 2) e[N - 2] = A[(size_t)(N - 2) * N + N - 1];
+}
+
+// Columns ids of Q Z_t, Q = H_0 H_1 ... H_{N-3} (reflectors stored in the
+// rows of A by householder_tridiag), Z_t = the QR rotations J_1 ... J_t:
+// identity columns, rotations replayed backwards, then the reflectors from
+// the last to the first.  Z is N x ncols row-major.
+void dense_vectors(const std::vector<Rot> &log, const double *A, const std::vector<double> &beta, int N,
+                   const int *ids, int ncols, double *Z) {
+    constexpr int TILE = 8;
+    const int ntiles = (ncols + TILE - 1) / TILE;
+    auto work = [&](int t0, int t1) {
+        std::vector<double> tile((size_t)N * TILE);
+        for (int t = t0; t < t1; ++t) {
+            const int c0 = t * TILE, nc = std::min(TILE, ncols - c0);
+            std::fill(tile.begin(), tile.end(), 0.0);
+            for (int j = 0; j < nc; ++j) tile[(size_t)ids[c0 + j] * TILE + j] = 1.0;
+            for (auto it = log.rbegin(); it != log.rend(); ++it) {
+                const Rot &g = *it;
+                double *a = &tile[(size_t)g.p * TILE];
+                double *b = a + TILE;
+                for (int j = 0; j < TILE; ++j) {
+                    const double u = a[j], v = b[j];
+                    a[j] = g.c * u - g.s * v;
+                    b[j] = g.s * u + g.c * v;
+                }
+            }
+            for (int k = N - 3; k >= 0; --k) {
+                const double bt = beta[k];
+                if (bt == 0.0) continue;
+                const double *v = A + (size_t)k * N + k + 1;
+                double *z = &tile[(size_t)(k + 1) * TILE];
+                const int len = N - k - 1;
+                double acc[TILE] = {};
+                for (int i = 0; i < len; ++i)
+                    for (int j = 0; j < TILE; ++j) acc[j] += v[i] * z[(size_t)i * TILE + j];
+                for (int j = 0; j < TILE; ++j) acc[j] *= bt;
+                for (int i = 0; i < len; ++i)
+                    for (int j = 0; j < TILE; ++j) z[(size_t)i * TILE + j] -= acc[j] * v[i];
+            }
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < nc; ++j) Z[(size_t)i * ncols + c0 + j] = tile[(size_t)i * TILE + j];
+        }
+    };
+    parallel_for(ntiles, nthreads_for((long)(log.size() + (size_t)N * N) * ncols, ntiles), work);
+}
+
+// Dense path: eigenvalues ascending in evals, selected columns (indices into
+// the ascending order) of the eigenvector matrix in Zcols (N x ncols).
+int dense_sym_eig(int N, const double *M, double *evals, const int *cols, int ncols, double *Zcols) {
+    std::vector<double> A((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) A[(size_t)i * N + j] = 0.5 * (M[(size_t)i * N + j] + M[(size_t)j * N + i]);
+    std::vector<double> d, e, beta;
+    householder_tridiag(N, A.data(), d, e, beta);
+    std::vector<Rot> log;
+    log.reserve((size_t)N * 4);
+    if (!tridiag_qr(d, e, log)) return -2;
+    std::vector<int> perm(N);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] < d[b]; });
+    for (int i = 0; i < N; ++i) evals[i] = d[perm[i]];
+    if (ncols > 0 && Zcols) {
+        std::vector<int> ids(ncols);
+        for (int j = 0; j < ncols; ++j) ids[j] = perm[cols[j]];
+        dense_vectors(log, A.data(), beta, N, ids.data(), ncols, Zcols);
+    }
+    return 0;
+}
+
 }  // namespace
+
+void set_eig_threads(int n) { tl_eig_threads = std::max(1, n); }
 
 int sym_eig_keep(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Zrows,
                  EigLog *keep) {
@@ -295,6 +427,8 @@ void eig_log_cols(const EigLog &L, const int *cols, int ncols, double *Zcols) {
 
 int sym_eig(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Zrows,
             const int *cols, int ncols, double *Zcols) {
+    if (N <= 0) return -1;
+    if (nrows == 0 && std::min(bw, N - 1) >= std::max(24, N / 8)) return dense_sym_eig(N, M, evals, cols, ncols, Zcols);
     if (ncols > 0 && Zcols) {
         EigLog L;
         const int rc = sym_eig_keep(N, bw, M, evals, rows, nrows, Zrows, &L);

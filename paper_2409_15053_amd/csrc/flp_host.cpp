@@ -9,11 +9,16 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <functional>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "flp_host.h"
@@ -66,14 +71,68 @@ hipError_t ensure(Buf &b, size_t bytes) {
 }
 
 void Workspace::release_all() {
-    Buf *all[] = {&U[0], &U[1], &U[2], &V32, &val32, &partials, &small, &W, &Vin, &Q, &Y, &AY, &X, &AX, &resid_part};
+    Buf *all[] = {&U[0], &U[1], &U[2], &V32, &Vg, &val32, &partials, &small, &W, &Vin, &Q, &Y, &AY, &X, &AX, &resid_part};
     for (Buf *b : all) b->release();
     val32_src = nullptr;
     val32_nnz = 0;
 }
 
+namespace {
+// Host worker pool for the convergence checks.  Each worker limits the
+// eigensolver's own inner threads so that concurrent checks share the cores.
+struct HostPool {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::function<void()>> q;
+    std::vector<std::thread> th;
+    bool stop = false;
+    HostPool() {
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        const int nw = std::max(1, std::min(8, hw / 2));
+        for (int i = 0; i < nw; ++i)
+            th.emplace_back([this, hw, nw]() {
+                set_eig_threads(std::max(1, std::min(16, hw) / nw));
+                for (;;) {
+                    std::function<void()> f;
+                    {
+                        std::unique_lock<std::mutex> lk(mu);
+                        cv.wait(lk, [&] { return stop || !q.empty(); });
+                        if (stop && q.empty()) return;
+                        f = std::move(q.front());
+                        q.pop_front();
+                    }
+                    f();
+                }
+            });
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        for (auto &t : th) t.join();
+    }
+};
+HostPool &host_pool() {
+    static HostPool p;
+    return p;
+}
+}  // namespace
+
+void host_pool_submit(std::function<void()> f) {
+    HostPool &p = host_pool();
+    {
+        std::lock_guard<std::mutex> lk(p.mu);
+        p.q.push_back(std::move(f));
+    }
+    p.cv.notify_one();
+}
+
 Workspace &ws() {
-    static Workspace w[64];
+    // per thread and device: the batched engine's finisher thread works
+    // beside its stepping thread
+    static thread_local Workspace w[64];
     int dev = 0;
     (void)hipGetDevice(&dev);
     return w[dev & 63];
@@ -202,22 +261,23 @@ std::vector<ClenshawStep> clenshaw_plan(const flp_filter *p, int r, const void *
 
 // Launch one planned step with the direct (single-matrix) kernel.
 int launch_plan_step(const flp_csr *A, const float *val32, int r, const ClenshawStep &st, bool fp32,
-                     hipStream_t s) {
+                     hipStream_t s, StepShape sh) {
     const int n = A->n;
     if (!fp32) {
         CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, r, (const double *)st.X, st.ldx,
                                             (const double *)st.V, st.ldv, (const double *)st.Y, st.ldy,
-                                            (double *)st.out, st.ldo, st.alpha, st.beta, st.gamma, st.delta, s));
+                                            (double *)st.out, st.ldo, st.alpha, st.beta, st.gamma, st.delta, s,
+                                            sh));
     } else if (st.out_f64) {
         CK(launch_cheb_step<float, double>(n, A->rowptr, A->colind, val32, r, (const float *)st.X, st.ldx,
                                            (const float *)st.V, st.ldv, (const float *)st.Y, st.ldy,
                                            (double *)st.out, st.ldo, (float)st.alpha, (float)st.beta,
-                                           (float)st.gamma, (float)st.delta, s));
+                                           (float)st.gamma, (float)st.delta, s, sh));
     } else {
         CK(launch_cheb_step<float, float>(n, A->rowptr, A->colind, val32, r, (const float *)st.X, st.ldx,
                                           (const float *)st.V, st.ldv, (const float *)st.Y, st.ldy,
                                           (float *)st.out, st.ldo, (float)st.alpha, (float)st.beta,
-                                          (float)st.gamma, (float)st.delta, s));
+                                          (float)st.gamma, (float)st.delta, s, sh));
     }
     return FLP_OK;
 }
@@ -272,23 +332,38 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
     Workspace &w = ws();
     const int n = A->n;
     const bool fp32 = prec == FLP_PREC_FP32_FILTER;
-    const int gw = filter_group_width(n, A->nnz, r, prec);
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
-    for (auto &u : w.U) CK(ensure(u, es * (size_t)n * gw));
+    for (auto &u : w.U) CK(ensure(u, es * (size_t)n * r));
+    void *U[3] = {w.U[0].p, w.U[1].p, w.U[2].p};
     const float *v32 = nullptr;
-    const void *vin = V;
-    int ldin = ldv;
+    const void *vfull = V;
+    int ldfull = ldv;
     if (fp32) {
         CKR(ensure_val32(A, w.val32, &w.val32_src, &w.val32_nnz, &v32, s));
         CK(ensure(w.V32, sizeof(float) * (size_t)n * r));
         CK(launch_copy_block(n, r, 1.0, V, ldv, DMat{nullptr, 0, 0, 0}, 0, (float *)w.V32.p, r, s));
-        vin = w.V32.p;
-        ldin = r;
+        vfull = w.V32.p;
+        ldfull = r;
     }
+    FilterTune tn;
+    CKR(tune_filter(A, v32, r, fp32, true, U, vfull, ldfull, s, &tn));
+    const int gw = tn.gw;
+    if (gw == r) {
+        auto plan = clenshaw_plan(p, r, vfull, ldfull, W, ldw, U[0], U[1], U[2], fp32);
+        for (const auto &st : plan) CKR(launch_plan_step(A, v32, r, st, fp32, s, tn.sh));
+        return FLP_OK;
+    }
+    // Each column group of V (converted to FP32 in that precision) is staged
+    // as a contiguous n x gw block: the filter reads V at every step, and a
+    // strided group would pull in the other groups' columns with each line.
+    CK(ensure(w.Vg, es * (size_t)n * gw));
     for (int j0 = 0; j0 < r; j0 += gw) {
-        const void *vg = fp32 ? (const void *)((const float *)vin + j0) : (const void *)((const double *)vin + j0);
-        auto plan = clenshaw_plan(p, gw, vg, ldin, W + j0, ldw, w.U[0].p, w.U[1].p, w.U[2].p, fp32);
-        for (const auto &st : plan) CKR(launch_plan_step(A, v32, gw, st, fp32, s));
+        if (fp32)
+            CK(launch_copy_block(n, gw, 1.0, V + j0, ldv, DMat{nullptr, 0, 0, 0}, 0, (float *)w.Vg.p, gw, s));
+        else
+            CK(launch_copy_block(n, gw, 1.0, V + j0, ldv, plain_mat((double *)w.Vg.p, gw), 0, nullptr, 0, s));
+        auto plan = clenshaw_plan(p, gw, w.Vg.p, gw, W + j0, ldw, U[0], U[1], U[2], fp32);
+        for (const auto &st : plan) CKR(launch_plan_step(A, v32, gw, st, fp32, s, tn.sh));
     }
     return FLP_OK;
 }

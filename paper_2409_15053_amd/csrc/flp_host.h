@@ -6,9 +6,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <deque>
+#include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "flp_internal.h"
@@ -32,6 +38,7 @@ constexpr double kDefaultTol = 1e-9;
 constexpr int kMaxDegree = 100000;
 constexpr int64_t kDefaultMaxBasis = 3072;
 constexpr int kPanelLog2 = 7;  // Lanczos basis panels of 128 columns
+constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
 
 int fail(int code, const std::string &msg);
 const char *last_error_cstr();
@@ -65,10 +72,11 @@ struct Buf {
 };
 hipError_t ensure(Buf &b, size_t bytes);
 
-// Per-device scratch shared by calls that run one after another.
+// Per-thread, per-device scratch shared by the calls one thread makes.
 struct Workspace {
     Buf U[3];      // Clenshaw vectors
     Buf V32;       // FP32 copy of the filter input
+    Buf Vg;        // one column group of the filter input, stored contiguously
     Buf val32;     // FP32 copy of the matrix values
     Buf partials;  // gemm_tn partial sums
     Buf small;     // small device matrices
@@ -113,7 +121,23 @@ struct ClenshawStep {
 std::vector<ClenshawStep> clenshaw_plan(const flp_filter *p, int r, const void *V, int ldv, double *W, int ldw,
                                         void *U0, void *U1, void *U2, bool fp32);
 int launch_plan_step(const flp_csr *A, const float *val32, int r, const ClenshawStep &st, bool fp32,
-                     hipStream_t s);
+                     hipStream_t s, StepShape sh = StepShape{});
+
+// ---------------------------------------------------------------- autotuner
+struct FilterTune {
+    int gw = 0;           // columns per filter launch (column-group width)
+    StepShape sh{};       // launch shape of each step
+    double us_per_step = 0.0;
+    int candidates = 0;   // configurations timed (0: default, not timed)
+};
+// Picks (gw, shape) for filtering r columns of A by timing candidates (see
+// flp_tune.cpp).  U: three device buffers of n x r filter-type elements
+// (scratch, overwritten); V: n x r input block (read only, ld ldv).
+int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
+                const void *V, int ldv, hipStream_t s, FilterTune *out);
+void set_autotune(int mode);
+int autotune_mode();
+void force_filter_shape(StepShape sh, int gw);
 
 // W = p(Ahat) V (V, W n x r with leading dimensions) through the
 // workspace's Clenshaw buffers.
@@ -144,6 +168,29 @@ struct SolveBufs {
 };
 
 // One filtered Lanczos solve advanced block step by block step.
+// One convergence check of T_k (Section 3.2.2) as a self-contained task:
+// a snapshot of T_k and S_k goes in; the Ritz values' candidate set, the
+// residual test and the eigen-decomposition's rotation log come out.  It
+// runs on a host pool thread while the solve keeps stepping.
+struct CheckTask {
+    int K = 0, r = 0;
+    double tau = 0, tol_p = 0;
+    bool fp32 = false;
+    std::vector<double> T, Sk;
+    int rc = FLP_OK;
+    std::string msg;
+    bool ok = false;  // every candidate's residual bound met
+    std::vector<int> cand, guard;
+    EigLog eig;
+    double secs = 0.0;
+    std::atomic<bool> ready{false};
+};
+void run_check(CheckTask &c);
+
+// Fixed pool of host threads for work that overlaps the device (the
+// convergence checks).  Tasks run in submission order per worker.
+void host_pool_submit(std::function<void()> f);
+
 struct Solve {
     // inputs
     const flp_csr *A = nullptr;
@@ -168,6 +215,7 @@ struct Solve {
     int steps = 0, prev_count = -1, kfinal = 0;
     bool converged = false, done = false;
     std::vector<int> cand;
+    std::vector<int> guard;  // FP32 filter: Ritz vectors just outside the candidates, polished with them
     flp_stats st{};
     double t_start = 0;
     int code = FLP_OK;  // first error
@@ -177,8 +225,10 @@ struct Solve {
     double *gdev = nullptr, *rdev = nullptr;
     std::vector<double> R1;
     bool slow = false;      // this step's block needed the rank repair path
-    int checked_step = -1;  // block step whose convergence check has run
-    EigLog eig;             // rotation log of the last check's T_k
+    int checked_step = -1;  // block step whose convergence check was started
+    EigLog eig;             // rotation log of the deciding check's T_k
+    std::shared_ptr<CheckTask> check;  // check in flight (its T_k may be behind the current step)
+    bool check_last = false;           // that check is the final one (no basis room left)
     double t_step0 = 0.0;   // host time the current block step started
     Solve() = default;
     Solve(const Solve &) = delete;
@@ -194,15 +244,18 @@ int solve_setup(Solve &S);
 //   step_orth_launch: CGS2 against the basis, Gram matrix of W (async);
 //   step_qr1:         D_j; first Cholesky factor; apply it; second Gram (async);
 //   step_qr2:         second Cholesky factor; apply it; S_j;
-//   step_check:       convergence check at the cadence (host only), else the
-//                     new block joins the basis and becomes the next input.
+//   step_check:       applies a finished convergence check; at the cadence
+//                     starts the next one on the host pool (the solve keeps
+//                     stepping meanwhile: if that check decides convergence,
+//                     the result comes from the checked T_k and the extra
+//                     steps are dropped); else the new block joins the basis
+//                     and becomes the next input.
 int step_orth_launch(Solve &S);
 int step_qr1(Solve &S);
 int step_qr2(Solve &S);
-int step_check(Solve &S);
-// the host part of step_check (thread-safe per solve): runs the check when
-// this block step is at the cadence and has not been checked yet
-int step_check_host(Solve &S);
+int step_check(Solve &S, bool async = true);
+// waits for and applies a check in flight (no-op when there is none)
+int wait_check(Solve &S);
 // all four phases with synchronisations (single solve)
 int solve_after_filter(Solve &S);
 // Ritz vectors, Rayleigh-Ritz with A, FP32 polish, result
@@ -214,6 +267,7 @@ int solve_finish(Solve &S, flp_result **out);
 struct Tables {
     int M = 0, cap = 0, r = 0;
     bool fp32 = false;
+    StepShape sh{};  // launch shape of the segmented steps
     std::vector<SegEntry> host;    // M x cap
     std::vector<int> nseg, tiles;  // per launch
     Buf dev;
@@ -230,14 +284,17 @@ struct Job {
     size_t footprint = 0;   // device bytes reserved at admission
     flp_csr A{};            // the caller's matrix descriptor
     std::string msg;        // error message of a failed request
+    bool finished = false;  // result handed back (set under the owner's lock)
 };
 
 // Advances a set of active solves in lockstep: per block step, one
 // segmented filter launch per Clenshaw step (replayed from a HIP graph while
 // the set is unchanged), then each solve's Gram-Schmidt, block QR and
-// convergence check, then Rayleigh-Ritz for the solves that finished.
+// convergence check; solves that converged go to the finisher thread for
+// their Ritz vectors, Rayleigh-Ritz and polish while the others step on.
 struct Engine {
     hipStream_t s = nullptr;
+    int device = 0;
     int r = 0, prec = 0;
     bool use_graph = true;
     std::vector<Job *> active;
@@ -247,16 +304,38 @@ struct Engine {
     hipGraphExec_t gexec = nullptr;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     flp_batch_stats stats{};
+    // Called once per job when it leaves the engine (result ready, or an
+    // error), from the stepping thread or the finisher thread, after the
+    // job's device buffers are released.
+    std::function<void(Job *)> on_done;
     Engine() = default;
     Engine(const Engine &) = delete;
     Engine &operator=(const Engine &) = delete;
     ~Engine();
     int init(int r, int prec, bool use_graph);
     void add(Job *j);
-    // one block step of every active solve; jobs that completed (result or
-    // error) leave the active set and are appended to finished
-    int step(std::vector<Job *> &finished);
+    // one block step of every active solve; converged solves leave the
+    // active set for the finisher
+    int step();
     void graph_reset();
+    // blocks until every handed-off solve is finished
+    void wait_finisher();
+    // engine statistics including the finisher's time
+    flp_batch_stats snapshot();
+
+  private:
+    // finisher: Ritz vectors, Rayleigh-Ritz and polish of converged solves
+    // on a second stream and host thread, overlapping later block steps
+    hipStream_t fs = nullptr;
+    std::thread fin;
+    std::mutex fmu;
+    std::condition_variable fcv, fdone;
+    std::deque<Job *> fq;
+    int fbusy = 0;
+    bool fstop = false;
+    double t_finish = 0.0;
+    void finisher_main();
+    void complete(Job *j);
 };
 
 // drivers

@@ -48,6 +48,10 @@ struct EigLog {
         perm.clear();
     }
 };
+// Caps the threads one eigensolver call started from the calling thread may
+// use (default 16).
+void set_eig_threads(int n);
+
 // sym_eig that also returns its rotation log in *keep
 int sym_eig_keep(int N, int bw, const double *M, double *evals, const int *rows, int nrows, double *Zrows,
                  EigLog *keep);
@@ -74,6 +78,18 @@ inline DMat panel_mat(const double *p, int64_t n, int lpw) {
 // ---------------------------------------------------------------- kernel launchers
 // All take a stream and return hipError_t from the launch.
 
+// Launch shape of a filter step: lpr lanes share one matrix row and each
+// owns vec consecutive columns of the block (lpr * vec = r), so a 256-thread
+// block covers 256 / lpr rows.  {0, 0} selects the default (16-byte pieces).
+// Every shape sums each output element in the same order, so all of them
+// give bit-identical results.
+struct StepShape {
+    int lpr = 0, vec = 0;
+};
+StepShape default_step_shape(int r, bool fp32);
+std::vector<StepShape> step_shape_candidates(int r, bool fp32);
+bool step_shape_ok(int r, bool fp32, StepShape sh);
+
 // out = alpha * (A X) + beta * X + gamma * V + delta * Y, row-major blocks of
 // r columns with leading dimensions; V / Y may be NULL (their terms skipped).
 // T = float or double selects the matrix values and the vector type; the
@@ -82,7 +98,7 @@ template <typename T, typename Tout>
 hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val,
                             int r, const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy,
                             Tout *out, int ldo, T alpha, T beta, T gamma, T delta,
-                            hipStream_t s);
+                            hipStream_t s, StepShape sh = StepShape{});
 
 // One segment of a segmented filter step: the current Clenshaw launch of
 // one solve in a batch (out = alpha AX + beta X + gamma V + delta Y).
@@ -101,9 +117,10 @@ struct SegEntry {
     double alpha, beta, gamma, delta;
 };
 // rows per tile of the segmented kernel for block width r and value type
-int seg_rows_per_tile(int r, bool fp32);
+int seg_rows_per_tile(int r, bool fp32, StepShape sh = StepShape{});
 // One launch over nseg segments (tab: device array sorted by tile0).
-hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s);
+hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s,
+                           StepShape sh = StepShape{});
 
 // Partial sums for C = A^T B over row chunks: A n x K (lda), B n x c (ldb).
 // partials[chunk][K * c] (row-major K x c).  Returns the number of chunks

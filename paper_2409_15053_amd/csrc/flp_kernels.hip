@@ -51,39 +51,65 @@ struct Vec<float, 4> {
     using type = float4;
 };
 
+// Loads and stores of VEC consecutive elements in 16-byte (or narrower)
+// pieces; the address is aligned to min(16, VEC * sizeof(T)) bytes.
 template <typename T, int VEC>
 __device__ __forceinline__ void load_vec(const T *p, T (&v)[VEC]) {
-    using V = typename Vec<T, VEC>::type;
-    V x = *reinterpret_cast<const V *>(p);
-    if constexpr (VEC == 1) {
-        v[0] = x;
-    } else if constexpr (VEC == 2) {
-        v[0] = x.x;
-        v[1] = x.y;
+    constexpr int C = 16 / (int)sizeof(T);
+    if constexpr (VEC > C) {
+        static_assert(VEC % C == 0, "vector width must be a multiple of 16 bytes");
+#pragma unroll
+        for (int k = 0; k < VEC / C; ++k) {
+            T t[C];
+            load_vec<T, C>(p + k * C, t);
+#pragma unroll
+            for (int j = 0; j < C; ++j) v[k * C + j] = t[j];
+        }
     } else {
-        v[0] = x.x;
-        v[1] = x.y;
-        v[2] = x.z;
-        v[3] = x.w;
+        using V = typename Vec<T, VEC>::type;
+        V x = *reinterpret_cast<const V *>(p);
+        if constexpr (VEC == 1) {
+            v[0] = x;
+        } else if constexpr (VEC == 2) {
+            v[0] = x.x;
+            v[1] = x.y;
+        } else {
+            v[0] = x.x;
+            v[1] = x.y;
+            v[2] = x.z;
+            v[3] = x.w;
+        }
     }
 }
 
 template <typename T, int VEC>
 __device__ __forceinline__ void store_vec(T *p, const T (&v)[VEC]) {
-    using V = typename Vec<T, VEC>::type;
-    V x;
-    if constexpr (VEC == 1) {
-        x = v[0];
-    } else if constexpr (VEC == 2) {
-        x.x = v[0];
-        x.y = v[1];
+    constexpr int C = 16 / (int)sizeof(T);
+    if constexpr (VEC > C) {
+        static_assert(VEC % C == 0, "vector width must be a multiple of 16 bytes");
+#pragma unroll
+        for (int k = 0; k < VEC / C; ++k) {
+            T t[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) t[j] = v[k * C + j];
+            store_vec<T, C>(p + k * C, t);
+        }
     } else {
-        x.x = v[0];
-        x.y = v[1];
-        x.z = v[2];
-        x.w = v[3];
+        using V = typename Vec<T, VEC>::type;
+        V x;
+        if constexpr (VEC == 1) {
+            x = v[0];
+        } else if constexpr (VEC == 2) {
+            x.x = v[0];
+            x.y = v[1];
+        } else {
+            x.x = v[0];
+            x.y = v[1];
+            x.z = v[2];
+            x.w = v[3];
+        }
+        *reinterpret_cast<V *>(p) = x;
     }
-    *reinterpret_cast<V *>(p) = x;
 }
 
 // ------------------------------------------------------------------ filter step
@@ -174,12 +200,47 @@ hipError_t cheb_launch(int n, const int32_t *rowptr, const int32_t *colind, cons
 
 }  // namespace
 
+// Aligned launch shapes (LPR lanes per row x VEC columns per lane) with a
+// kernel instance: FP64 in 16-, 32- and 64-byte pieces per lane, FP32 in 16-
+// and 32-byte pieces.
+#define FLP_SHAPES_F64(X) X(1, 2) X(2, 2) X(4, 2) X(8, 2) X(16, 2) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(1, 8) X(2, 8) X(4, 8)
+#define FLP_SHAPES_F32(X) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(1, 8) X(2, 8) X(4, 8)
+
+static bool shape_has_kernel(bool fp32, int lpr, int vec) {
+#define FLP_HAS(L, V) if (lpr == L && vec == V) return true;
+    if (fp32) {
+        FLP_SHAPES_F32(FLP_HAS)
+    } else {
+        FLP_SHAPES_F64(FLP_HAS)
+    }
+#undef FLP_HAS
+    return false;
+}
+
+StepShape default_step_shape(int r, bool fp32) {
+    const int v16 = fp32 ? 4 : 2;
+    if (r % v16 == 0 && shape_has_kernel(fp32, r / v16, v16)) return StepShape{r / v16, v16};
+    return StepShape{0, 0};
+}
+
+std::vector<StepShape> step_shape_candidates(int r, bool fp32) {
+    std::vector<StepShape> out;
+    for (int vec : {2, 4, 8})
+        if (r % vec == 0 && shape_has_kernel(fp32, r / vec, vec)) out.push_back(StepShape{r / vec, vec});
+    return out;
+}
+
+bool step_shape_ok(int r, bool fp32, StepShape sh) {
+    return sh.lpr > 0 && sh.lpr * sh.vec == r && shape_has_kernel(fp32, sh.lpr, sh.vec);
+}
+
 template <typename T, typename Tout>
 hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
                             const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
-                            int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s) {
+                            int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s, StepShape sh) {
     if (n <= 0) return hipSuccess;
-    // vector width: 16-byte loads when every leading dimension allows it
+    constexpr bool F32 = sizeof(T) == 4;
+    // vector loads need every leading dimension and base aligned to 16 bytes
     constexpr int V16 = 16 / (int)sizeof(T);
     auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     bool aligned16 = (ldx % V16 == 0) && (!V || ldv % V16 == 0) && (!Y || ldy % V16 == 0) &&
@@ -187,19 +248,15 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
 #define FLP_CHEB(LPR, VEC) \
     return cheb_launch<T, Tout, LPR, VEC>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s)
     if (aligned16 && r % V16 == 0) {
-        int lpr = r / V16;
-        if constexpr (sizeof(T) == 8) {
-            if (lpr == 1) FLP_CHEB(1, 2);
-            if (lpr == 2) FLP_CHEB(2, 2);
-            if (lpr == 4) FLP_CHEB(4, 2);
-            if (lpr == 8) FLP_CHEB(8, 2);
-            if (lpr == 16) FLP_CHEB(16, 2);
+        if (!step_shape_ok(r, F32, sh)) sh = default_step_shape(r, F32);
+        const int lpr = sh.lpr, vec = sh.vec;
+#define FLP_TRY(L, VV) if (lpr == L && vec == VV) { FLP_CHEB(L, VV); }
+        if constexpr (F32) {
+            FLP_SHAPES_F32(FLP_TRY)
         } else {
-            if (lpr == 1) FLP_CHEB(1, 4);
-            if (lpr == 2) FLP_CHEB(2, 4);
-            if (lpr == 4) FLP_CHEB(4, 4);
-            if (lpr == 8) FLP_CHEB(8, 4);
+            FLP_SHAPES_F64(FLP_TRY)
         }
+#undef FLP_TRY
     }
     if (r == 1) FLP_CHEB(1, 1);
     if (r == 2) FLP_CHEB(2, 1);
@@ -214,13 +271,15 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
 template hipError_t launch_cheb_step<double, double>(int, const int32_t *, const int32_t *, const double *, int,
                                                      const double *, int, const double *, int, const double *,
                                                      int, double *, int, double, double, double, double,
-                                                     hipStream_t);
+                                                     hipStream_t, StepShape);
 template hipError_t launch_cheb_step<float, float>(int, const int32_t *, const int32_t *, const float *, int,
                                                    const float *, int, const float *, int, const float *, int,
-                                                   float *, int, float, float, float, float, hipStream_t);
+                                                   float *, int, float, float, float, float, hipStream_t,
+                                                   StepShape);
 template hipError_t launch_cheb_step<float, double>(int, const int32_t *, const int32_t *, const float *, int,
                                                     const float *, int, const float *, int, const float *, int,
-                                                    double *, int, float, float, float, float, hipStream_t);
+                                                    double *, int, float, float, float, float, hipStream_t,
+                                                    StepShape);
 
 // ------------------------------------------------------------------ segmented filter step
 //
@@ -312,57 +371,54 @@ __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restric
 
 }  // namespace
 
-// lanes per row of the segmented kernel; must match launch_cheb_seg
-static int seg_lpr(int r, bool fp32) {
-    const int v16 = fp32 ? 4 : 2;
-    if (r % v16 == 0) {
-        const int l = r / v16;
-        if (l == 1 || l == 2 || l == 4 || l == 8 || (!fp32 && l == 16)) return l;
-    }
-    return r == 1 ? 1 : (r == 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32))));
+// Shape of the segmented kernel: the tuned or default aligned shape when
+// one exists for r, else one lane per column.  seg_rows_per_tile and
+// launch_cheb_seg must agree, so both resolve the shape here.
+static StepShape seg_shape(int r, bool fp32, StepShape sh) {
+    if (step_shape_ok(r, fp32, sh)) return sh;
+    StepShape d = default_step_shape(r, fp32);
+    if (d.lpr > 0) return d;
+    const int l = r == 1 ? 1 : (r == 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32))));
+    return StepShape{l, 1};
 }
 
-int seg_rows_per_tile(int r, bool fp32) { return 256 / seg_lpr(r, fp32); }
+int seg_rows_per_tile(int r, bool fp32, StepShape sh) { return 256 / seg_shape(r, fp32, sh).lpr; }
 
-hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s) {
+hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s,
+                           StepShape sh) {
     if (nseg <= 0 || total_tiles <= 0) return hipSuccess;
+    sh = seg_shape(r, fp32, sh);
+    const int lpr = sh.lpr, vec = sh.vec;
 #define FLP_SEG(T, LPR, VEC) \
-    hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC>), dim3(total_tiles), dim3(256), 0, s, tab, nseg); \
-    return hipGetLastError()
-    if (!fp32) {
-        if (r % 2 == 0) {
-            switch (r / 2) {
-                case 1: FLP_SEG(double, 1, 2);
-                case 2: FLP_SEG(double, 2, 2);
-                case 4: FLP_SEG(double, 4, 2);
-                case 8: FLP_SEG(double, 8, 2);
-                case 16: FLP_SEG(double, 16, 2);
-                default: break;
-            }
-        }
-        if (r == 1) { FLP_SEG(double, 1, 1); }
-        if (r == 2) { FLP_SEG(double, 2, 1); }
-        if (r <= 4) { FLP_SEG(double, 4, 1); }
-        if (r <= 8) { FLP_SEG(double, 8, 1); }
-        if (r <= 16) { FLP_SEG(double, 16, 1); }
-        if (r <= 32) { FLP_SEG(double, 32, 1); }
-    } else {
-        if (r % 4 == 0) {
-            switch (r / 4) {
-                case 1: FLP_SEG(float, 1, 4);
-                case 2: FLP_SEG(float, 2, 4);
-                case 4: FLP_SEG(float, 4, 4);
-                case 8: FLP_SEG(float, 8, 4);
-                default: break;
-            }
-        }
-        if (r == 1) { FLP_SEG(float, 1, 1); }
-        if (r == 2) { FLP_SEG(float, 2, 1); }
-        if (r <= 4) { FLP_SEG(float, 4, 1); }
-        if (r <= 8) { FLP_SEG(float, 8, 1); }
-        if (r <= 16) { FLP_SEG(float, 16, 1); }
-        if (r <= 32) { FLP_SEG(float, 32, 1); }
+    { \
+        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC>), dim3(total_tiles), dim3(256), 0, s, tab, nseg); \
+        return hipGetLastError(); \
     }
+#define FLP_SEG64(L, VV) if (lpr == L && vec == VV) FLP_SEG(double, L, VV)
+#define FLP_SEG32(L, VV) if (lpr == L && vec == VV) FLP_SEG(float, L, VV)
+    if (!fp32) {
+        FLP_SHAPES_F64(FLP_SEG64)
+        if (vec == 1) {
+            if (lpr == 1) FLP_SEG(double, 1, 1);
+            if (lpr == 2) FLP_SEG(double, 2, 1);
+            if (lpr == 4) FLP_SEG(double, 4, 1);
+            if (lpr == 8) FLP_SEG(double, 8, 1);
+            if (lpr == 16) FLP_SEG(double, 16, 1);
+            if (lpr == 32) FLP_SEG(double, 32, 1);
+        }
+    } else {
+        FLP_SHAPES_F32(FLP_SEG32)
+        if (vec == 1) {
+            if (lpr == 1) FLP_SEG(float, 1, 1);
+            if (lpr == 2) FLP_SEG(float, 2, 1);
+            if (lpr == 4) FLP_SEG(float, 4, 1);
+            if (lpr == 8) FLP_SEG(float, 8, 1);
+            if (lpr == 16) FLP_SEG(float, 16, 1);
+            if (lpr == 32) FLP_SEG(float, 32, 1);
+        }
+    }
+#undef FLP_SEG64
+#undef FLP_SEG32
 #undef FLP_SEG
     return hipErrorInvalidValue;
 }

@@ -63,19 +63,19 @@ size_t footprint(const flp_csr &A, const flp_opts &o) {
 
 void worker_main(flp_server *sv) {
     (void)hipSetDevice(sv->device);
-    std::vector<Job *> finished;
     for (;;) {
         std::vector<Job *> admit;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty() || !sv->eng.active.empty(); });
             if (sv->stop && sv->pending.empty() && sv->eng.active.empty()) break;
-            // admission: free engine slots and device memory
+            // admission: free engine slots and device memory (memory comes
+            // back when the finisher releases a solve's buffers)
             while (!sv->pending.empty() &&
                    (int)(sv->eng.active.size() + admit.size()) < sv->o.max_active) {
                 Job *j = sv->pending.front();
                 if (sv->mem_in_use + j->footprint > sv->mem_budget &&
-                    !(sv->eng.active.empty() && admit.empty()))
+                    !(sv->eng.active.empty() && admit.empty() && sv->mem_in_use == 0))
                     break;  // wait for memory (a lone request is always admitted)
                 sv->pending.pop_front();
                 sv->mem_in_use += j->footprint;
@@ -94,41 +94,49 @@ void worker_main(flp_server *sv) {
                 j->msg = last_error_cstr();
                 j->B.reset();
                 j->t_done = now();
-                finished.push_back(j);
+                sv->eng.on_done(j);
             }
         }
         if (!sv->eng.active.empty()) {
-            const int rc = sv->eng.step(finished);
+            const int rc = sv->eng.step();
             if (rc != FLP_OK) {
                 // a device failure ends every active request
-                std::lock_guard<std::mutex> lk(sv->mu);
-                sv->fatal = rc;
-                sv->fatal_msg = last_error_cstr();
-                for (Job *j : sv->eng.active) {
-                    j->code = rc;
-                    j->msg = sv->fatal_msg;
-                    j->t_done = now();
-                    finished.push_back(j);
+                std::string msg = last_error_cstr();
+                {
+                    std::lock_guard<std::mutex> lk(sv->mu);
+                    sv->fatal = rc;
+                    sv->fatal_msg = msg;
                 }
-                sv->eng.active.clear();
+                std::vector<Job *> act;
+                act.swap(sv->eng.active);
+                for (Job *j : act) {
+                    j->code = rc;
+                    j->msg = msg;
+                    j->t_done = now();
+                    j->B.reset();
+                    sv->eng.on_done(j);
+                }
             }
         }
+        const flp_batch_stats st = sv->eng.snapshot();
         {
             std::lock_guard<std::mutex> lk(sv->mu);
-            sv->snapshot = sv->eng.stats;
+            sv->snapshot = st;
             sv->snapshot.solves = (int32_t)sv->submitted;
         }
-        if (!finished.empty()) {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            for (Job *j : finished) {
-                sv->mem_in_use -= std::min(sv->mem_in_use, j->footprint);
-                if (j->res) j->res->stats.t_total = j->t_done - j->t_submit;  // request latency
-                j->footprint = 0;
-            }
-            finished.clear();
-            sv->cv_done.notify_all();
-        }
     }
+}
+
+// Completion of a request (stepping or finisher thread): memory returns to
+// the admission budget, waiters are woken.
+void on_job_done(flp_server *sv, Job *j) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->mem_in_use -= std::min(sv->mem_in_use, j->footprint);
+    if (j->res) j->res->stats.t_total = j->t_done - j->t_submit;  // request latency
+    j->footprint = 0;
+    j->finished = true;
+    sv->cv_done.notify_all();
+    sv->cv_work.notify_one();
 }
 
 int take_result(flp_server *sv, std::map<uint64_t, std::unique_ptr<Job>>::iterator it, flp_result **out) {
@@ -178,6 +186,7 @@ int flp_server_create(const flp_server_opts *opts, flp_server **out) {
         }
         CKR(sv->eng.init(o.block, o.prec, o.use_graph != 0));
         flp_server *p = sv.get();
+        p->eng.on_done = [p](Job *j) { on_job_done(p, j); };
         p->worker = std::thread(worker_main, p);
         *out = sv.release();
         return FLP_OK;
@@ -231,7 +240,7 @@ int flp_server_poll(flp_server *sv, uint64_t ticket, flp_result **out) {
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->jobs.find(ticket);
     if (it == sv->jobs.end()) return fail(FLP_E_ARG, "unknown ticket");
-    if (it->second->t_done == 0.0) return FLP_E_PENDING;
+    if (!it->second->finished) return FLP_E_PENDING;
     return take_result(sv, it, out);
 }
 
@@ -242,7 +251,7 @@ int flp_server_wait(flp_server *sv, uint64_t ticket, flp_result **out) {
     auto it = sv->jobs.find(ticket);
     if (it == sv->jobs.end()) return fail(FLP_E_ARG, "unknown ticket");
     Job *j = it->second.get();
-    sv->cv_done.wait(lk, [&] { return j->t_done != 0.0; });
+    sv->cv_done.wait(lk, [&] { return j->finished; });
     return take_result(sv, it, out);
 }
 
@@ -261,6 +270,7 @@ int flp_server_destroy(flp_server *sv) {
         sv->cv_work.notify_all();
     }
     if (sv->worker.joinable()) sv->worker.join();
+    sv->eng.wait_finisher();
     for (auto &kv : sv->jobs)
         if (kv.second->res) flp_result_free(kv.second->res);
     const int rc = sv->fatal;

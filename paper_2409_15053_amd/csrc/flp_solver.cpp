@@ -7,9 +7,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <thread>
 #include <vector>
 
 #include "flp_host.h"
@@ -113,6 +115,7 @@ int solve_setup(Solve &S) {
 }
 
 Solve::~Solve() {
+    // a check still in flight owns its snapshot (shared with the pool task)
     if (pin) (void)hipHostFree(pin);
 }
 
@@ -194,53 +197,112 @@ bool at_check(const Solve &S) {
     return S.steps % S.check_every == 0 || S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n;
 }
 
-int step_check_host(Solve &S) {
-    if (!at_check(S) || S.checked_step == S.steps) return FLP_OK;
-    S.checked_step = S.steps;
-    const int r = S.r;
-    const bool last = S.steps == S.max_steps || (int64_t)(S.steps + 1) * r > S.n;
-    // convergence check on the Ritz values of T_k (Section 3.2.2)
-    const double tc = now();
-    const int K = S.steps * r;
-    std::vector<double> T;
-    assemble_T(S, S.steps, T);
+namespace {
+bool at_last(const Solve &S) { return S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n; }
+}  // namespace
+
+void run_check(CheckTask &c) {
+    const double t0 = now();
+    const int K = c.K, r = c.r;
     std::vector<double> theta(K);
     std::vector<int> rows(r);
     for (int i = 0; i < r; ++i) rows[i] = K - r + i;
     std::vector<double> Zl((size_t)r * K);
-    if (sym_eig_keep(K, r, T.data(), theta.data(), rows.data(), r, Zl.data(), &S.eig) != 0)
-        return fail(FLP_E_DEVICE, "eigensolver for T_k did not converge");
-    // rho_i = || S_k E_k^T w_i ||
+    if (sym_eig_keep(K, r, c.T.data(), theta.data(), rows.data(), r, Zl.data(), &c.eig) != 0) {
+        c.rc = FLP_E_DEVICE;
+        c.msg = "eigensolver for T_k did not converge";
+        c.secs = now() - t0;
+        c.ready.store(true);
+        return;
+    }
+    // rho_i = || S_k E_k^T w_i ||; candidates theta_i >= tau
     double big = 1e-300;
     for (double t : theta) big = std::max(big, std::fabs(t));
-    S.cand.clear();
-    bool ok = true;
+    c.ok = true;
     for (int i = 0; i < K; ++i) {
-        if (theta[i] < S.tau) continue;
-        S.cand.push_back(i);
+        if (theta[i] < c.tau) continue;
+        c.cand.push_back(i);
         double rho2 = 0.0;
         for (int a = 0; a < r; ++a) {
             double t = 0.0;
-            for (int b = 0; b < r; ++b) t += S.Sj[a * r + b] * Zl[(size_t)b * K + i];
+            for (int b = 0; b < r; ++b) t += c.Sk[a * r + b] * Zl[(size_t)b * K + i];
             rho2 += t * t;
         }
-        if (std::sqrt(rho2) > S.tol_p * big) ok = false;
+        if (std::sqrt(rho2) > c.tol_p * big) c.ok = false;
     }
-    S.st.t_check += now() - tc;
-    if ((ok && (int)S.cand.size() == S.prev_count) || last) {
-        S.converged = ok && (int)S.cand.size() == S.prev_count;
-        S.kfinal = K;
+    if (c.fp32) {
+        // Guards for the FP64 polish: subspace iteration with p damps an
+        // error component along eigenvalue mu by |p(mu)| / p(lambda) per
+        // sweep, and that ratio nears 1/2 at the interval ends if the
+        // transition band next to the candidates is left out.  With every
+        // Ritz value down to |theta| >= tau / 4 included (the largest |theta|
+        // first, at most half the candidate count and at least 2r of them),
+        // the excluded part has |p| < tau / 4 and each sweep gains 8x.
+        std::vector<int> g;
+        for (int i = 0; i < K; ++i)
+            if (theta[i] < c.tau && std::fabs(theta[i]) >= 0.25 * c.tau) g.push_back(i);
+        std::sort(g.begin(), g.end(), [&](int a, int b) { return std::fabs(theta[a]) > std::fabs(theta[b]); });
+        const size_t cap = std::max<size_t>(c.cand.size() / 2, 2 * (size_t)r);
+        if (g.size() > cap) g.resize(cap);
+        std::sort(g.begin(), g.end());
+        c.guard = g;
+    }
+    c.secs = now() - t0;
+    c.ready.store(true);
+}
+
+int wait_check(Solve &S) {
+    if (!S.check) return FLP_OK;
+    std::shared_ptr<CheckTask> c = std::move(S.check);
+    S.check.reset();
+    while (!c->ready.load()) std::this_thread::sleep_for(std::chrono::microseconds(50));
+    S.st.t_check += c->secs;
+    if (c->rc != FLP_OK) return fail(c->rc, c->msg);
+    // stop rule: every candidate converged and the candidate count unchanged
+    // since the previous check, or no room left in the basis
+    const int cnt = (int)c->cand.size();
+    if ((c->ok && cnt == S.prev_count) || S.check_last) {
+        S.converged = c->ok && cnt == S.prev_count;
+        S.kfinal = c->K;
         S.done = true;
+        S.cand = std::move(c->cand);
+        S.guard = std::move(c->guard);
+        S.eig = std::move(c->eig);
         return FLP_OK;
     }
-    S.prev_count = (int)S.cand.size();
-    S.eig.clear();
+    S.prev_count = cnt;
     return FLP_OK;
 }
 
-int step_check(Solve &S) {
-    CKR(step_check_host(S));
-    if (S.done) return FLP_OK;
+int step_check(Solve &S, bool async) {
+    // a check that has finished in the background is applied first
+    if (S.check && S.check->ready.load()) {
+        CKR(wait_check(S));
+        if (S.done) return FLP_OK;
+    }
+    if (at_check(S) && S.checked_step != S.steps) {
+        // checks apply in order: one still running is waited for
+        CKR(wait_check(S));
+        if (S.done) return FLP_OK;
+        S.checked_step = S.steps;
+        auto c = std::make_shared<CheckTask>();
+        c->K = S.steps * S.r;
+        c->r = S.r;
+        c->tau = S.tau;
+        c->tol_p = S.tol_p;
+        c->fp32 = S.o.prec == FLP_PREC_FP32_FILTER;
+        assemble_T(S, S.steps, c->T);
+        c->Sk = S.Sj;
+        S.check = c;
+        S.check_last = at_last(S);
+        if (async && !S.check_last) {
+            host_pool_submit([c]() { run_check(*c); });
+        } else {
+            run_check(*c);
+            CKR(wait_check(S));
+            if (S.done) return FLP_OK;
+        }
+    }
     // the new block joins the basis and is the next filter input
     const int n = S.n, r = S.r, k = S.steps * r;
     CK(launch_copy_block(n, r, 1.0, S.W, r, S.Q, k, nullptr, 0, S.s));
@@ -276,15 +338,17 @@ int solve_finish(Solve &S, flp_result **out) {
     std::unique_ptr<flp_result, void (*)(flp_result *)> guard(res, flp_result_free);
     S.st.iters = S.steps;
     S.st.basis_cols = S.kfinal;
-    const int c = (int)S.cand.size();
+    std::vector<int> sel = S.cand;
+    sel.insert(sel.end(), S.guard.begin(), S.guard.end());
+    const int c = S.cand.empty() ? 0 : (int)sel.size();
     if (c > 0) {
         const int K = S.kfinal;
-        // eigenvectors of T_k for the candidates (eq. proj), from the rotation
-        // log the last convergence check kept
+        // eigenvectors of T_k for the candidates (eq. proj) and guards, from
+        // the rotation log the last convergence check kept
         std::vector<double> Zc((size_t)K * c);
         const double tc = now();
         if (S.eig.N != K) return fail(FLP_E_DEVICE, "internal: no eigen-decomposition of the final T_k");
-        eig_log_cols(S.eig, S.cand.data(), c, Zc.data());
+        eig_log_cols(S.eig, sel.data(), c, Zc.data());
         S.eig.clear();
         S.st.t_check += now() - tc;
         const int ldc = (c + 1) & ~1;
@@ -318,7 +382,7 @@ int solve_finish(Solve &S, flp_result **out) {
         int i0 = 0, i1 = 0;
         if (S.o.prec == FLP_PREC_FP32_FILTER) {
             // FP64 polish: X <- p(A) X, orthonormalise, Rayleigh-Ritz with A
-            while (worst(i0, i1) > tol && S.st.polish_sweeps < 3) {
+            while (worst(i0, i1) > tol && S.st.polish_sweeps < kMaxPolish) {
                 for (int j0 = 0; j0 < c; j0 += 16) {
                     const int cw = std::min(16, c - j0);
                     CKR(filter_apply_impl(S.filt.get(), A, X + j0, ldc, Y + j0, ldc, cw, FLP_PREC_FP64, s));
@@ -357,7 +421,7 @@ int solve_finish(Solve &S, flp_result **out) {
 
 namespace {
 SolveBufs &single_bufs() {
-    static SolveBufs b[64];
+    static thread_local SolveBufs b[64];
     int dev = 0;
     (void)hipGetDevice(&dev);
     return b[dev & 63];
@@ -382,18 +446,22 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     S.B = &single_bufs();
     CKR(solve_setup(S));
     const bool fp32 = o.prec == FLP_PREC_FP32_FILTER;
-    // filter in cache-sized column groups (the plan is rebuilt for the group width)
-    const int gw = filter_group_width(S.n, A->nnz, S.r, o.prec);
-    std::vector<ClenshawStep> plan;
-    for (int j0 = 0; j0 < S.r; j0 += gw) {
-        const void *vg = fp32 ? (const void *)(S.V32 + j0) : (const void *)(S.Vin + j0);
-        if (gw != S.r) {
-            // group scratch: the U buffers hold n x r, enough for n x gw
-            auto g = clenshaw_plan(S.filt.get(), gw, vg, S.r, S.W + j0, S.r, S.U[0], S.U[1], S.U[2], fp32);
-            plan.insert(plan.end(), g.begin(), g.end());
-        }
+    // filter in cache-sized column groups (the plan is rebuilt for the group
+    // width); each group of the input block is first staged as a contiguous
+    // n x gw block in the unused tail of the first recurrence buffer, so the
+    // V reads of every step touch only that group's bytes
+    FilterTune tn;
+    void *U[3] = {S.U[0], S.U[1], S.U[2]};
+    CKR(tune_filter(A, S.val32, S.r, fp32, true, U, fp32 ? (const void *)S.V32 : (const void *)S.Vin, S.r, S.s,
+                    &tn));
+    const int gw = tn.gw;
+    std::vector<ClenshawStep> gplan;
+    void *stage = nullptr;
+    if (gw != S.r) {
+        const size_t es = fp32 ? sizeof(float) : sizeof(double);
+        stage = (char *)S.U[0] + es * (size_t)S.n * gw;  // U buffers hold n x r >= 2 n x gw
+        gplan = clenshaw_plan(S.filt.get(), gw, stage, gw, S.W, S.r, S.U[0], S.U[1], S.U[2], fp32);
     }
-    if (gw == S.r) plan = S.plan;
     hipEvent_t ev[2];
     for (auto &e : ev) CK(hipEventCreate(&e));
     struct EvGuard {
@@ -405,7 +473,22 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     } evg{ev};
     while (!S.done) {
         CK(hipEventRecord(ev[0], S.s));
-        for (const auto &st : plan) CKR(launch_plan_step(A, S.val32, gw, st, fp32, S.s));
+        if (gw == S.r) {
+            for (const auto &st : S.plan) CKR(launch_plan_step(A, S.val32, S.r, st, fp32, S.s, tn.sh));
+        } else {
+            for (int j0 = 0; j0 < S.r; j0 += gw) {
+                if (fp32)
+                    CK(launch_copy_block(S.n, gw, 1.0, S.Vin + j0, S.r, DMat{nullptr, 0, 0, 0}, 0, (float *)stage,
+                                         gw, S.s));
+                else
+                    CK(launch_copy_block(S.n, gw, 1.0, S.Vin + j0, S.r, plain_mat((double *)stage, gw), 0,
+                                         nullptr, 0, S.s));
+                for (ClenshawStep st : gplan) {
+                    if (st.out == (void *)S.W) st.out = S.W + j0;  // the last step writes the group's columns of W
+                    CKR(launch_plan_step(A, S.val32, gw, st, fp32, S.s, tn.sh));
+                }
+            }
+        }
         CK(hipEventRecord(ev[1], S.s));
         CK(hipEventSynchronize(ev[1]));
         float ms = 0;

@@ -1,0 +1,167 @@
+// Autotuner for the filter step.
+//
+// The Clenshaw step is a CSR SpMM whose best launch shape depends on the
+// matrix (row length, n) and on how much of the step's working set stays in
+// the 256 MB Infinity Cache between steps.  Two choices are tuned:
+//   * the shape: lanes per matrix row and columns per lane, i.e. rows per
+//     wavefront (64 / lanes) and bytes gathered per lane per nonzero;
+//   * the column-group width of a single solve's filter: the block of r
+//     columns can be filtered as r / gw independent groups of gw columns,
+//     which re-reads the matrix per group but can keep a group's whole
+//     recurrence resident in the cache.
+// Each candidate is timed on the caller's matrix over a ring of six steps
+// (the pattern of the real recurrence: gather one buffer, read V and a
+// second buffer, write the third), after one untimed ring.  Results are cached
+// per (device, precision, r, n, nnz, grouping allowed).  Every shape and
+// width computes each output element with the same operations in the same
+// order, so tuning never changes results, only speed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "flp_host.h"
+
+namespace flp {
+
+namespace {
+
+std::atomic<int> g_mode{1};  // 1: tune on first use, 0: fixed defaults
+std::mutex g_mu;
+StepShape g_force_shape{};
+int g_force_gw = 0;
+
+using Key = std::tuple<int, int, int, int64_t, int64_t, int>;
+std::map<Key, FilterTune> &cache() {
+    static std::map<Key, FilterTune> c;
+    return c;
+}
+
+// Launches one ring of `steps` filter steps over gw columns with the given
+// shape; buffers hold n x gw (row-major, ld gw) elements of the filter type.
+int ring(const flp_csr *A, const float *val32, bool fp32, int gw, StepShape sh, void *const U[3], const void *V,
+         int ldv, int steps, hipStream_t s) {
+    for (int j = 0; j < steps; ++j) {
+        ClenshawStep st{};
+        st.X = U[j % 3];
+        st.ldx = gw;
+        st.V = V;
+        st.ldv = ldv;
+        st.Y = U[(j + 2) % 3];
+        st.ldy = gw;
+        st.out = U[(j + 1) % 3];
+        st.ldo = gw;
+        st.out_f64 = !fp32;
+        st.alpha = 2.0;
+        st.beta = -1.0;
+        st.gamma = 0.5;
+        st.delta = -1.0;
+        CKR(launch_plan_step(A, val32, gw, st, fp32, s, sh));
+    }
+    return FLP_OK;
+}
+
+}  // namespace
+
+void set_autotune(int mode) { g_mode.store(mode ? 1 : 0); }
+int autotune_mode() { return g_mode.load(); }
+
+void force_filter_shape(StepShape sh, int gw) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force_shape = sh;
+    g_force_gw = gw;
+}
+
+int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
+                const void *V, int ldv, hipStream_t s, FilterTune *out) {
+    const int n = A->n;
+    FilterTune def;
+    def.gw = allow_groups ? filter_group_width(n, A->nnz, r, fp32 ? FLP_PREC_FP32_FILTER : FLP_PREC_FP64) : r;
+    def.sh = default_step_shape(def.gw, fp32);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_force_shape.lpr > 0 || g_force_gw > 0) {
+            FilterTune f = def;
+            if (g_force_gw > 0 && r % g_force_gw == 0 && (allow_groups || g_force_gw == r)) f.gw = g_force_gw;
+            f.sh = step_shape_ok(f.gw, fp32, g_force_shape) ? g_force_shape : default_step_shape(f.gw, fp32);
+            *out = f;
+            return FLP_OK;
+        }
+    }
+    if (g_mode.load() == 0) {
+        *out = def;
+        return FLP_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    CK(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) {  // never time inside a capture
+        *out = def;
+        return FLP_OK;
+    }
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    const Key key{dev, fp32 ? 1 : 0, r, (int64_t)n, A->nnz, allow_groups ? 1 : 0};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = cache().find(key);
+        if (it != cache().end()) {
+            *out = it->second;
+            return FLP_OK;
+        }
+    }
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    // the ring starts from zeros so every candidate sees the same data
+    for (int i = 0; i < 3; ++i) CK(hipMemsetAsync(U[i], 0, es * (size_t)n * r, s));
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    struct G {
+        hipEvent_t a, b;
+        ~G() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    constexpr int kSteps = 6;
+    FilterTune best = def;
+    best.us_per_step = 1e300;
+    int tried = 0;
+    for (int gw = r; gw >= 1; gw /= 2) {
+        if (r % gw != 0 || (gw != r && !allow_groups)) continue;
+        for (StepShape sh : step_shape_candidates(gw, fp32)) {
+            // V: the caller's block (gw == r) or a contiguous n x gw group,
+            // taken from the unused half of the first buffer
+            const void *Vg = gw == r ? V : (const void *)((const char *)U[0] + es * (size_t)n * gw);
+            const int ldvg = gw == r ? ldv : gw;
+            if (gw != r && gw > r / 2) continue;
+            CKR(ring(A, val32, fp32, gw, sh, U, Vg, ldvg, kSteps, s));  // warm-up
+            CK(hipEventRecord(e0, s));
+            CKR(ring(A, val32, fp32, gw, sh, U, Vg, ldvg, kSteps, s));
+            CK(hipEventRecord(e1, s));
+            CK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            CK(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / kSteps * (r / gw);  // all r columns
+            ++tried;
+            if (us < best.us_per_step) {
+                best.gw = gw;
+                best.sh = sh;
+                best.us_per_step = us;
+            }
+        }
+    }
+    if (tried == 0) best = def;
+    best.candidates = tried;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        cache()[key] = best;
+    }
+    *out = best;
+    return FLP_OK;
+}
+
+}  // namespace flp

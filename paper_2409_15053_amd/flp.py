@@ -28,7 +28,7 @@ FLP_PREC_FP32_FILTER = 1
 EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
     "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval",
-    "flp_filter_apply", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
+    "flp_filter_apply", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_last_error", "flp_version",
     "flp_server_opts_default", "flp_server_create", "flp_server_submit", "flp_server_poll",
@@ -45,6 +45,12 @@ class FlpError(RuntimeError):
 class FlpCsrC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
                 ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val32", ctypes.c_void_p)]
+
+
+class FlpTuneInfoC(ctypes.Structure):
+    _fields_ = [("group_width", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
+                ("cols_per_lane", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("us_per_step", ctypes.c_double)]
 
 
 class FlpOptsC(ctypes.Structure):
@@ -106,6 +112,9 @@ def load(path: str = LIB_PATH):
         "flp_filter_info": (ctypes.c_int, [P, P]),
         "flp_filter_eval": (ctypes.c_int, [P, P, P, I32]),
         "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, P, I32, I32, P]),
+        "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, P, ctypes.POINTER(FlpTuneInfoC)]),
+        "flp_set_autotune": (None, [I32]),
+        "flp_set_filter_shape": (None, [I32, I32, I32]),
         "flp_spmm": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), P, I32, P, I32, I32, P]),
         "flp_block_orth": (ctypes.c_int, [P, I64, I32, I32, P, I32, P, P]),
         "flp_block_qr": (ctypes.c_int, [P, I32, I32, P, P]),
@@ -227,6 +236,22 @@ def flp_filter_apply(filt: Filter, A: DeviceCsr, V, W, prec: int = FLP_PREC_FP64
     r = 1 if V.dim() == 1 else V.shape[1]
     _check(load().flp_filter_apply(filt.h, ctypes.byref(A.c), V.data_ptr(), W.data_ptr(), r, prec,
                                    _stream_ptr(stream)))
+
+
+def flp_tune_filter(A: DeviceCsr, r: int, prec: int = FLP_PREC_FP64, stream=None) -> dict:
+    """The filter launch configuration for r columns of A (tuned on first use)."""
+    info = FlpTuneInfoC()
+    _check(load().flp_tune_filter(ctypes.byref(A.c), r, prec, _stream_ptr(stream), ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in FlpTuneInfoC._fields_}
+
+
+def flp_set_autotune(on: bool):
+    load().flp_set_autotune(1 if on else 0)
+
+
+def flp_set_filter_shape(lanes_per_row: int = 0, cols_per_lane: int = 0, group_width: int = 0):
+    """Force one filter launch configuration (all zeros: back to tuning)."""
+    load().flp_set_filter_shape(lanes_per_row, cols_per_lane, group_width)
 
 
 def flp_spmm(A: DeviceCsr, X, Y, stream=None):

@@ -84,7 +84,7 @@ def test_solve_rejects_bad_csr_without_gpu():
     assert lib.flp_solve(ctypes.byref(A), 0.0, 1.0, None, ctypes.byref(res)) == flp.FLP_E_ARG
 
 
-@pytest.mark.parametrize("N,bw", [(1, 0), (2, 1), (7, 1), (60, 1), (60, 3), (97, 8), (120, 16), (80, 79)])
+@pytest.mark.parametrize("N,bw", [(1, 0), (2, 1), (7, 1), (60, 1), (60, 3), (97, 8), (120, 16), (80, 79), (257, 40), (300, 299)])
 def test_host_banded_eigensolver_against_lapack(N, bw):
     g = np.random.Generator(np.random.PCG64(N * 100 + bw))
     M = g.standard_normal((N, N))
@@ -97,6 +97,21 @@ def test_host_banded_eigensolver_against_lapack(N, bw):
     assert np.max(np.abs(ev - w)) < 1e-13 * scale * max(1, N) ** 0.5
     assert np.max(np.abs(M @ Z - Z * ev)) < 1e-12 * scale * max(1, N) ** 0.5
     assert np.max(np.abs(Z.T @ Z - np.eye(N))) < 1e-12 * max(1, N) ** 0.5
+
+
+def test_host_dense_eigensolver_multiplicities():
+    # the dense (Householder) path on a Rayleigh-Ritz-like matrix: exact
+    # multiplicities, a 1e-13 cluster and a zero block
+    g = np.random.Generator(np.random.PCG64(11))
+    d = np.concatenate([np.full(40, 0.5), np.full(3, 2.0), [2.0 + 1e-13], g.uniform(-1, 3, 150), np.zeros(7)])
+    N = d.size
+    Qr, _ = np.linalg.qr(g.standard_normal((N, N)))
+    M = (Qr * d) @ Qr.T
+    M = 0.5 * (M + M.T)
+    ev, Z = flp.flp_host_sym_eig(M)
+    assert np.max(np.abs(ev - np.sort(d))) < 1e-13 * N
+    assert np.max(np.abs(Z.T @ Z - np.eye(N))) < 1e-13 * N
+    assert np.max(np.abs(M @ Z - Z * ev)) < 1e-13 * N
 
 
 def test_host_eigensolver_degenerate_and_clustered():

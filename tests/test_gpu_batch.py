@@ -94,3 +94,26 @@ def test_graph_replay_matches_eager(torch):
         assert a["count"] == b["count"]
         assert np.array_equal(a["evals"], b["evals"])
         assert np.array_equal(a["resid"], b["resid"])
+
+
+def test_tuned_segmented_shape_matches_default(torch):
+    """The batched engine tunes the segmented launch's shape on the largest
+    active matrix; the tuned and the default shapes give the same bits."""
+    cases = small_family([9, 12, 14], 1300, [10, 16, 20])
+    dAs = [flp.DeviceCsr.from_host(A, with_fp32=True) for A, *_ in cases]
+    args = ([c[1] for c in cases], [c[2] for c in cases])
+    for prec in (flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER):
+        try:
+            flp.flp_set_autotune(False)
+            r0, _ = flp.flp_solve_batch(dAs, *args, block=8, seeds=[4, 5, 6], prec=prec)
+            flp.flp_set_autotune(True)
+            flp.flp_set_filter_shape(1, 8, 0)  # a non-default shape for every launch
+            r1, _ = flp.flp_solve_batch(dAs, *args, block=8, seeds=[4, 5, 6], prec=prec)
+            flp.flp_set_filter_shape(0, 0, 0)
+            r2, _ = flp.flp_solve_batch(dAs, *args, block=8, seeds=[4, 5, 6], prec=prec)
+        finally:
+            flp.flp_set_filter_shape(0, 0, 0)
+            flp.flp_set_autotune(True)
+        for a, b, c in zip(r0, r1, r2):
+            assert a["count"] == b["count"] == c["count"]
+            assert np.array_equal(a["evals"], b["evals"]) and np.array_equal(a["evals"], c["evals"])

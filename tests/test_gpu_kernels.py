@@ -144,6 +144,60 @@ def test_filter_apply_ragged_large_grid(torch):
     assert np.max(np.abs(W.cpu().numpy() - want)) <= tol
 
 
+SHAPE_CASES = {
+    # (r, prec): forced (lanes per row, columns per lane, group width) configurations
+    (8, flp.FLP_PREC_FP64): [(4, 2, 8), (2, 4, 8), (1, 8, 8), (2, 2, 4), (1, 4, 4), (1, 2, 2)],
+    (16, flp.FLP_PREC_FP64): [(8, 2, 16), (4, 4, 16), (2, 8, 16), (4, 2, 8), (2, 4, 8), (1, 8, 8)],
+    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8), (1, 8, 8), (1, 4, 4)],
+    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16), (2, 8, 16), (2, 4, 8), (1, 8, 8)],
+}
+
+
+@pytest.mark.parametrize("r,prec", list(SHAPE_CASES))
+def test_filter_launch_shapes_bit_identical(torch, r, prec):
+    """Every launch configuration the autotuner may pick (rows per
+    wavefront, columns per lane, column-group width) sums each output element
+    in the same order: all of them give the same bits, and that result is
+    within the parity bound of the oracle."""
+    A = I.laplacian_3d_13pt(23, I.gaussian_wells(23, 7))  # n = 12167: ragged last tile
+    lmin, lmax = O.gershgorin(A)
+    f, b, V, lmin, lmax = filter_case(A, -3.0, -1.0, 12, r, seed=r + prec)
+    dA = flp.DeviceCsr.from_host(A)
+    Vd = dev(torch, V)
+    outs = []
+    try:
+        flp.flp_set_autotune(False)
+        W0 = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+        flp.flp_filter_apply(f, dA, Vd, W0, prec=prec)
+        for lpr, vec, gw in SHAPE_CASES[(r, prec)]:
+            flp.flp_set_filter_shape(lpr, vec, gw)
+            W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+            flp.flp_filter_apply(f, dA, Vd, W, prec=prec)
+            outs.append(((lpr, vec, gw), W))
+        flp.flp_set_filter_shape(0, 0, 0)
+        flp.flp_set_autotune(True)
+        info = flp.flp_tune_filter(dA, r, prec)
+        assert info["candidates"] >= 2 and info["us_per_step"] > 0
+        assert r % info["group_width"] == 0
+        assert info["lanes_per_row"] * info["cols_per_lane"] == info["group_width"]
+        Wt = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+        flp.flp_filter_apply(f, dA, Vd, Wt, prec=prec)
+        outs.append(("tuned", Wt))
+    finally:
+        flp.flp_set_filter_shape(0, 0, 0)
+        flp.flp_set_autotune(True)
+    torch.cuda.synchronize()
+    for cfg, W in outs:
+        assert torch.equal(W, W0), cfg
+    want = O.filter_apply(A, lmin, lmax, b, V)
+    k = max_row_nnz(A)
+    if prec == flp.FLP_PREC_FP64:
+        tol = 2 * 12 * 12 * (k + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    else:
+        tol = 2 * 12 * (k + 4) * U32 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    assert np.max(np.abs(W0.cpu().numpy() - want)) <= tol
+
+
 def test_filter_apply_errors(torch):
     A = I.laplacian_2d(5)
     dA = flp.DeviceCsr.from_host(A)
