@@ -89,8 +89,10 @@ typedef struct flp_opts {
 } flp_opts;
 
 typedef struct flp_stats {
-    int32_t iters;         /* block Lanczos steps (the paper's "iters") */
-    int64_t mv;            /* products with A inside the filter: r * m * iters */
+    int32_t iters;         /* block Lanczos steps behind the result (the paper's "iters") */
+    int64_t mv;            /* products with A inside the filter: r * m * (block steps taken),
+                              which may exceed r * m * iters by the few steps taken while
+                              the deciding convergence check ran on the host */
     int32_t basis_cols;    /* Lanczos basis columns at convergence */
     int32_t polish_sweeps; /* FP64 refinement sweeps (FP32 filter only) */
     double t_pre;          /* seconds: spectrum bounds (the paper's PREPROC) */
@@ -236,6 +238,26 @@ int flp_estimate_bounds(const flp_csr *A, int32_t k0, uint64_t seed, double *lmi
  * FLP_E_NOCONV, FLP_E_DEVICE. */
 int flp_solve(const flp_csr *A, double alpha, double beta, const flp_opts *opts,
               flp_result **out);
+
+/* Spectrum slicing on one GPU (Section 5 names slicing as the route to
+ * several devices): [alpha, beta] (clamped to the spectrum bounds, which
+ * are estimated once unless opts gives them) is cut into nslices
+ * sub-intervals of equal width in the angle acos((lambda - c) / e) of the
+ * mapped spectrum, so the degree rule gives each slice the same degree;
+ * each slice is an independent filtered Lanczos solve on A (seed
+ * opts->seed + i * 0x9E3779B97F4A7C15) and all of them advance together as
+ * one batch (flp_solve_batch).  The merged result holds every eigenpair in
+ * [alpha, beta] in ascending order: slice i contributes its eigenvalues below
+ * its upper end (the last slice up to beta), and an eigenpair found by both
+ * slices at a boundary (eigenvalues equal to 1e-8 ||A||, eigenvectors
+ * overlapping by more than 1/2) is kept once.  stats: work summed over the
+ * slices (mv, basis_cols, filter_bytes, t_orth, t_check, t_rr), iters and
+ * polish_sweeps the largest slice's, t_mv the shared filter launches' time.
+ *   nslices: 1 <= nslices <= 256.
+ * Synchronous.  Errors as flp_solve, plus FLP_E_ARG for a bad nslices or an
+ * interval too narrow to slice. */
+int flp_solve_sliced(const flp_csr *A, double alpha, double beta, int32_t nslices,
+                     const flp_opts *opts, flp_result **out);
 void flp_result_free(flp_result *res);
 /* Copy the result's eigenvectors (count x n doubles, column-major) into the
  * DEVICE buffer dst; stream-ordered (NULL = default stream). */

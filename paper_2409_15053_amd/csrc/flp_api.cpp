@@ -183,6 +183,23 @@ int flp_solve(const flp_csr *A, double alpha, double beta, const flp_opts *opts,
     }
 }
 
+int flp_solve_sliced(const flp_csr *A, double alpha, double beta, int32_t nslices, const flp_opts *opts,
+                     flp_result **out) {
+    if (!out) return fail(FLP_E_ARG, "out is NULL");
+    *out = nullptr;
+    CKR(check_csr(A));
+    flp_opts o;
+    flp_opts_default(&o);
+    if (opts) o = *opts;
+    try {
+        return solve_sliced_impl(A, alpha, beta, nslices, o, out);
+    } catch (const std::bad_alloc &) {
+        return fail(FLP_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(FLP_E_DEVICE, "unexpected exception");
+    }
+}
+
 void flp_result_free(flp_result *res) {
     if (!res) return;
     delete[] res->evals;

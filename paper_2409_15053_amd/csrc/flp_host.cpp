@@ -88,7 +88,7 @@ struct HostPool {
     bool stop = false;
     HostPool() {
         const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-        const int nw = std::max(1, std::min(8, hw / 2));
+        const int nw = std::max(2, std::min(16, hw / 2));
         for (int i = 0; i < nw; ++i)
             th.emplace_back([this, hw, nw]() {
                 set_eig_threads(std::max(1, std::min(16, hw) / nw));

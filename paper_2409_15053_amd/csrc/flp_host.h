@@ -39,6 +39,7 @@ constexpr int kMaxDegree = 100000;
 constexpr int64_t kDefaultMaxBasis = 3072;
 constexpr int kPanelLog2 = 7;  // Lanczos basis panels of 128 columns
 constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
+constexpr int kMaxSpeculative = 2;  // block steps a solve may take past a convergence check in flight
 
 int fail(int code, const std::string &msg);
 const char *last_error_cstr();
@@ -342,6 +343,8 @@ struct Engine {
 int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out);
 int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, const double *beta,
                      const flp_opts *opts, int use_graph, flp_result **results, int *codes, flp_batch_stats *bs);
+int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, const flp_opts &o,
+                      flp_result **out);
 void release_single_bufs();
 
 }  // namespace flp

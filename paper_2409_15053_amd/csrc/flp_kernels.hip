@@ -114,6 +114,41 @@ __device__ __forceinline__ void store_vec(T *p, const T (&v)[VEC]) {
 
 // ------------------------------------------------------------------ filter step
 //
+// acc += sum over the row's nonzeros p0..p1-1 of val[p] * X[colind[p], c0 ..
+// c0 + VEC), in order.  The nonzeros go in groups of UNR with every load of
+// a group issued before its products: a slot past the row's end re-reads the
+// row's last entry (a valid, cached address) with weight zero, so a short row
+// costs one round of dependent loads instead of one per leftover nonzero.
+template <typename T, int VEC, int UNR>
+__device__ __forceinline__ void row_gather(int p0, int p1, const int32_t *__restrict__ colind,
+                                           const T *__restrict__ val, const T *__restrict__ X, int ldx, int c0,
+                                           T (&acc)[VEC]) {
+    for (int p = p0; p < p1; p += UNR) {
+        int cc[UNR];
+        T aa[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int q = min(p + u, p1 - 1);
+            cc[u] = colind[q];
+            const T a = val[q];
+            aa[u] = (p + u < p1) ? a : T(0);
+        }
+        T xv[UNR][VEC];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) load_vec<T, VEC>(X + (int64_t)cc[u] * ldx + c0, xv[u]);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], xv[u][v], acc[v]);
+    }
+}
+
+// nonzeros per group: 8, or 4 when each lane gathers 64 bytes per nonzero
+template <typename T, int VEC>
+struct Unroll {
+    static constexpr int value = VEC * (int)sizeof(T) >= 64 ? 4 : 8;
+};
+
 // LPR lanes share one matrix row; lane `sub` owns columns
 // [sub*VEC, sub*VEC + VEC) of the block.  All lanes of a row walk the row's
 // nonzeros together (the column index and value loads of a row coalesce to
@@ -134,31 +169,7 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
     T acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = T(0);
-    int p = p0;
-    for (; p + 4 <= p1; p += 4) {
-        int cc[4];
-        T aa[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            cc[u] = colind[p + u];
-            aa[u] = val[p + u];
-        }
-        T xv[4][VEC];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) load_vec<T, VEC>(X + (int64_t)cc[u] * ldx + c0, xv[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], xv[u][v], acc[v]);
-    }
-    for (; p < p1; ++p) {
-        int cc = colind[p];
-        T aa = val[p];
-        T xv[VEC];
-        load_vec<T, VEC>(X + (int64_t)cc * ldx + c0, xv);
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = fma(aa, xv[v], acc[v]);
-    }
+    row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
     T xr[VEC];
     load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
     T res[VEC];
@@ -317,31 +328,7 @@ __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restric
     T acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = T(0);
-    int p = p0;
-    for (; p + 4 <= p1; p += 4) {
-        int cc[4];
-        T aa[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            cc[u] = colind[p + u];
-            aa[u] = val[p + u];
-        }
-        T xv[4][VEC];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) load_vec<T, VEC>(X + (int64_t)cc[u] * ldx + c0, xv[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], xv[u][v], acc[v]);
-    }
-    for (; p < p1; ++p) {
-        const int cc = colind[p];
-        const T aa = val[p];
-        T xv[VEC];
-        load_vec<T, VEC>(X + (int64_t)cc * ldx + c0, xv);
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = fma(aa, xv[v], acc[v]);
-    }
+    row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
     T xr[VEC];
     load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
     const T alpha = (T)e.alpha, beta = (T)e.beta, gamma = (T)e.gamma, delta = (T)e.delta;

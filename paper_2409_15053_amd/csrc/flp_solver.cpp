@@ -275,8 +275,10 @@ int wait_check(Solve &S) {
 }
 
 int step_check(Solve &S, bool async) {
-    // a check that has finished in the background is applied first
-    if (S.check && S.check->ready.load()) {
+    // a check that has finished in the background is applied first; one
+    // still running after kMaxSpeculative further block steps is waited for
+    // (speculative steps are wasted work if it decides convergence)
+    if (S.check && (S.check->ready.load() || S.steps - S.checked_step >= kMaxSpeculative)) {
         CKR(wait_check(S));
         if (S.done) return FLP_OK;
     }
@@ -336,7 +338,7 @@ int solve_finish(Solve &S, flp_result **out) {
     res->degree = S.filt->m;
     res->converged = S.converged ? 1 : 0;
     std::unique_ptr<flp_result, void (*)(flp_result *)> guard(res, flp_result_free);
-    S.st.iters = S.steps;
+    S.st.iters = S.kfinal / S.r;  // block steps behind the result (speculative ones after the deciding check are not counted)
     S.st.basis_cols = S.kfinal;
     std::vector<int> sel = S.cand;
     sel.insert(sel.end(), S.guard.begin(), S.guard.end());

@@ -29,7 +29,7 @@ EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
     "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval",
     "flp_filter_apply", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
-    "flp_solve", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
+    "flp_solve", "flp_solve_sliced", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_last_error", "flp_version",
     "flp_server_opts_default", "flp_server_create", "flp_server_submit", "flp_server_poll",
     "flp_server_wait", "flp_server_stats", "flp_server_destroy",
@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
         "flp_estimate_bounds": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, U64, P, P, P]),
         "flp_solve": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), F64, F64, ctypes.POINTER(FlpOptsC),
                                      ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
+        "flp_solve_sliced": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), F64, F64, I32, ctypes.POINTER(FlpOptsC),
+                                            ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
         "flp_solve_batch": (ctypes.c_int, [I32, P, P, P, P, I32, P, P, ctypes.POINTER(FlpBatchStatsC)]),
         "flp_result_free": (None, [ctypes.POINTER(FlpResultC)]),
         "flp_result_copy_evecs": (ctypes.c_int, [ctypes.POINTER(FlpResultC), P, P]),
@@ -346,6 +348,25 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
         stats = {f: getattr(st, f) for f, _ in FlpStatsC._fields_}
         out = dict(evals=evals, resid=resid, evecs=evecs, count=cnt, lmin=r.lmin, lmax=r.lmax,
                    degree=r.degree, converged=bool(r.converged), rc=rc, stats=stats)
+    finally:
+        lib.flp_result_free(res)
+    return out
+
+
+def flp_solve_sliced(A: DeviceCsr, alpha: float, beta: float, nslices: int, block: int = 8, degree: int = 0,
+                     seed: int = 0, prec: int = FLP_PREC_FP64, bounds=None, max_basis: int = 0,
+                     check_every: int = 0, eps: float = 0.0, k0: int = 0, want_vectors: bool = True,
+                     stream=None) -> dict:
+    """Every eigenpair of A in [alpha, beta] by nslices slices solved as one
+    batch (same return value as flp_solve)."""
+    lib = load()
+    o = _make_opts(block, degree, seed, prec, max_basis, check_every, eps, k0, bounds, stream)
+    res = ctypes.POINTER(FlpResultC)()
+    rc = lib.flp_solve_sliced(ctypes.byref(A.c), alpha, beta, nslices, ctypes.byref(o), ctypes.byref(res))
+    _check(rc, allow=(FLP_E_NOCONV,))
+    try:
+        out = _collect(res, A.n, A.val.device, want_vectors, stream)
+        out["rc"] = rc
     finally:
         lib.flp_result_free(res)
     return out

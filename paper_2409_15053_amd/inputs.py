@@ -261,22 +261,27 @@ def build_batch_matrix(spec: dict) -> Csr:
 
 
 def serve_family(count: int = 512, seed: int = BASE_SEED + 5, gmin: int = 30, gmax: int = 100,
-                 dmin: float = 4.5, dmax: float = 5.5, wells: int = 16) -> list:
+                 tmin: int = 10, tmax: int = 200, wells: int = 16, degree: int = 60) -> list:
     """Requests for the serving form: 4th-order 13-point Laplacian on a g^3
     grid plus 16 Gaussian wells (as the 120^3 Hamiltonian), g =
-    round(exp(U[ln gmin, ln gmax])), and a low-end interval [g_lo - 1, g_lo +
-    d], d ~ U[dmin, dmax], where g_lo is the matrix's Gershgorin lower bound
-    (a property of the input, computed when the matrix is built); it holds
-    tens to a few hundred bound states."""
+    round(exp(U[ln gmin, ln gmax])), a target count t ~ U{tmin..tmax} of
+    eigenvalues at the low end of the spectrum, and a fixed filter degree.
+    The interval is placed from t by build_serve_problem."""
     g = rng(seed)
     out = []
     for i in range(count):
         N = int(round(float(np.exp(g.uniform(np.log(gmin), np.log(gmax))))))
         pseed = int(g.integers(0, 2 ** 31))
-        d = float(g.uniform(dmin, dmax))
+        t = int(g.integers(tmin, tmax + 1))
         out.append(dict(name=f"lap3d13_{N}_wells{wells}_s{pseed}", N=N, potential_seed=pseed, wells=wells,
-                        delta=d))
+                        target=t, degree=degree))
     return out
+
+
+def weyl_count(V: np.ndarray, E: float) -> float:
+    """Semiclassical (Weyl) number of eigenvalues below E of -Laplacian + V
+    on a unit grid: sum over grid points of (E - V_i)_+^{3/2} / (6 pi^2)."""
+    return float(np.sum(np.clip(E - V, 0.0, None) ** 1.5) / (6.0 * np.pi ** 2))
 
 
 def gershgorin_lower(A: Csr) -> float:
@@ -291,10 +296,22 @@ def gershgorin_lower(A: Csr) -> float:
 
 
 def build_serve_problem(spec: dict):
-    """(A, alpha, beta) of one serving request."""
-    A = laplacian_3d_13pt(spec["N"], gaussian_wells(spec["N"], spec["potential_seed"], spec["wells"]))
+    """(A, alpha, beta) of one serving request: alpha one unit below the
+    matrix's Gershgorin lower bound, beta where the Weyl estimate of the
+    number of eigenvalues below it equals the request's target count (found
+    by bisection; the estimate tracks the true count of these matrices to a
+    few percent)."""
+    V = gaussian_wells(spec["N"], spec["potential_seed"], spec["wells"])
+    A = laplacian_3d_13pt(spec["N"], V)
     lo = gershgorin_lower(A)
-    return A, lo - 1.0, lo + spec["delta"]
+    a, b = float(np.min(V)), float(np.min(V)) + 20.0
+    for _ in range(100):
+        mid = 0.5 * (a + b)
+        if weyl_count(V, mid) < spec["target"]:
+            a = mid
+        else:
+            b = mid
+    return A, lo - 1.0, 0.5 * (a + b)
 
 
 def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
