@@ -42,6 +42,7 @@ WORKLOADS = {
     "batch64": dict(golden=None, kind="batch", count=64),
     "batch16": dict(golden=None, kind="batch", count=16),
     "serve": dict(golden=None, kind="serve"),
+    "lap3d13_120": dict(golden=None, kind="c3", N=120),
 }
 
 
@@ -382,6 +383,71 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c3(args):
+    """The 120^3 Hamiltonian (13-point 4th-order Laplacian + 16 Gaussian
+    wells, n = 1.728e6, nnz = 2.2e7, block 16): an interior window between the
+    Weyl estimates of 20 and 320 eigenvalues, degree --degree, solved with the
+    FP64 filter and with the FP32 filter (FP64 polish); reports both rates and
+    the largest relative eigenvalue difference between the two results.  The
+    oracle is not run at this size."""
+    import torch
+    from paper_2409_15053_amd import flp
+    from paper_2409_15053_amd import inputs as I
+    w = I.workload_c3(WORKLOADS[args.workload]["N"])
+    A = w["A"]
+    V = I.gaussian_wells(WORKLOADS[args.workload]["N"], I.BASE_SEED + 3)
+
+    def weyl_level(t):
+        a, b = float(V.min()), float(V.min()) + 20.0
+        for _ in range(100):
+            mid = 0.5 * (a + b)
+            a, b = (mid, b) if I.weyl_count(V, mid) < t else (a, mid)
+        return 0.5 * (a + b)
+
+    alpha, beta = weyl_level(20.5), weyl_level(320.5)
+    dA = flp.DeviceCsr.from_host(A, "cuda:0", with_fp32=True)
+    torch.cuda.synchronize()
+    out_runs = {}
+    for name, prec in (("fp64", flp.FLP_PREC_FP64), ("fp32", flp.FLP_PREC_FP32_FILTER)):
+        for i in range(args.warmup):
+            flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=100 + i, prec=prec,
+                          want_vectors=False)
+        lat, res = [], None
+        for i in range(args.steps):
+            t0 = time.perf_counter()
+            res = flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=i, prec=prec,
+                                want_vectors=False)
+            lat.append(time.perf_counter() - t0)
+            print(f"# {name} step {i + 1}/{args.steps}: {res['count']} pairs, {lat[-1]:.2f} s, iters "
+                  f"{res['stats']['iters']}, polish {res['stats']['polish_sweeps']}", file=sys.stderr, flush=True)
+        st = res["stats"]
+        ok = res["count"] if res["count"] and float(np.max(res["resid"])) <= 1e-9 else 0
+        out_runs[name] = {"eigenpairs_per_s": ok * len(lat) / sum(lat), "s_per_solve": float(np.mean(lat)),
+                          "count": res["count"], "max_resid": float(np.max(res["resid"])) if res["count"] else 0.0,
+                          "filter_GBps": st["filter_bytes"] / st["t_mv"] / 1e9 if st["t_mv"] > 0 else 0.0,
+                          "iters": st["iters"], "polish_sweeps": st["polish_sweeps"],
+                          "phases_s": {k: st[k] for k in ("t_pre", "t_mv", "t_orth", "t_check", "t_rr")},
+                          "evals": np.sort(res["evals"])}
+    e64, e32 = out_runs["fp64"].pop("evals"), out_runs["fp32"].pop("evals")
+    diff = float(np.max(np.abs(e32 - e64) / np.abs(e64))) if len(e32) == len(e64) and len(e64) else None
+    r32 = out_runs["fp32"]
+    out = {
+        "metric": METRIC, "value": r32["eigenpairs_per_s"], "unit": "eigenpairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["s_per_solve"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32-filter/f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w['name']}: 13-point 4th-order Laplacian 120^3 + 16 Gaussian wells, n={A.n}, "
+                               f"nnz={A.nnz}, block 16, degree {args.degree}, interval between the Weyl "
+                               f"estimates of 20 and 320 eigenvalues [{alpha:.6f}, {beta:.6f}]",
+                   "n": A.n, "nnz": A.nnz, "block": 16, "degree": args.degree},
+        "fp64_filter": out_runs["fp64"], "fp32_filter": r32,
+        "fp32_vs_fp64": {"same_count": len(e32) == len(e64), "max_rel_eval_diff": diff},
+        "speedup_fp32_vs_fp64": r32["eigenpairs_per_s"] / out_runs["fp64"]["eigenpairs_per_s"]
+        if out_runs["fp64"]["eigenpairs_per_s"] else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -407,6 +473,8 @@ def main():
         return bench_batch(args)
     if WORKLOADS[args.workload]["kind"] == "serve":
         return bench_serve(args)
+    if WORKLOADS[args.workload]["kind"] == "c3":
+        return bench_c3(args)
     w, alpha, beta, ref = load_workload(args.workload)
     A = w["A"]
     prec = flp.FLP_PREC_FP32_FILTER if args.prec == "fp32" else flp.FLP_PREC_FP64

@@ -176,10 +176,13 @@ typedef struct flp_tune_info {
     double us_per_step;    /* measured microseconds of one step over all r columns (0 if not timed) */
 } flp_tune_info;
 
-/* Autotuner.  The first time a (device, precision, r, n, nnz) combination
- * is filtered, every supported launch shape (rows per wavefront, columns per
- * lane) and column-group width is timed on the caller's matrix over a short
- * ring of filter steps and the fastest is kept for the process; the batched
+/* Autotuner.  The first time a (device, precision, r, size class)
+ * combination is filtered (size class: n to a quarter octave and nonzeros
+ * per row to a quarter), every supported launch shape (rows per wavefront,
+ * columns per lane) and column-group width is timed on the caller's matrix
+ * over a short ring of filter steps and the fastest is kept for the process
+ * (timings taken while other work shares the GPU may pick a slower shape,
+ * never a different result); the batched
  * and serving engines tune the shape of their segmented launches on the
  * largest active matrix.  All configurations compute every output element
  * with the same operations in the same order, so results are bit-identical.

@@ -90,26 +90,26 @@ int Engine::init(int r_, int prec_, bool graph_) {
     T.fp32 = prec == FLP_PREC_FP32_FILTER;
     CK(hipGetDevice(&device));
     CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    CK(hipStreamCreateWithFlags(&fs, hipStreamNonBlocking));
+    for (auto &f : fs) CK(hipStreamCreateWithFlags(&f, hipStreamNonBlocking));
     CK(hipEventCreate(&ev_a));
     CK(hipEventCreate(&ev_b));
-    fin = std::thread([this]() { finisher_main(); });
+    for (int w = 0; w < kFinishers; ++w) fin[w] = std::thread([this, w]() { finisher_main(w); });
     return FLP_OK;
 }
 
 Engine::~Engine() {
-    if (fin.joinable()) {
-        {
-            std::lock_guard<std::mutex> lk(fmu);
-            fstop = true;
-        }
-        fcv.notify_all();
-        fin.join();  // the queue is drained first
+    {
+        std::lock_guard<std::mutex> lk(fmu);
+        fstop = true;
     }
+    fcv.notify_all();
+    for (auto &t : fin)
+        if (t.joinable()) t.join();  // the queue is drained first
     graph_reset();
     if (ev_a) (void)hipEventDestroy(ev_a);
     if (ev_b) (void)hipEventDestroy(ev_b);
-    if (fs) (void)hipStreamDestroy(fs);
+    for (auto &f : fs)
+        if (f) (void)hipStreamDestroy(f);
     if (s) (void)hipStreamDestroy(s);
 }
 
@@ -117,7 +117,7 @@ void Engine::complete(Job *j) {
     if (on_done) on_done(j);
 }
 
-void Engine::finisher_main() {
+void Engine::finisher_main(int w) {
     (void)hipSetDevice(device);
     for (;;) {
         Job *j = nullptr;
@@ -130,7 +130,7 @@ void Engine::finisher_main() {
             ++fbusy;
         }
         const double t0 = now();
-        j->S->s = fs;
+        j->S->s = fs[w];
         j->code = solve_finish(*j->S, &j->res);
         if (j->code != FLP_OK && j->code != FLP_E_NOCONV) j->msg = last_error_cstr();
         j->t_done = now();

@@ -11,13 +11,14 @@
 //   2. implicit symmetric QR with the Wilkinson shift on the tridiagonal
 //      (Golub & Van Loan, "Matrix Computations", Sec. 8.3).
 // Every rotation is logged, so eigenvectors are built only where needed:
-//   * selected ROWS of the eigenvector matrix Z = J_1 J_2 ... J_t by
-//     replaying the log forwards on rows of the identity (the convergence
+//   * selected ROWS of the eigenvector matrix Z = J_1 J_2 ... J_t, applied
+//     to rows of the identity as the rotations are made (the convergence
 //     check needs the last r rows, for the Ritz residual bounds);
 //   * selected COLUMNS of Z by replaying the log backwards on columns of the
 //     identity, Z e_j = J_1 (J_2 (... (J_t e_j))) (the Ritz vectors need
 //     only the candidates' columns).
-// Both replays cost O(#rotations x #selected) and run in parallel threads.
+// Both cost O(#rotations x #selected); the column replay runs in parallel
+// threads.
 //
 // Dense matrices (the Rayleigh-Ritz projections, whose bandwidth is the full
 // order) take a different first phase: Householder reduction to tridiagonal
@@ -101,7 +102,20 @@ inline void rotate_band(Band &M, int p, double c, double s) {
 
 // Reduce a symmetric band matrix of semi-bandwidth b (stored with w = b + 1
 // so the bulge fits) to tridiagonal form in place, logging the rotations.
-void band_to_tridiag(Band &M, int b, std::vector<Rot> &log) {
+// Rows of the accumulated rotation product, applied as each rotation is
+// made: Zt is N x nr (row p holds the nr tracked rows' entries in column p),
+// a rotation on plane (p, p + 1) mixes entries p and p + 1.
+inline void rot_rows(double *Zt, int nr, int p, double c, double s) {
+    double *a = Zt + (size_t)p * nr;
+    double *b = a + nr;
+    for (int j = 0; j < nr; ++j) {
+        const double u = a[j], v = b[j];
+        a[j] = c * u + s * v;
+        b[j] = -s * u + c * v;
+    }
+}
+
+void band_to_tridiag(Band &M, int b, std::vector<Rot> &log, double *Zt, int nr) {
     const int N = M.N;
     for (int bw = b; bw >= 2; --bw) {
         for (int j = 0; j + bw < N; ++j) {
@@ -115,6 +129,7 @@ void band_to_tridiag(Band &M, int b, std::vector<Rot> &log) {
                 rotate_band(M, i - 1, c, s);
                 M.set(i, k, 0.0);
                 log.push_back({i - 1, c, s});
+                if (nr) rot_rows(Zt, nr, i - 1, c, s);
                 // the rotation fills (i-1+bw+1, i-1); chase it with plane (i-1+bw, i+bw)
                 k = i - 1;
                 i = i + bw;
@@ -125,7 +140,7 @@ void band_to_tridiag(Band &M, int b, std::vector<Rot> &log) {
 
 // Implicit QR with Wilkinson shift on the tridiagonal (d, e); e[i] couples
 // i and i+1.  On return d holds the eigenvalues (unsorted).
-bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot> &log) {
+bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot> &log, double *Zt, int nr) {
     const int N = (int)d.size();
     if (N <= 1) return true;
     int hi = N - 1;
@@ -172,6 +187,7 @@ bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot>
                 x = e[k];
             }
             log.push_back({k, c, s});
+            if (nr) rot_rows(Zt, nr, k, c, s);
         }
     }
     return true;
@@ -199,33 +215,6 @@ void parallel_for(int units, int nt, F f) {
         th.emplace_back(f, u0, u1);
     }
     for (auto &t : th) t.join();
-}
-
-// Rows R of (I J_1 J_2 ... J_t): identity rows, log replayed forwards.
-// Z is nrows x N row-major; rows[i] is the identity row for Z row i.
-void replay_rows(const std::vector<Rot> &log, int N, const int *rows, int nrows, double *Z) {
-    constexpr int TILE = 8;
-    const int ntiles = (nrows + TILE - 1) / TILE;
-    auto work = [&](int t0, int t1) {
-        std::vector<double> tile((size_t)N * TILE);
-        for (int t = t0; t < t1; ++t) {
-            const int r0 = t * TILE, nr = std::min(TILE, nrows - r0);
-            std::fill(tile.begin(), tile.end(), 0.0);
-            for (int i = 0; i < nr; ++i) tile[(size_t)rows[r0 + i] * TILE + i] = 1.0;
-            for (const Rot &g : log) {
-                double *a = &tile[(size_t)g.p * TILE];
-                double *b = a + TILE;
-                for (int i = 0; i < TILE; ++i) {
-                    const double u = a[i], v = b[i];
-                    a[i] = g.c * u + g.s * v;
-                    b[i] = -g.s * u + g.c * v;
-                }
-            }
-            for (int i = 0; i < nr; ++i)
-                for (int j = 0; j < N; ++j) Z[(size_t)(r0 + i) * N + j] = tile[(size_t)j * TILE + i];
-        }
-    };
-    parallel_for(ntiles, nthreads_for((long)log.size() * nrows, ntiles), work);
 }
 
 // Columns of J_1 J_2 ... J_t selected by ids (unsorted eigen-indices):
@@ -363,7 +352,7 @@ int dense_sym_eig(int N, const double *M, double *evals, const int *cols, int nc
     householder_tridiag(N, A.data(), d, e, beta);
     std::vector<Rot> log;
     log.reserve((size_t)N * 4);
-    if (!tridiag_qr(d, e, log)) return -2;
+    if (!tridiag_qr(d, e, log, nullptr, 0)) return -2;
     std::vector<int> perm(N);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] < d[b]; });
@@ -397,21 +386,23 @@ int sym_eig_keep(int N, int bw, const double *M, double *evals, const int *rows,
     std::vector<Rot> &log = keep ? keep->rot : local;
     log.clear();
     log.reserve((size_t)N * 4);
-    if (bw >= 2) band_to_tridiag(Bd, bw, log);
+    // the requested rows of the eigenvector matrix, accumulated as the
+    // rotations are made (independent of the rotation chain, so they fill
+    // its latency)
+    const int nr = (nrows > 0 && Zrows) ? nrows : 0;
+    std::vector<double> Zt((size_t)N * nr, 0.0);
+    for (int i = 0; i < nr; ++i) Zt[(size_t)rows[i] * nr + i] = 1.0;
+    if (bw >= 2) band_to_tridiag(Bd, bw, log, Zt.data(), nr);
     std::vector<double> d(N), e(std::max(N - 1, 0));
     for (int i = 0; i < N; ++i) d[i] = Bd.get(i, i);
     for (int i = 0; i + 1 < N; ++i) e[i] = Bd.get(i + 1, i);
-    if (!tridiag_qr(d, e, log)) return -2;
+    if (!tridiag_qr(d, e, log, Zt.data(), nr)) return -2;
     std::vector<int> perm(N);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] < d[b]; });
     for (int i = 0; i < N; ++i) evals[i] = d[perm[i]];
-    if (nrows > 0 && Zrows) {
-        std::vector<double> tmp((size_t)nrows * N);
-        replay_rows(log, N, rows, nrows, tmp.data());
-        for (int i = 0; i < nrows; ++i)
-            for (int j = 0; j < N; ++j) Zrows[(size_t)i * N + j] = tmp[(size_t)i * N + perm[j]];
-    }
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < N; ++j) Zrows[(size_t)i * N + j] = Zt[(size_t)perm[j] * nr + i];
     if (keep) {
         keep->N = N;
         keep->perm = perm;

@@ -325,17 +325,18 @@ struct Engine {
     flp_batch_stats snapshot();
 
   private:
-    // finisher: Ritz vectors, Rayleigh-Ritz and polish of converged solves
-    // on a second stream and host thread, overlapping later block steps
-    hipStream_t fs = nullptr;
-    std::thread fin;
+    // finishers: Ritz vectors, Rayleigh-Ritz and polish of converged solves,
+    // each on its own host thread and stream, overlapping later block steps
+    static constexpr int kFinishers = 4;
+    hipStream_t fs[kFinishers] = {};
+    std::thread fin[kFinishers];
     std::mutex fmu;
     std::condition_variable fcv, fdone;
     std::deque<Job *> fq;
     int fbusy = 0;
     bool fstop = false;
     double t_finish = 0.0;
-    void finisher_main();
+    void finisher_main(int w);
     void complete(Job *j);
 };
 

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -201,7 +202,26 @@ namespace {
 bool at_last(const Solve &S) { return S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n; }
 }  // namespace
 
+namespace {
+void run_check_body(CheckTask &c);
+}  // namespace
+
+// Runs on a pool thread: every failure comes back through c.rc.
 void run_check(CheckTask &c) {
+    try {
+        run_check_body(c);
+    } catch (const std::bad_alloc &) {
+        c.rc = FLP_E_NOMEM;
+        c.msg = "host allocation failed in the convergence check";
+    } catch (...) {
+        c.rc = FLP_E_DEVICE;
+        c.msg = "unexpected exception in the convergence check";
+    }
+    c.ready.store(true);
+}
+
+namespace {
+void run_check_body(CheckTask &c) {
     const double t0 = now();
     const int K = c.K, r = c.r;
     std::vector<double> theta(K);
@@ -212,7 +232,6 @@ void run_check(CheckTask &c) {
         c.rc = FLP_E_DEVICE;
         c.msg = "eigensolver for T_k did not converge";
         c.secs = now() - t0;
-        c.ready.store(true);
         return;
     }
     // rho_i = || S_k E_k^T w_i ||; candidates theta_i >= tau
@@ -248,8 +267,8 @@ void run_check(CheckTask &c) {
         c.guard = g;
     }
     c.secs = now() - t0;
-    c.ready.store(true);
 }
+}  // namespace
 
 int wait_check(Solve &S) {
     if (!S.check) return FLP_OK;

@@ -12,13 +12,15 @@
 // Each candidate is timed on the caller's matrix over a ring of six steps
 // (the pattern of the real recurrence: gather one buffer, read V and a
 // second buffer, write the third), after one untimed ring.  Results are cached
-// per (device, precision, r, n, nnz, grouping allowed).  Every shape and
+// per device, precision, r, grouping allowed and size class (n to a quarter
+// octave, nonzeros per row to a quarter).  Every shape and
 // width computes each output element with the same operations in the same
 // order, so tuning never changes results, only speed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -104,7 +106,9 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     }
     int dev = 0;
     CK(hipGetDevice(&dev));
-    const Key key{dev, fp32 ? 1 : 0, r, (int64_t)n, A->nnz, allow_groups ? 1 : 0};
+    // size class: n to a quarter octave, nonzeros per row to a quarter
+    const Key key{dev, fp32 ? 1 : 0, r, (int64_t)std::lround(4.0 * std::log2((double)n)),
+                  (int64_t)std::lround(4.0 * (double)A->nnz / n), allow_groups ? 1 : 0};
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = cache().find(key);
