@@ -173,13 +173,15 @@ typedef struct flp_tune_info {
     int32_t cols_per_lane; /* consecutive block columns owned by one lane */
     int32_t rows_per_wave; /* matrix rows per 64-lane wavefront (64 / lanes_per_row) */
     int32_t candidates;    /* configurations timed (0: default or forced, not timed) */
+    int32_t streaming_loads; /* 1: V and U_{k+2} are read with nontemporal loads */
     double us_per_step;    /* measured microseconds of one step over all r columns (0 if not timed) */
 } flp_tune_info;
 
 /* Autotuner.  The first time a (device, precision, r, size class)
  * combination is filtered (size class: n to a quarter octave and nonzeros
  * per row to a quarter), every supported launch shape (rows per wavefront,
- * columns per lane) and column-group width is timed on the caller's matrix
+ * columns per lane, ordinary or nontemporal loads of the streamed operands)
+ * and column-group width is timed on the caller's matrix
  * over a short ring of filter steps and the fastest is kept for the process
  * (timings taken while other work shares the GPU may pick a slower shape,
  * never a different result); the batched
@@ -199,8 +201,10 @@ void flp_set_autotune(int32_t on);
 /* Forces one configuration for every later filter launch (testing and
  * measurement); lanes_per_row = 0 and group_width = 0 restore tuning.  A
  * shape with no kernel for a given width falls back to the default shape;
- * a group width that does not divide r is ignored. */
-void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width);
+ * a group width that does not divide r is ignored; streaming_loads = 1
+ * reads V and U_{k+2} with nontemporal loads. */
+void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
+                          int32_t streaming_loads);
 
 /* Y = A X (plain CSR SpMM, Section 3.2.1).  X, Y: DEVICE n x r row-major
  * with leading dimensions ldx, ldy >= r; 1 <= r <= 32; FP64.  Async. */

@@ -113,6 +113,7 @@ int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp
         out->cols_per_lane = sh.lpr > 0 ? sh.vec : 1;
         out->rows_per_wave = 64 / out->lanes_per_row;
         out->candidates = tn.candidates;
+        out->streaming_loads = sh.lpr > 0 ? sh.nt : 0;
         out->us_per_step = tn.candidates > 0 ? tn.us_per_step : 0.0;
         return FLP_OK;
     } catch (const std::bad_alloc &) {
@@ -122,8 +123,10 @@ int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp
 
 void flp_set_autotune(int32_t on) { set_autotune(on); }
 
-void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width) {
-    force_filter_shape(StepShape{std::max(0, (int)lanes_per_row), std::max(0, (int)cols_per_lane)},
+void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
+                          int32_t streaming_loads) {
+    force_filter_shape(StepShape{std::max(0, (int)lanes_per_row), std::max(0, (int)cols_per_lane),
+                                 streaming_loads ? 1 : 0},
                        std::max(0, (int)group_width));
 }
 

@@ -618,8 +618,8 @@ int orthonormalize_cols(int n, int c, double *&Y, double *&tmp, int ldc, double 
 int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
                   double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s) {
     Workspace &w = ws();
-    for (int j0 = 0; j0 < c; j0 += 16) {
-        int cw = std::min(16, c - j0);
+    for (int j0 = 0; j0 < c; j0 += 32) {
+        int cw = std::min(32, c - j0);
         CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, cw, Y + j0, ldc, nullptr, 0, nullptr,
                                             0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
     }

@@ -80,11 +80,12 @@ inline DMat panel_mat(const double *p, int64_t n, int lpw) {
 
 // Launch shape of a filter step: lpr lanes share one matrix row and each
 // owns vec consecutive columns of the block (lpr * vec = r), so a 256-thread
-// block covers 256 / lpr rows.  {0, 0} selects the default (16-byte pieces).
-// Every shape sums each output element in the same order, so all of them
-// give bit-identical results.
+// block covers 256 / lpr rows; nt = 1 reads the streamed operands (V and
+// U_{k+2}) with nontemporal loads.  {0, 0, 0} selects the default (16-byte
+// pieces, ordinary loads).  Every shape sums each output element in the same
+// order, so all of them give bit-identical results.
 struct StepShape {
-    int lpr = 0, vec = 0;
+    int lpr = 0, vec = 0, nt = 0;
 };
 StepShape default_step_shape(int r, bool fp32);
 std::vector<StepShape> step_shape_candidates(int r, bool fp32);

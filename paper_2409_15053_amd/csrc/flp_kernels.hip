@@ -114,6 +114,19 @@ __device__ __forceinline__ void store_vec(T *p, const T (&v)[VEC]) {
 
 // ------------------------------------------------------------------ filter step
 //
+// Loads of the streamed operands V and U_{k+2}: with NT, nontemporal (they
+// are read once per step, so they need not displace the gathered vector
+// from the caches); otherwise as load_vec.
+template <typename T, int VEC, bool NT>
+__device__ __forceinline__ void load_stream(const T *p, T (&v)[VEC]) {
+    if constexpr (NT) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) v[i] = __builtin_nontemporal_load(p + i);
+    } else {
+        load_vec<T, VEC>(p, v);
+    }
+}
+
 // acc += sum over the row's nonzeros p0..p1-1 of val[p] * X[colind[p], c0 ..
 // c0 + VEC), in order.  The nonzeros go in groups of UNR with every load of
 // a group issued before its products: a slot past the row's end re-reads the
@@ -153,7 +166,7 @@ struct Unroll {
 // [sub*VEC, sub*VEC + VEC) of the block.  All lanes of a row walk the row's
 // nonzeros together (the column index and value loads of a row coalesce to
 // one request), and each gathers its VEC contiguous entries of X[col, :].
-template <typename T, typename Tout, int LPR, int VEC>
+template <typename T, typename Tout, int LPR, int VEC, bool NT>
 __global__ __launch_bounds__(256) void cheb_step_kernel(
     int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
     const T *__restrict__ val, int r, const T *__restrict__ X, int ldx, const T *__restrict__ V,
@@ -177,13 +190,13 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
     for (int v = 0; v < VEC; ++v) res[v] = alpha * acc[v] + beta * xr[v];
     if (V) {
         T vv[VEC];
-        load_vec<T, VEC>(V + (int64_t)row * ldv + c0, vv);
+        load_stream<T, VEC, NT>(V + (int64_t)row * ldv + c0, vv);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) res[v] = fma(gamma, vv[v], res[v]);
     }
     if (Y) {
         T yy[VEC];
-        load_vec<T, VEC>(Y + (int64_t)row * ldy + c0, yy);
+        load_stream<T, VEC, NT>(Y + (int64_t)row * ldy + c0, yy);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) res[v] = fma(delta, yy[v], res[v]);
     }
@@ -198,13 +211,13 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
     }
 }
 
-template <typename T, typename Tout, int LPR, int VEC>
+template <typename T, typename Tout, int LPR, int VEC, bool NT>
 hipError_t cheb_launch(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
                        const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
                        int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s) {
     constexpr int RPB = 256 / LPR;
     int grid = (n + RPB - 1) / RPB;
-    hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC>), dim3(grid), dim3(256), 0, s, n, rowptr,
+    hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT>), dim3(grid), dim3(256), 0, s, n, rowptr,
                        colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
     return hipGetLastError();
 }
@@ -236,8 +249,9 @@ StepShape default_step_shape(int r, bool fp32) {
 
 std::vector<StepShape> step_shape_candidates(int r, bool fp32) {
     std::vector<StepShape> out;
-    for (int vec : {2, 4, 8})
-        if (r % vec == 0 && shape_has_kernel(fp32, r / vec, vec)) out.push_back(StepShape{r / vec, vec});
+    for (int nt : {0, 1})
+        for (int vec : {2, 4, 8})
+            if (r % vec == 0 && shape_has_kernel(fp32, r / vec, vec)) out.push_back(StepShape{r / vec, vec, nt});
     return out;
 }
 
@@ -256,12 +270,21 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
     auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     bool aligned16 = (ldx % V16 == 0) && (!V || ldv % V16 == 0) && (!Y || ldy % V16 == 0) &&
                      (ldo % V16 == 0) && (sizeof(Tout) == sizeof(T)) && al(X) && al(V) && al(Y) && al(out);
-#define FLP_CHEB(LPR, VEC) \
-    return cheb_launch<T, Tout, LPR, VEC>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s)
+#define FLP_CHEB_NT(LPR, VEC, NT) \
+    return cheb_launch<T, Tout, LPR, VEC, NT>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s)
+#define FLP_CHEB(LPR, VEC) FLP_CHEB_NT(LPR, VEC, false)
     if (aligned16 && r % V16 == 0) {
         if (!step_shape_ok(r, F32, sh)) sh = default_step_shape(r, F32);
         const int lpr = sh.lpr, vec = sh.vec;
-#define FLP_TRY(L, VV) if (lpr == L && vec == VV) { FLP_CHEB(L, VV); }
+        const bool nt = sh.nt != 0;
+#define FLP_TRY(L, VV) \
+    if (lpr == L && vec == VV) {        \
+        if (nt) {                       \
+            FLP_CHEB_NT(L, VV, true);   \
+        } else {                        \
+            FLP_CHEB_NT(L, VV, false);  \
+        }                               \
+    }
         if constexpr (F32) {
             FLP_SHAPES_F32(FLP_TRY)
         } else {
@@ -276,6 +299,7 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
     if (r <= 16) FLP_CHEB(16, 1);
     if (r <= 32) FLP_CHEB(32, 1);
 #undef FLP_CHEB
+#undef FLP_CHEB_NT
     return hipErrorInvalidValue;
 }
 
@@ -302,19 +326,26 @@ template hipError_t launch_cheb_step<float, double>(int, const int32_t *, const 
 
 namespace {
 
-template <typename T, int LPR, int VEC>
+template <typename T, int LPR, int VEC, bool NT>
 __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg) {
     constexpr int RPB = 256 / LPR;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].tile0 <= tile)
-            lo = mid;
-        else
-            hi = mid - 1;
+    // The segment holding this tile: the tile offsets ascend, so the
+    // segments starting at or before the tile are a prefix; each wave counts
+    // it 64 segments at a time with one load per lane and a ballot.  The
+    // count is the same on every lane, so it is made wave-uniform and the
+    // segment's descriptor is then read through the scalar cache.
+    const int lane = threadIdx.x % WAVE;
+    int seg = -1;
+    for (int base = 0; base < nseg; base += WAVE) {
+        const int i = base + lane;
+        const bool le = i < nseg && tab[i].tile0 <= tile;
+        const unsigned long long m = __ballot(le);
+        seg += __popcll(m);
+        if (~m != 0ull) break;
     }
-    const SegEntry &e = tab[lo];
+    seg = __builtin_amdgcn_readfirstlane(seg);
+    const SegEntry &e = tab[seg];
     const int n = e.n;
     const int row = (tile - e.tile0) * RPB + threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * VEC;
@@ -337,13 +368,13 @@ __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restric
     for (int v = 0; v < VEC; ++v) res[v] = alpha * acc[v] + beta * xr[v];
     if (e.V) {
         T vv[VEC];
-        load_vec<T, VEC>((const T *)e.V + (int64_t)row * e.ldv + c0, vv);
+        load_stream<T, VEC, NT>((const T *)e.V + (int64_t)row * e.ldv + c0, vv);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) res[v] = fma(gamma, vv[v], res[v]);
     }
     if (e.Y) {
         T yy[VEC];
-        load_vec<T, VEC>((const T *)e.Y + (int64_t)row * e.ldy + c0, yy);
+        load_stream<T, VEC, NT>((const T *)e.Y + (int64_t)row * e.ldy + c0, yy);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) res[v] = fma(delta, yy[v], res[v]);
     }
@@ -376,13 +407,27 @@ hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int 
     if (nseg <= 0 || total_tiles <= 0) return hipSuccess;
     sh = seg_shape(r, fp32, sh);
     const int lpr = sh.lpr, vec = sh.vec;
-#define FLP_SEG(T, LPR, VEC) \
+    const bool nt = sh.nt != 0;
+#define FLP_SEG_NT(T, LPR, VEC, NT) \
     { \
-        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC>), dim3(total_tiles), dim3(256), 0, s, tab, nseg); \
+        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC, NT>), dim3(total_tiles), dim3(256), 0, s, tab, nseg); \
         return hipGetLastError(); \
     }
-#define FLP_SEG64(L, VV) if (lpr == L && vec == VV) FLP_SEG(double, L, VV)
-#define FLP_SEG32(L, VV) if (lpr == L && vec == VV) FLP_SEG(float, L, VV)
+#define FLP_SEG(T, LPR, VEC) FLP_SEG_NT(T, LPR, VEC, false)
+#define FLP_SEG64(L, VV) \
+    if (lpr == L && vec == VV) { \
+        if (nt) \
+            FLP_SEG_NT(double, L, VV, true) \
+        else \
+            FLP_SEG_NT(double, L, VV, false) \
+    }
+#define FLP_SEG32(L, VV) \
+    if (lpr == L && vec == VV) { \
+        if (nt) \
+            FLP_SEG_NT(float, L, VV, true) \
+        else \
+            FLP_SEG_NT(float, L, VV, false) \
+    }
     if (!fp32) {
         FLP_SHAPES_F64(FLP_SEG64)
         if (vec == 1) {
@@ -407,6 +452,7 @@ hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int 
 #undef FLP_SEG64
 #undef FLP_SEG32
 #undef FLP_SEG
+#undef FLP_SEG_NT
     return hipErrorInvalidValue;
 }
 

@@ -404,12 +404,12 @@ int solve_finish(Solve &S, flp_result **out) {
         if (S.o.prec == FLP_PREC_FP32_FILTER) {
             // FP64 polish: X <- p(A) X, orthonormalise, Rayleigh-Ritz with A
             while (worst(i0, i1) > tol && S.st.polish_sweeps < kMaxPolish) {
-                for (int j0 = 0; j0 < c; j0 += 16) {
-                    const int cw = std::min(16, c - j0);
+                for (int j0 = 0; j0 < c; j0 += 32) {
+                    const int cw = std::min(32, c - j0);
                     CKR(filter_apply_impl(S.filt.get(), A, X + j0, ldc, Y + j0, ldc, cw, FLP_PREC_FP64, s));
                 }
                 S.st.filter_bytes +=
-                    filter_step_bytes(n, A->nnz, 16, FLP_PREC_FP64) * S.filt->m * ((c + 15) / 16);
+                    filter_step_bytes(n, A->nnz, 32, FLP_PREC_FP64) * S.filt->m * ((c + 31) / 32);
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
                 CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));

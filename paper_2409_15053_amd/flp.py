@@ -50,7 +50,8 @@ class FlpCsrC(ctypes.Structure):
 class FlpTuneInfoC(ctypes.Structure):
     _fields_ = [("group_width", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("cols_per_lane", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("us_per_step", ctypes.c_double)]
+                ("candidates", ctypes.c_int32), ("streaming_loads", ctypes.c_int32),
+                ("us_per_step", ctypes.c_double)]
 
 
 class FlpOptsC(ctypes.Structure):
@@ -114,7 +115,7 @@ def load(path: str = LIB_PATH):
         "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, P, I32, I32, P]),
         "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, P, ctypes.POINTER(FlpTuneInfoC)]),
         "flp_set_autotune": (None, [I32]),
-        "flp_set_filter_shape": (None, [I32, I32, I32]),
+        "flp_set_filter_shape": (None, [I32, I32, I32, I32]),
         "flp_spmm": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), P, I32, P, I32, I32, P]),
         "flp_block_orth": (ctypes.c_int, [P, I64, I32, I32, P, I32, P, P]),
         "flp_block_qr": (ctypes.c_int, [P, I32, I32, P, P]),
@@ -251,9 +252,10 @@ def flp_set_autotune(on: bool):
     load().flp_set_autotune(1 if on else 0)
 
 
-def flp_set_filter_shape(lanes_per_row: int = 0, cols_per_lane: int = 0, group_width: int = 0):
+def flp_set_filter_shape(lanes_per_row: int = 0, cols_per_lane: int = 0, group_width: int = 0,
+                         streaming_loads: bool = False):
     """Force one filter launch configuration (all zeros: back to tuning)."""
-    load().flp_set_filter_shape(lanes_per_row, cols_per_lane, group_width)
+    load().flp_set_filter_shape(lanes_per_row, cols_per_lane, group_width, 1 if streaming_loads else 0)
 
 
 def flp_spmm(A: DeviceCsr, X, Y, stream=None):

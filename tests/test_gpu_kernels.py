@@ -145,18 +145,20 @@ def test_filter_apply_ragged_large_grid(torch):
 
 
 SHAPE_CASES = {
-    # (r, prec): forced (lanes per row, columns per lane, group width) configurations
-    (8, flp.FLP_PREC_FP64): [(4, 2, 8), (2, 4, 8), (1, 8, 8), (2, 2, 4), (1, 4, 4), (1, 2, 2)],
-    (16, flp.FLP_PREC_FP64): [(8, 2, 16), (4, 4, 16), (2, 8, 16), (4, 2, 8), (2, 4, 8), (1, 8, 8)],
-    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8), (1, 8, 8), (1, 4, 4)],
-    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16), (2, 8, 16), (2, 4, 8), (1, 8, 8)],
+    # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams)
+    (8, flp.FLP_PREC_FP64): [(4, 2, 8, 0), (2, 4, 8, 1), (1, 8, 8, 0), (2, 2, 4, 1), (1, 4, 4, 0), (1, 2, 2, 1)],
+    (16, flp.FLP_PREC_FP64): [(8, 2, 16, 1), (4, 4, 16, 0), (2, 8, 16, 1), (4, 2, 8, 0), (2, 4, 8, 1),
+                              (1, 8, 8, 0)],
+    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1), (1, 8, 8, 0), (1, 4, 4, 1)],
+    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0), (2, 8, 16, 1), (2, 4, 8, 1), (1, 8, 8, 0)],
 }
 
 
 @pytest.mark.parametrize("r,prec", list(SHAPE_CASES))
 def test_filter_launch_shapes_bit_identical(torch, r, prec):
     """Every launch configuration the autotuner may pick (rows per
-    wavefront, columns per lane, column-group width) sums each output element
+    wavefront, columns per lane, column-group width, ordinary or nontemporal
+    loads of the streamed operands) sums each output element
     in the same order: all of them give the same bits, and that result is
     within the parity bound of the oracle."""
     A = I.laplacian_3d_13pt(23, I.gaussian_wells(23, 7))  # n = 12167: ragged last tile
@@ -169,11 +171,11 @@ def test_filter_launch_shapes_bit_identical(torch, r, prec):
         flp.flp_set_autotune(False)
         W0 = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
         flp.flp_filter_apply(f, dA, Vd, W0, prec=prec)
-        for lpr, vec, gw in SHAPE_CASES[(r, prec)]:
-            flp.flp_set_filter_shape(lpr, vec, gw)
+        for lpr, vec, gw, nt in SHAPE_CASES[(r, prec)]:
+            flp.flp_set_filter_shape(lpr, vec, gw, bool(nt))
             W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
             flp.flp_filter_apply(f, dA, Vd, W, prec=prec)
-            outs.append(((lpr, vec, gw), W))
+            outs.append(((lpr, vec, gw, nt), W))
         flp.flp_set_filter_shape(0, 0, 0)
         flp.flp_set_autotune(True)
         info = flp.flp_tune_filter(dA, r, prec)
