@@ -4,7 +4,9 @@
 //   over a row-major block of r vectors with the affine map and the
 //   three-term update fused into the epilogue.
 // * gemm_tn / gemm_nn: the tall-skinny products of the full
-//   reorthogonalisation (Section 3.2.2) on FP64 MFMA (16x16x4).
+//   reorthogonalisation (Section 3.2.2): the update and wide projections on
+//   FP64 MFMA (16x16x4), the projection against at most 16 columns on FMA
+//   (2 flops per byte: bandwidth-bound either way).
 // * small helpers: Gershgorin bounds, counter-based normal generator,
 //   block copies, residual norms.
 #include "flp_internal.h"
@@ -696,8 +698,70 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, doubl
 
 }  // namespace
 
+namespace {
+
+// C partial (K x c, c <= C) over one chunk of rows without MFMA: thread q
+// owns column q of A and accumulates its c dot products with B over the
+// chunk's rows in order.  The B row is the same for the whole block (the
+// rows are walked in step), so it is read through the scalar cache; the A
+// loads of a wave are 64 consecutive doubles of one row.  With c <= 16
+// this product does 2c flops per 8-byte A element, far below what the FMA
+// units sustain at HBM speed, so it needs no matrix cores.
+template <int C, int UNR>
+__global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int c, int chunk_rows, DMat A,
+                                                          const double *__restrict__ B, int64_t ldb,
+                                                          double *__restrict__ partials) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int chunk = blockIdx.y;
+    const int r0 = chunk * chunk_rows, r1 = min(n, r0 + chunk_rows);
+    const double *col = col_base(A, min(q, K - 1));
+    const int64_t lda = A.ld;
+    double acc[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) acc[j] = 0.0;
+    int row = r0;
+    for (; row + UNR <= r1; row += UNR) {
+        double a[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) a[u] = col[(int64_t)(row + u) * lda];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const double *b = B + (int64_t)(row + u) * ldb;
+#pragma unroll
+            for (int j = 0; j < C; ++j) acc[j] = fma(a[u], j < c ? b[min(j, c - 1)] : 0.0, acc[j]);
+        }
+    }
+    for (; row < r1; ++row) {
+        const double a = col[(int64_t)row * lda];
+        const double *b = B + (int64_t)row * ldb;
+#pragma unroll
+        for (int j = 0; j < C; ++j) acc[j] = fma(a, j < c ? b[min(j, c - 1)] : 0.0, acc[j]);
+    }
+    if (q < K) {
+        double *d = partials + ((size_t)chunk * K + q) * c;
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+            if (j < c) d[j] = acc[j];
+    }
+}
+
+}  // namespace
+
 TnPlan plan_tn(int n, int K, int c) {
     TnPlan p;
+    if (c <= 16) {
+        // FMA path: about 2048 blocks of 256 columns x chunk_rows rows, the
+        // partial buffer kept near 32M doubles at most
+        const int ncb = (K + 255) / 256;
+        int nch = std::max(1, std::min(2048, 2048 / ncb));
+        int rows = std::max(64, (n + nch - 1) / nch);
+        rows = (rows + 63) / 64 * 64;
+        while ((size_t)((n + rows - 1) / rows) * K * c > (size_t)(32u << 20)) rows *= 2;
+        p.chunk_rows = rows;
+        p.nchunks = (n + rows - 1) / rows;
+        p.partial_elems = (size_t)p.nchunks * K * c;
+        return p;
+    }
     const int ntiles = ((K + 127) / 128) * ((c + 15) / 16);
     // aim for ~2048 blocks in total, at least 128 rows per block, and keep
     // the partial buffer near 32M doubles at most
@@ -715,6 +779,19 @@ TnPlan plan_tn(int n, int K, int c) {
 
 hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A, const double *B, int64_t ldb,
                                   double *partials, hipStream_t s) {
+    if (c <= 16) {
+        dim3 grid((K + 255) / 256, pl.nchunks);
+        if (c <= 4)
+            hipLaunchKernelGGL((gemm_tn_fma_kernel<4, 8>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B, ldb,
+                               partials);
+        else if (c <= 8)
+            hipLaunchKernelGGL((gemm_tn_fma_kernel<8, 8>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B, ldb,
+                               partials);
+        else
+            hipLaunchKernelGGL((gemm_tn_fma_kernel<16, 4>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B,
+                               ldb, partials);
+        return hipGetLastError();
+    }
     // 16-byte A loads need an even leading dimension and panel stride
     const bool aligned = !(A.ld & 1) && !(A.ps & 1) && !(reinterpret_cast<uintptr_t>(A.p) & 15);
     const int nt = K <= 32 ? 2 : (K <= 64 ? 4 : 8);
