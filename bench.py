@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter summary of the dominant kernel on the benchmark workload
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cheb_step_lap3d7_100_fp64_traffic.md")
-KERNEL_SOURCES = ["paper_2409_15053_amd/csrc/flp_kernels.hip", "paper_2409_15053_amd/csrc/flp_internal.h"]
+KERNEL_SOURCES = ["paper_2409_15053_amd/csrc/flp_filter.hip", "paper_2409_15053_amd/csrc/flp_device.h"]
 METRIC = "filter SpMM GB/s (% HBM roofline); eigenpairs/s; p50/p99 solve latency"
 
 WORKLOADS = {

@@ -1,0 +1,109 @@
+// Device-side helpers shared by the filter and the Gram-Schmidt kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace flp {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int NXCD = 8;
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Renumber so that each XCD receives one contiguous range of tiles:
+// neighbouring rows of the matrix then share that XCD's L2 for the gathered
+// vector entries.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    int q = G / NXCD, rem = G % NXCD;
+    int x = b % NXCD, s = b / NXCD;
+    return (x < rem) ? x * (q + 1) + s : rem * (q + 1) + (x - rem) * q + s;
+}
+
+template <typename T, int VEC>
+struct Vec;
+template <>
+struct Vec<double, 1> {
+    using type = double;
+};
+template <>
+struct Vec<double, 2> {
+    using type = double2;
+};
+template <>
+struct Vec<float, 1> {
+    using type = float;
+};
+template <>
+struct Vec<float, 2> {
+    using type = float2;
+};
+template <>
+struct Vec<float, 4> {
+    using type = float4;
+};
+
+// Loads and stores of VEC consecutive elements in 16-byte (or narrower)
+// pieces; the address is aligned to min(16, VEC * sizeof(T)) bytes.
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T *p, T (&v)[VEC]) {
+    constexpr int C = 16 / (int)sizeof(T);
+    if constexpr (VEC > C) {
+        static_assert(VEC % C == 0, "vector width must be a multiple of 16 bytes");
+#pragma unroll
+        for (int k = 0; k < VEC / C; ++k) {
+            T t[C];
+            load_vec<T, C>(p + k * C, t);
+#pragma unroll
+            for (int j = 0; j < C; ++j) v[k * C + j] = t[j];
+        }
+    } else {
+        using V = typename Vec<T, VEC>::type;
+        V x = *reinterpret_cast<const V *>(p);
+        if constexpr (VEC == 1) {
+            v[0] = x;
+        } else if constexpr (VEC == 2) {
+            v[0] = x.x;
+            v[1] = x.y;
+        } else {
+            v[0] = x.x;
+            v[1] = x.y;
+            v[2] = x.z;
+            v[3] = x.w;
+        }
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec(T *p, const T (&v)[VEC]) {
+    constexpr int C = 16 / (int)sizeof(T);
+    if constexpr (VEC > C) {
+        static_assert(VEC % C == 0, "vector width must be a multiple of 16 bytes");
+#pragma unroll
+        for (int k = 0; k < VEC / C; ++k) {
+            T t[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) t[j] = v[k * C + j];
+            store_vec<T, C>(p + k * C, t);
+        }
+    } else {
+        using V = typename Vec<T, VEC>::type;
+        V x;
+        if constexpr (VEC == 1) {
+            x = v[0];
+        } else if constexpr (VEC == 2) {
+            x.x = v[0];
+            x.y = v[1];
+        } else {
+            x.x = v[0];
+            x.y = v[1];
+            x.z = v[2];
+            x.w = v[3];
+        }
+        *reinterpret_cast<V *>(p) = x;
+    }
+}
+
+}  // namespace
+}  // namespace flp

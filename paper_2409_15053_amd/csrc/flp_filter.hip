@@ -1,0 +1,360 @@
+// Filter kernels of the filtered Lanczos procedure for gfx950 (CDNA4): one
+// Clenshaw step of the Chebyshev filter (Section 2.2) as a CSR SpMM over a
+// row-major block of r vectors, with the affine map and the three-term
+// update fused into the epilogue; the segmented form advances many solves'
+// filters in one launch.
+#include "flp_internal.h"
+#include "flp_device.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace flp {
+
+namespace {
+
+// ------------------------------------------------------------------ filter step
+//
+// Loads of the streamed operands V and U_{k+2}: with NT, nontemporal (they
+// are read once per step, so they need not displace the gathered vector
+// from the caches); otherwise as load_vec.
+template <typename T, int VEC, bool NT>
+__device__ __forceinline__ void load_stream(const T *p, T (&v)[VEC]) {
+    if constexpr (NT) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) v[i] = __builtin_nontemporal_load(p + i);
+    } else {
+        load_vec<T, VEC>(p, v);
+    }
+}
+
+// acc += sum over the row's nonzeros p0..p1-1 of val[p] * X[colind[p], c0 ..
+// c0 + VEC), in order.  The nonzeros go in groups of UNR with every load of
+// a group issued before its products: a slot past the row's end re-reads the
+// row's last entry (a valid, cached address) with weight zero, so a short row
+// costs one round of dependent loads instead of one per leftover nonzero.
+template <typename T, int VEC, int UNR>
+__device__ __forceinline__ void row_gather(int p0, int p1, const int32_t *__restrict__ colind,
+                                           const T *__restrict__ val, const T *__restrict__ X, int ldx, int c0,
+                                           T (&acc)[VEC]) {
+    for (int p = p0; p < p1; p += UNR) {
+        int cc[UNR];
+        T aa[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int q = min(p + u, p1 - 1);
+            cc[u] = colind[q];
+            const T a = val[q];
+            aa[u] = (p + u < p1) ? a : T(0);
+        }
+        T xv[UNR][VEC];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) load_vec<T, VEC>(X + (int64_t)cc[u] * ldx + c0, xv[u]);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], xv[u][v], acc[v]);
+    }
+}
+
+// nonzeros per group: 8, or 4 when each lane gathers 64 bytes per nonzero
+template <typename T, int VEC>
+struct Unroll {
+    static constexpr int value = VEC * (int)sizeof(T) >= 64 ? 4 : 8;
+};
+
+// LPR lanes share one matrix row; lane `sub` owns columns
+// [sub*VEC, sub*VEC + VEC) of the block.  All lanes of a row walk the row's
+// nonzeros together (the column index and value loads of a row coalesce to
+// one request), and each gathers its VEC contiguous entries of X[col, :].
+template <typename T, typename Tout, int LPR, int VEC, bool NT>
+__global__ __launch_bounds__(256) void cheb_step_kernel(
+    int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+    const T *__restrict__ val, int r, const T *__restrict__ X, int ldx, const T *__restrict__ V,
+    int ldv, const T *__restrict__ Y, int ldy, Tout *__restrict__ out, int ldo, T alpha, T beta,
+    T gamma, T delta) {
+    constexpr int RPB = 256 / LPR;  // rows per block
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int row = tile * RPB + threadIdx.x / LPR;
+    const int sub = threadIdx.x % LPR;
+    const int c0 = sub * VEC;
+    if (row >= n || c0 >= r) return;
+    const int p0 = rowptr[row], p1 = rowptr[row + 1];
+    T acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = T(0);
+    row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
+    T xr[VEC];
+    load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
+    T res[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) res[v] = alpha * acc[v] + beta * xr[v];
+    if (V) {
+        T vv[VEC];
+        load_stream<T, VEC, NT>(V + (int64_t)row * ldv + c0, vv);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(gamma, vv[v], res[v]);
+    }
+    if (Y) {
+        T yy[VEC];
+        load_stream<T, VEC, NT>(Y + (int64_t)row * ldy + c0, yy);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(delta, yy[v], res[v]);
+    }
+    if constexpr (sizeof(Tout) == sizeof(T)) {
+        store_vec<Tout, VEC>(out + (int64_t)row * ldo + c0, res);
+    } else {
+        Tout o[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) o[v] = (Tout)res[v];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) out[(int64_t)row * ldo + c0 + v] = o[v];
+    }
+}
+
+template <typename T, typename Tout, int LPR, int VEC, bool NT>
+hipError_t cheb_launch(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
+                       const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
+                       int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s) {
+    constexpr int RPB = 256 / LPR;
+    int grid = (n + RPB - 1) / RPB;
+    hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT>), dim3(grid), dim3(256), 0, s, n, rowptr,
+                       colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Aligned launch shapes (LPR lanes per row x VEC columns per lane) with a
+// kernel instance: FP64 in 16-, 32- and 64-byte pieces per lane, FP32 in 16-
+// and 32-byte pieces.
+#define FLP_SHAPES_F64(X) X(1, 2) X(2, 2) X(4, 2) X(8, 2) X(16, 2) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(1, 8) X(2, 8) X(4, 8)
+#define FLP_SHAPES_F32(X) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(1, 8) X(2, 8) X(4, 8)
+
+static bool shape_has_kernel(bool fp32, int lpr, int vec) {
+#define FLP_HAS(L, V) if (lpr == L && vec == V) return true;
+    if (fp32) {
+        FLP_SHAPES_F32(FLP_HAS)
+    } else {
+        FLP_SHAPES_F64(FLP_HAS)
+    }
+#undef FLP_HAS
+    return false;
+}
+
+StepShape default_step_shape(int r, bool fp32) {
+    const int v16 = fp32 ? 4 : 2;
+    if (r % v16 == 0 && shape_has_kernel(fp32, r / v16, v16)) return StepShape{r / v16, v16};
+    return StepShape{0, 0};
+}
+
+std::vector<StepShape> step_shape_candidates(int r, bool fp32) {
+    std::vector<StepShape> out;
+    for (int nt : {0, 1})
+        for (int vec : {2, 4, 8})
+            if (r % vec == 0 && shape_has_kernel(fp32, r / vec, vec)) out.push_back(StepShape{r / vec, vec, nt});
+    return out;
+}
+
+bool step_shape_ok(int r, bool fp32, StepShape sh) {
+    return sh.lpr > 0 && sh.lpr * sh.vec == r && shape_has_kernel(fp32, sh.lpr, sh.vec);
+}
+
+template <typename T, typename Tout>
+hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
+                            const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
+                            int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s, StepShape sh) {
+    if (n <= 0) return hipSuccess;
+    constexpr bool F32 = sizeof(T) == 4;
+    // vector loads need every leading dimension and base aligned to 16 bytes
+    constexpr int V16 = 16 / (int)sizeof(T);
+    auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    bool aligned16 = (ldx % V16 == 0) && (!V || ldv % V16 == 0) && (!Y || ldy % V16 == 0) &&
+                     (ldo % V16 == 0) && (sizeof(Tout) == sizeof(T)) && al(X) && al(V) && al(Y) && al(out);
+#define FLP_CHEB_NT(LPR, VEC, NT) \
+    return cheb_launch<T, Tout, LPR, VEC, NT>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s)
+#define FLP_CHEB(LPR, VEC) FLP_CHEB_NT(LPR, VEC, false)
+    if (aligned16 && r % V16 == 0) {
+        if (!step_shape_ok(r, F32, sh)) sh = default_step_shape(r, F32);
+        const int lpr = sh.lpr, vec = sh.vec;
+        const bool nt = sh.nt != 0;
+#define FLP_TRY(L, VV) \
+    if (lpr == L && vec == VV) {        \
+        if (nt) {                       \
+            FLP_CHEB_NT(L, VV, true);   \
+        } else {                        \
+            FLP_CHEB_NT(L, VV, false);  \
+        }                               \
+    }
+        if constexpr (F32) {
+            FLP_SHAPES_F32(FLP_TRY)
+        } else {
+            FLP_SHAPES_F64(FLP_TRY)
+        }
+#undef FLP_TRY
+    }
+    if (r == 1) FLP_CHEB(1, 1);
+    if (r == 2) FLP_CHEB(2, 1);
+    if (r <= 4) FLP_CHEB(4, 1);
+    if (r <= 8) FLP_CHEB(8, 1);
+    if (r <= 16) FLP_CHEB(16, 1);
+    if (r <= 32) FLP_CHEB(32, 1);
+#undef FLP_CHEB
+#undef FLP_CHEB_NT
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_cheb_step<double, double>(int, const int32_t *, const int32_t *, const double *, int,
+                                                     const double *, int, const double *, int, const double *,
+                                                     int, double *, int, double, double, double, double,
+                                                     hipStream_t, StepShape);
+template hipError_t launch_cheb_step<float, float>(int, const int32_t *, const int32_t *, const float *, int,
+                                                   const float *, int, const float *, int, const float *, int,
+                                                   float *, int, float, float, float, float, hipStream_t,
+                                                   StepShape);
+template hipError_t launch_cheb_step<float, double>(int, const int32_t *, const int32_t *, const float *, int,
+                                                    const float *, int, const float *, int, const float *, int,
+                                                    double *, int, float, float, float, float, hipStream_t,
+                                                    StepShape);
+
+// ------------------------------------------------------------------ segmented filter step
+//
+// One launch advances the filters of many independent solves by one
+// Clenshaw step: the launch's tiles are split into segments (one per solve,
+// each with its own matrix, vectors and coefficients) by a prefix sum of
+// tile counts; a block finds its segment by binary search and then runs the
+// same row mapping and fused epilogue as cheb_step_kernel.
+
+namespace {
+
+template <typename T, int LPR, int VEC, bool NT>
+__global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg) {
+    constexpr int RPB = 256 / LPR;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    // The segment holding this tile: the tile offsets ascend, so the
+    // segments starting at or before the tile are a prefix; each wave counts
+    // it 64 segments at a time with one load per lane and a ballot.  The
+    // count is the same on every lane, so it is made wave-uniform and the
+    // segment's descriptor is then read through the scalar cache.
+    const int lane = threadIdx.x % WAVE;
+    int seg = -1;
+    for (int base = 0; base < nseg; base += WAVE) {
+        const int i = base + lane;
+        const bool le = i < nseg && tab[i].tile0 <= tile;
+        const unsigned long long m = __ballot(le);
+        seg += __popcll(m);
+        if (~m != 0ull) break;
+    }
+    seg = __builtin_amdgcn_readfirstlane(seg);
+    const SegEntry &e = tab[seg];
+    const int n = e.n;
+    const int row = (tile - e.tile0) * RPB + threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * VEC;
+    if (row >= n) return;
+    const int32_t *__restrict__ rowptr = e.rowptr;
+    const int32_t *__restrict__ colind = e.colind;
+    const T *__restrict__ val = (const T *)e.val;
+    const T *__restrict__ X = (const T *)e.X;
+    const int ldx = e.ldx;
+    const int p0 = rowptr[row], p1 = rowptr[row + 1];
+    T acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = T(0);
+    row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
+    T xr[VEC];
+    load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
+    const T alpha = (T)e.alpha, beta = (T)e.beta, gamma = (T)e.gamma, delta = (T)e.delta;
+    T res[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) res[v] = alpha * acc[v] + beta * xr[v];
+    if (e.V) {
+        T vv[VEC];
+        load_stream<T, VEC, NT>((const T *)e.V + (int64_t)row * e.ldv + c0, vv);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(gamma, vv[v], res[v]);
+    }
+    if (e.Y) {
+        T yy[VEC];
+        load_stream<T, VEC, NT>((const T *)e.Y + (int64_t)row * e.ldy + c0, yy);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) res[v] = fma(delta, yy[v], res[v]);
+    }
+    if (e.out_f64) {
+        double *o = (double *)e.out + (int64_t)row * e.ldo + c0;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) o[v] = (double)res[v];
+    } else {
+        store_vec<T, VEC>((T *)e.out + (int64_t)row * e.ldo + c0, res);
+    }
+}
+
+}  // namespace
+
+// Shape of the segmented kernel: the tuned or default aligned shape when
+// one exists for r, else one lane per column.  seg_rows_per_tile and
+// launch_cheb_seg must agree, so both resolve the shape here.
+static StepShape seg_shape(int r, bool fp32, StepShape sh) {
+    if (step_shape_ok(r, fp32, sh)) return sh;
+    StepShape d = default_step_shape(r, fp32);
+    if (d.lpr > 0) return d;
+    const int l = r == 1 ? 1 : (r == 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32))));
+    return StepShape{l, 1};
+}
+
+int seg_rows_per_tile(int r, bool fp32, StepShape sh) { return 256 / seg_shape(r, fp32, sh).lpr; }
+
+hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s,
+                           StepShape sh) {
+    if (nseg <= 0 || total_tiles <= 0) return hipSuccess;
+    sh = seg_shape(r, fp32, sh);
+    const int lpr = sh.lpr, vec = sh.vec;
+    const bool nt = sh.nt != 0;
+#define FLP_SEG_NT(T, LPR, VEC, NT) \
+    { \
+        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC, NT>), dim3(total_tiles), dim3(256), 0, s, tab, nseg); \
+        return hipGetLastError(); \
+    }
+#define FLP_SEG(T, LPR, VEC) FLP_SEG_NT(T, LPR, VEC, false)
+#define FLP_SEG64(L, VV) \
+    if (lpr == L && vec == VV) { \
+        if (nt) \
+            FLP_SEG_NT(double, L, VV, true) \
+        else \
+            FLP_SEG_NT(double, L, VV, false) \
+    }
+#define FLP_SEG32(L, VV) \
+    if (lpr == L && vec == VV) { \
+        if (nt) \
+            FLP_SEG_NT(float, L, VV, true) \
+        else \
+            FLP_SEG_NT(float, L, VV, false) \
+    }
+    if (!fp32) {
+        FLP_SHAPES_F64(FLP_SEG64)
+        if (vec == 1) {
+            if (lpr == 1) FLP_SEG(double, 1, 1);
+            if (lpr == 2) FLP_SEG(double, 2, 1);
+            if (lpr == 4) FLP_SEG(double, 4, 1);
+            if (lpr == 8) FLP_SEG(double, 8, 1);
+            if (lpr == 16) FLP_SEG(double, 16, 1);
+            if (lpr == 32) FLP_SEG(double, 32, 1);
+        }
+    } else {
+        FLP_SHAPES_F32(FLP_SEG32)
+        if (vec == 1) {
+            if (lpr == 1) FLP_SEG(float, 1, 1);
+            if (lpr == 2) FLP_SEG(float, 2, 1);
+            if (lpr == 4) FLP_SEG(float, 4, 1);
+            if (lpr == 8) FLP_SEG(float, 8, 1);
+            if (lpr == 16) FLP_SEG(float, 16, 1);
+            if (lpr == 32) FLP_SEG(float, 32, 1);
+        }
+    }
+#undef FLP_SEG64
+#undef FLP_SEG32
+#undef FLP_SEG
+#undef FLP_SEG_NT
+    return hipErrorInvalidValue;
+}
+
+}  // namespace flp
