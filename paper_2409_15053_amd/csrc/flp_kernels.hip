@@ -255,15 +255,16 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, doubl
 
 namespace {
 
-// C partial (K x c, c <= C) over one chunk of rows without MFMA: thread q
-// owns column q of A and accumulates its c dot products with B over the
-// chunk's rows in order.  The B row is the same for the whole block (the
-// rows are walked in step), so it is read through the scalar cache; the A
-// loads of a wave are 64 consecutive doubles of one row.  With c <= 16
-// this product does 2c flops per 8-byte A element, far below what the FMA
-// units sustain at HBM speed, so it needs no matrix cores.
+// C partial (K x C) over one chunk of rows without MFMA, for B of exactly
+// C columns: thread q owns column q of A and accumulates its C dot products
+// with B over the chunk's rows in order.  The B row is the same for the
+// whole block (the rows are walked in step), so it is read through the
+// scalar cache as one wide load; the A loads of a wave are 64 consecutive
+// doubles of one row.  With C <= 16 this product does 2C flops per 8-byte A
+// element, far below what the FMA units sustain at HBM speed, so it needs
+// no matrix cores.
 template <int C, int UNR>
-__global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int c, int chunk_rows, DMat A,
+__global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int chunk_rows, DMat A,
                                                           const double *__restrict__ B, int64_t ldb,
                                                           double *__restrict__ partials) {
     const int q = blockIdx.x * 256 + threadIdx.x;
@@ -283,28 +284,32 @@ __global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int c, i
         for (int u = 0; u < UNR; ++u) {
             const double *b = B + (int64_t)(row + u) * ldb;
 #pragma unroll
-            for (int j = 0; j < C; ++j) acc[j] = fma(a[u], j < c ? b[min(j, c - 1)] : 0.0, acc[j]);
+            for (int j = 0; j < C; ++j) acc[j] = fma(a[u], b[j], acc[j]);
         }
     }
     for (; row < r1; ++row) {
         const double a = col[(int64_t)row * lda];
         const double *b = B + (int64_t)row * ldb;
 #pragma unroll
-        for (int j = 0; j < C; ++j) acc[j] = fma(a, j < c ? b[min(j, c - 1)] : 0.0, acc[j]);
+        for (int j = 0; j < C; ++j) acc[j] = fma(a, b[j], acc[j]);
     }
     if (q < K) {
-        double *d = partials + ((size_t)chunk * K + q) * c;
+        double *d = partials + ((size_t)chunk * K + q) * C;
 #pragma unroll
-        for (int j = 0; j < C; ++j)
-            if (j < c) d[j] = acc[j];
+        for (int j = 0; j < C; ++j) d[j] = acc[j];
     }
 }
 
 }  // namespace
 
+// The FMA projection serves B of exactly 8 or 16 columns against a basis
+// of at least 256 columns (thread per column: fewer columns leave most lanes
+// idle, where the MFMA kernel's row-parallel layout does better).
+static bool tn_use_fma(int K, int c) { return (c == 8 || c == 16) && K >= 256; }
+
 TnPlan plan_tn(int n, int K, int c) {
     TnPlan p;
-    if (c <= 16) {
+    if (tn_use_fma(K, c)) {
         // FMA path: about 2048 blocks of 256 columns x chunk_rows rows, the
         // partial buffer kept near 32M doubles at most
         const int ncb = (K + 255) / 256;
@@ -334,17 +339,14 @@ TnPlan plan_tn(int n, int K, int c) {
 
 hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A, const double *B, int64_t ldb,
                                   double *partials, hipStream_t s) {
-    if (c <= 16) {
+    if (tn_use_fma(K, c)) {
         dim3 grid((K + 255) / 256, pl.nchunks);
-        if (c <= 4)
-            hipLaunchKernelGGL((gemm_tn_fma_kernel<4, 8>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B, ldb,
-                               partials);
-        else if (c <= 8)
-            hipLaunchKernelGGL((gemm_tn_fma_kernel<8, 8>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B, ldb,
+        if (c == 8)
+            hipLaunchKernelGGL((gemm_tn_fma_kernel<8, 8>), grid, dim3(256), 0, s, n, K, pl.chunk_rows, A, B, ldb,
                                partials);
         else
-            hipLaunchKernelGGL((gemm_tn_fma_kernel<16, 4>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B,
-                               ldb, partials);
+            hipLaunchKernelGGL((gemm_tn_fma_kernel<16, 4>), grid, dim3(256), 0, s, n, K, pl.chunk_rows, A, B, ldb,
+                               partials);
         return hipGetLastError();
     }
     // 16-byte A loads need an even leading dimension and panel stride
