@@ -268,9 +268,10 @@ __global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int chun
                                                           const double *__restrict__ B, int64_t ldb,
                                                           double *__restrict__ partials) {
     const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= K) return;  // no block-level synchronisation follows: idle columns leave at once
     const int chunk = blockIdx.y;
     const int r0 = chunk * chunk_rows, r1 = min(n, r0 + chunk_rows);
-    const double *col = col_base(A, min(q, K - 1));
+    const double *col = col_base(A, q);
     const int64_t lda = A.ld;
     double acc[C];
 #pragma unroll
@@ -293,11 +294,9 @@ __global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int chun
 #pragma unroll
         for (int j = 0; j < C; ++j) acc[j] = fma(a, b[j], acc[j]);
     }
-    if (q < K) {
-        double *d = partials + ((size_t)chunk * K + q) * C;
+    double *d = partials + ((size_t)chunk * K + q) * C;
 #pragma unroll
-        for (int j = 0; j < C; ++j) d[j] = acc[j];
-    }
+    for (int j = 0; j < C; ++j) d[j] = acc[j];
 }
 
 }  // namespace
