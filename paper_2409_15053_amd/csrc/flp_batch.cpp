@@ -91,6 +91,7 @@ int Engine::init(int r_, int prec_, bool graph_) {
     CK(hipGetDevice(&device));
     CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     for (auto &f : fs) CK(hipStreamCreateWithFlags(&f, hipStreamNonBlocking));
+    for (auto &p : ps) CK(hipStreamCreateWithFlags(&p, hipStreamNonBlocking));
     CK(hipEventCreate(&ev_a));
     CK(hipEventCreate(&ev_b));
     for (int w = 0; w < kFinishers; ++w) fin[w] = std::thread([this, w]() { finisher_main(w); });
@@ -110,6 +111,8 @@ Engine::~Engine() {
     if (ev_b) (void)hipEventDestroy(ev_b);
     for (auto &f : fs)
         if (f) (void)hipStreamDestroy(f);
+    for (auto &p : ps)
+        if (p) (void)hipStreamDestroy(p);
     if (s) (void)hipStreamDestroy(s);
 }
 
@@ -131,6 +134,7 @@ void Engine::finisher_main(int w) {
         }
         const double t0 = now();
         j->S->s = fs[w];
+        j->S->part = nullptr;  // the finisher thread's own workspace
         j->code = solve_finish(*j->S, &j->res);
         if (j->code != FLP_OK && j->code != FLP_E_NOCONV) j->msg = last_error_cstr();
         j->t_done = now();
@@ -168,12 +172,24 @@ void Engine::graph_reset() {
 }
 
 void Engine::add(Job *j) {
+    // the solve's set-up ran on s; its block steps run on a phase stream
+    (void)hipStreamSynchronize(s);
+    j->S->s = ps[next_ps];
+    j->S->part = &ppart[next_ps];
+    next_ps = (next_ps + 1) % kPhaseStreams;
     active.push_back(j);
     tables_valid = false;
 }
 
+int Engine::sync_phase_streams() {
+    for (auto &p : ps) CK(hipStreamSynchronize(p));
+    return FLP_OK;
+}
+
 int Engine::step() {
     if (active.empty()) return FLP_OK;
+    // the previous step's basis and input copies must land before the filter
+    CKR(sync_phase_streams());
     std::vector<Solve *> act;
     for (Job *j : active) act.push_back(j->S.get());
     if (!tables_valid) {
@@ -230,9 +246,9 @@ int Engine::step() {
     };
     for (Solve *S : act) S->st.t_mv += ms * 1e-3;
     run_phase(step_orth_launch);
-    CK(hipStreamSynchronize(s));
+    CKR(sync_phase_streams());
     run_phase(step_qr1);
-    CK(hipStreamSynchronize(s));
+    CKR(sync_phase_streams());
     run_phase(step_qr2);
     // convergence checks: applied when their pool task has finished, started
     // at the cadence (the solves keep stepping meanwhile)
@@ -245,8 +261,8 @@ int Engine::step() {
             done.push_back(j);
     }
     if (!done.empty()) {
-        // the finisher reads what this stream wrote (the basis)
-        CK(hipStreamSynchronize(s));
+        // the finishers read what the phase streams wrote (the basis)
+        CKR(sync_phase_streams());
         for (Job *j : done) {
             if (j->code == FLP_OK) {
                 {

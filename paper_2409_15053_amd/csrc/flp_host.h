@@ -150,9 +150,11 @@ void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, 
 void upper_inverse(int r, const std::vector<double> &R, std::vector<double> &Ri);
 void matmul_upper(int r, const std::vector<double> &A, const std::vector<double> &B, std::vector<double> &C);
 
+// part: partial-sum scratch (null: the calling thread's workspace); work
+// that runs on several streams at once needs one per stream
 int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *dev_out, double *host_out,
-            hipStream_t s);
-int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s);
+            hipStream_t s, Buf *part = nullptr);
+int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s, Buf *part = nullptr);
 int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<double> &S, uint64_t seed,
                   uint64_t sid, hipStream_t s, bool *replaced, int depth = 0);
 int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s);
@@ -199,6 +201,7 @@ struct Solve {
     flp_opts o{};
     hipStream_t s = nullptr;
     SolveBufs *B = nullptr;
+    Buf *part = nullptr;  // partial-sum scratch of the solve's stream (null: the thread's workspace)
     // derived
     int n = 0, r = 0;
     double lmin = 0, lmax = 0, tau = 0, tol_p = 0;
@@ -323,8 +326,17 @@ struct Engine {
     void wait_finisher();
     // engine statistics including the finisher's time
     flp_batch_stats snapshot();
+    // waits for the per-solve work of the block steps issued so far
+    int sync_phase_streams();
 
   private:
+    // per-solve work of a block step (Gram-Schmidt, block QR, basis copies)
+    // goes to these streams round-robin, so independent solves' small
+    // kernels overlap on the device; the shared filter launches stay on s
+    static constexpr int kPhaseStreams = 8;
+    hipStream_t ps[kPhaseStreams] = {};
+    Buf ppart[kPhaseStreams];  // partial-sum scratch, one per phase stream
+    int next_ps = 0;
     // finishers: Ritz vectors, Rayleigh-Ritz and polish of converged solves,
     // each on its own host thread and stream, overlapping later block steps
     static constexpr int kFinishers = 4;

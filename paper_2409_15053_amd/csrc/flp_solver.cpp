@@ -128,13 +128,13 @@ int step_orth_launch(Solve &S) {
     S.st.filter_bytes += filter_step_bytes(n, S.A->nnz, r, S.o.prec) * S.filt->m;
     S.st.mv += (int64_t)r * S.filt->m;
     // full reorthogonalisation (Section 3.2.2): two passes of classical Gram-Schmidt
-    CKR(cgs2(S.Q, k, n, S.W, r, S.hdev, s));
+    CKR(cgs2(S.Q, k, n, S.W, r, S.hdev, s, S.part));
     const size_t rr = (size_t)r * r;
     CK(hipMemcpyAsync(S.pin, S.hdev + (size_t)(k - r) * r, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
     CK(hipMemcpyAsync(S.pin + rr, S.hdev + (size_t)k * r + (size_t)(k - r) * r, sizeof(double) * rr,
                       hipMemcpyDeviceToHost, s));
     // Gram matrix of the projected block (first Cholesky QR pass)
-    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s));
+    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s, S.part));
     CK(hipMemcpyAsync(S.pin + 2 * rr, S.gdev, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
     return FLP_OK;
 }
@@ -167,7 +167,7 @@ int step_qr1(Solve &S) {
     std::memcpy(S.pin + 3 * rr, Ri.data(), sizeof(double) * rr);
     CK(hipMemcpyAsync(S.rdev, S.pin + 3 * rr, sizeof(double) * rr, hipMemcpyHostToDevice, s));
     CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(S.W, r), S.rdev, r, 0.0, S.W, r, s));
-    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s));
+    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s, S.part));
     CK(hipMemcpyAsync(S.pin + 2 * rr, S.gdev, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
     return FLP_OK;
 }
