@@ -214,7 +214,7 @@ def test_filter_apply_errors(torch):
 
 @pytest.mark.parametrize("n,k,r", [(1000, 1, 1), (1000, 7, 3), (5003, 48, 8), (20011, 160, 16), (777, 16, 16),
                                    # bases of 256+ columns against 8 and 16 columns: the FMA projection
-                                   (30011, 300, 8), (20011, 520, 16), (4099, 256, 8)])
+                                   (30011, 300, 8), (20011, 520, 16), (4099, 256, 8), (9001, 130, 8)])
 def test_block_orth_parity(torch, n, k, r):
     g = np.random.Generator(np.random.PCG64(n + k))
     Q, _ = np.linalg.qr(g.standard_normal((n, k)))
