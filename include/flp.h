@@ -32,6 +32,7 @@
 #ifndef FLP_H
 #define FLP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -47,6 +48,7 @@ extern "C" {
 #define FLP_E_NOCONV     -5  /* basis limit reached before convergence (result still returned) */
 #define FLP_E_DEVICE     -6  /* HIP runtime error; message in flp_last_error() */
 #define FLP_E_PENDING    -7  /* serving: the request has not finished yet (flp_server_poll) */
+#define FLP_E_CANCELLED  -8  /* serving: the request was cancelled (flp_server_cancel) */
 
 /* precision of the filter recurrence (Section 2.2 applies p(A) by Clenshaw) */
 #define FLP_PREC_FP64         0  /* FP64 matrix values, vectors and accumulation */
@@ -86,6 +88,7 @@ typedef struct flp_opts {
     const double *start;  /* HOST n x block row-major start block, or NULL (random) */
     double lmin, lmax;    /* spectrum bounds to use if lmin < lmax; else estimated */
     void *stream;         /* hipStream_t, NULL = default stream */
+    double sym_tol;       /* >= 0: run flp_check_symmetric(A, sym_tol) first; < 0 (default): skip */
 } flp_opts;
 
 typedef struct flp_stats {
@@ -341,6 +344,13 @@ int flp_server_submit(flp_server *sv, const flp_csr *A, double alpha, double bet
 int flp_server_poll(flp_server *sv, uint64_t ticket, flp_result **out);
 /* As flp_server_poll, but blocks until the request has finished. */
 int flp_server_wait(flp_server *sv, uint64_t ticket, flp_result **out);
+/* Cancel a request that has not completed: a queued one is dropped at
+ * once, a running one at its next block-step boundary (its device memory
+ * returns to the admission budget); flp_server_poll/wait then return
+ * FLP_E_CANCELLED with *out = NULL.  A request whose result is already
+ * ready, or being assembled, is not affected.  Thread-safe.  Errors:
+ * FLP_E_ARG (unknown ticket). */
+int flp_server_cancel(flp_server *sv, uint64_t ticket);
 /* Engine statistics so far (solves = requests submitted). */
 int flp_server_stats(flp_server *sv, flp_batch_stats *out);
 /* Finish every queued request, stop the worker, free unretrieved results. */
@@ -358,6 +368,27 @@ int flp_host_sym_eig(int32_t N, int32_t bw, const double *M, double *evals, doub
 
 /* Free the calling thread's workspace on the current device. */
 void flp_release_workspace(void);
+
+/* Device memory.  By default the library allocates with hipMalloc and frees
+ * with hipFree.  flp_set_allocator routes every later device allocation
+ * (workspace, solve buffers, result eigenvectors) through alloc/free instead
+ * (for example a framework's caching allocator); alloc returns NULL on
+ * failure (reported as FLP_E_NOMEM).  Memory always goes back to the pair
+ * that allocated it, and the device is synchronised before it is handed to
+ * a caller's free function.  NULL, NULL restores hipMalloc/hipFree.  Change
+ * the setting while no call is running; the functions may be called from
+ * the library's own threads (server worker, finishers). */
+typedef void *(*flp_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*flp_free_fn)(void *ptr, void *ctx);
+void flp_set_allocator(flp_alloc_fn alloc, flp_free_fn free_fn, void *ctx);
+
+/* Opt-in symmetry check, O(nnz) on the device (the library assumes
+ * A = A^T with both triangles stored, Section 3.2.1): every stored a_ij
+ * needs a stored a_ji with |a_ij - a_ji| <= tol * max(|a_ij|, |a_ji|)
+ * (tol >= 0; 0 asks for equality).  Synchronous.  Returns FLP_OK, or
+ * FLP_E_NOTSYM with the number of failing entries in flp_last_error(), or
+ * FLP_E_ARG / FLP_E_DEVICE. */
+int flp_check_symmetric(const flp_csr *A, double tol, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *flp_last_error(void);

@@ -32,6 +32,7 @@ void flp_opts_default(flp_opts *o) {
     o->lmin = 0.0;
     o->lmax = 0.0;
     o->stream = nullptr;
+    o->sym_tol = -1.0;
 }
 
 int flp_build_filter(double alpha, double beta, int32_t degree, double lmin, double lmax, flp_filter **out) {
@@ -207,7 +208,7 @@ void flp_result_free(flp_result *res) {
     if (!res) return;
     delete[] res->evals;
     delete[] res->resid;
-    if (res->evecs) (void)hipFree(res->evecs);
+    if (res->evecs) (void)dev_free(res->evecs);
     delete res;
 }
 
@@ -246,6 +247,17 @@ int flp_host_sym_eig(int32_t N, int32_t bw, const double *M, double *evals, doub
         return fail(FLP_E_NOMEM, "host allocation failed");
     }
     return FLP_OK;
+}
+
+void flp_set_allocator(flp_alloc_fn alloc, flp_free_fn free_fn, void *ctx) { set_allocator(alloc, free_fn, ctx); }
+
+int flp_check_symmetric(const flp_csr *A, double tol, void *stream) {
+    CKR(check_csr(A));
+    try {
+        return check_symmetric(A, tol, (hipStream_t)stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FLP_E_NOMEM, "host allocation failed");
+    }
 }
 
 void flp_release_workspace(void) {

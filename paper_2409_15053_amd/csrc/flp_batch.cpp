@@ -135,8 +135,13 @@ void Engine::finisher_main(int w) {
         const double t0 = now();
         j->S->s = fs[w];
         j->S->part = nullptr;  // the finisher thread's own workspace
-        j->code = solve_finish(*j->S, &j->res);
-        if (j->code != FLP_OK && j->code != FLP_E_NOCONV) j->msg = last_error_cstr();
+        if (j->cancel.load()) {
+            j->code = FLP_E_CANCELLED;
+            j->msg = "request cancelled";
+        } else {
+            j->code = solve_finish(*j->S, &j->res);
+            if (j->code != FLP_OK && j->code != FLP_E_NOCONV) j->msg = last_error_cstr();
+        }
         j->t_done = now();
         j->B.reset();  // release this solve's device memory
         {
@@ -190,6 +195,24 @@ int Engine::step() {
     if (active.empty()) return FLP_OK;
     // the previous step's basis and input copies must land before the filter
     CKR(sync_phase_streams());
+    // cancelled requests leave at the step boundary
+    {
+        std::vector<Job *> keep;
+        for (Job *j : active) {
+            if (!j->cancel.load()) {
+                keep.push_back(j);
+                continue;
+            }
+            j->code = FLP_E_CANCELLED;
+            j->msg = "request cancelled";
+            j->t_done = now();
+            j->B.reset();
+            complete(j);
+            tables_valid = false;
+        }
+        active.swap(keep);
+        if (active.empty()) return FLP_OK;
+    }
     std::vector<Solve *> act;
     for (Job *j : active) act.push_back(j->S.get());
     if (!tables_valid) {

@@ -19,6 +19,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "flp_host.h"
@@ -41,12 +42,69 @@ double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// ------------------------------------------------------------------ device memory
+//
+// Every device allocation of the library goes through dev_alloc/dev_free:
+// hipMalloc/hipFree, or the caller's functions set by flp_set_allocator.
+// Each allocation remembers which pair made it, so memory is always returned
+// to its own allocator even if the setting changes in between.  A caller's
+// free function cannot see work still queued on the library's streams, so
+// the device is synchronised before memory is handed back to it.
+
+namespace {
+struct Allocator {
+    flp_alloc_fn alloc = nullptr;
+    flp_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+std::unordered_map<void *, Allocator> &custom_allocs() {
+    static std::unordered_map<void *, Allocator> m;
+    return m;
+}
+}  // namespace
+
+void set_allocator(flp_alloc_fn alloc, flp_free_fn free, void *ctx) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = (alloc && free) ? Allocator{alloc, free, ctx} : Allocator{};
+}
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+    Allocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        a = g_alloc;
+    }
+    if (!a.alloc) return hipMalloc(p, bytes);
+    *p = a.alloc(bytes, a.ctx);
+    if (!*p) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    custom_allocs()[*p] = a;
+    return hipSuccess;
+}
+
+hipError_t dev_free(void *p) {
+    if (!p) return hipSuccess;
+    Allocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        auto it = custom_allocs().find(p);
+        if (it == custom_allocs().end()) return hipFree(p);
+        a = it->second;
+        custom_allocs().erase(it);
+    }
+    const hipError_t e = hipDeviceSynchronize();
+    a.free(p, a.ctx);
+    return e;
+}
+
 // ------------------------------------------------------------------ workspace
 
 Buf::~Buf() { release(); }
 
 void Buf::release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)dev_free(p);
     p = nullptr;
     bytes = 0;
 }
@@ -54,13 +112,13 @@ void Buf::release() {
 hipError_t ensure(Buf &b, size_t bytes) {
     if (b.bytes >= bytes && b.p) return hipSuccess;
     if (b.p) {
-        hipError_t e = hipFree(b.p);
+        hipError_t e = dev_free(b.p);
         b.p = nullptr;
         b.bytes = 0;
         if (e != hipSuccess) return e;
     }
     size_t want = std::max<size_t>(bytes, 256);
-    hipError_t e = hipMalloc(&b.p, want);
+    hipError_t e = dev_alloc(&b.p, want);
     if (e != hipSuccess) {
         b.p = nullptr;
         (void)hipGetLastError();
@@ -422,6 +480,20 @@ hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
     hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
+}
+
+int check_symmetric(const flp_csr *A, double tol, hipStream_t s) {
+    if (!(tol >= 0.0)) return fail(FLP_E_ARG, "symmetry tolerance must be >= 0");
+    double *dev = nullptr;
+    CKR(small_dev(8, &dev));
+    unsigned int *bad = reinterpret_cast<unsigned int *>(dev);
+    CK(hipMemsetAsync(bad, 0, sizeof(unsigned int), s));
+    CK(launch_sym_check(A->n, A->rowptr, A->colind, A->val, tol, bad, s));
+    unsigned int h = 0;
+    CK(hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (h) return fail(FLP_E_NOTSYM, "matrix is not symmetric: " + std::to_string(h) + " entries without a matching transpose entry");
+    return FLP_OK;
 }
 
 int small_dev(size_t elems, double **out) {

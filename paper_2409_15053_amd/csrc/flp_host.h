@@ -90,6 +90,13 @@ struct Workspace {
 };
 Workspace &ws();
 
+// Device allocations of the library (hipMalloc/hipFree, or the caller's
+// allocator set by flp_set_allocator).
+hipError_t dev_alloc(void **p, size_t bytes);
+hipError_t dev_free(void *p);
+void set_allocator(flp_alloc_fn alloc, flp_free_fn free, void *ctx);
+int check_symmetric(const flp_csr *A, double tol, hipStream_t s);
+
 int check_csr(const flp_csr *A);
 hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s);
 int small_dev(size_t elems, double **out);
@@ -289,6 +296,7 @@ struct Job {
     flp_csr A{};            // the caller's matrix descriptor
     std::string msg;        // error message of a failed request
     bool finished = false;  // result handed back (set under the owner's lock)
+    std::atomic<bool> cancel{false};  // cancellation requested (serving)
 };
 
 // Advances a set of active solves in lockstep: per block step, one

@@ -147,6 +147,10 @@ hipError_t launch_gemm_nn(int n, int K, int c, double alpha, DMat A, const doubl
 hipError_t launch_gershgorin(int n, const int32_t *rowptr, const int32_t *colind, const double *val,
                              double *part, int part_cap, double *out, hipStream_t s);
 int gershgorin_blocks(int n);
+// *bad += entries a_ij of A without a stored a_ji within tol (relative); *bad
+// must be zeroed first.  Columns must be sorted within each row.
+hipError_t launch_sym_check(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double tol,
+                            unsigned int *bad, hipStream_t s);
 
 // N(0,1) entries from a counter-based generator: out[i] for i < count, with
 // leading-dimension layout rows x cols (ld).

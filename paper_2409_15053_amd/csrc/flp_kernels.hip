@@ -398,6 +398,43 @@ hipError_t launch_gemm_nn(int n, int K, int c, double alpha, DMat A, const doubl
 
 namespace {
 
+// Symmetry check, one thread per row: for each stored a_ij, a_ji is looked
+// up by binary search in row j (columns sorted) and compared; the count of
+// entries without a matching partner goes to *bad (vector atomics).
+__global__ void sym_check_kernel(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                                 const double *__restrict__ val, double tol, unsigned int *bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned int cnt = 0;
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        const int j = colind[p];
+        if (j < 0 || j >= n) {
+            ++cnt;
+            continue;
+        }
+        int lo = rowptr[j], hi = rowptr[j + 1] - 1, found = -1;
+        while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const int cm = colind[mid];
+            if (cm == i) {
+                found = mid;
+                break;
+            }
+            if (cm < i)
+                lo = mid + 1;
+            else
+                hi = mid - 1;
+        }
+        if (found < 0) {
+            ++cnt;
+            continue;
+        }
+        const double a = val[p], b = val[found];
+        if (fabs(a - b) > tol * fmax(fabs(a), fabs(b))) ++cnt;
+    }
+    if (cnt) atomicAdd(bad, cnt);
+}
+
 __global__ void gershgorin_kernel(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
                                   const double *__restrict__ val, double *__restrict__ part) {
     __shared__ double slo[256], shi[256];
@@ -552,6 +589,13 @@ __global__ void transpose_out_kernel(int n, int c, const double *__restrict__ sr
 }  // namespace
 
 int gershgorin_blocks(int n) { return (n + 255) / 256; }
+
+hipError_t launch_sym_check(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double tol,
+                            unsigned int *bad, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sym_check_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, rowptr, colind, val, tol, bad);
+    return hipGetLastError();
+}
 
 hipError_t launch_gershgorin(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double *part,
                              int part_cap, double *out, hipStream_t s) {

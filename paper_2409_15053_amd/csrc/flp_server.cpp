@@ -150,6 +150,27 @@ int take_result(flp_server *sv, std::map<uint64_t, std::unique_ptr<Job>>::iterat
     return code;
 }
 
+int cancel_request(flp_server *sv, uint64_t ticket) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(ticket);
+    if (it == sv->jobs.end()) return fail(FLP_E_ARG, "unknown ticket");
+    Job *j = it->second.get();
+    if (j->finished) return FLP_OK;  // the result is ready: nothing to cancel
+    auto q = std::find(sv->pending.begin(), sv->pending.end(), j);
+    if (q != sv->pending.end()) {
+        // still queued: it never touched the device
+        sv->pending.erase(q);
+        j->code = FLP_E_CANCELLED;
+        j->msg = "request cancelled";
+        j->t_done = now();
+        j->finished = true;
+        sv->cv_done.notify_all();
+        return FLP_OK;
+    }
+    j->cancel.store(true);  // the engine or a finisher drops it
+    return FLP_OK;
+}
+
 }  // namespace
 }  // namespace flp
 
@@ -254,6 +275,11 @@ int flp_server_wait(flp_server *sv, uint64_t ticket, flp_result **out) {
     Job *j = it->second.get();
     sv->cv_done.wait(lk, [&] { return j->finished; });
     return take_result(sv, it, out);
+}
+
+int flp_server_cancel(flp_server *sv, uint64_t ticket) {
+    if (!sv) return fail(FLP_E_ARG, "NULL argument");
+    return cancel_request(sv, ticket);
 }
 
 int flp_server_stats(flp_server *sv, flp_batch_stats *out) {

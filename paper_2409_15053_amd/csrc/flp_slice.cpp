@@ -119,7 +119,7 @@ int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, 
     if (cnt > 0) {
         R->evals = new double[cnt];
         R->resid = new double[cnt];
-        CK(hipMalloc(&R->evecs, sizeof(double) * (size_t)n * cnt));
+        CK(dev_alloc((void **)&R->evecs, sizeof(double) * (size_t)n * cnt));
         int w = 0;
         for (size_t p = 0; p < keep.size(); ++p) {
             if (drop[p]) continue;

@@ -54,6 +54,7 @@ int solve_setup(Solve &S) {
         return fail(FLP_E_ARG, "need finite alpha < beta");
     if (o.prec != FLP_PREC_FP64 && o.prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
     const bool fp32 = o.prec == FLP_PREC_FP32_FILTER;
+    if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
 
     // PREPROC: spectrum bounds
     double t0 = now();
@@ -426,7 +427,7 @@ int solve_finish(Solve &S, flp_result **out) {
                 res->evals[j] = lam[i0 + j];
                 res->resid[j] = rres[i0 + j] / anorm;
             }
-            CK(hipMalloc(&res->evecs, sizeof(double) * (size_t)n * cnt));
+            CK(dev_alloc((void **)&res->evecs, sizeof(double) * (size_t)n * cnt));
             CK(launch_transpose_out(n, cnt, X + i0, ldc, res->evecs, s));
             CK(hipStreamSynchronize(s));
         }

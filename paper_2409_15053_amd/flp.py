@@ -22,6 +22,7 @@ FLP_E_NOMEM = -4
 FLP_E_NOCONV = -5
 FLP_E_DEVICE = -6
 FLP_E_PENDING = -7
+FLP_E_CANCELLED = -8
 FLP_PREC_FP64 = 0
 FLP_PREC_FP32_FILTER = 1
 
@@ -30,9 +31,9 @@ EXPORTS = [
     "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval",
     "flp_filter_apply", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_sliced", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
-    "flp_release_workspace", "flp_last_error", "flp_version",
+    "flp_release_workspace", "flp_set_allocator", "flp_check_symmetric", "flp_last_error", "flp_version",
     "flp_server_opts_default", "flp_server_create", "flp_server_submit", "flp_server_poll",
-    "flp_server_wait", "flp_server_stats", "flp_server_destroy",
+    "flp_server_wait", "flp_server_cancel", "flp_server_stats", "flp_server_destroy",
 ]
 
 
@@ -59,7 +60,7 @@ class FlpOptsC(ctypes.Structure):
                 ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("max_basis", ctypes.c_int64), ("k0", ctypes.c_int32),
                 ("start", ctypes.c_void_p), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("sym_tol", ctypes.c_double)]
 
 
 class FlpStatsC(ctypes.Structure):
@@ -129,6 +130,9 @@ def load(path: str = LIB_PATH):
         "flp_result_copy_evecs": (ctypes.c_int, [ctypes.POINTER(FlpResultC), P, P]),
         "flp_host_sym_eig": (ctypes.c_int, [I32, I32, P, P, P]),
         "flp_release_workspace": (None, []),
+        "flp_set_allocator": (None, [P, P, P]),
+        "flp_check_symmetric": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), F64, P]),
+        "flp_server_cancel": (ctypes.c_int, [P, U64]),
         "flp_server_opts_default": (None, [ctypes.POINTER(FlpServerOptsC)]),
         "flp_server_create": (ctypes.c_int, [ctypes.POINTER(FlpServerOptsC), PP]),
         "flp_server_submit": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), F64, F64, ctypes.POINTER(FlpOptsC),
@@ -307,10 +311,11 @@ def default_opts() -> FlpOptsC:
 def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: int = 0, seed: int = 0,
               prec: int = FLP_PREC_FP64, start: np.ndarray | None = None, bounds=None, max_basis: int = 0,
               check_every: int = 0, eps: float = 0.0, k0: int = 0, want_vectors: bool = True,
-              stream=None) -> dict:
+              stream=None, sym_tol: float = -1.0) -> dict:
     """Every eigenpair of A in [alpha, beta].  Returns a dict with numpy
     ``evals``/``resid``, a torch ``evecs`` (n x count, float64, on A's
-    device) and the solve statistics."""
+    device) and the solve statistics.  ``sym_tol >= 0`` checks A for
+    symmetry first (FLP_E_NOTSYM if it is not)."""
     import torch
     lib = load()
     o = default_opts()
@@ -332,6 +337,7 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
     if bounds is not None:
         o.lmin, o.lmax = bounds
     o.stream = _stream_ptr(stream)
+    o.sym_tol = sym_tol
     res = ctypes.POINTER(FlpResultC)()
     rc = lib.flp_solve(ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(res))
     _check(rc, allow=(FLP_E_NOCONV,))
@@ -475,10 +481,15 @@ class Server:
         self._keep[t.value] = A  # the matrix must outlive the request
         return t.value
 
+    def cancel(self, ticket: int):
+        """Cancel a request that has not completed (wait/poll then raise
+        FlpError with code FLP_E_CANCELLED)."""
+        _check(load().flp_server_cancel(self.h, ticket))
+
     def _finish(self, ticket, rc, res, want_vectors):
+        A = self._keep.pop(ticket, None)
         try:
             _check(rc, allow=(FLP_E_NOCONV,))
-            A = self._keep.pop(ticket)
             d = _collect(res, A.n, A.val.device, want_vectors, None)
             d["rc"] = rc
             return d
@@ -514,6 +525,51 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocators = []  # every registered pair stays alive: memory returns to the pair that made it
+
+
+def flp_set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through alloc(nbytes) -> int
+    address (0 on failure) and free(address); no arguments restores
+    hipMalloc/hipFree."""
+    lib = load()
+    if alloc is None or free is None:
+        lib.flp_set_allocator(None, None, None)
+        return
+    a = _ALLOC_FN(lambda nbytes, ctx: int(alloc(int(nbytes)) or 0))
+    f = _FREE_FN(lambda ptr, ctx: free(int(ptr)))
+    _allocators.append((a, f))
+    lib.flp_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None)
+
+
+def torch_allocator():
+    """(alloc, free) backed by torch's caching allocator on the current device."""
+    import torch
+    dev = torch.cuda.current_device()
+    live = {}
+
+    def alloc(nbytes):
+        t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{dev}")
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(ptr):
+        live.pop(ptr, None)
+
+    return alloc, free
+
+
+def flp_check_symmetric(A: "DeviceCsr", tol: float = 0.0, stream=None) -> bool:
+    """True when every stored a_ij has a stored a_ji within tol (relative)."""
+    rc = load().flp_check_symmetric(ctypes.byref(A.c), tol, _stream_ptr(stream))
+    if rc == FLP_E_NOTSYM:
+        return False
+    _check(rc)
+    return True
 
 
 def flp_release_workspace():

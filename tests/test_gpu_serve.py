@@ -83,3 +83,39 @@ def test_server_poll_pending_and_errors(torch):
         assert "does not meet" in flp.load().flp_last_error().decode()
     finally:
         sv.close()
+
+
+def test_server_cancel(torch):
+    """Cancelled requests report FLP_E_CANCELLED (a queued one at once, a
+    running one at a block-step boundary); the others complete correctly and
+    the server keeps serving."""
+    cases = [I.laplacian_3d(N, I.uniform_potential(N, 50 + N)) for N in (10, 11, 12, 13, 14, 12)]
+    sv = flp.Server(block=4, prec=flp.FLP_PREC_FP64, max_active=2, max_basis=600)
+    try:
+        dAs = [flp.DeviceCsr.from_host(A) for A in cases]
+        tickets = []
+        for i, A in enumerate(cases):
+            lam = np.linalg.eigvalsh(A.to_dense())
+            tickets.append((sv.submit(dAs[i], lam[0] - 0.5, 0.5 * (lam[29] + lam[30]), seed=i), A, lam))
+        sv.cancel(tickets[5][0])                     # queued behind four others
+        sv.cancel(tickets[0][0])                     # probably running
+        cancelled = 0
+        for t, A, lam in tickets:
+            try:
+                r = sv.wait(t)
+            except flp.FlpError as e:
+                assert e.code == flp.FLP_E_CANCELLED
+                cancelled += 1
+                continue
+            want = lam[(lam >= lam[0] - 0.5) & (lam <= 0.5 * (lam[29] + lam[30]))]
+            assert r["count"] == len(want) == 30
+            assert np.max(np.abs(np.sort(r["evals"]) - want) / np.abs(want)) <= 1e-10
+        assert cancelled >= 1
+        # still serving after cancellations
+        lam = np.linalg.eigvalsh(cases[1].to_dense())
+        r = sv.wait(sv.submit(dAs[1], lam[0] - 0.5, 0.5 * (lam[19] + lam[20]), seed=9))
+        assert r["count"] == 20
+        with pytest.raises(flp.FlpError):
+            sv.cancel(123456789)                     # unknown ticket
+    finally:
+        sv.close()

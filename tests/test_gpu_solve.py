@@ -243,3 +243,61 @@ def test_full_size_lap3d7_100_against_oracle_reference(torch):
         assert res["count"] == ref["count"] == len(want)
         assert np.max(np.abs(np.sort(res["evals"]) - want) / want) <= 1e-10
         assert np.max(res["resid"]) <= 1e-9
+
+
+def test_symmetry_check(torch):
+    """The opt-in O(nnz) check: symmetric inputs pass; a perturbed value or a
+    missing transpose entry is FLP_E_NOTSYM, also through flp_solve."""
+    A = I.laplacian_3d(8, I.uniform_potential(8, 3))
+    assert flp.flp_check_symmetric(flp.DeviceCsr.from_host(A))
+    B = I.Csr(A.n, A.rowptr.copy(), A.colind.copy(), A.val.copy())
+    p = int(B.rowptr[10]) + 1                       # an off-diagonal entry of row 10
+    B.val[p] += 1e-6
+    dB = flp.DeviceCsr.from_host(B)
+    assert not flp.flp_check_symmetric(dB)
+    assert flp.flp_check_symmetric(dB, tol=1e-5)      # within a relative 1e-5
+    with pytest.raises(flp.FlpError) as e:
+        flp.flp_solve(dB, 1.0, 2.0, block=2, sym_tol=0.0)
+    assert e.value.code == flp.FLP_E_NOTSYM
+    r = flp.flp_solve(flp.DeviceCsr.from_host(A), 1.0, 1.5, block=2, sym_tol=0.0, want_vectors=False)
+    assert r["count"] > 0
+    # a stored a_ij whose a_ji is missing
+    dense = A.to_dense()
+    dense[3, 200] = -0.5                             # no (200, 3) partner
+    C = I.dense_to_csr(dense)
+    assert not flp.flp_check_symmetric(flp.DeviceCsr.from_host(C))
+
+
+def test_custom_allocator(torch):
+    """flp_set_allocator: every device allocation of a solve and of a batch
+    goes through the caller's functions (torch's caching allocator here),
+    every one comes back, and the results are those of hipMalloc memory."""
+    w = I.workload_c1()
+    A = w["A"]
+    dA = flp.DeviceCsr.from_host(A)
+    ref = flp.flp_solve(dA, 0.5, 1.0, block=2, degree=50, seed=3)
+    counts = {"alloc": 0, "free": 0}
+    alloc0, free0 = flp.torch_allocator()
+
+    def alloc(n):
+        counts["alloc"] += 1
+        return alloc0(n)
+
+    def free(p):
+        counts["free"] += 1
+        free0(p)
+
+    flp.flp_release_workspace()
+    flp.flp_set_allocator(alloc, free)
+    try:
+        got = flp.flp_solve(dA, 0.5, 1.0, block=2, degree=50, seed=3)
+        bres, _ = flp.flp_solve_batch([dA, dA], [0.5, 1.0], [1.0, 1.5], block=2, degree=50, seeds=[3, 4])
+        flp.flp_release_workspace()
+    finally:
+        flp.flp_set_allocator()
+    torch.cuda.synchronize()
+    assert counts["alloc"] > 0
+    assert counts["free"] == counts["alloc"]
+    assert got["count"] == ref["count"]
+    assert np.array_equal(got["evals"], ref["evals"])
+    assert np.array_equal(bres[0]["evals"], ref["evals"])
