@@ -9,8 +9,9 @@
 // is captured once into a HIP graph and replayed while the set of active
 // solves is unchanged; its segment tables live in device memory and stay
 // valid because every solve keeps its buffers for its whole life.  The
-// Gram-Schmidt, block QR and convergence checks of each solve follow on the
-// same stream.
+// Gram-Schmidt and block QR of all active solves follow as one segmented
+// launch sequence on the same stream (flp_seg_orth.hip), then each solve's
+// convergence check on the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,7 +92,6 @@ int Engine::init(int r_, int prec_, bool graph_) {
     CK(hipGetDevice(&device));
     CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     for (auto &f : fs) CK(hipStreamCreateWithFlags(&f, hipStreamNonBlocking));
-    for (auto &p : ps) CK(hipStreamCreateWithFlags(&p, hipStreamNonBlocking));
     CK(hipEventCreate(&ev_a));
     CK(hipEventCreate(&ev_b));
     for (int w = 0; w < kFinishers; ++w) fin[w] = std::thread([this, w]() { finisher_main(w); });
@@ -111,8 +111,9 @@ Engine::~Engine() {
     if (ev_b) (void)hipEventDestroy(ev_b);
     for (auto &f : fs)
         if (f) (void)hipStreamDestroy(f);
-    for (auto &p : ps)
-        if (p) (void)hipStreamDestroy(p);
+    if (s) (void)hipStreamSynchronize(s);
+    if (ostage) (void)hipHostFree(ostage);
+    if (oout_pin) (void)hipHostFree(oout_pin);
     if (s) (void)hipStreamDestroy(s);
 }
 
@@ -177,24 +178,150 @@ void Engine::graph_reset() {
 }
 
 void Engine::add(Job *j) {
-    // the solve's set-up ran on s; its block steps run on a phase stream
-    (void)hipStreamSynchronize(s);
-    j->S->s = ps[next_ps];
-    j->S->part = &ppart[next_ps];
-    next_ps = (next_ps + 1) % kPhaseStreams;
+    // the solve's set-up and its block steps run on s
+    j->S->s = s;
+    j->S->part = nullptr;
     active.push_back(j);
     tables_valid = false;
 }
 
-int Engine::sync_phase_streams() {
-    for (auto &p : ps) CK(hipStreamSynchronize(p));
+int Engine::sync_steps() {
+    CK(hipStreamSynchronize(s));
+    return FLP_OK;
+}
+
+namespace {
+
+// Grows a pinned host staging buffer (contents are not kept).
+int ensure_pinned(void **p, size_t *have, size_t bytes) {
+    if (*have >= bytes && *p) return FLP_OK;
+    if (*p) CK(hipHostFree(*p));
+    *p = nullptr;
+    *have = 0;
+    const size_t want = std::max<size_t>(bytes, 4096);
+    CK(hipHostMalloc(p, want, hipHostMallocDefault));
+    *have = want;
+    return FLP_OK;
+}
+
+// Row chunk for the partial sums of a K-column projection: 512 rows (one
+// basis column per thread walks them on FMA; four waves take 32 rows per
+// MFMA step), doubled while the partial sums of one solve exceed 4M
+// doubles.
+int orth_chunk_rows(int n, int K, int c) {
+    int rows = 512;
+    while ((size_t)((n + rows - 1) / rows) * K * c > ((size_t)4 << 20)) rows *= 2;
+    return rows;
+}
+
+}  // namespace
+
+// Full reorthogonalisation and block QR of every active solve (Section
+// 3.2.2, eq. lanczos) as one segmented launch sequence, one copy of the
+// tables in and one copy of D_j, S_j and the status flags out.
+int Engine::block_step(double filter_secs) {
+    const double t0 = now();
+    const int c = r, ns = (int)active.size();
+    const size_t cc = (size_t)c * c, slot = 2 * cc + 2;
+    otab_host.assign(ns, OrthSeg{});
+    opre_host.assign(kOrthKinds * (size_t)ns, 0);
+    int blocks[kOrthKinds] = {};
+    std::vector<size_t> poff(ns);
+    size_t ptotal = 0;
+    CK(ensure(oout, sizeof(double) * slot * ns));
+    for (int i = 0; i < ns; ++i) {
+        Solve &S = *active[i]->S;
+        OrthSeg &e = otab_host[i];
+        const int n = S.n, k = (S.steps + 1) * c;
+        e.n = n;
+        e.k = k;
+        e.qcap = (int)(S.npanels << kPanelLog2);
+        e.chunk_rows = orth_chunk_rows(n, k, c);
+        e.nchunks = (n + e.chunk_rows - 1) / e.chunk_rows;
+        e.gchunk_rows = orth_chunk_rows(n, c, c);
+        e.gnchunks = (n + e.gchunk_rows - 1) / e.gchunk_rows;
+        int add[kOrthKinds] = {};
+        add[k > 128 ? kOrthFma : kOrthMfma] = (k > 128 ? (k + 255) / 256 : 1) * e.nchunks;
+        add[kOrthGram] = e.gnchunks;
+        add[kOrthRed] = (int)((k * (size_t)c + 63) / 64);
+        add[kOrthGred] = (int)((cc + 63) / 64);
+        add[kOrthRows] = (n + 255) / 256;
+        for (int t = 0; t < kOrthKinds; ++t) {
+            opre_host[(size_t)t * ns + i] = blocks[t];
+            blocks[t] += add[t];
+        }
+        e.Q = S.Q;
+        e.W = S.W;
+        e.H = S.hdev;
+        e.G = S.gdev;
+        e.Ri = S.rdev;
+        e.R1 = S.gdev + 2 * cc;
+        e.R2 = S.gdev + 3 * cc;
+        e.out = (double *)oout.p + (size_t)i * slot;
+        e.Vin = S.Vin;
+        e.V32 = S.V32;
+        poff[i] = ptotal;
+        ptotal += std::max((size_t)e.nchunks * k * c, (size_t)e.gnchunks * cc);
+        S.t_step0 = t0;
+        S.st.filter_bytes += filter_step_bytes(n, S.A->nnz, c, S.o.prec) * S.filt->m;
+        S.st.mv += (int64_t)c * S.filt->m;
+    }
+    CK(ensure(opart, sizeof(double) * std::max<size_t>(ptotal, 1)));
+    for (int i = 0; i < ns; ++i) otab_host[i].part = (double *)opart.p + poff[i];
+    const size_t tb = sizeof(OrthSeg) * ns, pb = sizeof(int) * opre_host.size();
+    CKR(ensure_pinned((void **)&ostage, &ostage_bytes, tb + pb));
+    std::memcpy(ostage, otab_host.data(), tb);
+    std::memcpy(ostage + tb, opre_host.data(), pb);
+    CK(ensure(otab, tb + pb));
+    CK(hipMemcpyAsync(otab.p, ostage, tb + pb, hipMemcpyHostToDevice, s));
+    OrthPlan plan{(const OrthSeg *)otab.p, (const int *)((const char *)otab.p + tb), ns, {}};
+    for (int t = 0; t < kOrthKinds; ++t) plan.blocks[t] = blocks[t];
+    CK(launch_seg_orth(plan, c, s));
+    CKR(ensure_pinned((void **)&oout_pin, &oout_pin_bytes, sizeof(double) * slot * ns));
+    CK(hipMemcpyAsync(oout_pin, oout.p, sizeof(double) * slot * ns, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    const double dt = now() - t0;
+    for (int i = 0; i < ns; ++i) {
+        Job *j = active[i];
+        Solve &S = *j->S;
+        if (j->code != FLP_OK) continue;
+        S.st.t_mv += filter_secs;
+        const double *o = oout_pin + (size_t)i * slot;
+        const double status = o[2 * cc];
+        if (status == 2.0) {
+            j->code = fail(FLP_E_DEVICE, "block QR: second Cholesky pass broke down");
+            j->msg = last_error_cstr();
+            continue;
+        }
+        S.D_all.insert(S.D_all.end(), o, o + cc);
+        if (status == 1.0) {
+            // numerically dependent columns: the synchronous repair path on
+            // the projected block, then the copies the kernels skipped
+            const int k = (S.steps + 1) * c;
+            int rc = block_qr_impl(S.W, S.n, c, &S.Q, k, S.Sj, S.o.seed, 1000 + S.steps, s, nullptr);
+            if (rc == FLP_OK && k + c <= (int)(S.npanels << kPanelLog2) &&
+                launch_copy_block(S.n, c, 1.0, S.W, c, S.Q, k, nullptr, 0, s) != hipSuccess)
+                rc = fail(FLP_E_DEVICE, "basis copy failed");
+            if (rc == FLP_OK &&
+                launch_copy_block(S.n, c, 1.0, S.W, c, plain_mat(S.Vin, c), 0, S.V32, c, s) != hipSuccess)
+                rc = fail(FLP_E_DEVICE, "input copy failed");
+            if (rc != FLP_OK) {
+                j->code = rc;
+                j->msg = last_error_cstr();
+                continue;
+            }
+        } else {
+            S.Sj.assign(o + cc, o + 2 * cc);
+        }
+        S.S_all.insert(S.S_all.end(), S.Sj.begin(), S.Sj.end());
+        ++S.steps;
+        S.st.t_orth += dt;
+    }
     return FLP_OK;
 }
 
 int Engine::step() {
     if (active.empty()) return FLP_OK;
-    // the previous step's basis and input copies must land before the filter
-    CKR(sync_phase_streams());
     // cancelled requests leave at the step boundary
     {
         std::vector<Job *> keep;
@@ -257,8 +384,7 @@ int Engine::step() {
     stats.filter_launches += T.M;
     ++stats.block_steps;
     for (Solve *S : act) stats.filter_bytes += filter_step_bytes(S->n, S->A->nnz, S->r, S->o.prec) * S->filt->m;
-    // block step of every active solve, phase by phase with one shared
-    // synchronisation between phases
+    // Gram-Schmidt and block QR of every active solve, then their checks
     const double t1 = now();
     auto run_phase = [&](int (*phase)(Solve &)) {
         for (Job *j : active) {
@@ -267,15 +393,10 @@ int Engine::step() {
             if (j->code != FLP_OK) j->msg = last_error_cstr();
         }
     };
-    for (Solve *S : act) S->st.t_mv += ms * 1e-3;
-    run_phase(step_orth_launch);
-    CKR(sync_phase_streams());
-    run_phase(step_qr1);
-    CKR(sync_phase_streams());
-    run_phase(step_qr2);
+    CKR(block_step(ms * 1e-3));
     // convergence checks: applied when their pool task has finished, started
     // at the cadence (the solves keep stepping meanwhile)
-    run_phase([](Solve &S) { return step_check(S, true); });
+    run_phase([](Solve &S) { return step_check(S, true, false); });
     std::vector<Job *> keep, done;
     for (Job *j : active) {
         if (j->code == FLP_OK && !j->S->done)
@@ -284,8 +405,8 @@ int Engine::step() {
             done.push_back(j);
     }
     if (!done.empty()) {
-        // the finishers read what the phase streams wrote (the basis)
-        CKR(sync_phase_streams());
+        // the finishers read the basis (repair-path copies may be in flight)
+        CKR(sync_steps());
         for (Job *j : done) {
             if (j->code == FLP_OK) {
                 {

@@ -264,7 +264,9 @@ int solve_setup(Solve &S);
 int step_orth_launch(Solve &S);
 int step_qr1(Solve &S);
 int step_qr2(Solve &S);
-int step_check(Solve &S, bool async = true);
+// copy_next = false: the caller has already written the new block into the
+// basis and the next filter input
+int step_check(Solve &S, bool async = true, bool copy_next = true);
 // waits for and applies a check in flight (no-op when there is none)
 int wait_check(Solve &S);
 // all four phases with synchronisations (single solve)
@@ -301,9 +303,10 @@ struct Job {
 
 // Advances a set of active solves in lockstep: per block step, one
 // segmented filter launch per Clenshaw step (replayed from a HIP graph while
-// the set is unchanged), then each solve's Gram-Schmidt, block QR and
-// convergence check; solves that converged go to the finisher thread for
-// their Ritz vectors, Rayleigh-Ritz and polish while the others step on.
+// the set is unchanged), then one segmented launch sequence for the
+// Gram-Schmidt and block QR of all of them, then each solve's convergence
+// check; solves that converged go to the finisher threads for their Ritz
+// vectors, Rayleigh-Ritz and polish while the others step on.
 struct Engine {
     hipStream_t s = nullptr;
     int device = 0;
@@ -334,17 +337,21 @@ struct Engine {
     void wait_finisher();
     // engine statistics including the finisher's time
     flp_batch_stats snapshot();
-    // waits for the per-solve work of the block steps issued so far
-    int sync_phase_streams();
+    // waits for the block-step work issued so far
+    int sync_steps();
 
   private:
-    // per-solve work of a block step (Gram-Schmidt, block QR, basis copies)
-    // goes to these streams round-robin, so independent solves' small
-    // kernels overlap on the device; the shared filter launches stay on s
-    static constexpr int kPhaseStreams = 8;
-    hipStream_t ps[kPhaseStreams] = {};
-    Buf ppart[kPhaseStreams];  // partial-sum scratch, one per phase stream
-    int next_ps = 0;
+    // Gram-Schmidt and block QR of every active solve as one segmented
+    // launch sequence on s (tables, partial sums, per-solve outputs D_j,
+    // S_j and status; pinned staging for the one copy each way per step)
+    Buf otab, opart, oout;
+    unsigned char *ostage = nullptr;
+    size_t ostage_bytes = 0;
+    double *oout_pin = nullptr;
+    size_t oout_pin_bytes = 0;
+    std::vector<OrthSeg> otab_host;
+    std::vector<int> opre_host;
+    int block_step(double filter_secs);
     // finishers: Ritz vectors, Rayleigh-Ritz and polish of converged solves,
     // each on its own host thread and stream, overlapping later block steps
     static constexpr int kFinishers = 4;

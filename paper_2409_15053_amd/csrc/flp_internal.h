@@ -123,6 +123,42 @@ int seg_rows_per_tile(int r, bool fp32, StepShape sh = StepShape{});
 hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s,
                            StepShape sh = StepShape{});
 
+// One solve's part of a segmented block step (full reorthogonalisation of
+// the filtered block W against the basis Q, then W = Q_{j+1} S_j by
+// Cholesky QR twice) with block width c <= 16; every pointer is device memory.
+struct OrthSeg {
+    int n;                        // rows
+    int k;                        // basis columns so far (Q_1 .. Q_j)
+    int qcap;                     // basis capacity in columns
+    int chunk_rows, nchunks;      // row chunks of the projection partial sums
+    int gchunk_rows, gnchunks;    // row chunks of the Gram partial sums
+    int pad;
+    DMat Q;                       // basis (panelled)
+    double *W;                    // n x c, ld c: the filtered block
+    double *H;                    // H1 then H2, k x c each (row-major)
+    double *G;                    // c x c Gram matrix
+    double *R1, *R2, *Ri;         // c x c: first and second factor, current inverse
+    double *part;                 // partial sums: max(nchunks k, gnchunks c) c doubles
+    double *out;                  // D_j (c x c), S_j (c x c), status (0 ok, 1 dependent columns, 2 breakdown)
+    double *Vin;                  // next filter input, n x c
+    float *V32;                   // its FP32 copy (or null)
+};
+// Launch kinds of a segmented block step: projection on FMA (solves with
+// k > 128) or MFMA (k <= 128), Gram matrix, reduction of k x c, reduction
+// of c x c, blocks of 256 rows.  A solve has no blocks in a kind it skips.
+enum { kOrthFma = 0, kOrthMfma, kOrthGram, kOrthRed, kOrthGred, kOrthRows, kOrthKinds };
+// Launch bookkeeping of one segmented block step: the device table, one
+// prefix array of first blocks per kind (nseg each, kind-major) and each
+// kind's block count.
+struct OrthPlan {
+    const OrthSeg *tab;
+    const int *pre;
+    int nseg;
+    int blocks[kOrthKinds];
+};
+// The 14 or 16 launches of one block step for every solve in the plan.
+hipError_t launch_seg_orth(const OrthPlan &p, int c, hipStream_t s);
+
 // Partial sums for C = A^T B over row chunks: A n x K (lda), B n x c (ldb).
 // partials[chunk][K * c] (row-major K x c).  Returns the number of chunks
 // used via *nchunks (caller sizes partials with plan_tn()).

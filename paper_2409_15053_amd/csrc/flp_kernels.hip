@@ -8,123 +8,24 @@
 //   block copies, residual norms.
 #include "flp_internal.h"
 #include "flp_device.h"
+#include "flp_gemm.h"
 
 #include <algorithm>
 
 namespace flp {
 
-// ------------------------------------------------------------------ MFMA helpers
-//
-// v_mfma_f64_16x16x4f64: D(16x16) = A(16x4) B(4x16) + C.  Lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; it holds D[l/16 + 4 v][l % 16]
-// for v = 0..3 (rows interleaved across the four lane groups; checked on
-// gfx950 with a one-hot probe).
-
 namespace {
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ const double *col_base(const DMat &m, int q) {
-    return m.p + (int64_t)(q >> m.lpw) * m.ps + (q & ((1 << m.lpw) - 1));
-}
-
-// C partial (K x c) over one chunk of rows.  Each wave owns NT output
-// tiles of 16 A-columns x 16 B-columns, taken in pairs: the pair (2p, 2p+1)
-// covers 32 consecutive A columns, lane (k, m) reads columns 2m and 2m+1 of
-// the pair with one 16-byte load and feeds the first to tile 2p and the
-// second to tile 2p+1 (tile 2p's row i is column 2i of the pair).  The
-// block's 4 waves split the chunk's rows and combine through LDS.  A group
-// of NT tiles never straddles a panel (16 NT divides the panel width).
-// Loads are unconditional: in a group that runs past K the A columns are
-// clamped to valid addresses (they only feed discarded output rows), and B
-// rows past the chunk are zeroed.
-template <int NT, bool VEC, bool CLAMP>
-__device__ __forceinline__ void tn_rows(int g0, int r1, int K, int q0, const double *abase, int64_t lda,
-                                        const double *__restrict__ B, int64_t ldb, int bcol, int kr, int mc,
-                                        dbl4 (&acc)[NT]) {
-    constexpr int NP = NT / 2;
-    int aoff[NP][2];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        aoff[p][0] = CLAMP ? min(p * 32 + 2 * mc, K - 1 - q0) : p * 32 + 2 * mc;
-        aoff[p][1] = CLAMP ? min(p * 32 + 2 * mc + 1, K - 1 - q0) : p * 32 + 2 * mc + 1;
-    }
-    for (int g = g0; g < r1; g += 4 * 4 * 2) {
-        double bv[2];
-        double2 av[2][NP];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int row = g + u * 16 + kr;
-            const int rc = min(row, r1 - 1);
-            const double x = B[(int64_t)rc * ldb + bcol];
-            bv[u] = row < r1 ? x : 0.0;
-            const double *ar = abase + (int64_t)rc * lda;
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                if constexpr (VEC) {
-                    av[u][p] = *reinterpret_cast<const double2 *>(ar + aoff[p][0]);
-                } else {
-                    av[u][p].x = ar[aoff[p][0]];
-                    av[u][p].y = ar[aoff[p][1]];
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                acc[2 * p] = mfma16x16x4(av[u][p].x, bv[u], acc[2 * p]);
-                acc[2 * p + 1] = mfma16x16x4(av[u][p].y, bv[u], acc[2 * p + 1]);
-            }
-    }
-}
 
 template <int NT>
 __global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int c, int chunk_rows, DMat A,
                                                               const double *__restrict__ B, int64_t ldb,
                                                               double *__restrict__ partials, bool aligned) {
     __shared__ double red[4][4][WAVE];
-    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-    const int ntb = (c + 15) / 16;            // B tiles
+    const int ntb = (c + 15) / 16;  // B tiles
     const int chunk = blockIdx.x;
-    const int tg = blockIdx.y / ntb;          // group of NT A tiles
-    const int tb = blockIdx.y % ntb;          // B tile
     const int r0 = chunk * chunk_rows;
-    const int r1 = min(n, r0 + chunk_rows);
-    const int kr = lane / 16, mc = lane % 16;
-    const int q0 = tg * NT * 16;
-    const double *abase = col_base(A, q0);
-    const int bcol = min(tb * 16 + mc, c - 1);
-    dbl4 acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-    if (q0 + 16 * NT > K)
-        tn_rows<NT, false, true>(r0 + wave * 4, r1, K, q0, abase, A.ld, B, ldb, bcol, kr, mc, acc);
-    else if (aligned)
-        tn_rows<NT, true, false>(r0 + wave * 4, r1, K, q0, abase, A.ld, B, ldb, bcol, kr, mc, acc);
-    else
-        tn_rows<NT, false, false>(r0 + wave * 4, r1, K, q0, abase, A.ld, B, ldb, bcol, kr, mc, acc);
-    // combine the 4 waves one output tile at a time through LDS
-    double *dst = partials + (size_t)chunk * K * c;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        if (q0 + (t & ~1) * 16 >= K) break;  // uniform
-#pragma unroll
-        for (int v = 0; v < 4; ++v) red[wave][v][lane] = acc[t][v];
-        __syncthreads();
-        {
-            const int v = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
-            double s = red[0][v][l] + red[1][v][l] + red[2][v][l] + red[3][v][l];
-            int i = q0 + (t / 2) * 32 + 2 * ((l / 16) + 4 * v) + (t & 1);
-            int j = tb * 16 + (l % 16);
-            if (i < K && j < c) dst[(size_t)i * c + j] = s;
-        }
-        __syncthreads();
-    }
+    tn_mfma_block<NT>(r0, min(n, r0 + chunk_rows), K, c, (blockIdx.y / ntb) * NT * 16, blockIdx.y % ntb, A, B, ldb,
+                      aligned, partials + (size_t)chunk * K * c, red);
 }
 
 // Sum of the per-chunk partials in a fixed order (deterministic): each
@@ -153,102 +54,15 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int nchunks, int t
     if (ty == 0 && o < total) C[(size_t)(o / c) * ldc + o % c] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
 }
 
-// C = beta C + alpha A B: each wave computes MT row tiles (16 rows each) x
-// NT column tiles (16 columns each).  The k index inside a group of 16 is
-// permuted (k = 4 * (l/16) + step) so each lane reads 4 contiguous A
-// entries with two 16-byte loads.  A group of 16 k values never straddles a
-// panel.  Loads are unconditional: rows past n and columns past c are
-// clamped (they only feed outputs that are not written) and B rows past K
-// are zeroed.  A and C may be the same block (in-place C = A B): each wave
-// reads all of its rows of A before it writes those rows of C.
+// C = beta C + alpha A B (see gemm_nn_rows): one block of 4 waves per
+// 4 x 16 MT rows and 16 NT columns, blocks renumbered per XCD.
 template <int MT, int NT>
 __global__ __launch_bounds__(256) void gemm_nn_kernel(int n, int K, int c, double alpha, DMat A,
                                                       const double *__restrict__ B, int64_t ldb, double beta,
                                                       double *C, int64_t ldc, bool vec_a) {
-    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int nct = (c + 16 * NT - 1) / (16 * NT);
     const int wg = xcd_tile(blockIdx.x, gridDim.x);
-    const int rblk = wg / nct, cblk = wg % nct;
-    const int row0 = (rblk * 4 + wave) * (16 * MT);
-    if (row0 >= n) return;
-    const int kq = lane / 16, m = lane % 16;
-    dbl4 acc[MT][NT];
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    int col[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) col[j] = min((cblk * NT + j) * 16 + m, c - 1);
-    int64_t roff[MT];
-#pragma unroll
-    for (int i = 0; i < MT; ++i) roff[i] = (int64_t)min(row0 + i * 16 + m, n - 1) * A.ld;
-    const int kfull = vec_a ? (K & ~15) : 0;
-    int k0 = 0;
-    for (; k0 < kfull; k0 += 16) {
-        const int kb = k0 + 4 * kq;  // this lane's 4 contiguous k values
-        const double *abase = col_base(A, kb);
-        double a[MT][4];
-#pragma unroll
-        for (int i = 0; i < MT; ++i) {
-            const double *ap = abase + roff[i];
-            double2 x0 = *reinterpret_cast<const double2 *>(ap);
-            double2 x1 = *reinterpret_cast<const double2 *>(ap + 2);
-            a[i][0] = x0.x;
-            a[i][1] = x0.y;
-            a[i][2] = x1.x;
-            a[i][3] = x1.y;
-        }
-        double b[4][NT];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int j = 0; j < NT; ++j) b[q][j] = B[(int64_t)(kb + q) * ldb + col[j]];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int i = 0; i < MT; ++i)
-#pragma unroll
-                for (int j = 0; j < NT; ++j) acc[i][j] = mfma16x16x4(a[i][q], b[q][j], acc[i][j]);
-    }
-    for (; k0 < K; k0 += 16) {  // ragged tail (or unaligned A): scalar loads
-        const int kb = k0 + 4 * kq;
-        double a[MT][4], b[4][NT];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int kk = min(kb + q, K - 1);
-            const double *ap = col_base(A, kk);
-#pragma unroll
-            for (int i = 0; i < MT; ++i) a[i][q] = ap[roff[i]];
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const double x = B[(int64_t)kk * ldb + col[j]];
-                b[q][j] = (kb + q < K) ? x : 0.0;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int i = 0; i < MT; ++i)
-#pragma unroll
-                for (int j = 0; j < NT; ++j) acc[i][j] = mfma16x16x4(a[i][q], b[q][j], acc[i][j]);
-    }
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int cj = (cblk * NT + j) * 16 + m;
-            if (cj >= c) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int row = row0 + i * 16 + kq + 4 * v;
-                if (row < n) {
-                    double *cp = C + (int64_t)row * ldc + cj;
-                    double prev = (beta != 0.0) ? beta * *cp : 0.0;
-                    *cp = prev + alpha * acc[i][j][v];
-                }
-            }
-        }
+    gemm_nn_rows<MT, NT>(n, K, c, alpha, A, B, ldb, beta, C, ldc, vec_a, wg / nct, wg % nct);
 }
 
 }  // namespace
@@ -271,29 +85,8 @@ __global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int chun
     if (q >= K) return;  // no block-level synchronisation follows: idle columns leave at once
     const int chunk = blockIdx.y;
     const int r0 = chunk * chunk_rows, r1 = min(n, r0 + chunk_rows);
-    const double *col = col_base(A, q);
-    const int64_t lda = A.ld;
     double acc[C];
-#pragma unroll
-    for (int j = 0; j < C; ++j) acc[j] = 0.0;
-    int row = r0;
-    for (; row + UNR <= r1; row += UNR) {
-        double a[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) a[u] = col[(int64_t)(row + u) * lda];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const double *b = B + (int64_t)(row + u) * ldb;
-#pragma unroll
-            for (int j = 0; j < C; ++j) acc[j] = fma(a[u], b[j], acc[j]);
-        }
-    }
-    for (; row < r1; ++row) {
-        const double a = col[(int64_t)row * lda];
-        const double *b = B + (int64_t)row * ldb;
-#pragma unroll
-        for (int j = 0; j < C; ++j) acc[j] = fma(a, b[j], acc[j]);
-    }
+    tn_fma_column<C, UNR>(col_base(A, q), A.ld, r0, r1, B, ldb, acc);
     double *d = partials + ((size_t)chunk * K + q) * C;
 #pragma unroll
     for (int j = 0; j < C; ++j) d[j] = acc[j];

@@ -107,7 +107,7 @@ void worker_main(flp_server *sv) {
                     sv->fatal = rc;
                     sv->fatal_msg = msg;
                 }
-                (void)sv->eng.sync_phase_streams();  // nothing may still use the buffers freed below
+                (void)sv->eng.sync_steps();  // nothing may still use the buffers freed below
                 std::vector<Job *> act;
                 act.swap(sv->eng.active);
                 for (Job *j : act) {

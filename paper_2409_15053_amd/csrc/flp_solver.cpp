@@ -294,7 +294,7 @@ int wait_check(Solve &S) {
     return FLP_OK;
 }
 
-int step_check(Solve &S, bool async) {
+int step_check(Solve &S, bool async, bool copy_next) {
     // a check that has finished in the background is applied first; one
     // still running after kMaxSpeculative further block steps is waited for
     // (speculative steps are wasted work if it decides convergence)
@@ -325,6 +325,7 @@ int step_check(Solve &S, bool async) {
             if (S.done) return FLP_OK;
         }
     }
+    if (!copy_next) return FLP_OK;
     // the new block joins the basis and is the next filter input
     const int n = S.n, r = S.r, k = S.steps * r;
     CK(launch_copy_block(n, r, 1.0, S.W, r, S.Q, k, nullptr, 0, S.s));
