@@ -57,6 +57,8 @@ def parse():
                     help="filter degree (default: 110 for the 100^3 workload, the fastest of a 100..200 sweep "
                          "there; 100 for the 120^3 Hamiltonian)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-every", type=int, default=0,
+                    help="block steps between convergence checks (0: the library default, 30)")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--no-graph", action="store_true", help="batched form: eager launches instead of HIP graphs")
     ap.add_argument("--no-plain", action="store_true", help="batched form: skip the sequential FP64 comparison")
@@ -179,6 +181,12 @@ def cpu_baseline(w, alpha, beta, degree, gpu_res, budget_s):
     }
 
 
+def check_cadence(args, r):
+    """Block steps between convergence checks: --check-every, else the
+    library's rule for block size r (flp_opts.check_every <= 0)."""
+    return args.check_every if args.check_every > 0 else min(30, max(1, (90 + r // 2) // r))
+
+
 def bench_batch(args):
     """Batched form: the problems of inputs.batch_family solved together
     (segmented filter launches, HIP graph replay), FP32 filter with FP64
@@ -198,7 +206,8 @@ def bench_batch(args):
 
     def run_batch(seed0):
         return flp.flp_solve_batch(dAs, alphas, betas, block=8, seeds=[seed0 + i for i in range(len(dAs))],
-                                   prec=prec, use_graph=not args.no_graph, want_vectors=False)
+                                   prec=prec, use_graph=not args.no_graph, want_vectors=False,
+                                   check_every=args.check_every)
 
     for i in range(args.warmup):
         run_batch(1000 * (i + 1))
@@ -239,12 +248,17 @@ def bench_batch(args):
         "config": {"workload": f"batch of {len(As)} independent solves: 3D 7-point Laplacian g^3 + U[0,1) "
                                f"potential, g log-uniform in [20, 60], low-end intervals of ~10-60 eigenvalues, "
                                f"block 8, auto degree; sum n = {n_total}, sum nnz = {nnz_total}",
-                   "solves": len(As), "block": 8, "prec": args.prec, "graph": not args.no_graph},
+                   "solves": len(As), "block": 8, "prec": args.prec, "graph": not args.no_graph,
+                   "check_every": check_cadence(args, 8)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "per-solve completion time inside the batch"},
         "accuracy": {"max_resid": max_res, "pairs_passing": ok_pairs},
         "batch_stats": st,
         "filter": {"GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS},
+        "orth": {"GBps": st["orth_bytes"] / st["t_orth"] / 1e9 if st["t_orth"] > 0 else 0.0,
+                 "frac_hbm": (st["orth_bytes"] / st["t_orth"] / 1e9 / HBM_PEAK_GBS) if st["t_orth"] > 0 else 0.0,
+                 "what": "segmented Gram-Schmidt + block QR of all active solves: the basis read twice per "
+                         "pass, over the wall time of those launches (shared with the finishers' work)"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "cheb_seg_kernel (segmented CSR SpMM + fused Clenshaw update)"},
@@ -255,7 +269,8 @@ def bench_batch(args):
         tp = time.perf_counter()
         pairs = 0
         for i, dA in enumerate(dAs):
-            r = flp.flp_solve(dA, alphas[i], betas[i], block=8, seed=i, want_vectors=False)
+            r = flp.flp_solve(dA, alphas[i], betas[i], block=8, seed=i, want_vectors=False,
+                              check_every=args.check_every)
             pairs += r["count"] if (r["count"] and float(np.max(r["resid"])) <= 1e-9) else 0
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - tp
@@ -293,7 +308,8 @@ def bench_serve(args):
                     dt = arrivals[i] - (time.perf_counter() - t0)
                     if dt > 0:
                         time.sleep(dt)
-                tickets[i] = sv.submit(dAs[i], a, b, seed=seed0 + i, degree=fam[i]["degree"])
+                tickets[i] = sv.submit(dAs[i], a, b, seed=seed0 + i, degree=fam[i]["degree"],
+                                       check_every=args.check_every)
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -342,7 +358,7 @@ def bench_serve(args):
         pres = []
         for i, (A, a, b) in enumerate(probs):
             pres.append(flp.flp_solve(dAs[i], a, b, block=16, degree=fam[i]["degree"], seed=i, want_vectors=False,
-                                      max_basis=2048))
+                                      max_basis=2048, check_every=args.check_every))
             print(f"#   plain {i + 1}/{len(probs)}: count={pres[-1]['count']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
@@ -366,7 +382,8 @@ def bench_serve(args):
                                f"~U{{10..200}} eigenvalues (Weyl estimate), degree 60, "
                                f"block 16, Poisson arrivals at {rate:.3f} req/s ({args.load} x closed-loop "
                                f"throughput)", "requests": len(dAs), "rate_req_s": rate, "block": 16,
-                   "prec": args.prec, "sum_n": int(sum(A.n for A, _, _ in probs))},
+                   "prec": args.prec, "sum_n": int(sum(A.n for A, _, _ in probs)),
+                   "check_every": check_cadence(args, 16)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "request latency, arrival to result (open loop)",
                        "closed_loop_p50": float(np.percentile(lat_c, 50)),
@@ -414,12 +431,12 @@ def bench_c3(args):
     for name, prec in (("fp64", flp.FLP_PREC_FP64), ("fp32", flp.FLP_PREC_FP32_FILTER)):
         for i in range(args.warmup):
             flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=100 + i, prec=prec,
-                          want_vectors=False)
+                          want_vectors=False, check_every=args.check_every)
         lat, res = [], None
         for i in range(args.steps):
             t0 = time.perf_counter()
             res = flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=i, prec=prec,
-                                want_vectors=False)
+                                want_vectors=False, check_every=args.check_every)
             lat.append(time.perf_counter() - t0)
             print(f"# {name} step {i + 1}/{args.steps}: {res['count']} pairs, {lat[-1]:.2f} s, iters "
                   f"{res['stats']['iters']}, polish {res['stats']['polish_sweeps']}", file=sys.stderr, flush=True)
@@ -442,7 +459,8 @@ def bench_c3(args):
         "config": {"workload": f"{w['name']}: 13-point 4th-order Laplacian 120^3 + 16 Gaussian wells, n={A.n}, "
                                f"nnz={A.nnz}, block 16, degree {args.degree}, interval between the Weyl "
                                f"estimates of 20 and 320 eigenvalues [{alpha:.6f}, {beta:.6f}]",
-                   "n": A.n, "nnz": A.nnz, "block": 16, "degree": args.degree},
+                   "n": A.n, "nnz": A.nnz, "block": 16, "degree": args.degree,
+                   "check_every": check_cadence(args, 16)},
         "fp64_filter": out_runs["fp64"], "fp32_filter": r32,
         "fp32_vs_fp64": {"same_count": len(e32) == len(e64), "max_rel_eval_diff": diff},
         "speedup_fp32_vs_fp64": r32["eigenpairs_per_s"] / out_runs["fp64"]["eigenpairs_per_s"]
@@ -488,7 +506,7 @@ def main():
 
     def solve(seed):
         return flp.flp_solve(dA, alpha, beta, block=w["block"], degree=args.degree, seed=seed, prec=prec,
-                             want_vectors=False)
+                             want_vectors=False, check_every=args.check_every)
 
     for i in range(args.warmup):
         solve(1000 + i)
@@ -547,6 +565,7 @@ def main():
                                f"potential, n={A.n}, nnz={A.nnz}, block={w['block']}, degree={args.degree}, "
                                f"interval=[{alpha}, {beta:.9f}]",
                    "n": A.n, "nnz": A.nnz, "block": w["block"], "degree": args.degree,
+                   "check_every": check_cadence(args, w["block"]),
                    "alpha": alpha, "beta": beta, "prec": args.prec},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "all": [round(x, 3) for x in lat_ms.tolist()]},
@@ -562,6 +581,11 @@ def main():
                            "column-grouped kernel"},
         "phases_s": {k: float(np.mean([s[k] for s in st])) for k in
                      ("t_pre", "t_mv", "t_orth", "t_check", "t_rr", "t_total")},
+        "orth": {"GBps": float(np.mean([s["orth_bytes"] / s["t_orth"] / 1e9 for s in st])),
+                 "frac_hbm": float(np.mean([s["orth_bytes"] / s["t_orth"] / 1e9 for s in st])) / HBM_PEAK_GBS,
+                 "bytes_per_solve": float(np.mean([s["orth_bytes"] for s in st])),
+                 "what": "full reorthogonalisation: the basis (n x k doubles) read twice per Gram-Schmidt "
+                         "pass, two passes per block step, over the host-timed block-QR phase (t_orth)"},
         "iters": [s["iters"] for s in st],
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None,

@@ -80,7 +80,9 @@ typedef struct flp_opts {
     int32_t degree;       /* filter degree m; <= 0 selects it by eq. optimaldegree */
     double eps;           /* tolerance of the degree rule; default 0.31227 */
     double tol;           /* required ||Ax - lambda x|| / ||A||; default 1e-9 */
-    int32_t check_every;  /* block steps between convergence checks; default 30 */
+    int32_t check_every;  /* block steps between convergence checks; <= 0 (default) picks
+                             min(30, round(90 / block)): the paper's spacing of 90 basis
+                             columns (30 steps at block size 3), at most 30 steps */
     int32_t prec;         /* FLP_PREC_FP64 (default) or FLP_PREC_FP32_FILTER */
     uint64_t seed;        /* seed of the random start block and bounds start vector */
     int64_t max_basis;    /* cap on Lanczos basis columns; <= 0 picks min(n, memory) */
@@ -105,6 +107,8 @@ typedef struct flp_stats {
     double t_rr;           /* seconds: Rayleigh-Ritz, residuals, polish */
     double t_total;        /* seconds: whole call */
     double filter_bytes;   /* algorithmic bytes moved by the filter SpMMs */
+    double orth_bytes;     /* algorithmic bytes of the reorthogonalisation: the basis
+                              (n x k doubles) read twice per Gram-Schmidt pass */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */
@@ -286,6 +290,9 @@ typedef struct flp_batch_stats {
     double t_orth_check;      /* seconds: Gram-Schmidt, block QR, convergence checks */
     double t_finish;          /* seconds: Rayleigh-Ritz and polish of finished solves */
     double filter_bytes;      /* algorithmic bytes of the segmented filter launches */
+    double t_orth;            /* seconds: the segmented Gram-Schmidt and block QR launches
+                                 (part of t_orth_check) */
+    double orth_bytes;        /* algorithmic bytes of those launches (basis read twice per pass) */
 } flp_batch_stats;
 
 /* Every eigenpair in [alpha[i], beta[i]] of each A[i], for count independent

@@ -23,7 +23,7 @@ void flp_opts_default(flp_opts *o) {
     o->degree = 0;
     o->eps = kDefaultEps;
     o->tol = kDefaultTol;
-    o->check_every = kDefaultCheck;
+    o->check_every = 0;  // chosen from the block size (default_check_every)
     o->prec = FLP_PREC_FP64;
     o->seed = 0;
     o->max_basis = 0;

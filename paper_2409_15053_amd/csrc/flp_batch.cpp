@@ -135,7 +135,6 @@ void Engine::finisher_main(int w) {
         }
         const double t0 = now();
         j->S->s = fs[w];
-        j->S->part = nullptr;  // the finisher thread's own workspace
         if (j->cancel.load()) {
             j->code = FLP_E_CANCELLED;
             j->msg = "request cancelled";
@@ -180,7 +179,10 @@ void Engine::graph_reset() {
 void Engine::add(Job *j) {
     // the solve's set-up and its block steps run on s
     j->S->s = s;
-    j->S->part = nullptr;
+    // spread the solves' convergence checks over the block steps (solves
+    // admitted together would otherwise all hand their checks to the host
+    // pool on the same step and wait for them together)
+    j->S->check_offset = (int)(n_added++ % (uint64_t)j->S->check_every);
     active.push_back(j);
     tables_valid = false;
 }
@@ -265,6 +267,8 @@ int Engine::block_step(double filter_secs) {
         S.t_step0 = t0;
         S.st.filter_bytes += filter_step_bytes(n, S.A->nnz, c, S.o.prec) * S.filt->m;
         S.st.mv += (int64_t)c * S.filt->m;
+        S.st.orth_bytes += 4.0 * 8.0 * (double)n * k;
+        stats.orth_bytes += 4.0 * 8.0 * (double)n * k;
     }
     CK(ensure(opart, sizeof(double) * std::max<size_t>(ptotal, 1)));
     for (int i = 0; i < ns; ++i) otab_host[i].part = (double *)opart.p + poff[i];
@@ -281,6 +285,7 @@ int Engine::block_step(double filter_secs) {
     CK(hipMemcpyAsync(oout_pin, oout.p, sizeof(double) * slot * ns, hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     const double dt = now() - t0;
+    stats.t_orth += dt;
     for (int i = 0; i < ns; ++i) {
         Job *j = active[i];
         Solve &S = *j->S;

@@ -507,8 +507,8 @@ int small_dev(size_t elems, double **out) {
 // dev_out: device K x c row-major; host_out (optional) receives a copy
 // (synchronises the stream).
 int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *dev_out,
-            double *host_out, hipStream_t s, Buf *part) {
-    Buf &pb = part ? *part : ws().partials;
+            double *host_out, hipStream_t s) {
+    Buf &pb = ws().partials;
     TnPlan pl = plan_tn(n, K, c);
     CK(ensure(pb, pl.partial_elems * sizeof(double)));
     CK(launch_gemm_tn_partial(pl, n, K, c, A, B, ldb, (double *)pb.p, s));
@@ -522,10 +522,10 @@ int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *d
 
 // Two passes of classical Gram-Schmidt of W (n x r, ld r) against
 // the first k columns of Q.  H1, H2 (k x r each) stay on the device in hdev[0..2kr).
-int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s, Buf *part) {
+int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s) {
     for (int pass = 0; pass < 2; ++pass) {
         double *H = hdev + (size_t)pass * k * r;
-        CKR(gram_tn(n, k, r, Q, W, r, H, nullptr, s, part));
+        CKR(gram_tn(n, k, r, Q, W, r, H, nullptr, s));
         CK(launch_gemm_nn(n, k, r, -1.0, Q, H, r, 1.0, W, r, s));
     }
     return FLP_OK;

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <cstdint>
@@ -32,13 +33,20 @@ struct flp_filter {
 namespace flp {
 
 constexpr double kDefaultEps = 0.31227;
-constexpr int kDefaultCheck = 30;
+// Block steps between convergence checks when the caller leaves it open:
+// the paper checks every 30 block steps at block size 3 (Table 2), i.e.
+// every 90 basis columns; larger blocks keep that spacing in columns
+// (r = 8: 11 steps, r = 16: 6), smaller ones stay at 30 steps.
+inline int default_check_every(int r) { return std::min(30, std::max(1, (90 + r / 2) / r)); }
 constexpr int kDefaultK0 = 40;
 constexpr double kDefaultTol = 1e-9;
 constexpr int kMaxDegree = 100000;
 constexpr int64_t kDefaultMaxBasis = 3072;
 constexpr int kPanelLog2 = 7;  // Lanczos basis panels of 128 columns
 constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
+// relative residual above which an in-interval Ritz pair of an FP32-filter
+// solve counts as a mixture of eigenvectors (converged pairs sit near 1e-7)
+constexpr double kMixedResid = 1e-4;
 constexpr int kMaxSpeculative = 2;  // block steps a solve may take past a convergence check in flight
 
 int fail(int code, const std::string &msg);
@@ -157,11 +165,9 @@ void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, 
 void upper_inverse(int r, const std::vector<double> &R, std::vector<double> &Ri);
 void matmul_upper(int r, const std::vector<double> &A, const std::vector<double> &B, std::vector<double> &C);
 
-// part: partial-sum scratch (null: the calling thread's workspace); work
-// that runs on several streams at once needs one per stream
 int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *dev_out, double *host_out,
-            hipStream_t s, Buf *part = nullptr);
-int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s, Buf *part = nullptr);
+            hipStream_t s);
+int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s);
 int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<double> &S, uint64_t seed,
                   uint64_t sid, hipStream_t s, bool *replaced, int depth = 0);
 int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s);
@@ -208,12 +214,12 @@ struct Solve {
     flp_opts o{};
     hipStream_t s = nullptr;
     SolveBufs *B = nullptr;
-    Buf *part = nullptr;  // partial-sum scratch of the solve's stream (null: the thread's workspace)
     // derived
     int n = 0, r = 0;
     double lmin = 0, lmax = 0, tau = 0, tol_p = 0;
     std::unique_ptr<flp_filter> filt;
     int check_every = 0, max_steps = 0;
+    int check_offset = 0;  // checks fall on steps with (steps + check_offset) % check_every == 0
     int64_t npanels = 0;
     DMat Q{};
     double *W = nullptr, *Vin = nullptr, *hdev = nullptr;
@@ -249,9 +255,10 @@ struct Solve {
 
 // bounds, filter, buffers, start block (PREPROC and set-up)
 int solve_setup(Solve &S);
-// One block step after the filter has produced W, in phases separated by a
-// stream synchronisation (the batched driver runs each phase for all solves
-// before one shared synchronisation):
+// One block step of a single solve after the filter has produced W, in
+// phases separated by a stream synchronisation (the batched engine does the
+// first three for all its solves at once with the segmented launches of
+// Engine::block_step, then calls step_check per solve):
 //   step_orth_launch: CGS2 against the basis, Gram matrix of W (async);
 //   step_qr1:         D_j; first Cholesky factor; apply it; second Gram (async);
 //   step_qr2:         second Cholesky factor; apply it; S_j;
@@ -313,6 +320,7 @@ struct Engine {
     int r = 0, prec = 0;
     bool use_graph = true;
     std::vector<Job *> active;
+    uint64_t n_added = 0;
     Tables T;
     bool tables_valid = false;
     hipGraph_t graph = nullptr;

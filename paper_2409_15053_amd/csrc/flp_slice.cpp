@@ -147,6 +147,7 @@ int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, 
         st.t_check += r->stats.t_check;
         st.t_rr += r->stats.t_rr;
         st.filter_bytes += r->stats.filter_bytes;
+        st.orth_bytes += r->stats.orth_bytes;
     }
     st.t_mv = bs.t_filter;  // the slices share the segmented launches
     st.t_pre = bs.t_setup;

@@ -71,7 +71,7 @@ int solve_setup(Solve &S) {
     S.filt.reset(pf);
     S.tau = 0.5 * std::min(cheb_scalar(S.filt->b, S.filt->a1), cheb_scalar(S.filt->b, S.filt->b1));
     S.tol_p = fp32 ? 1e-5 : 1e-10;
-    S.check_every = o.check_every > 0 ? o.check_every : kDefaultCheck;
+    S.check_every = o.check_every > 0 ? o.check_every : default_check_every(r);
 
     int64_t maxb = o.max_basis > 0 ? o.max_basis : kDefaultMaxBasis;
     maxb = std::min<int64_t>(maxb, n);
@@ -128,14 +128,15 @@ int step_orth_launch(Solve &S) {
     const int k = (S.steps + 1) * r;  // basis columns so far
     S.st.filter_bytes += filter_step_bytes(n, S.A->nnz, r, S.o.prec) * S.filt->m;
     S.st.mv += (int64_t)r * S.filt->m;
+    S.st.orth_bytes += 4.0 * 8.0 * (double)n * k;
     // full reorthogonalisation (Section 3.2.2): two passes of classical Gram-Schmidt
-    CKR(cgs2(S.Q, k, n, S.W, r, S.hdev, s, S.part));
+    CKR(cgs2(S.Q, k, n, S.W, r, S.hdev, s));
     const size_t rr = (size_t)r * r;
     CK(hipMemcpyAsync(S.pin, S.hdev + (size_t)(k - r) * r, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
     CK(hipMemcpyAsync(S.pin + rr, S.hdev + (size_t)k * r + (size_t)(k - r) * r, sizeof(double) * rr,
                       hipMemcpyDeviceToHost, s));
     // Gram matrix of the projected block (first Cholesky QR pass)
-    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s, S.part));
+    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s));
     CK(hipMemcpyAsync(S.pin + 2 * rr, S.gdev, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
     return FLP_OK;
 }
@@ -168,7 +169,7 @@ int step_qr1(Solve &S) {
     std::memcpy(S.pin + 3 * rr, Ri.data(), sizeof(double) * rr);
     CK(hipMemcpyAsync(S.rdev, S.pin + 3 * rr, sizeof(double) * rr, hipMemcpyHostToDevice, s));
     CK(launch_gemm_nn(n, r, r, 1.0, plain_mat(S.W, r), S.rdev, r, 0.0, S.W, r, s));
-    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s, S.part));
+    CKR(gram_tn(n, r, r, plain_mat(S.W, r), S.W, r, S.gdev, nullptr, s));
     CK(hipMemcpyAsync(S.pin + 2 * rr, S.gdev, sizeof(double) * rr, hipMemcpyDeviceToHost, s));
     return FLP_OK;
 }
@@ -196,7 +197,8 @@ int step_qr2(Solve &S) {
 }
 
 bool at_check(const Solve &S) {
-    return S.steps % S.check_every == 0 || S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n;
+    return (S.steps >= S.check_every && (S.steps + S.check_offset) % S.check_every == 0) ||
+           S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n;
 }
 
 namespace {
@@ -374,7 +376,10 @@ int solve_finish(Solve &S, flp_result **out) {
         eig_log_cols(S.eig, sel.data(), c, Zc.data());
         S.eig.clear();
         S.st.t_check += now() - tc;
-        const int ldc = (c + 1) & ~1;
+        // FP32 filter: room for the separation step below (at most c more columns)
+        const bool fp32 = S.o.prec == FLP_PREC_FP32_FILTER;
+        const int cap = fp32 ? 2 * c : c;
+        const int ldc = (cap + 1) & ~1;
         std::vector<double> Wc((size_t)K * ldc, 0.0);
         for (int i = 0; i < K; ++i)
             for (int j = 0; j < c; ++j) Wc[(size_t)i * ldc + j] = Zc[(size_t)i * c + j];
@@ -384,7 +389,7 @@ int solve_finish(Solve &S, flp_result **out) {
         CK(ensure(w.AX, sizeof(double) * (size_t)n * ldc));
         double *Y = (double *)w.Y.p, *AY = (double *)w.AY.p, *X = (double *)w.X.p, *AX = (double *)w.AX.p;
         double *sdev = nullptr;
-        CKR(small_dev((size_t)std::max(K, c) * ldc * 2 + 4 * (size_t)ldc + 64, &sdev));
+        CKR(small_dev((size_t)std::max(K, cap) * ldc * 2 + 4 * (size_t)ldc + 64, &sdev));
         CK(h2d(sdev, Wc.data(), sizeof(double) * Wc.size(), s));
         // Ritz vectors of p(A): Y = Q_k W_C
         CK(launch_gemm_nn(n, K, c, 1.0, S.Q, sdev, ldc, 0.0, Y, ldc, s));
@@ -392,20 +397,48 @@ int solve_finish(Solve &S, flp_result **out) {
         std::vector<double> lam, rres;
         CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
         const double alpha = S.alpha, beta = S.beta;
+        int cur = c;  // Ritz vectors in the block
         auto worst = [&](int &i0, int &i1) {
             i0 = 0;
-            while (i0 < c && lam[i0] < alpha) ++i0;
+            while (i0 < cur && lam[i0] < alpha) ++i0;
             i1 = i0;
-            while (i1 < c && lam[i1] <= beta) ++i1;
+            while (i1 < cur && lam[i1] <= beta) ++i1;
             double m = 0.0;
             for (int j = i0; j < i1; ++j) m = std::max(m, rres[j] / anorm);
             return m;
         };
         const double tol = S.o.tol > 0 ? S.o.tol : kDefaultTol;
         int i0 = 0, i1 = 0;
-        if (S.o.prec == FLP_PREC_FP32_FILTER) {
-            // FP64 polish: X <- p(A) X, orthonormalise, Rayleigh-Ritz with A
-            while (worst(i0, i1) > tol && S.st.polish_sweeps < kMaxPolish) {
+        if (fp32) {
+            int separations = 0;
+            for (;;) {
+                // A Ritz pair inside [alpha, beta] whose residual is far above
+                // what the FP32 filter leaves (about 1e-7) approximates no
+                // eigenvector: a guard vector mixing eigenvectors from both
+                // sides of the interval whose filter values nearly coincide,
+                // which subspace iteration with p cannot split.  Rayleigh-Ritz
+                // with A on span{X, A x} for such x does split it (its parts
+                // land outside the interval); the block grows by one column
+                // per such pair.
+                worst(i0, i1);
+                std::vector<int> mixed;
+                for (int j = i0; j < i1; ++j)
+                    if (rres[j] / anorm > kMixedResid) mixed.push_back(j);
+                if (!mixed.empty() && separations < 2 && cur + (int)mixed.size() <= cap) {
+                    CK(launch_copy_block(n, cur, 1.0, X, ldc, plain_mat(Y, ldc), 0, nullptr, 0, s));
+                    for (size_t t = 0; t < mixed.size(); ++t)
+                        CK(launch_copy_block(n, 1, 1.0, AX + mixed[t], ldc, plain_mat(Y, ldc), cur + (int)t, nullptr,
+                                             0, s));
+                    cur += (int)mixed.size();
+                    CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
+                    CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
+                    CKR(rayleigh_ritz(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+                    ++separations;
+                    continue;
+                }
+                if (worst(i0, i1) <= tol || S.st.polish_sweeps >= kMaxPolish) break;
+                // FP64 polish: X <- p(A) X, orthonormalise, Rayleigh-Ritz with A
+                const int c = cur;
                 for (int j0 = 0; j0 < c; j0 += 32) {
                     const int cw = std::min(32, c - j0);
                     CKR(filter_apply_impl(S.filt.get(), A, X + j0, ldc, Y + j0, ldc, cw, FLP_PREC_FP64, s));

@@ -67,7 +67,7 @@ class FlpStatsC(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("mv", ctypes.c_int64), ("basis_cols", ctypes.c_int32),
                 ("polish_sweeps", ctypes.c_int32), ("t_pre", ctypes.c_double), ("t_mv", ctypes.c_double),
                 ("t_orth", ctypes.c_double), ("t_check", ctypes.c_double), ("t_rr", ctypes.c_double),
-                ("t_total", ctypes.c_double), ("filter_bytes", ctypes.c_double)]
+                ("t_total", ctypes.c_double), ("filter_bytes", ctypes.c_double), ("orth_bytes", ctypes.c_double)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
@@ -75,7 +75,7 @@ class FlpBatchStatsC(ctypes.Structure):
                 ("graph_captures", ctypes.c_int32), ("graph_replays", ctypes.c_int32),
                 ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_filter", ctypes.c_double),
                 ("t_orth_check", ctypes.c_double), ("t_finish", ctypes.c_double),
-                ("filter_bytes", ctypes.c_double)]
+                ("filter_bytes", ctypes.c_double), ("t_orth", ctypes.c_double), ("orth_bytes", ctypes.c_double)]
 
 
 class FlpServerOptsC(ctypes.Structure):

@@ -276,6 +276,7 @@ def test_custom_allocator(torch):
     A = w["A"]
     dA = flp.DeviceCsr.from_host(A)
     ref = flp.flp_solve(dA, 0.5, 1.0, block=2, degree=50, seed=3)
+    bref, _ = flp.flp_solve_batch([dA, dA], [0.5, 1.0], [1.0, 1.5], block=2, degree=50, seeds=[3, 4])
     counts = {"alloc": 0, "free": 0}
     alloc0, free0 = flp.torch_allocator()
 
@@ -300,4 +301,7 @@ def test_custom_allocator(torch):
     assert counts["free"] == counts["alloc"]
     assert got["count"] == ref["count"]
     assert np.array_equal(got["evals"], ref["evals"])
-    assert np.array_equal(bres[0]["evals"], ref["evals"])
+    for a, b in zip(bres, bref):                     # the batch against itself on hipMalloc memory
+        assert a["count"] == b["count"] and np.array_equal(a["evals"], b["evals"])
+    # and the batch agrees with the single solve to the parity tolerance
+    assert np.max(np.abs(bres[0]["evals"] - ref["evals"]) / np.abs(ref["evals"])) <= 1e-12
