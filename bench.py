@@ -57,6 +57,8 @@ def parse():
                     help="filter degree (default: 110 for the 100^3 workload, the fastest of a 100..200 sweep "
                          "there; 100 for the 120^3 Hamiltonian)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--polish-degree", type=int, default=0,
+                    help="FP32 filter: degree of the FP64 polish filter (0: the solve's degree)")
     ap.add_argument("--check-every", type=int, default=0,
                     help="block steps between convergence checks (0: the library default, 30)")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -207,7 +209,7 @@ def bench_batch(args):
     def run_batch(seed0):
         return flp.flp_solve_batch(dAs, alphas, betas, block=8, seeds=[seed0 + i for i in range(len(dAs))],
                                    prec=prec, use_graph=not args.no_graph, want_vectors=False,
-                                   check_every=args.check_every)
+                                   check_every=args.check_every, polish_degree=args.polish_degree)
 
     for i in range(args.warmup):
         run_batch(1000 * (i + 1))
@@ -270,7 +272,7 @@ def bench_batch(args):
         pairs = 0
         for i, dA in enumerate(dAs):
             r = flp.flp_solve(dA, alphas[i], betas[i], block=8, seed=i, want_vectors=False,
-                              check_every=args.check_every)
+                              check_every=args.check_every, polish_degree=args.polish_degree)
             pairs += r["count"] if (r["count"] and float(np.max(r["resid"])) <= 1e-9) else 0
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - tp
@@ -309,7 +311,7 @@ def bench_serve(args):
                     if dt > 0:
                         time.sleep(dt)
                 tickets[i] = sv.submit(dAs[i], a, b, seed=seed0 + i, degree=fam[i]["degree"],
-                                       check_every=args.check_every)
+                                       check_every=args.check_every, polish_degree=args.polish_degree)
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -358,7 +360,7 @@ def bench_serve(args):
         pres = []
         for i, (A, a, b) in enumerate(probs):
             pres.append(flp.flp_solve(dAs[i], a, b, block=16, degree=fam[i]["degree"], seed=i, want_vectors=False,
-                                      max_basis=2048, check_every=args.check_every))
+                                      max_basis=2048, check_every=args.check_every, polish_degree=args.polish_degree))
             print(f"#   plain {i + 1}/{len(probs)}: count={pres[-1]['count']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
@@ -431,12 +433,12 @@ def bench_c3(args):
     for name, prec in (("fp64", flp.FLP_PREC_FP64), ("fp32", flp.FLP_PREC_FP32_FILTER)):
         for i in range(args.warmup):
             flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=100 + i, prec=prec,
-                          want_vectors=False, check_every=args.check_every)
+                          want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree)
         lat, res = [], None
         for i in range(args.steps):
             t0 = time.perf_counter()
             res = flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=i, prec=prec,
-                                want_vectors=False, check_every=args.check_every)
+                                want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree)
             lat.append(time.perf_counter() - t0)
             print(f"# {name} step {i + 1}/{args.steps}: {res['count']} pairs, {lat[-1]:.2f} s, iters "
                   f"{res['stats']['iters']}, polish {res['stats']['polish_sweeps']}", file=sys.stderr, flush=True)
@@ -506,7 +508,7 @@ def main():
 
     def solve(seed):
         return flp.flp_solve(dA, alpha, beta, block=w["block"], degree=args.degree, seed=seed, prec=prec,
-                             want_vectors=False, check_every=args.check_every)
+                             want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree)
 
     for i in range(args.warmup):
         solve(1000 + i)

@@ -91,6 +91,8 @@ typedef struct flp_opts {
     double lmin, lmax;    /* spectrum bounds to use if lmin < lmax; else estimated */
     void *stream;         /* hipStream_t, NULL = default stream */
     double sym_tol;       /* >= 0: run flp_check_symmetric(A, sym_tol) first; < 0 (default): skip */
+    int32_t polish_degree;  /* FP32 filter only: degree of the FP64 polish filter on the same
+                               interval; <= 0 (default) uses the solve's degree */
 } flp_opts;
 
 typedef struct flp_stats {
@@ -156,6 +158,12 @@ int32_t flp_filter_coeffs(const flp_filter *p, double *coeffs, int32_t cap);
 int flp_filter_info(const flp_filter *p, double *out6);
 /* Evaluate p at host points z (already in [-1,1] units), host in/out. */
 int flp_filter_eval(const flp_filter *p, const double *z, double *out, int32_t count);
+/* Chebyshev coefficients c_0..c_{m-1} of g(z) = (p(z) - p(t)) / (z - t), the
+ * divided difference of the filter at t (in [-1,1] units), into host
+ * coeffs[0..cap); returns m (or a negative error).  The FP32-filter polish
+ * applies g to each Ritz vector's residual: p(Ahat) x = p(t) x + g(Ahat) r
+ * when Ahat x = t x + r. */
+int32_t flp_filter_divided(const flp_filter *p, double t, double *coeffs, int32_t cap);
 
 /* W = p(Ahat) V, Ahat = (A - cI)/e (eq. transf), by Clenshaw's backward
  * recurrence (Section 2.2) with the affine map and the three-term update

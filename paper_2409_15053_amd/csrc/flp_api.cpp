@@ -33,6 +33,7 @@ void flp_opts_default(flp_opts *o) {
     o->lmax = 0.0;
     o->stream = nullptr;
     o->sym_tol = -1.0;
+    o->polish_degree = 0;
 }
 
 int flp_build_filter(double alpha, double beta, int32_t degree, double lmin, double lmax, flp_filter **out) {
@@ -75,6 +76,14 @@ int flp_filter_eval(const flp_filter *p, const double *z, double *o, int32_t cou
     if (!p || (count > 0 && (!z || !o)) || count < 0) return fail(FLP_E_ARG, "bad argument");
     for (int i = 0; i < count; ++i) o[i] = cheb_scalar(p->b, z[i]);
     return FLP_OK;
+}
+
+int32_t flp_filter_divided(const flp_filter *p, double t, double *coeffs, int32_t cap) {
+    if (!p || !coeffs || cap < 0) return fail(FLP_E_ARG, "bad argument");
+    std::vector<double> c;
+    cheb_divided(p->b, t, c);
+    for (int i = 0; i < (int)c.size() && i < cap; ++i) coeffs[i] = c[i];
+    return (int32_t)c.size();
 }
 
 int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, double *W, int32_t r, int32_t prec,

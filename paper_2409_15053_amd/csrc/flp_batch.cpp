@@ -231,13 +231,15 @@ int Engine::block_step(double filter_secs) {
     std::vector<size_t> poff(ns);
     size_t ptotal = 0;
     CK(ensure(oout, sizeof(double) * slot * ns));
+    // room in each basis for this step's projection and the next block
+    for (Job *j : active) CKR(ensure_basis(*j->S, (int64_t)(j->S->steps + 2) * c));
     for (int i = 0; i < ns; ++i) {
         Solve &S = *active[i]->S;
         OrthSeg &e = otab_host[i];
         const int n = S.n, k = (S.steps + 1) * c;
         e.n = n;
         e.k = k;
-        e.qcap = (int)(S.npanels << kPanelLog2);
+        e.qcap = (int)(S.qpanels << kPanelLog2);
         e.chunk_rows = orth_chunk_rows(n, k, c);
         e.nchunks = (n + e.chunk_rows - 1) / e.chunk_rows;
         e.gchunk_rows = orth_chunk_rows(n, c, c);
@@ -304,7 +306,7 @@ int Engine::block_step(double filter_secs) {
             // the projected block, then the copies the kernels skipped
             const int k = (S.steps + 1) * c;
             int rc = block_qr_impl(S.W, S.n, c, &S.Q, k, S.Sj, S.o.seed, 1000 + S.steps, s, nullptr);
-            if (rc == FLP_OK && k + c <= (int)(S.npanels << kPanelLog2) &&
+            if (rc == FLP_OK && k + c <= (int)(S.qpanels << kPanelLog2) &&
                 launch_copy_block(S.n, c, 1.0, S.W, c, S.Q, k, nullptr, 0, s) != hipSuccess)
                 rc = fail(FLP_E_DEVICE, "basis copy failed");
             if (rc == FLP_OK &&

@@ -129,7 +129,8 @@ hipError_t ensure(Buf &b, size_t bytes) {
 }
 
 void Workspace::release_all() {
-    Buf *all[] = {&U[0], &U[1], &U[2], &V32, &Vg, &val32, &partials, &small, &W, &Vin, &Q, &Y, &AY, &X, &AX, &resid_part};
+    Buf *all[] = {&U[0], &U[1], &U[2], &V32, &Vg, &val32, &partials, &small, &W, &Vin, &Q, &Y, &AY, &X, &AX,
+                  &resid_part, &PU[0], &PU[1], &PU[2], &PR, &PC};
     for (Buf *b : all) b->release();
     val32_src = nullptr;
     val32_nnz = 0;
@@ -217,6 +218,23 @@ double cheb_scalar(const std::vector<double> &b, double z) {
         u1 = u;
     }
     return b[0] + z * u1 - u2;
+}
+
+// Chebyshev coefficients c_0..c_{m-1} of g(z) = (p(z) - p(t)) / (z - t) for
+// p = sum_k b_k T_k (degree m >= 1): synthetic division by (z - t) in the
+// Chebyshev basis.  With z T_0 = T_1 and z T_k = (T_{k+1} + T_{k-1}) / 2,
+// matching the coefficients of (z - t) g = p - p(t) from T_m down gives
+// c_{m-1} = 2 b_m, c_{j-1} = 2 (b_j + t c_j) - c_{j+1} (j = m-1 .. 2) and
+// c_0 = b_1 + t c_1 - c_2 / 2 (the T_0 equation then holds by itself).
+void cheb_divided(const std::vector<double> &b, double t, std::vector<double> &c) {
+    const int m = (int)b.size() - 1;
+    c.assign(std::max(m, 1) + 2, 0.0);
+    if (m >= 2) {
+        c[m - 1] = 2.0 * b[m];
+        for (int j = m - 1; j >= 2; --j) c[j - 1] = 2.0 * (b[j] + t * c[j]) - c[j + 1];
+    }
+    if (m >= 1) c[0] = b[1] + t * c[1] - 0.5 * c[2];
+    c.resize(std::max(m, 1));
 }
 
 // b_0..b_m of the indicator of [a, b] in [-1, 1] (closed form of Section 2.2).
@@ -422,6 +440,61 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
             CK(launch_copy_block(n, gw, 1.0, V + j0, ldv, plain_mat((double *)w.Vg.p, gw), 0, nullptr, 0, s));
         auto plan = clenshaw_plan(p, gw, w.Vg.p, gw, W + j0, ldw, U[0], U[1], U[2], fp32);
         for (const auto &st : plan) CKR(launch_plan_step(A, v32, gw, st, fp32, s, tn.sh));
+    }
+    return FLP_OK;
+}
+
+int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int c, const double *X,
+                 const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
+                 double *bytes) {
+    Workspace &w = ws();
+    const int n = A->n, PW = polish_block_width();
+    const int mg = std::max(p->m, 1);  // coefficients of the divided differences
+    for (auto &u : w.PU) CK(ensure(u, sizeof(float) * (size_t)n * PW));
+    CK(ensure(w.PR, sizeof(float) * (size_t)n * PW));
+    const size_t tab_bytes = ((sizeof(float) * (size_t)mg * PW + 255) / 256) * 256;
+    CK(ensure(w.PC, tab_bytes + sizeof(double) * 2 * PW));
+    float *U[3] = {(float *)w.PU[0].p, (float *)w.PU[1].p, (float *)w.PU[2].p};
+    float *R = (float *)w.PR.p;
+    float *coef = (float *)w.PC.p;
+    double *lp = (double *)((char *)w.PC.p + tab_bytes);  // Ritz values, then p(t_j)
+    const double cc = p->c, e = p->e;
+    const float a2 = (float)(2.0 / e), b2 = (float)(-2.0 * cc / e), a1 = (float)(1.0 / e), b1 = (float)(-cc / e);
+    std::vector<float> tab((size_t)mg * PW);
+    std::vector<double> lph(2 * PW), g;
+    for (int j0 = 0; j0 < c; j0 += PW) {
+        const int wc = std::min(PW, c - j0);
+        std::fill(tab.begin(), tab.end(), 0.0f);
+        std::fill(lph.begin(), lph.end(), 0.0);
+        for (int j = 0; j < wc; ++j) {
+            const double t = (lam[j0 + j] - cc) / e;
+            cheb_divided(p->b, t, g);
+            for (int k = 0; k < mg; ++k) tab[(size_t)k * PW + j] = (float)g[k];
+            lph[j] = lam[j0 + j];
+            lph[PW + j] = cheb_scalar(p->b, t);
+        }
+        CK(h2d(coef, tab.data(), sizeof(float) * tab.size(), s));
+        CK(h2d(lp, lph.data(), sizeof(double) * lph.size(), s));
+        CK(launch_polish_resid(n, wc, X + j0, AX + j0, ldc, lp, 1.0 / e, R, s));
+        // Clenshaw for sum_k g_k T_k(Ahat) r: u_k = g_k r + 2 Ahat u_{k+1} - u_{k+2}
+        // (k = mg-1 .. 1), result g_0 r + Ahat u_1 - u_2, plus p(t_j) x_j
+        const float *u1 = nullptr, *u2 = nullptr;
+        int next = 0;
+        for (int k = mg - 1; k >= 1; --k) {
+            float *out = U[next];
+            next = (next + 1) % 3;
+            CK(launch_polish_step(n, A->rowptr, A->colind, val32, u1, u2, R, coef + (size_t)k * PW, a2, b2, out, s));
+            u2 = u1;
+            u1 = out;
+        }
+        CK(launch_polish_last(n, A->rowptr, A->colind, val32, u1, u2, R, coef, a1, b1, Y + j0, ldc, wc, X + j0, ldc,
+                              lp + PW, s));
+    }
+    if (bytes) {
+        // per step: the matrix in FP32 once, the gathered block, U_{k+2},
+        // the residual block and the output (FP32); plus the FP64 in/out
+        const double step = (double)A->nnz * 8.0 + 4.0 * (n + 1) + 4.0 * (double)n * PW * 4.0;
+        *bytes = step * mg * ((c + PW - 1) / PW) + 8.0 * 4.0 * (double)n * c;
     }
     return FLP_OK;
 }

@@ -43,6 +43,7 @@ constexpr double kDefaultTol = 1e-9;
 constexpr int kMaxDegree = 100000;
 constexpr int64_t kDefaultMaxBasis = 3072;
 constexpr int kPanelLog2 = 7;  // Lanczos basis panels of 128 columns
+constexpr int64_t kInitPanels = 4;  // basis panels allocated at set-up (more on demand)
 constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
 // relative residual above which an in-interval Ritz pair of an FP32-filter
 // solve counts as a mixture of eigenvectors (converged pairs sit near 1e-7)
@@ -86,6 +87,7 @@ struct Workspace {
     Buf U[3];      // Clenshaw vectors
     Buf V32;       // FP32 copy of the filter input
     Buf Vg;        // one column group of the filter input, stored contiguously
+    Buf PU[3], PR, PC;  // residual-form polish: FP32 recurrence and residual blocks, coefficients
     Buf val32;     // FP32 copy of the matrix values
     Buf partials;  // gemm_tn partial sums
     Buf small;     // small device matrices
@@ -111,6 +113,8 @@ int small_dev(size_t elems, double **out);
 
 // ---------------------------------------------------------------- filter
 double cheb_scalar(const std::vector<double> &b, double z);
+// Chebyshev coefficients (m of them) of (p(z) - p(t)) / (z - t), p = sum b_k T_k
+void cheb_divided(const std::vector<double> &b, double t, std::vector<double> &c);
 int make_filter(double alpha, double beta, int degree, double lmin, double lmax, double eps, flp_filter **out);
 double filter_step_bytes(int n, int64_t nnz, int r, int prec);
 int filter_group_width(int n, int64_t nnz, int r, int prec);
@@ -159,6 +163,13 @@ void force_filter_shape(StepShape sh, int gw);
 // workspace's Clenshaw buffers.
 int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, int ldv, double *W, int ldw, int r,
                       int prec, hipStream_t s);
+// Y = p(Ahat) X for c Ritz vectors of A (X, AX = A X, Ritz values lam;
+// n x c blocks with leading dimension ldc) by the residual form: X diag(p(t))
+// in FP64 plus the divided-difference recurrences on the residuals in FP32
+// (val32: FP32 copy of A's values).  Returns the algorithmic bytes moved.
+int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int c, const double *X,
+                 const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
+                 double *bytes);
 
 // ---------------------------------------------------------------- dense helpers
 void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, std::vector<int> &bad);
@@ -220,7 +231,8 @@ struct Solve {
     std::unique_ptr<flp_filter> filt;
     int check_every = 0, max_steps = 0;
     int check_offset = 0;  // checks fall on steps with (steps + check_offset) % check_every == 0
-    int64_t npanels = 0;
+    int64_t npanels = 0;   // panels the basis may grow to (max_basis)
+    int64_t qpanels = 0;   // panels allocated (grown on demand)
     DMat Q{};
     double *W = nullptr, *Vin = nullptr, *hdev = nullptr;
     const float *val32 = nullptr;
@@ -255,6 +267,9 @@ struct Solve {
 
 // bounds, filter, buffers, start block (PREPROC and set-up)
 int solve_setup(Solve &S);
+// Grows the basis allocation (by doubling, on S.s, synchronous) so that it
+// holds at least cols columns (capped at max_basis).
+int ensure_basis(Solve &S, int64_t cols);
 // One block step of a single solve after the filter has produced W, in
 // phases separated by a stream synchronisation (the batched engine does the
 // first three for all its solves at once with the segmented launches of

@@ -80,7 +80,11 @@ int solve_setup(Solve &S) {
     // row-major n x 128 block (the reorthogonalisation streams whole panels)
     S.npanels = ((int64_t)S.max_steps * r + (1 << kPanelLog2) - 1) >> kPanelLog2;
     SolveBufs &B = *S.B;
-    CK(ensure(B.Q, sizeof(double) * (size_t)n * (size_t)(S.npanels << kPanelLog2)));
+    // the basis starts with a few panels and grows as the solve needs them
+    // (max_basis columns would mostly stay unused)
+    const size_t panel_bytes = (sizeof(double) * (size_t)n) << kPanelLog2;
+    CK(ensure(B.Q, panel_bytes * (size_t)std::min<int64_t>(S.npanels, kInitPanels)));
+    S.qpanels = std::min<int64_t>(S.npanels, (int64_t)(B.Q.bytes / panel_bytes));
     CK(ensure(B.W, sizeof(double) * (size_t)n * r));
     CK(ensure(B.Vin, sizeof(double) * (size_t)n * r));
     const size_t hcols = (size_t)(S.npanels << kPanelLog2);
@@ -121,8 +125,32 @@ Solve::~Solve() {
     if (pin) (void)hipHostFree(pin);
 }
 
+int ensure_basis(Solve &S, int64_t cols) {
+    cols = std::min<int64_t>(cols, S.npanels << kPanelLog2);
+    const int64_t need = (cols + (1 << kPanelLog2) - 1) >> kPanelLog2;
+    if (need <= S.qpanels) return FLP_OK;
+    const int64_t want = std::min(S.npanels, std::max(need, 2 * S.qpanels));
+    const size_t panel_bytes = (sizeof(double) * (size_t)S.n) << kPanelLog2;
+    void *p = nullptr;
+    CK(dev_alloc(&p, panel_bytes * (size_t)want));
+    hipError_t e = hipMemcpyAsync(p, S.B->Q.p, panel_bytes * (size_t)S.qpanels, hipMemcpyDeviceToDevice, S.s);
+    if (e == hipSuccess) e = hipStreamSynchronize(S.s);
+    if (e != hipSuccess) {
+        (void)dev_free(p);
+        CK(e);
+    }
+    Buf &q = S.B->Q;
+    (void)dev_free(q.p);
+    q.p = p;
+    q.bytes = panel_bytes * (size_t)want;
+    S.qpanels = want;
+    S.Q = panel_mat((double *)p, S.n, kPanelLog2);
+    return FLP_OK;
+}
+
 int step_orth_launch(Solve &S) {
     const int n = S.n, r = S.r;
+    CKR(ensure_basis(S, (int64_t)(S.steps + 2) * r));  // the projection's columns and the next block
     hipStream_t s = S.s;
     S.t_step0 = now();
     const int k = (S.steps + 1) * r;  // basis columns so far
@@ -410,6 +438,16 @@ int solve_finish(Solve &S, flp_result **out) {
         const double tol = S.o.tol > 0 ? S.o.tol : kDefaultTol;
         int i0 = 0, i1 = 0;
         if (fp32) {
+            // the polish filter: the solve's own, or one of the requested degree
+            const flp_filter *pf = S.filt.get();
+            std::unique_ptr<flp_filter> pown;
+            if (S.o.polish_degree > 0 && S.o.polish_degree != S.filt->m) {
+                flp_filter *q = nullptr;
+                CKR(make_filter(S.alpha, S.beta, S.o.polish_degree, S.lmin, S.lmax,
+                                S.o.eps > 0 ? S.o.eps : kDefaultEps, &q));
+                pown.reset(q);
+                pf = q;
+            }
             int separations = 0;
             for (;;) {
                 // A Ritz pair inside [alpha, beta] whose residual is far above
@@ -437,14 +475,12 @@ int solve_finish(Solve &S, flp_result **out) {
                     continue;
                 }
                 if (worst(i0, i1) <= tol || S.st.polish_sweeps >= kMaxPolish) break;
-                // FP64 polish: X <- p(A) X, orthonormalise, Rayleigh-Ritz with A
+                // polish: X <- p(Ahat) X in FP64 accuracy (residual form, FP32
+                // recurrences), orthonormalise, Rayleigh-Ritz with A
                 const int c = cur;
-                for (int j0 = 0; j0 < c; j0 += 32) {
-                    const int cw = std::min(32, c - j0);
-                    CKR(filter_apply_impl(S.filt.get(), A, X + j0, ldc, Y + j0, ldc, cw, FLP_PREC_FP64, s));
-                }
-                S.st.filter_bytes +=
-                    filter_step_bytes(n, A->nnz, 32, FLP_PREC_FP64) * S.filt->m * ((c + 31) / 32);
+                double pbytes = 0.0;
+                CKR(polish_apply(pf, A, S.val32, c, X, AX, ldc, lam, Y, s, &pbytes));
+                S.st.filter_bytes += pbytes;
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
                 CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));

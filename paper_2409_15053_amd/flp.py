@@ -28,7 +28,7 @@ FLP_PREC_FP32_FILTER = 1
 
 EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
-    "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval",
+    "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval", "flp_filter_divided",
     "flp_filter_apply", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_sliced", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_set_allocator", "flp_check_symmetric", "flp_last_error", "flp_version",
@@ -60,7 +60,7 @@ class FlpOptsC(ctypes.Structure):
                 ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("max_basis", ctypes.c_int64), ("k0", ctypes.c_int32),
                 ("start", ctypes.c_void_p), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double),
-                ("stream", ctypes.c_void_p), ("sym_tol", ctypes.c_double)]
+                ("stream", ctypes.c_void_p), ("sym_tol", ctypes.c_double), ("polish_degree", ctypes.c_int32)]
 
 
 class FlpStatsC(ctypes.Structure):
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
         "flp_filter_coeffs": (I32, [P, P, I32]),
         "flp_filter_info": (ctypes.c_int, [P, P]),
         "flp_filter_eval": (ctypes.c_int, [P, P, P, I32]),
+        "flp_filter_divided": (I32, [P, F64, P, I32]),
         "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, P, I32, I32, P]),
         "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, P, ctypes.POINTER(FlpTuneInfoC)]),
         "flp_set_autotune": (None, [I32]),
@@ -225,6 +226,14 @@ class Filter:
         _check(load().flp_filter_eval(self.h, _np_ptr(z), _np_ptr(out), z.size))
         return out
 
+    def divided(self, t: float) -> np.ndarray:
+        """Chebyshev coefficients of (p(z) - p(t)) / (z - t)."""
+        m = max(self.degree, 1)
+        out = np.zeros(m)
+        got = load().flp_filter_divided(self.h, float(t), _np_ptr(out), m)
+        _check(0 if got == m else (got if got < 0 else -1))
+        return out
+
 
 def flp_build_filter(alpha: float, beta: float, degree: int, lmin: float, lmax: float,
                      eps: float | None = None) -> Filter:
@@ -311,7 +320,7 @@ def default_opts() -> FlpOptsC:
 def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: int = 0, seed: int = 0,
               prec: int = FLP_PREC_FP64, start: np.ndarray | None = None, bounds=None, max_basis: int = 0,
               check_every: int = 0, eps: float = 0.0, k0: int = 0, want_vectors: bool = True,
-              stream=None, sym_tol: float = -1.0) -> dict:
+              stream=None, sym_tol: float = -1.0, polish_degree: int = 0) -> dict:
     """Every eigenpair of A in [alpha, beta].  Returns a dict with numpy
     ``evals``/``resid``, a torch ``evecs`` (n x count, float64, on A's
     device) and the solve statistics.  ``sym_tol >= 0`` checks A for
@@ -338,6 +347,7 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
         o.lmin, o.lmax = bounds
     o.stream = _stream_ptr(stream)
     o.sym_tol = sym_tol
+    o.polish_degree = polish_degree
     res = ctypes.POINTER(FlpResultC)()
     rc = lib.flp_solve(ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(res))
     _check(rc, allow=(FLP_E_NOCONV,))
@@ -364,11 +374,12 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
 def flp_solve_sliced(A: DeviceCsr, alpha: float, beta: float, nslices: int, block: int = 8, degree: int = 0,
                      seed: int = 0, prec: int = FLP_PREC_FP64, bounds=None, max_basis: int = 0,
                      check_every: int = 0, eps: float = 0.0, k0: int = 0, want_vectors: bool = True,
-                     stream=None) -> dict:
+                     stream=None, polish_degree: int = 0) -> dict:
     """Every eigenpair of A in [alpha, beta] by nslices slices solved as one
     batch (same return value as flp_solve)."""
     lib = load()
-    o = _make_opts(block, degree, seed, prec, max_basis, check_every, eps, k0, bounds, stream)
+    o = _make_opts(block, degree, seed, prec, max_basis, check_every, eps, k0, bounds, stream,
+                   polish_degree=polish_degree)
     res = ctypes.POINTER(FlpResultC)()
     rc = lib.flp_solve_sliced(ctypes.byref(A.c), alpha, beta, nslices, ctypes.byref(o), ctypes.byref(res))
     _check(rc, allow=(FLP_E_NOCONV,))
@@ -380,8 +391,10 @@ def flp_solve_sliced(A: DeviceCsr, alpha: float, beta: float, nslices: int, bloc
     return out
 
 
-def _make_opts(block, degree, seed, prec, max_basis, check_every, eps, k0, bounds, stream, start=None):
+def _make_opts(block, degree, seed, prec, max_basis, check_every, eps, k0, bounds, stream, start=None,
+               polish_degree=0):
     o = default_opts()
+    o.polish_degree = polish_degree
     o.block = block
     o.degree = degree
     o.seed = seed
@@ -420,7 +433,7 @@ def _collect(res_ptr, n, device, want_vectors, stream):
 
 def flp_solve_batch(As, alphas, betas, block: int = 8, degree=0, seeds=None, prec: int = FLP_PREC_FP64,
                     use_graph: bool = True, max_basis: int = 0, check_every: int = 0, eps: float = 0.0,
-                    k0: int = 0, want_vectors: bool = True, stream=None):
+                    k0: int = 0, want_vectors: bool = True, stream=None, polish_degree: int = 0):
     """Solve len(As) independent problems together (segmented filter
     launches).  Returns (list of per-solve dicts like flp_solve, batch stats)."""
     import torch
@@ -431,7 +444,8 @@ def flp_solve_batch(As, alphas, betas, block: int = 8, degree=0, seeds=None, pre
     degrees = degree if isinstance(degree, (list, tuple)) else [degree] * cnt
     opts = (FlpOptsC * cnt)()
     for i in range(cnt):
-        opts[i] = _make_opts(block, degrees[i], seeds[i], prec, max_basis, check_every, eps, k0, None, stream)
+        opts[i] = _make_opts(block, degrees[i], seeds[i], prec, max_basis, check_every, eps, k0, None, stream,
+                             polish_degree=polish_degree)
     arr = (ctypes.POINTER(FlpCsrC) * cnt)(*[ctypes.pointer(A.c) for A in As])
     al = np.ascontiguousarray(alphas, dtype=np.float64)
     be = np.ascontiguousarray(betas, dtype=np.float64)
@@ -473,8 +487,8 @@ class Server:
         self._keep = {}
 
     def submit(self, A: DeviceCsr, alpha: float, beta: float, seed: int = 0, degree: int = 0,
-               max_basis: int = 0, check_every: int = 0) -> int:
-        o = _make_opts(1, degree, seed, 0, max_basis, check_every, 0.0, 0, None, None)
+               max_basis: int = 0, check_every: int = 0, polish_degree: int = 0) -> int:
+        o = _make_opts(1, degree, seed, 0, max_basis, check_every, 0.0, 0, None, None, polish_degree=polish_degree)
         o.stream = None
         t = ctypes.c_uint64()
         _check(load().flp_server_submit(self.h, ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(t)))

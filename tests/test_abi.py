@@ -132,3 +132,25 @@ def test_opts_defaults_and_new_codes():
     assert o.sym_tol < 0          # the symmetry check is opt-in
     assert o.block == 1 and o.check_every == 0 and abs(o.eps - 0.31227) < 1e-12
     assert flp.FLP_E_CANCELLED == -8 and flp.FLP_E_NOTSYM == -3
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 17, 100])
+def test_filter_divided_difference(m):
+    """The polish's divided difference g(z) = (p(z) - p(t)) / (z - t), from
+    Chebyshev synthetic division, against its definition at sample points:
+    (z - t) g(z) = p(z) - p(t) with g evaluated by numpy's Chebyshev series."""
+    f = flp.flp_build_filter(-0.6, -0.2, m, -1.0, 1.0)
+    b = f.coeffs()
+    rng = np.random.default_rng(m)
+    for t in [-0.999, -0.4, 0.0, 0.35, 0.999, rng.uniform(-1, 1)]:
+        c = f.divided(t)
+        assert len(c) == m
+        z = np.concatenate([rng.uniform(-1, 1, 50), [-1.0, 1.0]])
+        z = z[np.abs(z - t) > 1e-3]
+        g = np.polynomial.chebyshev.chebval(z, c)
+        lhs = (z - t) * g
+        rhs = np.polynomial.chebyshev.chebval(z, b) - np.polynomial.chebyshev.chebval(t, b)
+        assert np.max(np.abs(lhs - rhs)) <= 1e-12 * max(1.0, np.max(np.abs(b)) * m)
+        # the limit at z = t is p'(t)
+        dp = np.polynomial.chebyshev.chebval(t, np.polynomial.chebyshev.chebder(b))
+        assert abs(np.polynomial.chebyshev.chebval(t, c) - dp) <= 1e-9 * max(1.0, abs(dp))
