@@ -679,25 +679,31 @@ int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, 
     CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, dev, &g, s));
     if (!(g > 0.0)) return fail(FLP_E_DEVICE, "bounds: zero start vector");
     CK(launch_copy_block(n, 1, 1.0 / std::sqrt(g), wv, 1, plain_mat(Qb, ldb), 0, nullptr, 0, s));
-    std::vector<double> al, be;
-    std::vector<double> h1(k), h2(k);
-    double beta_k = 0.0;
-    int steps = 0;
+    // k steps without a host round trip: the Gram-Schmidt coefficients, the
+    // norm and the next vector stay on the device (dev: H1, H2 in [0, 2 ldb),
+    // ||w||^2 at 2 ldb, alpha_j / beta_j pairs from 2 ldb + 8)
+    double *gdev = dev + 2 * ldb, *abdev = dev + 2 * ldb + 8;
     for (int j = 0; j < k; ++j) {
         // w = A q_j
         CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, 1, Qb + j, ldb, nullptr, 0, nullptr,
                                             0, wv, 1, 1.0, 0.0, 0.0, 0.0, s));
         CKR(cgs2(plain_mat(Qb, ldb), j + 1, n, wv, 1, dev, s));
-        CK(hipMemcpyAsync(h1.data(), dev, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-        CK(hipMemcpyAsync(h2.data(), dev + (j + 1), sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-        CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, dev + 2 * ldb, &g, s));
-        al.push_back(h1[j] + h2[j]);
-        double bj = std::sqrt(std::max(g, 0.0));
-        be.push_back(bj);
+        CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, gdev, nullptr, s));
+        CK(launch_lanczos_next(n, wv, Qb + j + 1, ldb, gdev, dev, dev + (j + 1), j, abdev, s));
+    }
+    std::vector<double> ab(2 * (size_t)k);
+    CK(hipMemcpyAsync(ab.data(), abdev, sizeof(double) * ab.size(), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    // the recurrence ends at the first breakdown (beta_j = 0) or after k steps
+    std::vector<double> al, be;
+    double beta_k = 0.0;
+    int steps = 0;
+    for (int j = 0; j < k; ++j) {
+        al.push_back(ab[2 * j]);
+        be.push_back(ab[2 * j + 1]);
         steps = j + 1;
-        beta_k = bj;
-        if (bj == 0.0 || j == k - 1) break;
-        CK(launch_copy_block(n, 1, 1.0 / bj, wv, 1, plain_mat(Qb, ldb), j + 1, nullptr, 0, s));
+        beta_k = ab[2 * j + 1];
+        if (beta_k == 0.0) break;
     }
     // Ritz values of the tridiagonal and the last eigenvector row
     std::vector<double> T((size_t)steps * steps, 0.0);
