@@ -37,7 +37,7 @@ KERNEL_SOURCES = ["paper_2409_15053_amd/csrc/flp_filter.hip", "paper_2409_15053_
 METRIC = "filter SpMM GB/s (% HBM roofline); eigenpairs/s; p50/p99 solve latency"
 
 WORKLOADS = {
-    "lap3d7_100": dict(golden="c2_lap3d7_100_U01.json", N=100, kind="c2", degree=110),
+    "lap3d7_100": dict(golden="c2_lap3d7_100_U01.json", N=100, kind="c2", degree=100),
     "lap3d7_30": dict(golden=None, N=30, kind="c2"),
     "batch64": dict(golden=None, kind="batch", count=64),
     "batch16": dict(golden=None, kind="batch", count=16),

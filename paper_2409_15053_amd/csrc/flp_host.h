@@ -377,7 +377,7 @@ struct Engine {
     int block_step(double filter_secs);
     // finishers: Ritz vectors, Rayleigh-Ritz and polish of converged solves,
     // each on its own host thread and stream, overlapping later block steps
-    static constexpr int kFinishers = 4;
+    static constexpr int kFinishers = 8;
     hipStream_t fs[kFinishers] = {};
     std::thread fin[kFinishers];
     std::mutex fmu;

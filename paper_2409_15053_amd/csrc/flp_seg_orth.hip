@@ -138,82 +138,98 @@ __global__ __launch_bounds__(256) void seg_nn_kernel(const OrthSeg *__restrict__
     gemm_nn_rows<4, 1>(e.n, e.k, c, -1.0, e.Q, e.H + (size_t)which * e.k * c, c, 1.0, e.W, c, true, lb, 0);
 }
 
-// Cholesky factor R (upper, row-major c x c) of G with the dependent-column
-// rule of the block QR: a pivot d_i <= thr2 marks column i (returns false).
-__device__ bool chol_upper(int c, const double *G, double thr2, double *R) {
-    bool ok = true;
-    for (int i = 0; i < c * c; ++i) R[i] = 0.0;
-    for (int i = 0; i < c; ++i) {
-        double d = G[i * c + i];
-        for (int k = 0; k < i; ++k) d -= R[k * c + i] * R[k * c + i];
-        if (!(d > thr2)) {
-            ok = false;
-            R[i * c + i] = 1.0;
-            continue;
-        }
-        const double rii = sqrt(d);
-        R[i * c + i] = rii;
-        for (int j = i + 1; j < c; ++j) {
-            double t = G[i * c + j];
-            for (int k = 0; k < i; ++k) t -= R[k * c + i] * R[k * c + j];
-            R[i * c + j] = t / rii;
-        }
-    }
-    return ok;
-}
-
-// Ri = R^{-1} (upper triangular).
-__device__ void upper_inv(int c, const double *R, double *Ri) {
-    for (int i = 0; i < c * c; ++i) Ri[i] = 0.0;
-    for (int j = 0; j < c; ++j) {
-        Ri[j * c + j] = 1.0 / R[j * c + j];
-        for (int i = j - 1; i >= 0; --i) {
-            double t = 0.0;
-            for (int k = i + 1; k <= j; ++k) t += R[i * c + k] * Ri[k * c + j];
-            Ri[i * c + j] = -t / R[i * c + i];
-        }
-    }
-}
-
-// One lane per solve.  Pass 1: D_j = sym(diagonal blocks of H1 + H2) to
-// out[0, c^2); first factor R1 of G with the dependent-column threshold
-// (1e-7 ||W||_F on a pivot; status 1 when a column is dependent), R1^{-1}.
-// Pass 2: second factor R2 (status 2 if it breaks down), R2^{-1}, and
-// S_j = R2 R1 to out[c^2, 2 c^2).
+// The r x r factorisations of one solve on one wavefront, through LDS.
+// Pass 1: D_j = sym(diagonal blocks of H1 + H2) to out[0, c^2); the first
+// factor R1 of G (upper, row-major) by right-looking Cholesky with the
+// block QR's dependent-column rule (a pivot at or below (1e-7 ||W||_F)^2
+// marks the column: status 1, the later launches skip the solve and the host
+// repairs it), then R1^{-1}.  Pass 2: the second factor R2 (status 2 if it
+// breaks down), R2^{-1} and S_j = R2 R1 to out[c^2, 2 c^2).  Lane j computes
+// column j of an inverse; the other steps spread the c x c entries over the
+// lanes.
 __global__ __launch_bounds__(64) void seg_chol_kernel(const OrthSeg *__restrict__ tab, int c, int pass) {
-    if (threadIdx.x != 0) return;
+    __shared__ double M[16 * 16], T[16 * 16];
+    __shared__ int bad;
     const OrthSeg &e = tab[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int cc = c * c;
     double *out = e.out;
-    double *status = out + 2 * c * c;
+    double *status = out + 2 * cc;
+    if (pass == 2 && *status != 0.0) return;  // uniform: every lane reads the same flag
     if (pass == 1) {
         const double *h1 = e.H + (size_t)(e.k - c) * c;
         const double *h2 = e.H + (size_t)e.k * c + (size_t)(e.k - c) * c;
-        for (int i = 0; i < c; ++i)
-            for (int j = 0; j < c; ++j) {
-                const double a = h1[i * c + j] + h2[i * c + j], b = h1[j * c + i] + h2[j * c + i];
-                out[i * c + j] = 0.5 * (a + b);
-            }
-        double fro2 = 0.0;
-        for (int i = 0; i < c; ++i) fro2 += fmax(e.G[i * c + i], 0.0);
-        const double thr = 1e-7 * sqrt(fro2);
-        const bool ok = chol_upper(c, e.G, fmax(thr * thr, 1e-300), e.R1);
-        *status = ok ? 0.0 : 1.0;
-        if (ok) upper_inv(c, e.R1, e.Ri);
-        return;
-    }
-    if (*status != 0.0) return;
-    if (!chol_upper(c, e.G, 1e-300, e.R2)) {
-        *status = 2.0;
-        return;
-    }
-    upper_inv(c, e.R2, e.Ri);
-    double *Sj = out + c * c;
-    for (int i = 0; i < c; ++i)
-        for (int j = 0; j < c; ++j) {
-            double t = 0.0;
-            for (int k = 0; k < c; ++k) t += e.R2[i * c + k] * e.R1[k * c + j];
-            Sj[i * c + j] = t;
+        for (int t = lane; t < cc; t += WAVE) {
+            const int i = t / c, j = t % c;
+            const double a = h1[i * c + j] + h2[i * c + j], b = h1[j * c + i] + h2[j * c + i];
+            out[t] = 0.5 * (a + b);
         }
+    }
+    for (int t = lane; t < cc; t += WAVE) M[t] = e.G[t];
+    if (lane == 0) bad = 0;
+    __syncthreads();
+    double thr2 = 1e-300;
+    if (pass == 1) {
+        double fro2 = 0.0;
+        for (int i = 0; i < c; ++i) fro2 += fmax(M[i * c + i], 0.0);
+        const double thr = 1e-7 * sqrt(fro2);
+        thr2 = fmax(thr * thr, 1e-300);
+    }
+    // right-looking Cholesky in place: row k of M becomes row k of R
+    for (int k = 0; k < c; ++k) {
+        const double d = M[k * c + k];
+        const bool ok = d > thr2;
+        const double rkk = ok ? sqrt(d) : 1.0;
+        __syncthreads();
+        if (lane == 0) {
+            M[k * c + k] = rkk;
+            if (!ok) bad = 1;
+        }
+        for (int j = k + 1 + lane; j < c; j += WAVE) M[k * c + j] = ok ? M[k * c + j] / rkk : 0.0;
+        __syncthreads();
+        // trailing update of the upper triangle: M[i][j] -= R[k][i] R[k][j]
+        for (int t = lane; t < cc; t += WAVE) {
+            const int i = t / c, j = t % c;
+            if (i > k && j >= i) M[t] -= M[k * c + i] * M[k * c + j];
+        }
+        __syncthreads();
+    }
+    // lower triangle of R is zero
+    for (int t = lane; t < cc; t += WAVE)
+        if (t / c > t % c) M[t] = 0.0;
+    __syncthreads();
+    if (bad) {
+        if (lane == 0) *status = pass == 1 ? 1.0 : 2.0;
+        return;
+    }
+    // Ri = R^{-1}: lane j solves for column j by back substitution
+    if (lane < c) {
+        const int j = lane;
+        for (int i = c - 1; i >= 0; --i) {
+            double t = (i == j) ? 1.0 : 0.0;
+            if (i <= j)
+                for (int k = i + 1; k <= j; ++k) t -= M[i * c + k] * T[k * c + j];
+            T[i * c + j] = i <= j ? t / M[i * c + i] : 0.0;
+        }
+    }
+    __syncthreads();
+    double *Rk = pass == 1 ? e.R1 : e.R2;
+    for (int t = lane; t < cc; t += WAVE) {
+        Rk[t] = M[t];
+        e.Ri[t] = T[t];
+    }
+    if (pass == 1) {
+        if (lane == 0) *status = 0.0;
+        return;
+    }
+    // S_j = R2 R1 (both upper triangular)
+    double *Sj = out + cc;
+    for (int t = lane; t < cc; t += WAVE) {
+        const int i = t / c, j = t % c;
+        double acc = 0.0;
+        for (int k = i; k <= j; ++k) acc += M[i * c + k] * e.R1[k * c + j];
+        Sj[t] = acc;
+    }
 }
 
 // W <- W Ri row by row (one row per thread).  final: the result is the new
@@ -288,7 +304,7 @@ hipError_t launch_seg_orth_t(const OrthPlan &p, int c, hipStream_t s) {
                            pre[kOrthGram], ns, c, chk);
         hipLaunchKernelGGL(seg_reduce_kernel, dim3(p.blocks[kOrthGred]), dim3(256), 0, s, tab, pre[kOrthGred], ns,
                            c, 2, chk);
-        hipLaunchKernelGGL(seg_chol_kernel, dim3(ns), dim3(64), 0, s, tab, c, pass);
+        hipLaunchKernelGGL(seg_chol_kernel, dim3(ns), dim3(WAVE), 0, s, tab, c, pass);
         hipLaunchKernelGGL((seg_rscale_kernel<CM, EXACT>), dim3(p.blocks[kOrthRows]), dim3(256), 0, s, tab,
                            pre[kOrthRows], ns, c, pass == 2 ? 1 : 0);
     }

@@ -117,3 +117,29 @@ def test_tuned_segmented_shape_matches_default(torch):
         for a, b, c in zip(r0, r1, r2):
             assert a["count"] == b["count"] == c["count"]
             assert np.array_equal(a["evals"], b["evals"]) and np.array_equal(a["evals"], c["evals"])
+
+
+def test_batch_dependent_blocks_repaired(torch):
+    """Solves whose filtered blocks become numerically dependent (an
+    eigenvalue of multiplicity above the block size, a matrix with few
+    distinct eigenvalues) go through the host repair of the segmented block
+    step (random replacement, Section 2.3); every solve of the batch, the
+    repaired ones and a regular one, meets the contract."""
+    d1 = np.concatenate([np.linspace(-3, -1, 150), np.full(5, 0.5), np.linspace(1, 4, 150)])
+    d2 = np.concatenate([np.linspace(-3, -1, 100), np.repeat([0.25, 0.75], 6), np.linspace(1.5, 4, 100)])
+    A3 = I.laplacian_3d(9, I.uniform_potential(9, 31))
+    lam3 = np.linalg.eigvalsh(A3.to_dense())
+    mats = [I.diagonal_csr(d1), I.diagonal_csr(d2), A3]
+    alphas = [0.0, 0.0, lam3[0] - 0.5]
+    betas = [0.9, 1.0, 0.5 * (lam3[11] + lam3[12])]
+    dAs = [flp.DeviceCsr.from_host(A) for A in mats]
+    res, _ = flp.flp_solve_batch(dAs, alphas, betas, block=4, seeds=[4, 5, 6])
+    for i in range(2):  # the same solves alone (single-solve path) agree
+        alone = flp.flp_solve(dAs[i], alphas[i], betas[i], block=4, seed=4 + i)
+        assert alone["count"] == res[i]["count"]
+    assert res[0]["count"] == 5
+    assert np.max(np.abs(res[0]["evals"] - 0.5)) < 1e-12 and np.max(res[0]["resid"]) <= 1e-9
+    assert res[1]["count"] == 12
+    assert np.max(np.abs(np.sort(res[1]["evals"]) - np.repeat([0.25, 0.75], 6))) < 1e-12
+    assert np.max(res[1]["resid"]) <= 1e-9
+    check(res[2], A3, alphas[2], betas[2], lam3)
