@@ -123,7 +123,8 @@ typedef struct flp_result {
     double lmin, lmax;    /* spectrum bounds used for the affine map (eq. transf) */
     double alpha, beta;   /* the interval as given */
     int32_t degree;       /* filter degree used */
-    int32_t converged;    /* 1 if the stopping rule was met */
+    int32_t converged;    /* 1 if the stopping rule was met and every returned pair has
+                             resid <= opts.tol (else the call returns FLP_E_NOCONV) */
     flp_stats stats;
 } flp_result;
 

@@ -48,6 +48,7 @@ constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
 // relative residual above which an in-interval Ritz pair of an FP32-filter
 // solve counts as a mixture of eigenvectors (converged pairs sit near 1e-7)
 constexpr double kMixedResid = 1e-4;
+constexpr int kMaxSeparations = 8;  // Rayleigh-Ritz rounds on span{X, A x} for mixed pairs
 constexpr int kMaxSpeculative = 2;  // block steps a solve may take past a convergence check in flight
 
 int fail(int code, const std::string &msg);

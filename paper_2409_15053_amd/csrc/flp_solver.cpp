@@ -462,7 +462,7 @@ int solve_finish(Solve &S, flp_result **out) {
                 std::vector<int> mixed;
                 for (int j = i0; j < i1; ++j)
                     if (rres[j] / anorm > kMixedResid) mixed.push_back(j);
-                if (!mixed.empty() && separations < 2 && cur + (int)mixed.size() <= cap) {
+                if (!mixed.empty() && separations < kMaxSeparations && cur + (int)mixed.size() <= cap) {
                     CK(launch_copy_block(n, cur, 1.0, X, ldc, plain_mat(Y, ldc), 0, nullptr, 0, s));
                     for (size_t t = 0; t < mixed.size(); ++t)
                         CK(launch_copy_block(n, 1, 1.0, AX + mixed[t], ldc, plain_mat(Y, ldc), cur + (int)t, nullptr,
@@ -487,7 +487,12 @@ int solve_finish(Solve &S, flp_result **out) {
                 ++S.st.polish_sweeps;
             }
         }
-        worst(i0, i1);
+        // a pair inside [alpha, beta] that still misses the tolerance makes the
+        // result non-converged (reported, never passed off as an eigenpair)
+        if (worst(i0, i1) > tol) {
+            S.converged = false;
+            res->converged = 0;
+        }
         const int cnt = i1 - i0;
         res->count = cnt;
         if (cnt > 0) {

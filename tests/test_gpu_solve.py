@@ -305,3 +305,39 @@ def test_custom_allocator(torch):
         assert a["count"] == b["count"] and np.array_equal(a["evals"], b["evals"])
     # and the batch agrees with the single solve to the parity tolerance
     assert np.max(np.abs(bres[0]["evals"] - ref["evals"]) / np.abs(ref["evals"])) <= 1e-12
+
+
+def test_full_size_kronecker_13pt_120(torch):
+    """The c3 shape at full size (13-point stencil on 120^3, n = 1.728e6,
+    block 16) with a separable potential, so the spectrum is every sum of the
+    three 1D operators' eigenvalues (dense eigh of 120 x 120): about 300
+    eigenvalues above the lowest 20, both filter precisions, exact count,
+    1e-10 relative, residuals <= 1e-9."""
+    N = 120
+    field, vx, vy, vz = I.separable_potential(N, seed=1203)
+    A = I.laplacian_3d_13pt(N, field)
+    st = {0: I.FOURTH_ORDER_1D[0], 1: I.FOURTH_ORDER_1D[1], 2: I.FOURTH_ORDER_1D[2]}
+
+    def one_d(v):
+        T = np.zeros((N, N))
+        for d, cf in st.items():
+            idx = np.arange(N - d)
+            T[idx, idx + d] = cf
+            T[idx + d, idx] = cf
+        np.fill_diagonal(T, st[0] + v)
+        return np.linalg.eigvalsh(T)
+
+    a, b, c = one_d(vx), one_d(vy), one_d(vz)
+    lo = np.sort((a[:, None, None] + b[None, :, None] + c[None, None, :]).ravel())[:2000]
+    # endpoints in the widest gaps near eigenvalues 20 and 320
+    g0 = 15 + int(np.argmax(np.diff(lo[15:26])))
+    g1 = 315 + int(np.argmax(np.diff(lo[315:326])))
+    alpha = 0.5 * (lo[g0] + lo[g0 + 1])
+    beta = 0.5 * (lo[g1] + lo[g1 + 1])
+    want = lo[g0 + 1:g1 + 1]
+    dA = flp.DeviceCsr.from_host(A, with_fp32=True)
+    for prec in (flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER):
+        res = flp.flp_solve(dA, alpha, beta, block=16, degree=100, seed=11, prec=prec, want_vectors=False)
+        assert res["count"] == len(want), (prec, res["count"], len(want))
+        assert np.max(np.abs(np.sort(res["evals"]) - want) / np.abs(want)) <= 1e-10
+        assert np.max(res["resid"]) <= 1e-9
