@@ -272,6 +272,7 @@ int flp_check_symmetric(const flp_csr *A, double tol, void *stream) {
 void flp_release_workspace(void) {
     ws().release_all();
     release_single_bufs();
+    release_dev_cache();
 }
 
 const char *flp_last_error(void) { return last_error_cstr(); }

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <mutex>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -67,7 +69,7 @@ int build_tables(const std::vector<Solve *> &act, Tables &T, hipStream_t s) {
         T.nseg[t] = ns;
         T.tiles[t] = tiles;
     }
-    CK(ensure(T.dev, sizeof(SegEntry) * std::max<size_t>(T.host.size(), 1)));
+    CK(ensure_grow(T.dev, sizeof(SegEntry) * std::max<size_t>(T.host.size(), 1)));
     CK(h2d(T.dev.p, T.host.data(), sizeof(SegEntry) * T.host.size(), s));
     return FLP_OK;
 }
@@ -134,7 +136,7 @@ void Engine::finisher_main(int w) {
             ++fbusy;
         }
         const double t0 = now();
-        j->S->s = fs[w];
+        j->S->s = fs[w % kFinisherStreams];
         if (j->cancel.load()) {
             j->code = FLP_E_CANCELLED;
             j->msg = "request cancelled";
@@ -200,7 +202,7 @@ int ensure_pinned(void **p, size_t *have, size_t bytes) {
     if (*p) CK(hipHostFree(*p));
     *p = nullptr;
     *have = 0;
-    const size_t want = std::max<size_t>(bytes, 4096);
+    const size_t want = std::max<size_t>({bytes, 4096, *have + *have / 2});
     CK(hipHostMalloc(p, want, hipHostMallocDefault));
     *have = want;
     return FLP_OK;
@@ -230,7 +232,7 @@ int Engine::block_step(double filter_secs) {
     int blocks[kOrthKinds] = {};
     std::vector<size_t> poff(ns);
     size_t ptotal = 0;
-    CK(ensure(oout, sizeof(double) * slot * ns));
+    CK(ensure_grow(oout, sizeof(double) * slot * ns));
     // room in each basis for this step's projection and the next block
     for (Job *j : active) CKR(ensure_basis(*j->S, (int64_t)(j->S->steps + 2) * c));
     for (int i = 0; i < ns; ++i) {
@@ -272,13 +274,13 @@ int Engine::block_step(double filter_secs) {
         S.st.orth_bytes += 4.0 * 8.0 * (double)n * k;
         stats.orth_bytes += 4.0 * 8.0 * (double)n * k;
     }
-    CK(ensure(opart, sizeof(double) * std::max<size_t>(ptotal, 1)));
+    CK(ensure_grow(opart, sizeof(double) * std::max<size_t>(ptotal, 1)));
     for (int i = 0; i < ns; ++i) otab_host[i].part = (double *)opart.p + poff[i];
     const size_t tb = sizeof(OrthSeg) * ns, pb = sizeof(int) * opre_host.size();
     CKR(ensure_pinned((void **)&ostage, &ostage_bytes, tb + pb));
     std::memcpy(ostage, otab_host.data(), tb);
     std::memcpy(ostage + tb, opre_host.data(), pb);
-    CK(ensure(otab, tb + pb));
+    CK(ensure_grow(otab, tb + pb));
     CK(hipMemcpyAsync(otab.p, ostage, tb + pb, hipMemcpyHostToDevice, s));
     OrthPlan plan{(const OrthSeg *)otab.p, (const int *)((const char *)otab.p + tb), ns, {}};
     for (int t = 0; t < kOrthKinds; ++t) plan.blocks[t] = blocks[t];
@@ -363,6 +365,7 @@ int Engine::step() {
         T.sh = tn.sh;
         CKR(build_tables(act, T, s));
         if (use_graph) {
+            std::shared_lock<std::shared_mutex> cl(capture_mutex());  // no device-wide sync meanwhile
             CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             const int rc = launch_tables(T, s);
             hipGraph_t g = nullptr;
@@ -470,20 +473,50 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
         S.beta = beta[i];
         S.o = opts ? opts[i] : o0;
         S.o.stream = nullptr;
-        S.s = E.s;
-        j->code = check_csr(A[i]);
-        if (j->code == FLP_OK) {
-            j->B = std::make_unique<SolveBufs>();
-            S.B = j->B.get();
-            j->code = solve_setup(S);
-        }
-        if (j->code != FLP_OK) j->msg = last_error_cstr();
-        if (j->code == FLP_OK)
-            E.add(j.get());
-        else
-            j->B.reset();
         jobs[i] = std::move(j);
     }
+    // Set-up (bounds estimate, filter, buffers, start block) is a chain of
+    // small launches and host round trips per solve: the solves' set-ups run
+    // on a few threads at once, each with a stream of its own (the threads'
+    // workspaces are released when they join), and join the engine in order.
+    {
+        const int nt = std::max(1, std::min(count, kSetupThreads));
+        const int dev = E.device;
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t)
+            th.emplace_back([&jobs, count, nt, t, dev]() {
+                hipStream_t st = nullptr;
+                const bool ok = hipSetDevice(dev) == hipSuccess &&
+                                hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+                for (int i = t; i < count; i += nt) {
+                    Job *jp = jobs[i].get();
+                    Solve &S = *jp->S;
+                    if (!ok) {
+                        jp->code = fail(FLP_E_DEVICE, "could not create a set-up stream");
+                    } else {
+                        S.s = st;
+                        jp->code = check_csr(S.A);
+                        if (jp->code == FLP_OK) {
+                            jp->B = std::make_unique<SolveBufs>();
+                            S.B = jp->B.get();
+                            jp->code = solve_setup(S);
+                        }
+                        if (hipStreamSynchronize(st) != hipSuccess && jp->code == FLP_OK)
+                            jp->code = fail(FLP_E_DEVICE, "set-up stream failed");
+                        S.s = nullptr;
+                    }
+                    if (jp->code != FLP_OK) {
+                        jp->msg = last_error_cstr();
+                        jp->B.reset();
+                    }
+                }
+                if (st) (void)hipStreamDestroy(st);
+                ws().release_all();  // this thread's scratch (bounds estimate) goes back now
+            });
+        for (auto &x : th) x.join();
+    }
+    for (auto &j : jobs)
+        if (j->code == FLP_OK) E.add(j.get());
     E.stats.t_setup = now() - t0;
     int rc = FLP_OK;
     while (!E.active.empty() && rc == FLP_OK) rc = E.step();

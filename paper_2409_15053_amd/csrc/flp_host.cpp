@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -45,11 +46,19 @@ double now() {
 // ------------------------------------------------------------------ device memory
 //
 // Every device allocation of the library goes through dev_alloc/dev_free:
-// hipMalloc/hipFree, or the caller's functions set by flp_set_allocator.
-// Each allocation remembers which pair made it, so memory is always returned
-// to its own allocator even if the setting changes in between.  A caller's
-// free function cannot see work still queued on the library's streams, so
-// the device is synchronised before memory is handed back to it.
+// the library's own cache over hipMalloc, or the caller's functions set by
+// flp_set_allocator.  Each allocation remembers which allocator made it, so
+// memory is always returned to its own allocator even if the setting
+// changes in between.  A free synchronises the device first (work still
+// queued on any of the library's streams may use the block), as hipFree
+// would.
+//
+// The cache: blocks of 1 MiB and more are rounded up to 2 MiB and, when
+// freed, kept per device (up to kDevCacheBytes) for the next request they fit
+// within 25 %.  The batched engine and the server allocate and release tens
+// of GB per batch (bases, recurrence vectors, Ritz blocks); returning them to
+// the driver every time made later batches stall for seconds.
+// flp_release_workspace() hands the cached blocks back.
 
 namespace {
 struct Allocator {
@@ -57,13 +66,37 @@ struct Allocator {
     flp_free_fn free = nullptr;
     void *ctx = nullptr;
 };
+struct Block {
+    int device;
+    size_t bytes;  // 0: not cached (small, straight hipMalloc)
+};
+constexpr size_t kCacheMin = (size_t)1 << 20;
+constexpr size_t kCacheGrain = (size_t)2 << 20;
+constexpr size_t kDevCacheBytes = (size_t)64 << 30;
 std::mutex g_alloc_mu;
 Allocator g_alloc;
 std::unordered_map<void *, Allocator> &custom_allocs() {
     static std::unordered_map<void *, Allocator> m;
     return m;
 }
+std::unordered_map<void *, Block> &own_blocks() {
+    static std::unordered_map<void *, Block> m;
+    return m;
+}
+struct DevCache {
+    std::multimap<size_t, void *> free;  // size -> block
+    size_t bytes = 0;
+};
+std::map<int, DevCache> &dev_cache() {
+    static std::map<int, DevCache> m;
+    return m;
+}
 }  // namespace
+
+std::shared_mutex &capture_mutex() {
+    static std::shared_mutex m;
+    return m;
+}
 
 void set_allocator(flp_alloc_fn alloc, flp_free_fn free, void *ctx) {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
@@ -76,27 +109,120 @@ hipError_t dev_alloc(void **p, size_t bytes) {
         std::lock_guard<std::mutex> lk(g_alloc_mu);
         a = g_alloc;
     }
-    if (!a.alloc) return hipMalloc(p, bytes);
-    *p = a.alloc(bytes, a.ctx);
-    if (!*p) return hipErrorOutOfMemory;
+    if (a.alloc) {
+        *p = a.alloc(bytes, a.ctx);
+        if (!*p) return hipErrorOutOfMemory;
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        custom_allocs()[*p] = a;
+        return hipSuccess;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (bytes < kCacheMin) {
+        e = hipMalloc(p, bytes);
+        if (e == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_alloc_mu);
+            own_blocks()[*p] = Block{dev, 0};
+        }
+        return e;
+    }
+    const size_t want = (bytes + kCacheGrain - 1) / kCacheGrain * kCacheGrain;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        DevCache &c = dev_cache()[dev];
+        auto it = c.free.lower_bound(want);
+        if (it != c.free.end() && it->first <= want + want / 4) {
+            *p = it->second;
+            own_blocks()[*p] = Block{dev, it->first};
+            c.bytes -= it->first;
+            c.free.erase(it);
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // the cached blocks may be what is in the way
+        release_dev_cache();
+        e = hipMalloc(p, want);
+        if (e != hipSuccess) return e;
+    }
     std::lock_guard<std::mutex> lk(g_alloc_mu);
-    custom_allocs()[*p] = a;
+    own_blocks()[*p] = Block{dev, want};
     return hipSuccess;
 }
 
 hipError_t dev_free(void *p) {
     if (!p) return hipSuccess;
     Allocator a;
+    Block b{0, 0};
+    bool custom = false, own = false;
     {
         std::lock_guard<std::mutex> lk(g_alloc_mu);
         auto it = custom_allocs().find(p);
-        if (it == custom_allocs().end()) return hipFree(p);
-        a = it->second;
-        custom_allocs().erase(it);
+        if (it != custom_allocs().end()) {
+            a = it->second;
+            custom_allocs().erase(it);
+            custom = true;
+        } else {
+            auto ob = own_blocks().find(p);
+            if (ob != own_blocks().end()) {
+                b = ob->second;
+                own_blocks().erase(ob);
+                own = true;
+            }
+        }
     }
-    const hipError_t e = hipDeviceSynchronize();
-    a.free(p, a.ctx);
-    return e;
+    if (custom) {
+        hipError_t e;
+        {
+            std::unique_lock<std::shared_mutex> cl(capture_mutex());
+            e = hipDeviceSynchronize();
+        }
+        a.free(p, a.ctx);
+        return e;
+    }
+    if (!own || b.bytes == 0) return hipFree(p);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != b.device) (void)hipSetDevice(b.device);
+    hipError_t e;
+    {
+        std::unique_lock<std::shared_mutex> cl(capture_mutex());
+        e = hipDeviceSynchronize();
+    }
+    if (cur != b.device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        DevCache &c = dev_cache()[b.device];
+        if (c.bytes + b.bytes <= kDevCacheBytes) {
+            c.free.emplace(b.bytes, p);
+            c.bytes += b.bytes;
+            return hipSuccess;
+        }
+    }
+    return hipFree(p);
+}
+
+void release_dev_cache() {
+    std::vector<std::pair<int, void *>> all;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        for (auto &kv : dev_cache()) {
+            for (auto &f : kv.second.free) all.emplace_back(kv.first, f.second);
+            kv.second.free.clear();
+            kv.second.bytes = 0;
+        }
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &d : all) {
+        (void)hipSetDevice(d.first);
+        (void)hipFree(d.second);
+    }
+    (void)hipSetDevice(cur);
 }
 
 // ------------------------------------------------------------------ workspace
@@ -107,6 +233,11 @@ void Buf::release() {
     if (p) (void)dev_free(p);
     p = nullptr;
     bytes = 0;
+}
+
+hipError_t ensure_grow(Buf &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return hipSuccess;
+    return ensure(b, std::max(bytes, b.bytes + b.bytes / 2));
 }
 
 hipError_t ensure(Buf &b, size_t bytes) {

@@ -14,6 +14,7 @@
 #include <functional>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -49,6 +50,7 @@ constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
 // solve counts as a mixture of eigenvectors (converged pairs sit near 1e-7)
 constexpr double kMixedResid = 1e-4;
 constexpr int kMaxSeparations = 8;  // Rayleigh-Ritz rounds on span{X, A x} for mixed pairs
+constexpr int kSetupThreads = 8;  // host threads for the set-up of a batch's solves
 constexpr int kMaxSpeculative = 2;  // block steps a solve may take past a convergence check in flight
 
 int fail(int code, const std::string &msg);
@@ -82,6 +84,9 @@ struct Buf {
     void release();
 };
 hipError_t ensure(Buf &b, size_t bytes);
+// ensure() that grows by at least half the current size (buffers whose
+// demand creeps up: fewer reallocations, each a device-wide wait)
+hipError_t ensure_grow(Buf &b, size_t bytes);
 
 // Per-thread, per-device scratch shared by the calls one thread makes.
 struct Workspace {
@@ -105,6 +110,12 @@ Workspace &ws();
 // allocator set by flp_set_allocator).
 hipError_t dev_alloc(void **p, size_t bytes);
 hipError_t dev_free(void *p);
+// hands the allocator's cached device blocks back to the driver
+void release_dev_cache();
+// Held shared by the library's graph captures and exclusively around the
+// device synchronisation of a free: a device-wide synchronisation in one
+// thread invalidates a capture in progress in another.
+std::shared_mutex &capture_mutex();
 void set_allocator(flp_alloc_fn alloc, flp_free_fn free, void *ctx);
 int check_symmetric(const flp_csr *A, double tol, hipStream_t s);
 
@@ -193,6 +204,9 @@ struct SolveBufs {
     Buf Q, W, Vin, U[3], V32, val32, hdev;
     const double *val32_src = nullptr;
     int64_t val32_nnz = 0;
+    // earlier, smaller basis allocations: freed with the rest (a device free
+    // waits for all work on the device, so it is kept out of the block steps)
+    std::deque<Buf> retired;
 };
 
 // One filtered Lanczos solve advanced block step by block step.
@@ -379,7 +393,12 @@ struct Engine {
     // finishers: Ritz vectors, Rayleigh-Ritz and polish of converged solves,
     // each on its own host thread and stream, overlapping later block steps
     static constexpr int kFinishers = 8;
-    hipStream_t fs[kFinishers] = {};
+    // The finisher threads share kFinisherStreams streams: HIP maps streams
+    // onto a few hardware queues (4 per process by default), and a stream that
+    // shares a queue with the stepping stream s would hold the lockstep block
+    // steps behind a finisher's Rayleigh-Ritz and polish work.
+    static constexpr int kFinisherStreams = 2;
+    hipStream_t fs[kFinisherStreams] = {};
     std::thread fin[kFinishers];
     std::mutex fmu;
     std::condition_variable fcv, fdone;

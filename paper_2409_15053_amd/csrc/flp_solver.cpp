@@ -140,7 +140,9 @@ int ensure_basis(Solve &S, int64_t cols) {
         CK(e);
     }
     Buf &q = S.B->Q;
-    (void)dev_free(q.p);
+    S.B->retired.emplace_back();
+    S.B->retired.back().p = q.p;
+    S.B->retired.back().bytes = q.bytes;
     q.p = p;
     q.bytes = panel_bytes * (size_t)want;
     S.qpanels = want;
@@ -411,10 +413,10 @@ int solve_finish(Solve &S, flp_result **out) {
         std::vector<double> Wc((size_t)K * ldc, 0.0);
         for (int i = 0; i < K; ++i)
             for (int j = 0; j < c; ++j) Wc[(size_t)i * ldc + j] = Zc[(size_t)i * c + j];
-        CK(ensure(w.Y, sizeof(double) * (size_t)n * ldc));
-        CK(ensure(w.AY, sizeof(double) * (size_t)n * ldc));
-        CK(ensure(w.X, sizeof(double) * (size_t)n * ldc));
-        CK(ensure(w.AX, sizeof(double) * (size_t)n * ldc));
+        CK(ensure_grow(w.Y, sizeof(double) * (size_t)n * ldc));
+        CK(ensure_grow(w.AY, sizeof(double) * (size_t)n * ldc));
+        CK(ensure_grow(w.X, sizeof(double) * (size_t)n * ldc));
+        CK(ensure_grow(w.AX, sizeof(double) * (size_t)n * ldc));
         double *Y = (double *)w.Y.p, *AY = (double *)w.AY.p, *X = (double *)w.X.p, *AX = (double *)w.AX.p;
         double *sdev = nullptr;
         CKR(small_dev((size_t)std::max(K, cap) * ldc * 2 + 4 * (size_t)ldc + 64, &sdev));
