@@ -93,6 +93,11 @@ typedef struct flp_opts {
     double sym_tol;       /* >= 0: run flp_check_symmetric(A, sym_tol) first; < 0 (default): skip */
     int32_t polish_degree;  /* FP32 filter only: degree of the FP64 polish filter on the same
                                interval; <= 0 (default) uses the solve's degree */
+    int32_t unfiltered;   /* 1: plain block Lanczos with Ahat itself in place of p(Ahat) (the
+                             unfiltered Lanczos that Section 4.1 sets beside the filtered one); FP64 only and flp_solve
+                             only (FLP_E_ARG elsewhere).  Ritz values of Ahat inside the
+                             mapped interval, and the nearest one outside on each side, must
+                             converge; max_basis <= 0 then means min(n, 12288). */
 } flp_opts;
 
 typedef struct flp_stats {

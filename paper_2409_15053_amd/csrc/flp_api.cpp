@@ -34,6 +34,7 @@ void flp_opts_default(flp_opts *o) {
     o->stream = nullptr;
     o->sym_tol = -1.0;
     o->polish_degree = 0;
+    o->unfiltered = 0;
 }
 
 int flp_build_filter(double alpha, double beta, int32_t degree, double lmin, double lmax, flp_filter **out) {

@@ -43,6 +43,9 @@ constexpr int kDefaultK0 = 40;
 constexpr double kDefaultTol = 1e-9;
 constexpr int kMaxDegree = 100000;
 constexpr int64_t kDefaultMaxBasis = 3072;
+// Unfiltered Lanczos resolves an interval only once its Ritz values there
+// have converged without a filter's help, which takes many more columns.
+constexpr int64_t kUnfilteredMaxBasis = 12288;
 constexpr int kPanelLog2 = 7;  // Lanczos basis panels of 128 columns
 constexpr int64_t kInitPanels = 4;  // basis panels allocated at set-up (more on demand)
 constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
@@ -218,6 +221,10 @@ struct CheckTask {
     int K = 0, r = 0;
     double tau = 0, tol_p = 0;
     bool fp32 = false;
+    // unfiltered Lanczos: candidates are the Ritz values in [lo, hi] plus
+    // the nearest one on each side
+    bool unfiltered = false;
+    double lo = 0, hi = 0;
     std::vector<double> T, Sk;
     int rc = FLP_OK;
     std::string msg;
@@ -243,6 +250,7 @@ struct Solve {
     // derived
     int n = 0, r = 0;
     double lmin = 0, lmax = 0, tau = 0, tol_p = 0;
+    bool unfiltered = false;  // p(Ahat) = Ahat (plain block Lanczos)
     std::unique_ptr<flp_filter> filt;
     int check_every = 0, max_steps = 0;
     int check_offset = 0;  // checks fall on steps with (steps + check_offset) % check_every == 0

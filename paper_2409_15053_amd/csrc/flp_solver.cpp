@@ -54,6 +54,8 @@ int solve_setup(Solve &S) {
         return fail(FLP_E_ARG, "need finite alpha < beta");
     if (o.prec != FLP_PREC_FP64 && o.prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
     const bool fp32 = o.prec == FLP_PREC_FP32_FILTER;
+    S.unfiltered = o.unfiltered != 0;
+    if (S.unfiltered && fp32) return fail(FLP_E_ARG, "unfiltered Lanczos runs in FP64 only");
     if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
 
     // PREPROC: spectrum bounds
@@ -67,13 +69,15 @@ int solve_setup(Solve &S) {
     S.st.t_pre = now() - t0;
 
     flp_filter *pf = nullptr;
-    CKR(make_filter(S.alpha, S.beta, o.degree, S.lmin, S.lmax, o.eps > 0 ? o.eps : kDefaultEps, &pf));
+    CKR(make_filter(S.alpha, S.beta, S.unfiltered ? 1 : o.degree, S.lmin, S.lmax, o.eps > 0 ? o.eps : kDefaultEps,
+                    &pf));
     S.filt.reset(pf);
+    if (S.unfiltered) S.filt->b = {0.0, 1.0};  // p = T_1: one product with Ahat per block step
     S.tau = 0.5 * std::min(cheb_scalar(S.filt->b, S.filt->a1), cheb_scalar(S.filt->b, S.filt->b1));
     S.tol_p = fp32 ? 1e-5 : 1e-10;
     S.check_every = o.check_every > 0 ? o.check_every : default_check_every(r);
 
-    int64_t maxb = o.max_basis > 0 ? o.max_basis : kDefaultMaxBasis;
+    int64_t maxb = o.max_basis > 0 ? o.max_basis : S.unfiltered ? kUnfilteredMaxBasis : kDefaultMaxBasis;
     maxb = std::min<int64_t>(maxb, n);
     S.max_steps = std::max<int>(1, (int)(maxb / r));
     // Lanczos basis: column panels of 128 columns, each a contiguous
@@ -227,8 +231,12 @@ int step_qr2(Solve &S) {
 }
 
 bool at_check(const Solve &S) {
-    return (S.steps >= S.check_every && (S.steps + S.check_offset) % S.check_every == 0) ||
-           S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n;
+    if (S.steps == S.max_steps || (int64_t)(S.steps + 1) * S.r > S.n) return true;
+    // unfiltered Lanczos runs to bases of thousands of columns, where one
+    // eigensolve of T_k costs many block steps: its checks are also spaced
+    // by a tenth of the basis at least
+    if (S.unfiltered && S.checked_step > 0 && 10 * (S.steps - S.checked_step) < S.checked_step) return false;
+    return S.steps >= S.check_every && (S.steps + S.check_offset) % S.check_every == 0;
 }
 
 namespace {
@@ -267,12 +275,28 @@ void run_check_body(CheckTask &c) {
         c.secs = now() - t0;
         return;
     }
-    // rho_i = || S_k E_k^T w_i ||; candidates theta_i >= tau
+    // rho_i = || S_k E_k^T w_i ||; candidates theta_i >= tau, or for
+    // unfiltered Lanczos theta_i in [lo, hi] and its two outside neighbours
+    // (with them converged, no Ritz value is still moving into the interval)
     double big = 1e-300;
     for (double t : theta) big = std::max(big, std::fabs(t));
+    int ilo = K, ihi = -1;  // unfiltered: first and last index taken (theta ascending)
+    if (c.unfiltered) {
+        for (int i = 0; i < K; ++i)
+            if (theta[i] >= c.lo && theta[i] <= c.hi) {
+                ilo = std::min(ilo, i);
+                ihi = i;
+            }
+        if (ihi < 0) {  // none inside: the neighbours around where the interval sits
+            ilo = (int)(std::lower_bound(theta.begin(), theta.end(), c.lo) - theta.begin());
+            ihi = ilo - 1;
+        }
+        ilo = std::max(ilo - 1, 0);
+        ihi = std::min(ihi + 1, K - 1);
+    }
     c.ok = true;
     for (int i = 0; i < K; ++i) {
-        if (theta[i] < c.tau) continue;
+        if (c.unfiltered ? (i < ilo || i > ihi) : theta[i] < c.tau) continue;
         c.cand.push_back(i);
         double rho2 = 0.0;
         for (int a = 0; a < r; ++a) {
@@ -343,6 +367,9 @@ int step_check(Solve &S, bool async, bool copy_next) {
         c->K = S.steps * S.r;
         c->r = S.r;
         c->tau = S.tau;
+        c->unfiltered = S.unfiltered;
+        c->lo = S.filt->a1;
+        c->hi = S.filt->b1;
         c->tol_p = S.tol_p;
         c->fp32 = S.o.prec == FLP_PREC_FP32_FILTER;
         assemble_T(S, S.steps, c->T);
