@@ -262,7 +262,9 @@ int flp_estimate_bounds(const flp_csr *A, int32_t k0, uint64_t seed, double *lmi
  * convergence checks on the Ritz values of T_k -> Rayleigh-Ritz with A
  * (eq. rayleigh, eq. proj).  opts may be NULL (defaults).  Synchronous.
  * On FLP_OK or FLP_E_NOCONV *out holds a result to free with
- * flp_result_free().  Errors: FLP_E_ARG, FLP_E_INTERVAL, FLP_E_NOMEM,
+ * flp_result_free().  Errors: FLP_E_ARG (also for a filtered solve whose
+ * interval, clamped to the bounds, covers all of [lmin, lmax]: the ideal
+ * filter is then the constant 1), FLP_E_INTERVAL, FLP_E_NOMEM,
  * FLP_E_NOCONV, FLP_E_DEVICE. */
 int flp_solve(const flp_csr *A, double alpha, double beta, const flp_opts *opts,
               flp_result **out);

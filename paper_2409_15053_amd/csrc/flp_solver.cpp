@@ -73,6 +73,11 @@ int solve_setup(Solve &S) {
                     &pf));
     S.filt.reset(pf);
     if (S.unfiltered) S.filt->b = {0.0, 1.0};  // p = T_1: one product with Ahat per block step
+    // an interval covering the whole mapped spectrum makes the ideal filter
+    // the constant 1 on [-1, 1]: p(Ahat) = I separates nothing
+    if (!S.unfiltered && S.alpha <= S.lmin && S.beta >= S.lmax)
+        return fail(FLP_E_ARG, "[alpha, beta] covers the whole spectrum [lmin, lmax]: the filter is the constant 1 "
+                               "(unfiltered Lanczos or a dense solver applies)");
     S.tau = 0.5 * std::min(cheb_scalar(S.filt->b, S.filt->a1), cheb_scalar(S.filt->b, S.filt->b1));
     S.tol_p = fp32 ? 1e-5 : 1e-10;
     S.check_every = o.check_every > 0 ? o.check_every : default_check_every(r);
@@ -337,8 +342,10 @@ int wait_check(Solve &S) {
     // stop rule: every candidate converged and the candidate count unchanged
     // since the previous check, or no room left in the basis
     const int cnt = (int)c->cand.size();
-    if ((c->ok && cnt == S.prev_count) || S.check_last) {
-        S.converged = c->ok && cnt == S.prev_count;
+    // (a basis of all n columns spans the whole space: its Ritz pairs are exact)
+    const bool settled = cnt == S.prev_count || c->K >= S.n;
+    if ((c->ok && settled) || S.check_last) {
+        S.converged = c->ok && settled;
         S.kfinal = c->K;
         S.done = true;
         S.cand = std::move(c->cand);

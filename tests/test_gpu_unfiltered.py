@@ -125,3 +125,17 @@ def test_unfiltered_rejected_outside_flp_solve(torch):
     one = ctypes.POINTER(flp.FlpResultC)()
     rc = lib.flp_solve_sliced(ctypes.byref(dA.c), 0.5, 0.9, 2, ctypes.byref(o), ctypes.byref(one))
     assert rc == flp.FLP_E_ARG
+
+
+def test_whole_spectrum(torch):
+    """An interval around the whole spectrum: the ideal filter is the
+    constant 1, so the filtered solve refuses it; unfiltered Lanczos returns
+    every eigenpair once the basis spans the space (n a multiple of r)."""
+    A = I.random_sym(200, 0.05, seed=3, diag_shift=10.0)  # eigenvalues away from 0
+    lam = np.linalg.eigvalsh(A.to_dense())
+    dA = flp.DeviceCsr.from_host(A)
+    with pytest.raises(flp.FlpError) as e:
+        flp.flp_solve(dA, lam[0] - 1.0, lam[-1] + 1.0, block=4)
+    assert e.value.code == flp.FLP_E_ARG
+    res = flp.flp_solve(dA, lam[0] - 1.0, lam[-1] + 1.0, block=4, seed=1, unfiltered=True)
+    contract(res, lam)
