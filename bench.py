@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=32, help="serving form: number of requests")
     ap.add_argument("--gmin", type=int, default=30, help="serving form: smallest grid edge")
     ap.add_argument("--gmax", type=int, default=100, help="serving form: largest grid edge")
+    ap.add_argument("--format", default="csr", choices=["csr", "sell"],
+                    help="storage the single-solve filter reads A in: CSR, or a sliced ELL copy")
     ap.add_argument("--unfiltered-compare", action="store_true",
                     help="also run one unfiltered block Lanczos solve of the same problem (FP64) and report "
                          "its basis size and time beside the filtered solve's")
@@ -184,6 +186,10 @@ def cpu_baseline(w, alpha, beta, degree, gpu_res, budget_s):
                    f"{t_solve:.1f} s"),
         "est_solve_s": t_solve,
     }
+
+
+def fmt_code(flp, args):
+    return flp.FLP_FORMAT_SELL if args.format == "sell" else flp.FLP_FORMAT_CSR
 
 
 def check_cadence(args, r):
@@ -436,12 +442,14 @@ def bench_c3(args):
     for name, prec in (("fp64", flp.FLP_PREC_FP64), ("fp32", flp.FLP_PREC_FP32_FILTER)):
         for i in range(args.warmup):
             flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=100 + i, prec=prec,
-                          want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree)
+                          want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree,
+                          format=fmt_code(flp, args))
         lat, res = [], None
         for i in range(args.steps):
             t0 = time.perf_counter()
             res = flp.flp_solve(dA, alpha, beta, block=16, degree=args.degree, seed=i, prec=prec,
-                                want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree)
+                                want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree,
+                                format=fmt_code(flp, args))
             lat.append(time.perf_counter() - t0)
             print(f"# {name} step {i + 1}/{args.steps}: {res['count']} pairs, {lat[-1]:.2f} s, iters "
                   f"{res['stats']['iters']}, polish {res['stats']['polish_sweeps']}", file=sys.stderr, flush=True)
@@ -465,7 +473,7 @@ def bench_c3(args):
                                f"nnz={A.nnz}, block 16, degree {args.degree}, interval between the Weyl "
                                f"estimates of 20 and 320 eigenvalues [{alpha:.6f}, {beta:.6f}]",
                    "n": A.n, "nnz": A.nnz, "block": 16, "degree": args.degree,
-                   "check_every": check_cadence(args, 16)},
+                   "check_every": check_cadence(args, 16), "format": args.format},
         "fp64_filter": out_runs["fp64"], "fp32_filter": r32,
         "fp32_vs_fp64": {"same_count": len(e32) == len(e64), "max_rel_eval_diff": diff},
         "speedup_fp32_vs_fp64": r32["eigenpairs_per_s"] / out_runs["fp64"]["eigenpairs_per_s"]
@@ -518,7 +526,8 @@ def main():
 
     def solve(seed):
         return flp.flp_solve(dA, alpha, beta, block=w["block"], degree=args.degree, seed=seed, prec=prec,
-                             want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree)
+                             want_vectors=False, check_every=args.check_every, polish_degree=args.polish_degree,
+                             format=fmt_code(flp, args))
 
     for i in range(args.warmup):
         solve(1000 + i)
@@ -578,7 +587,7 @@ def main():
                                f"interval=[{alpha}, {beta:.9f}]",
                    "n": A.n, "nnz": A.nnz, "block": w["block"], "degree": args.degree,
                    "check_every": check_cadence(args, w["block"]),
-                   "alpha": alpha, "beta": beta, "prec": args.prec},
+                   "alpha": alpha, "beta": beta, "prec": args.prec, "format": args.format},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "all": [round(x, 3) for x in lat_ms.tolist()]},
         "accuracy": {"count": results[-1]["count"], "ref_count": ref["count"] if ref else None,

@@ -54,6 +54,10 @@ extern "C" {
 #define FLP_PREC_FP64         0  /* FP64 matrix values, vectors and accumulation */
 #define FLP_PREC_FP32_FILTER  1  /* FP32 values/vectors/accumulation in the filter only */
 
+/* storage formats of the filter's SpMMs (flp_opts.format) */
+#define FLP_FORMAT_CSR 0
+#define FLP_FORMAT_SELL 1
+
 /* ------------------------------------------------------------------ types */
 
 /* Sparse symmetric matrix in CSR form (Section 3.2.1).  All pointers are
@@ -98,6 +102,10 @@ typedef struct flp_opts {
                              only (FLP_E_ARG elsewhere).  Ritz values of Ahat inside the
                              mapped interval, and the nearest one outside on each side, must
                              converge; max_basis <= 0 then means min(n, 12288). */
+    int32_t format;       /* storage the filter's SpMMs read A in: FLP_FORMAT_CSR (default) or
+                             FLP_FORMAT_SELL, a sliced ELL copy built at set-up (slices of 64
+                             rows padded to their longest row, column-major inside a slice;
+                             the "other sparse formats" of Section 5).  flp_solve only. */
 } flp_opts;
 
 typedef struct flp_stats {

@@ -457,6 +457,7 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
         if (o.block != r || o.prec != prec)
             return fail(FLP_E_ARG, "all solves of a batch need the same block size and precision");
         if (o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos runs through flp_solve only");
+        if (o.format != FLP_FORMAT_CSR) return fail(FLP_E_ARG, "the batched filter reads CSR only");
     }
     CK(hipStreamSynchronize(user));
     Engine E;

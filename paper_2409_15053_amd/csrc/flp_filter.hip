@@ -63,11 +63,41 @@ struct Unroll {
     static constexpr int value = VEC * (int)sizeof(T) >= 64 ? 4 : 8;
 };
 
+// The same sum for a matrix in sliced ELL form (slices of kSellC rows, each
+// padded to its longest row with zero weights on the row's own column;
+// entry k of row `row` at q0 + k * kSellC): the row's nonzeros in their CSR
+// order, so the sum is bit-identical to row_gather's.
+template <typename T, int VEC, int UNR>
+__device__ __forceinline__ void sell_gather(int q0, int w, const int32_t *__restrict__ colind,
+                                            const T *__restrict__ val, const T *__restrict__ X, int ldx, int c0,
+                                            T (&acc)[VEC]) {
+    for (int k = 0; k < w; k += UNR) {
+        int cc[UNR];
+        T aa[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int q = q0 + min(k + u, w - 1) * kSellC;
+            cc[u] = colind[q];
+            const T a = val[q];
+            aa[u] = (k + u < w) ? a : T(0);
+        }
+        T xv[UNR][VEC];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) load_vec<T, VEC>(X + (int64_t)cc[u] * ldx + c0, xv[u]);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], xv[u][v], acc[v]);
+    }
+}
+
 // LPR lanes share one matrix row; lane `sub` owns columns
 // [sub*VEC, sub*VEC + VEC) of the block.  All lanes of a row walk the row's
 // nonzeros together (the column index and value loads of a row coalesce to
 // one request), and each gathers its VEC contiguous entries of X[col, :].
-template <typename T, typename Tout, int LPR, int VEC, bool NT>
+// SELL: rowptr holds the slice offsets and colind / val the sliced ELL
+// arrays (sell_gather).
+template <typename T, typename Tout, int LPR, int VEC, bool NT, bool SELL>
 __global__ __launch_bounds__(256) void cheb_step_kernel(
     int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
     const T *__restrict__ val, int r, const T *__restrict__ X, int ldx, const T *__restrict__ V,
@@ -79,11 +109,18 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
     const int sub = threadIdx.x % LPR;
     const int c0 = sub * VEC;
     if (row >= n || c0 >= r) return;
-    const int p0 = rowptr[row], p1 = rowptr[row + 1];
     T acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = T(0);
-    row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
+    if constexpr (SELL) {
+        const int sl = row / kSellC;
+        const int o0 = rowptr[sl], o1 = rowptr[sl + 1];
+        sell_gather<T, VEC, Unroll<T, VEC>::value>(o0 + row % kSellC, (o1 - o0) / kSellC, colind, val, X, ldx, c0,
+                                                   acc);
+    } else {
+        const int p0 = rowptr[row], p1 = rowptr[row + 1];
+        row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
+    }
     T xr[VEC];
     load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
     T res[VEC];
@@ -115,12 +152,40 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
 template <typename T, typename Tout, int LPR, int VEC, bool NT>
 hipError_t cheb_launch(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
                        const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
-                       int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s) {
+                       int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s, bool sell) {
     constexpr int RPB = 256 / LPR;
     int grid = (n + RPB - 1) / RPB;
-    hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT>), dim3(grid), dim3(256), 0, s, n, rowptr,
-                       colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
+    if (sell)
+        hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT, true>), dim3(grid), dim3(256), 0, s, n, rowptr,
+                           colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
+    else
+        hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT, false>), dim3(grid), dim3(256), 0, s, n,
+                           rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
     return hipGetLastError();
+}
+
+// Sliced ELL copy of a CSR matrix: thread t fills slot t % kSellC of slice
+// t / kSellC (its row's nonzeros in order, then zero weights on the row's
+// own column; slots past row n - 1 get column 0 and weight 0).  val64 /
+// val32 (either may be null) receive the FP64 / FP32 values.
+__global__ __launch_bounds__(256) void sell_fill_kernel(int n, int nslots, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ colind,
+                                                        const double *__restrict__ v64,
+                                                        const float *__restrict__ v32, const int32_t *__restrict__ off,
+                                                        int32_t *__restrict__ col, double *__restrict__ val64,
+                                                        float *__restrict__ val32) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nslots) return;
+    const int sl = t / kSellC;
+    const int q0 = off[sl] + t % kSellC, w = (off[sl + 1] - off[sl]) / kSellC;
+    const int p0 = t < n ? rowptr[t] : 0, len = t < n ? rowptr[t + 1] - p0 : 0;
+    for (int k = 0; k < w; ++k) {
+        const int q = q0 + k * kSellC;
+        const bool real = k < len;
+        col[q] = real ? colind[p0 + k] : (t < n ? t : 0);
+        if (val64) val64[q] = real ? v64[p0 + k] : 0.0;
+        if (val32) val32[q] = real ? v32[p0 + k] : 0.0f;
+    }
 }
 
 }  // namespace
@@ -163,7 +228,7 @@ bool step_shape_ok(int r, bool fp32, StepShape sh) {
 template <typename T, typename Tout>
 hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
                             const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
-                            int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s, StepShape sh) {
+                            int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s, StepShape sh, bool sell) {
     if (n <= 0) return hipSuccess;
     constexpr bool F32 = sizeof(T) == 4;
     // vector loads need every leading dimension and base aligned to 16 bytes
@@ -172,7 +237,7 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
     bool aligned16 = (ldx % V16 == 0) && (!V || ldv % V16 == 0) && (!Y || ldy % V16 == 0) &&
                      (ldo % V16 == 0) && (sizeof(Tout) == sizeof(T)) && al(X) && al(V) && al(Y) && al(out);
 #define FLP_CHEB_NT(LPR, VEC, NT) \
-    return cheb_launch<T, Tout, LPR, VEC, NT>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s)
+    return cheb_launch<T, Tout, LPR, VEC, NT>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s, sell)
 #define FLP_CHEB(LPR, VEC) FLP_CHEB_NT(LPR, VEC, false)
     if (aligned16 && r % V16 == 0) {
         if (!step_shape_ok(r, F32, sh)) sh = default_step_shape(r, F32);
@@ -207,15 +272,25 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
 template hipError_t launch_cheb_step<double, double>(int, const int32_t *, const int32_t *, const double *, int,
                                                      const double *, int, const double *, int, const double *,
                                                      int, double *, int, double, double, double, double,
-                                                     hipStream_t, StepShape);
+                                                     hipStream_t, StepShape, bool);
 template hipError_t launch_cheb_step<float, float>(int, const int32_t *, const int32_t *, const float *, int,
                                                    const float *, int, const float *, int, const float *, int,
                                                    float *, int, float, float, float, float, hipStream_t,
-                                                   StepShape);
+                                                   StepShape, bool);
 template hipError_t launch_cheb_step<float, double>(int, const int32_t *, const int32_t *, const float *, int,
                                                     const float *, int, const float *, int, const float *, int,
                                                     double *, int, float, float, float, float, hipStream_t,
-                                                    StepShape);
+                                                    StepShape, bool);
+
+hipError_t launch_sell_fill(int n, const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
+                            const int32_t *off, int nslices, int32_t *col, double *val64, float *val32,
+                            hipStream_t s) {
+    const int nslots = nslices * kSellC;
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sell_fill_kernel, dim3((nslots + 255) / 256), dim3(256), 0, s, n, nslots, rowptr, colind, v64,
+                       v32, off, col, val64, val32);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------------ segmented filter step
 //

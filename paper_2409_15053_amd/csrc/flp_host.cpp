@@ -468,24 +468,61 @@ std::vector<ClenshawStep> clenshaw_plan(const flp_filter *p, int r, const void *
 
 // Launch one planned step with the direct (single-matrix) kernel.
 int launch_plan_step(const flp_csr *A, const float *val32, int r, const ClenshawStep &st, bool fp32,
-                     hipStream_t s, StepShape sh) {
+                     hipStream_t s, StepShape sh, bool sell) {
     const int n = A->n;
     if (!fp32) {
         CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, r, (const double *)st.X, st.ldx,
                                             (const double *)st.V, st.ldv, (const double *)st.Y, st.ldy,
                                             (double *)st.out, st.ldo, st.alpha, st.beta, st.gamma, st.delta, s,
-                                            sh));
+                                            sh, sell));
     } else if (st.out_f64) {
         CK(launch_cheb_step<float, double>(n, A->rowptr, A->colind, val32, r, (const float *)st.X, st.ldx,
                                            (const float *)st.V, st.ldv, (const float *)st.Y, st.ldy,
                                            (double *)st.out, st.ldo, (float)st.alpha, (float)st.beta,
-                                           (float)st.gamma, (float)st.delta, s, sh));
+                                           (float)st.gamma, (float)st.delta, s, sh, sell));
     } else {
         CK(launch_cheb_step<float, float>(n, A->rowptr, A->colind, val32, r, (const float *)st.X, st.ldx,
                                           (const float *)st.V, st.ldv, (const float *)st.Y, st.ldy,
                                           (float *)st.out, st.ldo, (float)st.alpha, (float)st.beta,
-                                          (float)st.gamma, (float)st.delta, s, sh));
+                                          (float)st.gamma, (float)st.delta, s, sh, sell));
     }
+    return FLP_OK;
+}
+
+int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, flp_csr *out, const float **out32,
+               hipStream_t s) {
+    const int n = A->n;
+    std::vector<int32_t> rp((size_t)n + 1);
+    CK(hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    const int nsl = (n + kSellC - 1) / kSellC;
+    std::vector<int32_t> off((size_t)nsl + 1);
+    int64_t tot = 0;
+    for (int i = 0; i < nsl; ++i) {
+        int w = 0;
+        for (int j = i * kSellC; j < std::min(n, (i + 1) * kSellC); ++j) w = std::max(w, rp[j + 1] - rp[j]);
+        off[i] = (int32_t)tot;
+        tot += (int64_t)w * kSellC;
+        if (tot > INT32_MAX) return fail(FLP_E_ARG, "the sliced ELL copy of A would exceed 2^31 entries");
+    }
+    off[nsl] = (int32_t)tot;
+    const size_t ents = (size_t)std::max<int64_t>(tot, 1);
+    CK(ensure(B.sell_off, sizeof(int32_t) * ((size_t)nsl + 1)));
+    CK(ensure(B.sell_col, sizeof(int32_t) * ents));
+    CK(ensure(B.sell_val, (fp32 ? sizeof(float) : sizeof(double)) * ents));
+    CK(h2d(B.sell_off.p, off.data(), sizeof(int32_t) * ((size_t)nsl + 1), s));
+    auto *col = (int32_t *)B.sell_col.p;
+    CK(launch_sell_fill(n, A->rowptr, A->colind, fp32 ? nullptr : A->val, fp32 ? val32 : nullptr,
+                        (const int32_t *)B.sell_off.p, nsl, col, fp32 ? nullptr : (double *)B.sell_val.p,
+                        fp32 ? (float *)B.sell_val.p : nullptr, s));
+    CK(hipStreamSynchronize(s));
+    *out = *A;
+    out->rowptr = (const int32_t *)B.sell_off.p;
+    out->colind = col;
+    out->nnz = tot;
+    out->val = fp32 ? nullptr : (const double *)B.sell_val.p;
+    out->val32 = nullptr;
+    *out32 = fp32 ? (const float *)B.sell_val.p : nullptr;
     return FLP_OK;
 }
 

@@ -135,6 +135,12 @@ double filter_step_bytes(int n, int64_t nnz, int r, int prec);
 int filter_group_width(int n, int64_t nnz, int r, int prec);
 int ensure_val32(const flp_csr *A, Buf &buf, const double **src_cache, int64_t *nnz_cache, const float **out,
                  hipStream_t s);
+struct SolveBufs;
+// Sliced ELL copy of A into B.sell_* (FP64 values, or FP32 ones from val32
+// when fp32): *out describes it (rowptr = slice offsets, nnz = stored
+// entries, val = FP64 values or null), *out32 the FP32 values.  Synchronous.
+int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, flp_csr *out, const float **out32,
+               hipStream_t s);
 
 // One launch of the Clenshaw recurrence (Section 2.2):
 // out = alpha (A X) + beta X + gamma V + delta Y on row-major blocks.
@@ -156,7 +162,7 @@ struct ClenshawStep {
 std::vector<ClenshawStep> clenshaw_plan(const flp_filter *p, int r, const void *V, int ldv, double *W, int ldw,
                                         void *U0, void *U1, void *U2, bool fp32);
 int launch_plan_step(const flp_csr *A, const float *val32, int r, const ClenshawStep &st, bool fp32,
-                     hipStream_t s, StepShape sh = StepShape{});
+                     hipStream_t s, StepShape sh = StepShape{}, bool sell = false);
 
 // ---------------------------------------------------------------- autotuner
 struct FilterTune {
@@ -205,6 +211,7 @@ int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, d
 // Device buffers one solve keeps across block steps.
 struct SolveBufs {
     Buf Q, W, Vin, U[3], V32, val32, hdev;
+    Buf sell_off, sell_col, sell_val;  // sliced ELL copy of A for the filter (FLP_FORMAT_SELL)
     const double *val32_src = nullptr;
     int64_t val32_nnz = 0;
     // earlier, smaller basis allocations: freed with the rest (a device free
@@ -251,6 +258,9 @@ struct Solve {
     int n = 0, r = 0;
     double lmin = 0, lmax = 0, tau = 0, tol_p = 0;
     bool unfiltered = false;  // p(Ahat) = Ahat (plain block Lanczos)
+    bool sell = false;        // the filter reads A's sliced ELL copy SA (values sval32 in FP32)
+    flp_csr SA{};
+    const float *sval32 = nullptr;
     std::unique_ptr<flp_filter> filt;
     int check_every = 0, max_steps = 0;
     int check_offset = 0;  // checks fall on steps with (steps + check_offset) % check_every == 0

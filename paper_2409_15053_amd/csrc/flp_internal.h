@@ -94,12 +94,25 @@ bool step_shape_ok(int r, bool fp32, StepShape sh);
 // out = alpha * (A X) + beta * X + gamma * V + delta * Y, row-major blocks of
 // r columns with leading dimensions; V / Y may be NULL (their terms skipped).
 // T = float or double selects the matrix values and the vector type; the
-// output type is Tout.
+// output type is Tout.  sell: A is in sliced ELL form (rowptr = the slice
+// offsets, colind / val = the sliced arrays; see launch_sell_fill).
 template <typename T, typename Tout>
 hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val,
                             int r, const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy,
                             Tout *out, int ldo, T alpha, T beta, T gamma, T delta,
-                            hipStream_t s, StepShape sh = StepShape{});
+                            hipStream_t s, StepShape sh = StepShape{}, bool sell = false);
+
+// Sliced ELL (SELL-C with C = kSellC rows per slice, rows in their original
+// order): slice i holds entries off[i] .. off[i + 1] - 1, its width
+// w_i = (off[i + 1] - off[i]) / kSellC, entry k of its row j at
+// off[i] + k * kSellC + j; rows shorter than w_i are padded with weight 0 on
+// their own column.  off (nslices + 1 entries, built on the host from
+// rowptr) is the caller's; the fill writes col and the FP64 / FP32 values
+// (val64 / val32 may be null) from the CSR arrays.
+constexpr int kSellC = 64;
+hipError_t launch_sell_fill(int n, const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
+                            const int32_t *off, int nslices, int32_t *col, double *val64, float *val32,
+                            hipStream_t s);
 
 // One segment of a segmented filter step: the current Clenshaw launch of
 // one solve in a batch (out = alpha AX + beta X + gamma V + delta Y).

@@ -55,6 +55,7 @@ int solve_setup(Solve &S) {
     if (o.prec != FLP_PREC_FP64 && o.prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
     const bool fp32 = o.prec == FLP_PREC_FP32_FILTER;
     S.unfiltered = o.unfiltered != 0;
+    if (o.format != FLP_FORMAT_CSR && o.format != FLP_FORMAT_SELL) return fail(FLP_E_ARG, "bad storage format");
     if (S.unfiltered && fp32) return fail(FLP_E_ARG, "unfiltered Lanczos runs in FP64 only");
     if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
 
@@ -113,6 +114,8 @@ int solve_setup(Solve &S) {
         CK(ensure(B.V32, sizeof(float) * (size_t)n * r));
         S.V32 = (float *)B.V32.p;
     }
+    S.sell = o.format == FLP_FORMAT_SELL;
+    if (S.sell) CKR(build_sell(A, S.val32, fp32, B, &S.SA, &S.sval32, s));
     S.plan = clenshaw_plan(S.filt.get(), r, fp32 ? (const void *)S.V32 : (const void *)S.Vin, r, S.W, r, S.U[0],
                            S.U[1], S.U[2], fp32);
 
@@ -588,6 +591,8 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     CKR(tune_filter(A, S.val32, S.r, fp32, true, U, fp32 ? (const void *)S.V32 : (const void *)S.Vin, S.r, S.s,
                     &tn));
     const int gw = tn.gw;
+    const flp_csr *fA = S.sell ? &S.SA : A;  // the filter's copy of A
+    const float *fv32 = S.sell ? S.sval32 : S.val32;
     std::vector<ClenshawStep> gplan;
     void *stage = nullptr;
     if (gw != S.r) {
@@ -607,7 +612,7 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     while (!S.done) {
         CK(hipEventRecord(ev[0], S.s));
         if (gw == S.r) {
-            for (const auto &st : S.plan) CKR(launch_plan_step(A, S.val32, S.r, st, fp32, S.s, tn.sh));
+            for (const auto &st : S.plan) CKR(launch_plan_step(fA, fv32, S.r, st, fp32, S.s, tn.sh, S.sell));
         } else {
             for (int j0 = 0; j0 < S.r; j0 += gw) {
                 if (fp32)
@@ -618,7 +623,7 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
                                          nullptr, 0, S.s));
                 for (ClenshawStep st : gplan) {
                     if (st.out == (void *)S.W) st.out = S.W + j0;  // the last step writes the group's columns of W
-                    CKR(launch_plan_step(A, S.val32, gw, st, fp32, S.s, tn.sh));
+                    CKR(launch_plan_step(fA, fv32, gw, st, fp32, S.s, tn.sh, S.sell));
                 }
             }
         }

@@ -25,6 +25,8 @@ FLP_E_PENDING = -7
 FLP_E_CANCELLED = -8
 FLP_PREC_FP64 = 0
 FLP_PREC_FP32_FILTER = 1
+FLP_FORMAT_CSR = 0
+FLP_FORMAT_SELL = 1
 
 EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
@@ -61,7 +63,7 @@ class FlpOptsC(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("max_basis", ctypes.c_int64), ("k0", ctypes.c_int32),
                 ("start", ctypes.c_void_p), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("sym_tol", ctypes.c_double), ("polish_degree", ctypes.c_int32),
-                ("unfiltered", ctypes.c_int32)]
+                ("unfiltered", ctypes.c_int32), ("format", ctypes.c_int32)]
 
 
 class FlpStatsC(ctypes.Structure):
@@ -321,13 +323,15 @@ def default_opts() -> FlpOptsC:
 def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: int = 0, seed: int = 0,
               prec: int = FLP_PREC_FP64, start: np.ndarray | None = None, bounds=None, max_basis: int = 0,
               check_every: int = 0, eps: float = 0.0, k0: int = 0, want_vectors: bool = True,
-              stream=None, sym_tol: float = -1.0, polish_degree: int = 0, unfiltered: bool = False) -> dict:
+              stream=None, sym_tol: float = -1.0, polish_degree: int = 0, unfiltered: bool = False,
+              format: int = 0) -> dict:
     """Every eigenpair of A in [alpha, beta].  Returns a dict with numpy
     ``evals``/``resid``, a torch ``evecs`` (n x count, float64, on A's
     device) and the solve statistics.  ``sym_tol >= 0`` checks A for
     symmetry first (FLP_E_NOTSYM if it is not).  ``unfiltered=True`` runs
     plain block Lanczos with the mapped matrix in place of the filter (FP64
-    only)."""
+    only).  ``format=FLP_FORMAT_SELL`` has the filter read a sliced ELL copy
+    of A instead of the CSR arrays."""
     import torch
     lib = load()
     o = default_opts()
@@ -352,6 +356,7 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
     o.sym_tol = sym_tol
     o.polish_degree = polish_degree
     o.unfiltered = 1 if unfiltered else 0
+    o.format = format
     res = ctypes.POINTER(FlpResultC)()
     rc = lib.flp_solve(ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(res))
     _check(rc, allow=(FLP_E_NOCONV,))
