@@ -67,8 +67,12 @@ def parse():
     ap.add_argument("--requests", type=int, default=32, help="serving form: number of requests")
     ap.add_argument("--gmin", type=int, default=30, help="serving form: smallest grid edge")
     ap.add_argument("--gmax", type=int, default=100, help="serving form: largest grid edge")
-    ap.add_argument("--format", default="csr", choices=["csr", "sell"],
-                    help="storage the single-solve filter reads A in: CSR, or a sliced ELL copy")
+    ap.add_argument("--format", default="auto", choices=["auto", "csr", "sell"],
+                    help="storage the single-solve filter reads A in: CSR, a sliced ELL copy, or the "
+                         "library's choice")
+    ap.add_argument("--force-shape", default=None, metavar="GW,LPR,VEC,NT",
+                    help="single-solve filter: use this launch configuration (columns per launch, lanes per "
+                         "row, columns per lane, nontemporal loads 0/1) instead of the tuned one")
     ap.add_argument("--unfiltered-compare", action="store_true",
                     help="also run one unfiltered block Lanczos solve of the same problem (FP64) and report "
                          "its basis size and time beside the filtered solve's")
@@ -87,7 +91,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, prec, tuned):
+def measured_traffic(workload, prec, tuned, fmt):
     """HBM bytes per launch of the filter kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a
     plain copy of known size gives), or None when the kernel sources or the
@@ -98,15 +102,16 @@ def measured_traffic(workload, prec, tuned):
     except OSError:
         return None, "no counter summary"
     kv = dict(re.findall(r"^- (\w+): (.+?)\s*$", text, re.M))
+    per_cfg = dict(re.findall(r"^- traffic_bytes_per_launch\[(.+?)\]: (\S+)\s*$", text, re.M))
     if kv.get("workload") != f"{workload} {prec}":
         return None, "counters were taken on another workload"
     if kv.get("kernel_sources_sha256") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
     cfg = (f"gw={tuned['group_width']} lpr={tuned['lanes_per_row']} vec={tuned['cols_per_lane']} "
-           f"nt={tuned['streaming_loads']}")
-    if kv.get("launch_config") != cfg:
-        return None, f"launch configuration {cfg} differs from the profiled {kv.get('launch_config')}"
-    return float(kv["traffic_bytes_per_launch"]), TRAFFIC_PROFILE[len(ROOT) + 1:]
+           f"nt={tuned['streaming_loads']} fmt={fmt}")
+    if cfg not in per_cfg:
+        return None, f"launch configuration {cfg} was not among the profiled ones {sorted(per_cfg)}"
+    return float(per_cfg[cfg]), TRAFFIC_PROFILE[len(ROOT) + 1:]
 
 
 def group_width(A, r, prec):
@@ -189,7 +194,11 @@ def cpu_baseline(w, alpha, beta, degree, gpu_res, budget_s):
 
 
 def fmt_code(flp, args):
-    return flp.FLP_FORMAT_SELL if args.format == "sell" else flp.FLP_FORMAT_CSR
+    return {"auto": flp.FLP_FORMAT_AUTO, "csr": flp.FLP_FORMAT_CSR, "sell": flp.FLP_FORMAT_SELL}[args.format]
+
+
+def fmt_name(flp, code):
+    return "sell" if code == flp.FLP_FORMAT_SELL else "csr"
 
 
 def check_cadence(args, r):
@@ -520,6 +529,9 @@ def main():
         return bench_c3(args)
     w, alpha, beta, ref = load_workload(args.workload)
     A = w["A"]
+    if args.force_shape:
+        gw, lpr, vec, nt = (int(x) for x in args.force_shape.split(","))
+        flp.flp_set_filter_shape(lanes_per_row=lpr, cols_per_lane=vec, group_width=gw, streaming_loads=bool(nt))
     prec = flp.FLP_PREC_FP32_FILTER if args.prec == "fp32" else flp.FLP_PREC_FP64
     dA = flp.DeviceCsr.from_host(A, "cuda:0", with_fp32=(prec == flp.FLP_PREC_FP32_FILTER))
     torch.cuda.synchronize()
@@ -561,7 +573,11 @@ def main():
                 good = good and rel <= 1e-10
         ok_pairs += res["count"] if good else 0
 
-    tuned = flp.flp_tune_filter(dA, w["block"], prec)  # the cached choice the solves used
+    s_last = results[-1]["stats"]  # the launch configuration the solves used
+    tuned = {"group_width": s_last["filter_group_width"], "lanes_per_row": s_last["filter_lanes_per_row"],
+             "cols_per_lane": s_last["filter_cols_per_lane"],
+             "rows_per_wave": 64 // max(1, s_last["filter_lanes_per_row"]),
+             "streaming_loads": s_last["filter_streaming_loads"]}
     st = [r["stats"] for r in results]
     fbytes = sum(s["filter_bytes"] for s in st)
     t_mv = sum(s["t_mv"] for s in st)
@@ -587,7 +603,8 @@ def main():
                                f"interval=[{alpha}, {beta:.9f}]",
                    "n": A.n, "nnz": A.nnz, "block": w["block"], "degree": args.degree,
                    "check_every": check_cadence(args, w["block"]),
-                   "alpha": alpha, "beta": beta, "prec": args.prec, "format": args.format},
+                   "alpha": alpha, "beta": beta, "prec": args.prec, "format": args.format,
+                   "forced_shape": args.force_shape},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "all": [round(x, 3) for x in lat_ms.tolist()]},
         "accuracy": {"count": results[-1]["count"], "ref_count": ref["count"] if ref else None,
@@ -610,12 +627,14 @@ def main():
         "iters": [s["iters"] for s in st],
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "cheb_step_kernel (CSR SpMM + fused Clenshaw update)",
+                     "kernel": "cheb_step_kernel (sparse matrix times block, Clenshaw update fused)",
                      "algorithmic_bytes_per_launch": per_launch_bytes * tuned["group_width"] / w["block"],
                      "avg_launch_us": (t_mv / launches * 1e6 * tuned["group_width"] / w["block"]
                                        if launches else None)},
     }
-    traffic, src = measured_traffic(args.workload, args.prec, tuned)
+    used_fmt = fmt_name(flp, results[-1]["stats"]["filter_format"])
+    out["config"]["filter_format"] = used_fmt
+    traffic, src = measured_traffic(args.workload, args.prec, tuned, used_fmt)
     out["roofline"]["traffic"] = traffic
     out["roofline"]["traffic_over_algorithmic"] = (traffic / out["roofline"]["algorithmic_bytes_per_launch"]
                                                    if traffic else None)

@@ -55,8 +55,9 @@ extern "C" {
 #define FLP_PREC_FP32_FILTER  1  /* FP32 values/vectors/accumulation in the filter only */
 
 /* storage formats of the filter's SpMMs (flp_opts.format) */
-#define FLP_FORMAT_CSR 0
-#define FLP_FORMAT_SELL 1
+#define FLP_FORMAT_AUTO 0
+#define FLP_FORMAT_CSR 1
+#define FLP_FORMAT_SELL 2
 
 /* ------------------------------------------------------------------ types */
 
@@ -102,10 +103,13 @@ typedef struct flp_opts {
                              only (FLP_E_ARG elsewhere).  Ritz values of Ahat inside the
                              mapped interval, and the nearest one outside on each side, must
                              converge; max_basis <= 0 then means min(n, 12288). */
-    int32_t format;       /* storage the filter's SpMMs read A in: FLP_FORMAT_CSR (default) or
-                             FLP_FORMAT_SELL, a sliced ELL copy built at set-up (slices of 64
-                             rows padded to their longest row, column-major inside a slice;
-                             the "other sparse formats" of Section 5).  flp_solve only. */
+    int32_t format;       /* storage the filter's SpMMs read A in: FLP_FORMAT_CSR, FLP_FORMAT_SELL
+                             (a sliced ELL copy built at set-up: slices of 64 rows padded to
+                             their longest row, column-major inside a slice; the "other
+                             sparse formats" of Section 5), or FLP_FORMAT_AUTO (default):
+                             SELL unless padding would add more than 25 % to the stored
+                             entries.  Results are bit-identical either way.  SELL is for
+                             flp_solve only (FLP_E_ARG elsewhere; AUTO means CSR there). */
 } flp_opts;
 
 typedef struct flp_stats {
@@ -124,6 +128,11 @@ typedef struct flp_stats {
     double filter_bytes;   /* algorithmic bytes moved by the filter SpMMs */
     double orth_bytes;     /* algorithmic bytes of the reorthogonalisation: the basis
                               (n x k doubles) read twice per Gram-Schmidt pass */
+    int32_t filter_format; /* storage the filter read A in: FLP_FORMAT_CSR or FLP_FORMAT_SELL */
+    int32_t filter_group_width;     /* filter launch configuration used: columns per launch, */
+    int32_t filter_lanes_per_row;   /* lanes per matrix row, */
+    int32_t filter_cols_per_lane;   /* columns per lane and */
+    int32_t filter_streaming_loads; /* nontemporal loads of V and U_{k+2} (1) or not (0) */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */

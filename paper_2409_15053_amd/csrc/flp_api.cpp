@@ -35,7 +35,7 @@ void flp_opts_default(flp_opts *o) {
     o->sym_tol = -1.0;
     o->polish_degree = 0;
     o->unfiltered = 0;
-    o->format = FLP_FORMAT_CSR;
+    o->format = FLP_FORMAT_AUTO;
 }
 
 int flp_build_filter(double alpha, double beta, int32_t degree, double lmin, double lmax, flp_filter **out) {

@@ -457,7 +457,7 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
         if (o.block != r || o.prec != prec)
             return fail(FLP_E_ARG, "all solves of a batch need the same block size and precision");
         if (o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos runs through flp_solve only");
-        if (o.format != FLP_FORMAT_CSR) return fail(FLP_E_ARG, "the batched filter reads CSR only");
+        if (o.format == FLP_FORMAT_SELL) return fail(FLP_E_ARG, "the batched filter reads CSR only");
     }
     CK(hipStreamSynchronize(user));
     Engine E;
@@ -474,6 +474,7 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
         S.alpha = alpha[i];
         S.beta = beta[i];
         S.o = opts ? opts[i] : o0;
+        S.o.format = FLP_FORMAT_CSR;  // the segmented filter reads the CSR arrays
         S.o.stream = nullptr;
         jobs[i] = std::move(j);
     }

@@ -490,7 +490,8 @@ int launch_plan_step(const flp_csr *A, const float *val32, int r, const Clenshaw
 }
 
 int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, flp_csr *out, const float **out32,
-               hipStream_t s) {
+               hipStream_t s, double max_pad, bool *built) {
+    *built = false;
     const int n = A->n;
     std::vector<int32_t> rp((size_t)n + 1);
     CK(hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
@@ -506,6 +507,7 @@ int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, fl
         if (tot > INT32_MAX) return fail(FLP_E_ARG, "the sliced ELL copy of A would exceed 2^31 entries");
     }
     off[nsl] = (int32_t)tot;
+    if ((double)tot > max_pad * (double)A->nnz + kSellC) return FLP_OK;
     const size_t ents = (size_t)std::max<int64_t>(tot, 1);
     CK(ensure(B.sell_off, sizeof(int32_t) * ((size_t)nsl + 1)));
     CK(ensure(B.sell_col, sizeof(int32_t) * ents));
@@ -523,6 +525,7 @@ int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, fl
     out->val = fp32 ? nullptr : (const double *)B.sell_val.p;
     out->val32 = nullptr;
     *out32 = fp32 ? (const float *)B.sell_val.p : nullptr;
+    *built = true;
     return FLP_OK;
 }
 

@@ -43,6 +43,9 @@ constexpr int kDefaultK0 = 40;
 constexpr double kDefaultTol = 1e-9;
 constexpr int kMaxDegree = 100000;
 constexpr int64_t kDefaultMaxBasis = 3072;
+// FLP_FORMAT_AUTO keeps CSR when the sliced ELL copy would store more than
+// this many times the nonzeros
+constexpr double kSellMaxPad = 1.25;
 // Unfiltered Lanczos resolves an interval only once its Ritz values there
 // have converged without a filter's help, which takes many more columns.
 constexpr int64_t kUnfilteredMaxBasis = 12288;
@@ -138,9 +141,11 @@ int ensure_val32(const flp_csr *A, Buf &buf, const double **src_cache, int64_t *
 struct SolveBufs;
 // Sliced ELL copy of A into B.sell_* (FP64 values, or FP32 ones from val32
 // when fp32): *out describes it (rowptr = slice offsets, nnz = stored
-// entries, val = FP64 values or null), *out32 the FP32 values.  Synchronous.
+// entries, val = FP64 values or null), *out32 the FP32 values.  If the copy
+// would store more than max_pad times A's nonzeros nothing is built and
+// *built is false.  Synchronous.
 int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, flp_csr *out, const float **out32,
-               hipStream_t s);
+               hipStream_t s, double max_pad, bool *built);
 
 // One launch of the Clenshaw recurrence (Section 2.2):
 // out = alpha (A X) + beta X + gamma V + delta Y on row-major blocks.
@@ -175,7 +180,7 @@ struct FilterTune {
 // flp_tune.cpp).  U: three device buffers of n x r filter-type elements
 // (scratch, overwritten); V: n x r input block (read only, ld ldv).
 int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
-                const void *V, int ldv, hipStream_t s, FilterTune *out);
+                const void *V, int ldv, hipStream_t s, FilterTune *out, bool sell = false);
 void set_autotune(int mode);
 int autotune_mode();
 void force_filter_shape(StepShape sh, int gw);

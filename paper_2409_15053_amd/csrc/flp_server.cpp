@@ -234,7 +234,8 @@ int flp_server_submit(flp_server *sv, const flp_csr *A, double alpha, double bet
         flp_opts_default(&S.o);
         if (opts) S.o = *opts;
         if (S.o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos runs through flp_solve only");
-        if (S.o.format != FLP_FORMAT_CSR) return fail(FLP_E_ARG, "the batched filter reads CSR only");
+        if (S.o.format == FLP_FORMAT_SELL) return fail(FLP_E_ARG, "the batched filter reads CSR only");
+        S.o.format = FLP_FORMAT_CSR;  // the segmented filter reads the CSR arrays
         S.o.block = sv->o.block;
         S.o.prec = sv->o.prec;
         if (S.o.max_basis <= 0) S.o.max_basis = sv->o.max_basis;

@@ -33,7 +33,7 @@ int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, 
     *out = nullptr;
     if (nslices < 1 || nslices > 256) return fail(FLP_E_ARG, "nslices must be in [1, 256]");
     if (o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos runs through flp_solve only");
-    if (o.format != FLP_FORMAT_CSR) return fail(FLP_E_ARG, "the batched filter reads CSR only");
+    if (o.format == FLP_FORMAT_SELL) return fail(FLP_E_ARG, "the batched filter reads CSR only");
     if (!(std::isfinite(alpha) && std::isfinite(beta)) || !(alpha < beta))
         return fail(FLP_E_ARG, "need finite alpha < beta");
     hipStream_t s = (hipStream_t)o.stream;

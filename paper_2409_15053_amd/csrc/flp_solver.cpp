@@ -55,7 +55,8 @@ int solve_setup(Solve &S) {
     if (o.prec != FLP_PREC_FP64 && o.prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
     const bool fp32 = o.prec == FLP_PREC_FP32_FILTER;
     S.unfiltered = o.unfiltered != 0;
-    if (o.format != FLP_FORMAT_CSR && o.format != FLP_FORMAT_SELL) return fail(FLP_E_ARG, "bad storage format");
+    if (o.format != FLP_FORMAT_AUTO && o.format != FLP_FORMAT_CSR && o.format != FLP_FORMAT_SELL)
+        return fail(FLP_E_ARG, "bad storage format");
     if (S.unfiltered && fp32) return fail(FLP_E_ARG, "unfiltered Lanczos runs in FP64 only");
     if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
 
@@ -114,8 +115,11 @@ int solve_setup(Solve &S) {
         CK(ensure(B.V32, sizeof(float) * (size_t)n * r));
         S.V32 = (float *)B.V32.p;
     }
-    S.sell = o.format == FLP_FORMAT_SELL;
-    if (S.sell) CKR(build_sell(A, S.val32, fp32, B, &S.SA, &S.sval32, s));
+    S.sell = false;
+    if (o.format != FLP_FORMAT_CSR)
+        CKR(build_sell(A, S.val32, fp32, B, &S.SA, &S.sval32, s, o.format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad,
+                       &S.sell));
+    S.st.filter_format = S.sell ? FLP_FORMAT_SELL : FLP_FORMAT_CSR;
     S.plan = clenshaw_plan(S.filt.get(), r, fp32 ? (const void *)S.V32 : (const void *)S.Vin, r, S.W, r, S.U[0],
                            S.U[1], S.U[2], fp32);
 
@@ -588,11 +592,18 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     // V reads of every step touch only that group's bytes
     FilterTune tn;
     void *U[3] = {S.U[0], S.U[1], S.U[2]};
-    CKR(tune_filter(A, S.val32, S.r, fp32, true, U, fp32 ? (const void *)S.V32 : (const void *)S.Vin, S.r, S.s,
-                    &tn));
-    const int gw = tn.gw;
     const flp_csr *fA = S.sell ? &S.SA : A;  // the filter's copy of A
     const float *fv32 = S.sell ? S.sval32 : S.val32;
+    CKR(tune_filter(fA, fv32, S.r, fp32, true, U, fp32 ? (const void *)S.V32 : (const void *)S.Vin, S.r, S.s, &tn,
+                    S.sell));
+    const int gw = tn.gw;
+    {
+        const StepShape used = step_shape_ok(gw, fp32, tn.sh) ? tn.sh : default_step_shape(gw, fp32);
+        S.st.filter_group_width = gw;
+        S.st.filter_lanes_per_row = used.lpr;
+        S.st.filter_cols_per_lane = used.vec;
+        S.st.filter_streaming_loads = used.nt;
+    }
     std::vector<ClenshawStep> gplan;
     void *stage = nullptr;
     if (gw != S.r) {

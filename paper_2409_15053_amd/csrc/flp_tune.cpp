@@ -38,7 +38,7 @@ std::mutex g_mu;
 StepShape g_force_shape{};
 int g_force_gw = 0;
 
-using Key = std::tuple<int, int, int, int64_t, int64_t, int>;
+using Key = std::tuple<int, int, int, int64_t, int64_t, int, int>;
 std::map<Key, FilterTune> &cache() {
     static std::map<Key, FilterTune> c;
     return c;
@@ -47,7 +47,7 @@ std::map<Key, FilterTune> &cache() {
 // Launches one ring of `steps` filter steps over gw columns with the given
 // shape; buffers hold n x gw (row-major, ld gw) elements of the filter type.
 int ring(const flp_csr *A, const float *val32, bool fp32, int gw, StepShape sh, void *const U[3], const void *V,
-         int ldv, int steps, hipStream_t s) {
+         int ldv, int steps, hipStream_t s, bool sell) {
     for (int j = 0; j < steps; ++j) {
         ClenshawStep st{};
         st.X = U[j % 3];
@@ -63,7 +63,7 @@ int ring(const flp_csr *A, const float *val32, bool fp32, int gw, StepShape sh, 
         st.beta = -1.0;
         st.gamma = 0.5;
         st.delta = -1.0;
-        CKR(launch_plan_step(A, val32, gw, st, fp32, s, sh));
+        CKR(launch_plan_step(A, val32, gw, st, fp32, s, sh, sell));
     }
     return FLP_OK;
 }
@@ -80,7 +80,7 @@ void force_filter_shape(StepShape sh, int gw) {
 }
 
 int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
-                const void *V, int ldv, hipStream_t s, FilterTune *out) {
+                const void *V, int ldv, hipStream_t s, FilterTune *out, bool sell) {
     const int n = A->n;
     FilterTune def;
     def.gw = allow_groups ? filter_group_width(n, A->nnz, r, fp32 ? FLP_PREC_FP32_FILTER : FLP_PREC_FP64) : r;
@@ -109,7 +109,7 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     CK(hipGetDevice(&dev));
     // size class: n to a quarter octave, nonzeros per row to a quarter
     const Key key{dev, fp32 ? 1 : 0, r, (int64_t)std::lround(4.0 * std::log2((double)n)),
-                  (int64_t)std::lround(4.0 * (double)A->nnz / n), allow_groups ? 1 : 0};
+                  (int64_t)std::lround(4.0 * (double)A->nnz / n), allow_groups ? 1 : 0, sell ? 1 : 0};
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = cache().find(key);
@@ -142,9 +142,9 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
             const void *Vg = gw == r ? V : (const void *)((const char *)U[0] + es * (size_t)n * gw);
             const int ldvg = gw == r ? ldv : gw;
             if (gw != r && gw > r / 2) continue;
-            CKR(ring(A, val32, fp32, gw, sh, U, Vg, ldvg, kSteps, s));  // warm-up
+            CKR(ring(A, val32, fp32, gw, sh, U, Vg, ldvg, kSteps, s, sell));  // warm-up
             CK(hipEventRecord(e0, s));
-            CKR(ring(A, val32, fp32, gw, sh, U, Vg, ldvg, kSteps, s));
+            CKR(ring(A, val32, fp32, gw, sh, U, Vg, ldvg, kSteps, s, sell));
             CK(hipEventRecord(e1, s));
             CK(hipEventSynchronize(e1));
             float ms = 0.0f;

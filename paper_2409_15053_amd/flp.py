@@ -25,8 +25,9 @@ FLP_E_PENDING = -7
 FLP_E_CANCELLED = -8
 FLP_PREC_FP64 = 0
 FLP_PREC_FP32_FILTER = 1
-FLP_FORMAT_CSR = 0
-FLP_FORMAT_SELL = 1
+FLP_FORMAT_AUTO = 0
+FLP_FORMAT_CSR = 1
+FLP_FORMAT_SELL = 2
 
 EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
@@ -70,7 +71,10 @@ class FlpStatsC(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("mv", ctypes.c_int64), ("basis_cols", ctypes.c_int32),
                 ("polish_sweeps", ctypes.c_int32), ("t_pre", ctypes.c_double), ("t_mv", ctypes.c_double),
                 ("t_orth", ctypes.c_double), ("t_check", ctypes.c_double), ("t_rr", ctypes.c_double),
-                ("t_total", ctypes.c_double), ("filter_bytes", ctypes.c_double), ("orth_bytes", ctypes.c_double)]
+                ("t_total", ctypes.c_double), ("filter_bytes", ctypes.c_double), ("orth_bytes", ctypes.c_double),
+                ("filter_format", ctypes.c_int32), ("filter_group_width", ctypes.c_int32),
+                ("filter_lanes_per_row", ctypes.c_int32), ("filter_cols_per_lane", ctypes.c_int32),
+                ("filter_streaming_loads", ctypes.c_int32)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
@@ -330,8 +334,9 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
     device) and the solve statistics.  ``sym_tol >= 0`` checks A for
     symmetry first (FLP_E_NOTSYM if it is not).  ``unfiltered=True`` runs
     plain block Lanczos with the mapped matrix in place of the filter (FP64
-    only).  ``format=FLP_FORMAT_SELL`` has the filter read a sliced ELL copy
-    of A instead of the CSR arrays."""
+    only).  ``format`` picks the storage the filter reads A in
+    (FLP_FORMAT_AUTO, FLP_FORMAT_CSR or FLP_FORMAT_SELL, a sliced ELL copy);
+    ``stats["filter_format"]`` reports the one used."""
     import torch
     lib = load()
     o = default_opts()

@@ -131,7 +131,7 @@ def test_opts_defaults_and_new_codes():
     o = flp.default_opts()
     assert o.sym_tol < 0          # the symmetry check is opt-in
     assert o.block == 1 and o.check_every == 0 and abs(o.eps - 0.31227) < 1e-12
-    assert o.unfiltered == 0 and o.polish_degree == 0 and o.format == flp.FLP_FORMAT_CSR
+    assert o.unfiltered == 0 and o.polish_degree == 0 and o.format == flp.FLP_FORMAT_AUTO
     assert flp.FLP_E_CANCELLED == -8 and flp.FLP_E_NOTSYM == -3
 
 

@@ -52,11 +52,27 @@ def test_sell_solve_matches_csr(torch, name, block, prec):
         assert np.max(np.abs(np.sort(sell["evals"]) - want) / np.abs(want)) <= 1e-10
 
 
+@pytest.mark.parametrize("name,want_fmt", [("13pt15", flp.FLP_FORMAT_SELL), ("2d40", flp.FLP_FORMAT_SELL),
+                                           ("rand", flp.FLP_FORMAT_CSR)])
+def test_auto_format_choice(torch, name, want_fmt):
+    """FLP_FORMAT_AUTO (the default) takes the sliced copy unless padding
+    adds more than a quarter to the stored entries (the random matrix's
+    row lengths vary inside a slice); either way the results equal CSR's."""
+    A, alpha, beta, want = case(name)
+    dA = flp.DeviceCsr.from_host(A)
+    auto = flp.flp_solve(dA, alpha, beta, block=8, seed=6, want_vectors=False)
+    csr = flp.flp_solve(dA, alpha, beta, block=8, seed=6, want_vectors=False, format=flp.FLP_FORMAT_CSR)
+    assert auto["stats"]["filter_format"] == want_fmt
+    assert csr["stats"]["filter_format"] == flp.FLP_FORMAT_CSR
+    assert np.array_equal(auto["evals"], csr["evals"])
+    assert auto["count"] == len(want)
+
+
 def test_sell_rejected_in_batched_paths(torch):
     A = I.laplacian_3d(10)
     dA = flp.DeviceCsr.from_host(A)
     with pytest.raises(flp.FlpError):
-        flp.flp_solve(dA, 0.5, 0.9, block=4, format=7)
+        flp.flp_solve(dA, 0.5, 0.9, block=4, format=9)
     lib = flp.load()
     o = flp.default_opts()
     o.block = 4
