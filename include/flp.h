@@ -436,6 +436,12 @@ const char *flp_last_error(void);
 /* Library version string. */
 const char *flp_version(void);
 
+/* Sizes in bytes of the ABI structs, for bindings to check their mirrors:
+ * writes up to cap values to sizes[] in the order flp_csr, flp_opts,
+ * flp_stats, flp_result, flp_tune_info, flp_batch_stats, flp_server_opts
+ * and returns how many there are (7).  Host only; needs no device. */
+int32_t flp_abi_sizes(int64_t *sizes, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -281,4 +281,14 @@ const char *flp_last_error(void) { return last_error_cstr(); }
 
 const char *flp_version(void) { return "flp-mi355x 0.1"; }
 
+int32_t flp_abi_sizes(int64_t *sizes, int32_t cap) {
+    const int64_t s[] = {(int64_t)sizeof(flp_csr),       (int64_t)sizeof(flp_opts),
+                         (int64_t)sizeof(flp_stats),     (int64_t)sizeof(flp_result),
+                         (int64_t)sizeof(flp_tune_info), (int64_t)sizeof(flp_batch_stats),
+                         (int64_t)sizeof(flp_server_opts)};
+    const int32_t n = (int32_t)(sizeof(s) / sizeof(s[0]));
+    for (int32_t i = 0; sizes && i < n && i < cap; ++i) sizes[i] = s[i];
+    return n;
+}
+
 }  // extern "C"

@@ -35,6 +35,7 @@ EXPORTS = [
     "flp_filter_apply", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_sliced", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_set_allocator", "flp_check_symmetric", "flp_last_error", "flp_version",
+    "flp_abi_sizes",
     "flp_server_opts_default", "flp_server_create", "flp_server_submit", "flp_server_poll",
     "flp_server_wait", "flp_server_cancel", "flp_server_stats", "flp_server_destroy",
 ]
@@ -151,6 +152,7 @@ def load(path: str = LIB_PATH):
         "flp_server_destroy": (ctypes.c_int, [P]),
         "flp_last_error": (ctypes.c_char_p, []),
         "flp_version": (ctypes.c_char_p, []),
+        "flp_abi_sizes": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

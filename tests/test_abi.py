@@ -31,6 +31,19 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(flp.EXPORTS)
 
 
+def test_struct_mirrors_match_the_header():
+    """Every ctypes mirror in the binding has the size of its C struct (a
+    short mirror would let the library write past it)."""
+    lib = flp.load()
+    sizes = (ctypes.c_int64 * 16)()
+    n = lib.flp_abi_sizes(sizes, 16)
+    mirrors = [flp.FlpCsrC, flp.FlpOptsC, flp.FlpStatsC, flp.FlpResultC, flp.FlpTuneInfoC, flp.FlpBatchStatsC,
+               flp.FlpServerOptsC]
+    assert n == len(mirrors)
+    for m, s in zip(mirrors, sizes[:n]):
+        assert ctypes.sizeof(m) == s, (m.__name__, ctypes.sizeof(m), s)
+
+
 def test_version():
     assert flp.flp_version().startswith("flp-mi355x")
 
