@@ -108,8 +108,9 @@ typedef struct flp_opts {
                              their longest row, column-major inside a slice; the "other
                              sparse formats" of Section 5), or FLP_FORMAT_AUTO (default):
                              SELL unless padding would add more than 25 % to the stored
-                             entries.  Results are bit-identical either way.  SELL is for
-                             flp_solve only (FLP_E_ARG elsewhere; AUTO means CSR there). */
+                             entries.  Results are bit-identical either way.  The batched
+                             and serving forms take it per solve; flp_solve_sliced keeps CSR
+                             (its slices share A) and refuses SELL with FLP_E_ARG. */
 } flp_opts;
 
 typedef struct flp_stats {

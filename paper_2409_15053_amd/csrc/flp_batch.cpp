@@ -45,9 +45,11 @@ int build_tables(const std::vector<Solve *> &act, Tables &T, hipStream_t s) {
             if (j < 0) continue;
             const ClenshawStep &st = S->plan[j];
             SegEntry e{};
-            e.rowptr = S->A->rowptr;
-            e.colind = S->A->colind;
-            e.val = T.fp32 ? (const void *)S->val32 : (const void *)S->A->val;
+            const flp_csr *fa = S->sell ? &S->SA : S->A;  // the filter's copy of A
+            e.rowptr = fa->rowptr;
+            e.colind = fa->colind;
+            e.val = T.fp32 ? (const void *)(S->sell ? S->sval32 : S->val32) : (const void *)fa->val;
+            e.sell = S->sell ? 1 : 0;
             e.X = st.X;
             e.V = st.V;
             e.Y = st.Y;
@@ -360,8 +362,8 @@ int Engine::step() {
             if (S->A->nnz > big->A->nnz) big = S;
         FilterTune tn;
         void *U[3] = {big->U[0], big->U[1], big->U[2]};
-        CKR(tune_filter(big->A, big->val32, r, T.fp32, false, U,
-                        T.fp32 ? (const void *)big->V32 : (const void *)big->Vin, r, s, &tn));
+        CKR(tune_filter(big->sell ? &big->SA : big->A, big->sell ? big->sval32 : big->val32, r, T.fp32, false, U,
+                        T.fp32 ? (const void *)big->V32 : (const void *)big->Vin, r, s, &tn, big->sell));
         T.sh = tn.sh;
         CKR(build_tables(act, T, s));
         if (use_graph) {
@@ -457,7 +459,6 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
         if (o.block != r || o.prec != prec)
             return fail(FLP_E_ARG, "all solves of a batch need the same block size and precision");
         if (o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos runs through flp_solve only");
-        if (o.format == FLP_FORMAT_SELL) return fail(FLP_E_ARG, "the batched filter reads CSR only");
     }
     CK(hipStreamSynchronize(user));
     Engine E;
@@ -474,7 +475,6 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
         S.alpha = alpha[i];
         S.beta = beta[i];
         S.o = opts ? opts[i] : o0;
-        S.o.format = FLP_FORMAT_CSR;  // the segmented filter reads the CSR arrays
         S.o.stream = nullptr;
         jobs[i] = std::move(j);
     }

@@ -331,11 +331,18 @@ __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restric
     const T *__restrict__ val = (const T *)e.val;
     const T *__restrict__ X = (const T *)e.X;
     const int ldx = e.ldx;
-    const int p0 = rowptr[row], p1 = rowptr[row + 1];
     T acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = T(0);
-    row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
+    if (e.sell) {
+        const int sl = row / kSellC;
+        const int o0 = rowptr[sl], o1 = rowptr[sl + 1];
+        sell_gather<T, VEC, Unroll<T, VEC>::value>(o0 + row % kSellC, (o1 - o0) / kSellC, colind, val, X, ldx, c0,
+                                                   acc);
+    } else {
+        const int p0 = rowptr[row], p1 = rowptr[row + 1];
+        row_gather<T, VEC, Unroll<T, VEC>::value>(p0, p1, colind, val, X, ldx, c0, acc);
+    }
     T xr[VEC];
     load_vec<T, VEC>(X + (int64_t)row * ldx + c0, xr);
     const T alpha = (T)e.alpha, beta = (T)e.beta, gamma = (T)e.gamma, delta = (T)e.delta;

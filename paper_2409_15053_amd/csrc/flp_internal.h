@@ -127,7 +127,7 @@ struct SegEntry {
     int n, tile0;     // rows; first tile of this segment in the launch
     int ldx, ldv, ldy, ldo;
     int out_f64;      // 1: output in FP64 (last step of an FP32 filter)
-    int pad;
+    int sell;         // 1: rowptr / colind / val are a sliced ELL copy (launch_sell_fill)
     double alpha, beta, gamma, delta;
 };
 // rows per tile of the segmented kernel for block width r and value type

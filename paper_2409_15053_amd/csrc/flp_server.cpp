@@ -57,6 +57,8 @@ size_t footprint(const flp_csr &A, const flp_opts &o) {
     b += n * r * 8 * 2;                     // W, Vin
     b += n * r * (fp32 ? 4 : 8) * 3;        // recurrence vectors
     if (fp32) b += n * r * 4 + (A.val32 ? 0 : (size_t)A.nnz * 4);
+    // sliced ELL copy of A (AUTO keeps it within 1.25x the nonzeros)
+    if (o.format != FLP_FORMAT_CSR) b += (size_t)(1.25 * (double)A.nnz + 64.0) * (fp32 ? 8 : 12) + n / 16 + 8;
     b += (2 * cols * r + 4 * r * r + 64) * 8;
     return b;
 }
@@ -234,8 +236,6 @@ int flp_server_submit(flp_server *sv, const flp_csr *A, double alpha, double bet
         flp_opts_default(&S.o);
         if (opts) S.o = *opts;
         if (S.o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos runs through flp_solve only");
-        if (S.o.format == FLP_FORMAT_SELL) return fail(FLP_E_ARG, "the batched filter reads CSR only");
-        S.o.format = FLP_FORMAT_CSR;  // the segmented filter reads the CSR arrays
         S.o.block = sv->o.block;
         S.o.prec = sv->o.prec;
         if (S.o.max_basis <= 0) S.o.max_basis = sv->o.max_basis;

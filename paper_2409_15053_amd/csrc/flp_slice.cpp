@@ -33,7 +33,8 @@ int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, 
     *out = nullptr;
     if (nslices < 1 || nslices > 256) return fail(FLP_E_ARG, "nslices must be in [1, 256]");
     if (o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos runs through flp_solve only");
-    if (o.format == FLP_FORMAT_SELL) return fail(FLP_E_ARG, "the batched filter reads CSR only");
+    if (o.format == FLP_FORMAT_SELL)
+        return fail(FLP_E_ARG, "slices share A's CSR arrays (a sliced ELL copy per slice would repeat it)");
     if (!(std::isfinite(alpha) && std::isfinite(beta)) || !(alpha < beta))
         return fail(FLP_E_ARG, "need finite alpha < beta");
     hipStream_t s = (hipStream_t)o.stream;
@@ -59,6 +60,7 @@ int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, 
         os[i].lmin = lmin;
         os[i].lmax = lmax;
         os[i].seed = o.seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+        os[i].format = FLP_FORMAT_CSR;
     }
     std::vector<flp_result *> res(nslices, nullptr);
     std::vector<int> codes(nslices, FLP_OK);
