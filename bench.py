@@ -496,7 +496,7 @@ def main():
     if args.degree is None:
         args.degree = WORKLOADS[args.workload].get("degree", 150)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "single-GPU benchmark: the solver runs on one GPU, so --gpus must be 1"}), flush=True)
         sys.exit(2)
     import torch
     from paper_2409_15053_amd import flp
