@@ -130,7 +130,8 @@ typedef struct flp_stats {
     double orth_bytes;     /* algorithmic bytes of the reorthogonalisation: the basis
                               (n x k doubles) read twice per Gram-Schmidt pass */
     int32_t filter_format; /* storage the filter read A in: FLP_FORMAT_CSR or FLP_FORMAT_SELL */
-    int32_t filter_group_width;     /* filter launch configuration used: columns per launch, */
+    int32_t filter_group_width;     /* filter launch configuration of a single solve (0 in
+                                       batched and serving results): columns per launch, */
     int32_t filter_lanes_per_row;   /* lanes per matrix row, */
     int32_t filter_cols_per_lane;   /* columns per lane and */
     int32_t filter_streaming_loads; /* nontemporal loads of V and U_{k+2} (1) or not (0) */

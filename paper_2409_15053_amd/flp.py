@@ -408,9 +408,10 @@ def flp_solve_sliced(A: DeviceCsr, alpha: float, beta: float, nslices: int, bloc
 
 
 def _make_opts(block, degree, seed, prec, max_basis, check_every, eps, k0, bounds, stream, start=None,
-               polish_degree=0):
+               polish_degree=0, format=FLP_FORMAT_AUTO):
     o = default_opts()
     o.polish_degree = polish_degree
+    o.format = format
     o.block = block
     o.degree = degree
     o.seed = seed
@@ -449,7 +450,8 @@ def _collect(res_ptr, n, device, want_vectors, stream):
 
 def flp_solve_batch(As, alphas, betas, block: int = 8, degree=0, seeds=None, prec: int = FLP_PREC_FP64,
                     use_graph: bool = True, max_basis: int = 0, check_every: int = 0, eps: float = 0.0,
-                    k0: int = 0, want_vectors: bool = True, stream=None, polish_degree: int = 0):
+                    k0: int = 0, want_vectors: bool = True, stream=None, polish_degree: int = 0,
+                    format: int = FLP_FORMAT_AUTO):
     """Solve len(As) independent problems together (segmented filter
     launches).  Returns (list of per-solve dicts like flp_solve, batch stats)."""
     import torch
@@ -461,7 +463,7 @@ def flp_solve_batch(As, alphas, betas, block: int = 8, degree=0, seeds=None, pre
     opts = (FlpOptsC * cnt)()
     for i in range(cnt):
         opts[i] = _make_opts(block, degrees[i], seeds[i], prec, max_basis, check_every, eps, k0, None, stream,
-                             polish_degree=polish_degree)
+                             polish_degree=polish_degree, format=format)
     arr = (ctypes.POINTER(FlpCsrC) * cnt)(*[ctypes.pointer(A.c) for A in As])
     al = np.ascontiguousarray(alphas, dtype=np.float64)
     be = np.ascontiguousarray(betas, dtype=np.float64)

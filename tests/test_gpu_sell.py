@@ -68,6 +68,26 @@ def test_auto_format_choice(torch, name, want_fmt):
     assert auto["count"] == len(want)
 
 
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER])
+def test_batch_mixing_storages(torch, prec):
+    """A batch whose solves read different storages (AUTO keeps CSR for the
+    random matrix, takes the sliced copy for the stencils): the segmented
+    launches branch per segment and every solve's results equal those of
+    the all-CSR batch, bit for bit."""
+    cases = [case("rand"), case("13pt15"), case("2d40")]
+    dAs = [flp.DeviceCsr.from_host(c[0], with_fp32=True) for c in cases]
+    kw = dict(block=8, seeds=[1, 2, 3], prec=prec, want_vectors=False, degree=40)
+    auto, _ = flp.flp_solve_batch(dAs, [c[1] for c in cases], [c[2] for c in cases], **kw)
+    csr, _ = flp.flp_solve_batch(dAs, [c[1] for c in cases], [c[2] for c in cases], format=flp.FLP_FORMAT_CSR, **kw)
+    assert [r["stats"]["filter_format"] for r in auto] == [flp.FLP_FORMAT_CSR, flp.FLP_FORMAT_SELL,
+                                                         flp.FLP_FORMAT_SELL]
+    for a, c, cs in zip(auto, csr, cases):
+        assert c["stats"]["filter_format"] == flp.FLP_FORMAT_CSR
+        assert np.array_equal(a["evals"], c["evals"]) and np.array_equal(a["resid"], c["resid"])
+        if a["converged"]:
+            assert a["count"] == len(cs[3])
+
+
 def test_sell_rejected_in_batched_paths(torch):
     A = I.laplacian_3d(10)
     dA = flp.DeviceCsr.from_host(A)
