@@ -617,8 +617,13 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
 
 int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int c, const double *X,
                  const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
-                 double *bytes) {
+                 double *bytes, const flp_csr *sellA, const float *sell32) {
     Workspace &w = ws();
+    // the recurrence reads the sliced ELL copy when the solve holds one
+    const bool sell = sellA != nullptr;
+    const int32_t *mrow = sell ? sellA->rowptr : A->rowptr;
+    const int32_t *mcol = sell ? sellA->colind : A->colind;
+    const float *mval = sell ? sell32 : val32;
     const int n = A->n, PW = polish_block_width();
     const int mg = std::max(p->m, 1);  // coefficients of the divided differences
     for (auto &u : w.PU) CK(ensure(u, sizeof(float) * (size_t)n * PW));
@@ -654,12 +659,12 @@ int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int 
         for (int k = mg - 1; k >= 1; --k) {
             float *out = U[next];
             next = (next + 1) % 3;
-            CK(launch_polish_step(n, A->rowptr, A->colind, val32, u1, u2, R, coef + (size_t)k * PW, a2, b2, out, s));
+            CK(launch_polish_step(n, mrow, mcol, mval, u1, u2, R, coef + (size_t)k * PW, a2, b2, out, s, sell));
             u2 = u1;
             u1 = out;
         }
-        CK(launch_polish_last(n, A->rowptr, A->colind, val32, u1, u2, R, coef, a1, b1, Y + j0, ldc, wc, X + j0, ldc,
-                              lp + PW, s));
+        CK(launch_polish_last(n, mrow, mcol, mval, u1, u2, R, coef, a1, b1, Y + j0, ldc, wc, X + j0, ldc, lp + PW, s,
+                              sell));
     }
     if (bytes) {
         // per step: the matrix in FP32 once, the gathered block, U_{k+2},

@@ -195,7 +195,8 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
 // (val32: FP32 copy of A's values).  Returns the algorithmic bytes moved.
 int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int c, const double *X,
                  const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
-                 double *bytes);
+                 double *bytes,
+                 const flp_csr *sellA = nullptr, const float *sell32 = nullptr);
 
 // ---------------------------------------------------------------- dense helpers
 void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, std::vector<int> &bad);

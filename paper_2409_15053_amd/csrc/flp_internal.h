@@ -143,11 +143,11 @@ hipError_t launch_polish_resid(int n, int w, const double *X, const double *AX, 
                                double inv_e, float *R32, hipStream_t s);
 hipError_t launch_polish_step(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
-                              float b, float *out, hipStream_t s);
+                              float b, float *out, hipStream_t s, bool sell = false);
 hipError_t launch_polish_last(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
                               float b, double *Y, int64_t ldy, int w, const double *X, int64_t ldx,
-                              const double *ptheta, hipStream_t s);
+                              const double *ptheta, hipStream_t s, bool sell = false);
 
 // One solve's part of a segmented block step (full reorthogonalisation of
 // the filtered block W against the basis Q, then W = Q_{j+1} S_j by

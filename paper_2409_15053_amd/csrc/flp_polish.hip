@@ -43,8 +43,10 @@ __global__ __launch_bounds__(256) void polish_resid_kernel(int n, int w, const d
 //   out = a (A U1) + b U1 + coef[j] R - U2
 // (U1 == null: the first step, out = coef[j] R; U2 == null: no U2 term).
 // LAST: the final step; it writes Y[:, j] = out_j + ptheta[j] X[:, j] in FP64
-// for the w real columns.
-template <bool LAST>
+// for the w real columns.  SELL: rowptr / colind / val are the sliced ELL
+// copy (slice offsets; entry k of a row at q0 + k * kSellC); its padding adds
+// exact zeros after the row's nonzeros, which it visits in their CSR order.
+template <bool LAST, bool SELL>
 __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *__restrict__ rowptr,
                                                           const int32_t *__restrict__ colind,
                                                           const float *__restrict__ val, const float *U1,
@@ -59,15 +61,26 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
     float acc[PV] = {0.0f, 0.0f, 0.0f, 0.0f};
     float u1[PV] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (U1) {
-        const int p0 = rowptr[row], p1 = rowptr[row + 1];
-        int p = p0;
-        for (; p + 4 <= p1; p += 4) {
+        int base, stride, cnt;  // entry i of the row at base + i * stride
+        if constexpr (SELL) {
+            const int sl = row / kSellC;
+            base = rowptr[sl] + row % kSellC;
+            stride = kSellC;
+            cnt = (rowptr[sl + 1] - rowptr[sl]) / kSellC;
+        } else {
+            base = rowptr[row];
+            stride = 1;
+            cnt = rowptr[row + 1] - base;
+        }
+        int i = 0;
+        for (; i + 4 <= cnt; i += 4) {
             float v[4];
             float4 x[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                v[u] = val[p + u];
-                x[u] = *reinterpret_cast<const float4 *>(U1 + (int64_t)colind[p + u] * PW + c0);
+                const int q = base + (i + u) * stride;
+                v[u] = val[q];
+                x[u] = *reinterpret_cast<const float4 *>(U1 + (int64_t)colind[q] * PW + c0);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -77,9 +90,10 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
                 acc[3] = fmaf(v[u], x[u].w, acc[3]);
             }
         }
-        for (; p < p1; ++p) {
-            const float v = val[p];
-            const float4 x = *reinterpret_cast<const float4 *>(U1 + (int64_t)colind[p] * PW + c0);
+        for (; i < cnt; ++i) {
+            const int q = base + i * stride;
+            const float v = val[q];
+            const float4 x = *reinterpret_cast<const float4 *>(U1 + (int64_t)colind[q] * PW + c0);
             acc[0] = fmaf(v, x.x, acc[0]);
             acc[1] = fmaf(v, x.y, acc[1]);
             acc[2] = fmaf(v, x.z, acc[2]);
@@ -130,19 +144,27 @@ hipError_t launch_polish_resid(int n, int w, const double *X, const double *AX, 
 
 hipError_t launch_polish_step(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
-                              float b, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(polish_step_kernel<false>, dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr, colind,
-                       val32, U1, U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr);
+                              float b, float *out, hipStream_t s, bool sell) {
+    if (sell)
+        hipLaunchKernelGGL((polish_step_kernel<false, true>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
+                           colind, val32, U1, U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr);
+    else
+        hipLaunchKernelGGL((polish_step_kernel<false, false>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
+                           colind, val32, U1, U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_polish_last(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
                               float b, double *Y, int64_t ldy, int w, const double *X, int64_t ldx,
-                              const double *ptheta, hipStream_t s) {
+                              const double *ptheta, hipStream_t s, bool sell) {
     if (w < 1 || w > PW) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(polish_step_kernel<true>, dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr, colind,
-                       val32, U1, U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, ptheta);
+    if (sell)
+        hipLaunchKernelGGL((polish_step_kernel<true, true>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
+                           colind, val32, U1, U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, ptheta);
+    else
+        hipLaunchKernelGGL((polish_step_kernel<true, false>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
+                           colind, val32, U1, U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, ptheta);
     return hipGetLastError();
 }
 

@@ -522,7 +522,8 @@ int solve_finish(Solve &S, flp_result **out) {
                 // recurrences), orthonormalise, Rayleigh-Ritz with A
                 const int c = cur;
                 double pbytes = 0.0;
-                CKR(polish_apply(pf, A, S.val32, c, X, AX, ldc, lam, Y, s, &pbytes));
+                CKR(polish_apply(pf, A, S.val32, c, X, AX, ldc, lam, Y, s, &pbytes, S.sell ? &S.SA : nullptr,
+                                 S.sell ? S.sval32 : nullptr));
                 S.st.filter_bytes += pbytes;
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
