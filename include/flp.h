@@ -108,9 +108,11 @@ typedef struct flp_opts {
                              their longest row, column-major inside a slice; the "other
                              sparse formats" of Section 5), or FLP_FORMAT_AUTO (default):
                              SELL unless padding would add more than 25 % to the stored
-                             entries.  Results are bit-identical either way.  The batched
-                             and serving forms take it per solve; flp_solve_sliced keeps CSR
-                             (its slices share A) and refuses SELL with FLP_E_ARG. */
+                             entries.  Results are bit-identical either way.  Each solve
+                             builds its own copy (device memory about that of A's column
+                             indices and values), also in the batched and serving forms;
+                             flp_solve_sliced keeps CSR (its slices share A) and refuses SELL
+                             with FLP_E_ARG. */
 } flp_opts;
 
 typedef struct flp_stats {
