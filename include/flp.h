@@ -137,6 +137,9 @@ typedef struct flp_stats {
     int32_t filter_lanes_per_row;   /* lanes per matrix row, */
     int32_t filter_cols_per_lane;   /* columns per lane and */
     int32_t filter_streaming_loads; /* nontemporal loads of V and U_{k+2} (1) or not (0) */
+    double polish_bytes;   /* FP32 filter only: algorithmic bytes of the residual-form polish
+                              sweeps (not part of filter_bytes) */
+    double t_polish;       /* seconds: those sweeps' device time (part of t_rr, not of t_mv) */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */
@@ -195,17 +198,32 @@ int32_t flp_filter_divided(const flp_filter *p, double t, double *coeffs, int32_
 /* W = p(Ahat) V, Ahat = (A - cI)/e (eq. transf), by Clenshaw's backward
  * recurrence (Section 2.2) with the affine map and the three-term update
  * fused into each sparse-matrix product: m products with A.
- *   V: DEVICE n x r row-major (ld = r), float64.
- *   W: DEVICE n x r row-major (ld = r), float64; must not alias V.
+ *   V: DEVICE n x r row-major, float64, entry (i, j) at V[i * ldv + j].
+ *   ldv: leading dimension of V, ldv >= r.
+ *   W: DEVICE n x r row-major, float64, entry (i, j) at W[i * ldw + j]; its
+ *      rows must not overlap V's (W != V and no aliasing of the two blocks).
+ *   ldw: leading dimension of W, ldw >= r.  Columns r .. ld-1 of either
+ *      block are neither read nor written.
  *   r: 1 <= r <= 32.
  *   prec: FLP_PREC_FP64, or FLP_PREC_FP32_FILTER (V is rounded to FP32,
  *         the recurrence runs in FP32, W is written in FP64).
+ *   format: storage the products read A in: FLP_FORMAT_CSR (A itself),
+ *         FLP_FORMAT_SELL (a sliced ELL copy of A, the storage flp_solve uses
+ *         by default; the same sums in the same order, so W is bit-identical
+ *         to the CSR result) or FLP_FORMAT_AUTO (SELL unless it would store
+ *         more than 1.25 times A's nonzeros).  The sliced copy is built on
+ *         first use and kept in the calling thread's workspace for later
+ *         calls with the same A (the same device arrays and sizes); a caller
+ *         that changes A's entries in place between calls releases it first
+ *         with flp_release_workspace().  Building it synchronises the stream.
  * Stream-ordered and asynchronous (no host synchronisation unless the
- * workspace must grow, or the launch configuration for this precision, r
- * and matrix size is being tuned; see flp_tune_filter).
- * Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
-int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, double *W,
-                     int32_t r, int32_t prec, void *stream);
+ * workspace must grow, the sliced copy is built, or the launch configuration
+ * for this precision, r and matrix size is being tuned; see
+ * flp_tune_filter).
+ * Errors: FLP_E_ARG (NULL or aliasing blocks, r or ld out of range, bad prec
+ *         or format), FLP_E_NOMEM, FLP_E_DEVICE. */
+int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, int64_t ldv, double *W,
+                     int64_t ldw, int32_t r, int32_t prec, int32_t format, void *stream);
 
 /* Launch configuration of the filter's sparse-matrix step (the Clenshaw
  * step of Section 2.2 as a CSR SpMM over r columns). */
@@ -234,6 +252,16 @@ typedef struct flp_tune_info {
  * reports the choice.  A: as for flp_solve (val32 may be NULL).  Synchronises
  * the stream.  Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
 int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp_tune_info *out);
+
+/* The launch shape a filter step runs with, before any tuning: for one
+ * solve's kernel (segmented = 0) or the batched engine's segmented kernel
+ * (segmented = 1) over a block of r columns (1 <= r <= 32) in precision prec.
+ * Fills group_width (= r), lanes_per_row, cols_per_lane and rows_per_wave;
+ * lanes_per_row * cols_per_lane >= r always, and where it exceeds r the
+ * lanes past column r - 1 have no column and leave the kernel at once.
+ * candidates = 0, us_per_step = 0.  Host only; needs no device.
+ * Errors: FLP_E_ARG. */
+int flp_filter_launch_shape(int32_t r, int32_t prec, int32_t segmented, flp_tune_info *out);
 
 /* on = 1: tune on first use (the default); on = 0: fixed default
  * configuration (16-byte pieces per lane, column groups sized for the

@@ -8,6 +8,7 @@ all device code (-packed-fp32-ops).
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -44,7 +45,7 @@ def build(verbose: bool = False) -> str:
     """Compile every source (always; this is the build check) and link."""
     objdir = os.path.join(ROOT, "_build", "flp")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         cmd = [HIPCC] + COMMON + DEVICE + ["-c", src, "-o", obj]
@@ -52,8 +53,13 @@ def build(verbose: bool = False) -> str:
             cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    # the translation units compile independently: a few at a time
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1), 16))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for fut in [pool.submit(subprocess.run, c, check=True) for c in cmds]:
+            fut.result()
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-pthread"]
     if verbose:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <new>
 #include <string>
@@ -88,15 +89,41 @@ int32_t flp_filter_divided(const flp_filter *p, double t, double *coeffs, int32_
     return (int32_t)c.size();
 }
 
-int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, double *W, int32_t r, int32_t prec,
-                     void *stream) {
+int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, int64_t ldv, double *W, int64_t ldw,
+                     int32_t r, int32_t prec, int32_t format, void *stream) {
     if (!p) return fail(FLP_E_ARG, "filter is NULL");
     CKR(check_csr(A));
     if (r < 1 || r > 32) return fail(FLP_E_ARG, "r must be in [1, 32]");
     if (!V || !W) return fail(FLP_E_ARG, "V and W must be non-NULL");
-    if (V == W) return fail(FLP_E_ARG, "W must not alias V");
+    if (ldv < r || ldw < r || ldv > INT32_MAX || ldw > INT32_MAX)
+        return fail(FLP_E_ARG, "leading dimensions must be in [r, 2^31)");
+    // the blocks' extents: rows 0..n-1, columns 0..r-1
+    const double *vend = V + (size_t)(A->n - 1) * ldv + r;
+    const double *wend = W + (size_t)(A->n - 1) * ldw + r;
+    if (V < wend && W < vend) return fail(FLP_E_ARG, "W must not overlap V");
     if (prec != FLP_PREC_FP64 && prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
-    return filter_apply_impl(p, A, V, r, W, r, r, prec, (hipStream_t)stream);
+    if (format != FLP_FORMAT_AUTO && format != FLP_FORMAT_CSR && format != FLP_FORMAT_SELL)
+        return fail(FLP_E_ARG, "bad storage format");
+    try {
+        return filter_apply_impl(p, A, V, (int)ldv, W, (int)ldw, r, prec, (hipStream_t)stream, format);
+    } catch (const std::bad_alloc &) {
+        return fail(FLP_E_NOMEM, "host allocation failed");
+    }
+}
+
+int flp_filter_launch_shape(int32_t r, int32_t prec, int32_t segmented, flp_tune_info *out) {
+    if (!out) return fail(FLP_E_ARG, "out is NULL");
+    if (r < 1 || r > 32) return fail(FLP_E_ARG, "r must be in [1, 32]");
+    if (prec != FLP_PREC_FP64 && prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
+    const bool fp32 = prec == FLP_PREC_FP32_FILTER;
+    const StepShape sh = segmented ? seg_launch_shape(r, fp32) : step_launch_shape(r, fp32);
+    std::memset(out, 0, sizeof(*out));
+    out->group_width = r;
+    out->lanes_per_row = sh.lpr;
+    out->cols_per_lane = sh.vec;
+    out->rows_per_wave = 64 / sh.lpr;
+    out->streaming_loads = sh.nt;
+    return FLP_OK;
 }
 
 int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp_tune_info *out) {

@@ -225,6 +225,22 @@ bool step_shape_ok(int r, bool fp32, StepShape sh) {
     return sh.lpr > 0 && sh.lpr * sh.vec == r && shape_has_kernel(fp32, sh.lpr, sh.vec);
 }
 
+// One lane per column on the next power of two >= r lanes: the shape for
+// block widths with no aligned kernel (the lanes past column r - 1 leave).
+static StepShape one_column_shape(int r) {
+    const int l = r == 1 ? 1 : (r == 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32))));
+    return StepShape{l, 1};
+}
+
+StepShape step_launch_shape(int r, bool fp32) {
+    const int v16 = fp32 ? 4 : 2;
+    if (r % v16 == 0) {
+        const StepShape d = default_step_shape(r, fp32);
+        if (d.lpr > 0) return d;
+    }
+    return one_column_shape(r);
+}
+
 template <typename T, typename Tout>
 hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
                             const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
@@ -302,8 +318,11 @@ hipError_t launch_sell_fill(int n, const int32_t *rowptr, const int32_t *colind,
 
 namespace {
 
+// Lane `sub` of a row owns columns [sub*VEC, sub*VEC + VEC); when LPR * VEC
+// exceeds the block width r (the one-column-per-lane shapes for r that is
+// not a power of two), lanes past column r - 1 have no column and leave.
 template <typename T, int LPR, int VEC, bool NT>
-__global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg) {
+__global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg, int r) {
     constexpr int RPB = 256 / LPR;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     // The segment holding this tile: the tile offsets ascend, so the
@@ -325,7 +344,7 @@ __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restric
     const int n = e.n;
     const int row = (tile - e.tile0) * RPB + threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * VEC;
-    if (row >= n) return;
+    if (row >= n || c0 >= r) return;
     const int32_t *__restrict__ rowptr = e.rowptr;
     const int32_t *__restrict__ colind = e.colind;
     const T *__restrict__ val = (const T *)e.val;
@@ -379,21 +398,25 @@ static StepShape seg_shape(int r, bool fp32, StepShape sh) {
     if (step_shape_ok(r, fp32, sh)) return sh;
     StepShape d = default_step_shape(r, fp32);
     if (d.lpr > 0) return d;
-    const int l = r == 1 ? 1 : (r == 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32))));
-    return StepShape{l, 1};
+    return one_column_shape(r);
 }
 
 int seg_rows_per_tile(int r, bool fp32, StepShape sh) { return 256 / seg_shape(r, fp32, sh).lpr; }
 
+StepShape seg_launch_shape(int r, bool fp32, StepShape sh) { return seg_shape(r, fp32, sh); }
+
 hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s,
                            StepShape sh) {
     if (nseg <= 0 || total_tiles <= 0) return hipSuccess;
+    if (r < 1 || r > 32) return hipErrorInvalidValue;
     sh = seg_shape(r, fp32, sh);
     const int lpr = sh.lpr, vec = sh.vec;
+    // every column needs a lane (the kernel drops lanes past column r - 1)
+    if (lpr * vec < r) return hipErrorInvalidValue;
     const bool nt = sh.nt != 0;
 #define FLP_SEG_NT(T, LPR, VEC, NT) \
     { \
-        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC, NT>), dim3(total_tiles), dim3(256), 0, s, tab, nseg); \
+        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC, NT>), dim3(total_tiles), dim3(256), 0, s, tab, nseg, r); \
         return hipGetLastError(); \
     }
 #define FLP_SEG(T, LPR, VEC) FLP_SEG_NT(T, LPR, VEC, false)

@@ -260,11 +260,13 @@ hipError_t ensure(Buf &b, size_t bytes) {
 }
 
 void Workspace::release_all() {
-    Buf *all[] = {&U[0], &U[1], &U[2], &V32, &Vg, &val32, &partials, &small, &W, &Vin, &Q, &Y, &AY, &X, &AX,
-                  &resid_part, &PU[0], &PU[1], &PU[2], &PR, &PC};
+    Buf *all[] = {&U[0],   &U[1],   &U[2],       &V32,  &Vg,    &val32,    &partials, &small,
+                  &W,      &Vin,    &Q,          &Y,    &AY,    &X,        &AX,       &resid_part,
+                  &PU[0],  &PU[1],  &PU[2],      &PR,   &PC,    &sell_off, &sell_col, &sell_val};
     for (Buf *b : all) b->release();
     val32_src = nullptr;
     val32_nnz = 0;
+    sell_valid = false;
 }
 
 namespace {
@@ -489,8 +491,8 @@ int launch_plan_step(const flp_csr *A, const float *val32, int r, const Clenshaw
     return FLP_OK;
 }
 
-int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, flp_csr *out, const float **out32,
-               hipStream_t s, double max_pad, bool *built) {
+int build_sell(const flp_csr *A, const float *val32, bool fp32, Buf &boff, Buf &bcol, Buf &bval, flp_csr *out,
+               const float **out32, hipStream_t s, double max_pad, bool *built) {
     *built = false;
     const int n = A->n;
     std::vector<int32_t> rp((size_t)n + 1);
@@ -509,22 +511,22 @@ int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, fl
     off[nsl] = (int32_t)tot;
     if ((double)tot > max_pad * (double)A->nnz + kSellC) return FLP_OK;
     const size_t ents = (size_t)std::max<int64_t>(tot, 1);
-    CK(ensure(B.sell_off, sizeof(int32_t) * ((size_t)nsl + 1)));
-    CK(ensure(B.sell_col, sizeof(int32_t) * ents));
-    CK(ensure(B.sell_val, (fp32 ? sizeof(float) : sizeof(double)) * ents));
-    CK(h2d(B.sell_off.p, off.data(), sizeof(int32_t) * ((size_t)nsl + 1), s));
-    auto *col = (int32_t *)B.sell_col.p;
+    CK(ensure(boff, sizeof(int32_t) * ((size_t)nsl + 1)));
+    CK(ensure(bcol, sizeof(int32_t) * ents));
+    CK(ensure(bval, (fp32 ? sizeof(float) : sizeof(double)) * ents));
+    CK(h2d(boff.p, off.data(), sizeof(int32_t) * ((size_t)nsl + 1), s));
+    auto *col = (int32_t *)bcol.p;
     CK(launch_sell_fill(n, A->rowptr, A->colind, fp32 ? nullptr : A->val, fp32 ? val32 : nullptr,
-                        (const int32_t *)B.sell_off.p, nsl, col, fp32 ? nullptr : (double *)B.sell_val.p,
-                        fp32 ? (float *)B.sell_val.p : nullptr, s));
+                        (const int32_t *)boff.p, nsl, col, fp32 ? nullptr : (double *)bval.p,
+                        fp32 ? (float *)bval.p : nullptr, s));
     CK(hipStreamSynchronize(s));
     *out = *A;
-    out->rowptr = (const int32_t *)B.sell_off.p;
+    out->rowptr = (const int32_t *)boff.p;
     out->colind = col;
     out->nnz = tot;
-    out->val = fp32 ? nullptr : (const double *)B.sell_val.p;
+    out->val = fp32 ? nullptr : (const double *)bval.p;
     out->val32 = nullptr;
-    *out32 = fp32 ? (const float *)B.sell_val.p : nullptr;
+    *out32 = fp32 ? (const float *)bval.p : nullptr;
     *built = true;
     return FLP_OK;
 }
@@ -575,7 +577,7 @@ int filter_group_width(int n, int64_t nnz, int r, int prec) {
 // W = p(Ahat) V with the workspace's Clenshaw buffers (V, W: n x r with
 // leading dimensions ldv, ldw), filtered in column groups.
 int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, int ldv, double *W, int ldw, int r,
-                      int prec, hipStream_t s) {
+                      int prec, hipStream_t s, int format) {
     Workspace &w = ws();
     const int n = A->n;
     const bool fp32 = prec == FLP_PREC_FP32_FILTER;
@@ -592,12 +594,38 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
         vfull = w.V32.p;
         ldfull = r;
     }
+    // the storage the products read: A, or its sliced ELL copy (built once
+    // per matrix and precision, then reused)
+    const flp_csr *fA = A;
+    const float *fv32 = v32;
+    bool sell = false;
+    if (format != FLP_FORMAT_CSR) {
+        const bool same = w.sell_valid && w.sell_fp32 == fp32 && w.sell_src.n == A->n && w.sell_src.nnz == A->nnz &&
+                          w.sell_src.rowptr == A->rowptr && w.sell_src.colind == A->colind &&
+                          w.sell_src.val == A->val && w.sell_src.val32 == v32;
+        if (!same) {
+            w.sell_valid = false;
+            bool built = false;
+            CKR(build_sell(A, v32, fp32, w.sell_off, w.sell_col, w.sell_val, &w.sell_A, &w.sell_val32, s,
+                           format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad, &built));
+            w.sell_src = *A;
+            w.sell_src.val32 = v32;
+            w.sell_fp32 = fp32;
+            w.sell_built = built;
+            w.sell_valid = true;
+        }
+        if (w.sell_built) {
+            sell = true;
+            fA = &w.sell_A;
+            fv32 = w.sell_val32;
+        }
+    }
     FilterTune tn;
-    CKR(tune_filter(A, v32, r, fp32, true, U, vfull, ldfull, s, &tn));
+    CKR(tune_filter(fA, fv32, r, fp32, true, U, vfull, ldfull, s, &tn, sell));
     const int gw = tn.gw;
     if (gw == r) {
         auto plan = clenshaw_plan(p, r, vfull, ldfull, W, ldw, U[0], U[1], U[2], fp32);
-        for (const auto &st : plan) CKR(launch_plan_step(A, v32, r, st, fp32, s, tn.sh));
+        for (const auto &st : plan) CKR(launch_plan_step(fA, fv32, r, st, fp32, s, tn.sh, sell));
         return FLP_OK;
     }
     // Each column group of V (converted to FP32 in that precision) is staged
@@ -610,7 +638,7 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
         else
             CK(launch_copy_block(n, gw, 1.0, V + j0, ldv, plain_mat((double *)w.Vg.p, gw), 0, nullptr, 0, s));
         auto plan = clenshaw_plan(p, gw, w.Vg.p, gw, W + j0, ldw, U[0], U[1], U[2], fp32);
-        for (const auto &st : plan) CKR(launch_plan_step(A, v32, gw, st, fp32, s, tn.sh));
+        for (const auto &st : plan) CKR(launch_plan_step(fA, fv32, gw, st, fp32, s, tn.sh, sell));
     }
     return FLP_OK;
 }

@@ -108,6 +108,13 @@ struct Workspace {
     Buf resid_part;
     const double *val32_src = nullptr;  // val the FP32 copy was made from
     int64_t val32_nnz = 0;
+    // sliced ELL copy of the last matrix flp_filter_apply read in that
+    // storage, with the arrays and precision it was built from
+    Buf sell_off, sell_col, sell_val;
+    flp_csr sell_src{};
+    bool sell_fp32 = false, sell_built = false, sell_valid = false;
+    flp_csr sell_A{};
+    const float *sell_val32 = nullptr;
     void release_all();
 };
 Workspace &ws();
@@ -139,13 +146,13 @@ int filter_group_width(int n, int64_t nnz, int r, int prec);
 int ensure_val32(const flp_csr *A, Buf &buf, const double **src_cache, int64_t *nnz_cache, const float **out,
                  hipStream_t s);
 struct SolveBufs;
-// Sliced ELL copy of A into B.sell_* (FP64 values, or FP32 ones from val32
+// Sliced ELL copy of A into off / col / val (FP64 values, or FP32 ones from val32
 // when fp32): *out describes it (rowptr = slice offsets, nnz = stored
 // entries, val = FP64 values or null), *out32 the FP32 values.  If the copy
 // would store more than max_pad times A's nonzeros nothing is built and
 // *built is false.  Synchronous.
-int build_sell(const flp_csr *A, const float *val32, bool fp32, SolveBufs &B, flp_csr *out, const float **out32,
-               hipStream_t s, double max_pad, bool *built);
+int build_sell(const flp_csr *A, const float *val32, bool fp32, Buf &off, Buf &col, Buf &val, flp_csr *out,
+               const float **out32, hipStream_t s, double max_pad, bool *built);
 
 // One launch of the Clenshaw recurrence (Section 2.2):
 // out = alpha (A X) + beta X + gamma V + delta Y on row-major blocks.
@@ -187,8 +194,10 @@ void force_filter_shape(StepShape sh, int gw);
 
 // W = p(Ahat) V (V, W n x r with leading dimensions) through the
 // workspace's Clenshaw buffers.
+// format: FLP_FORMAT_CSR, _SELL or _AUTO (the sliced copy is cached in the
+// workspace, keyed by A's arrays).
 int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, int ldv, double *W, int ldw, int r,
-                      int prec, hipStream_t s);
+                      int prec, hipStream_t s, int format = FLP_FORMAT_CSR);
 // Y = p(Ahat) X for c Ritz vectors of A (X, AX = A X, Ritz values lam;
 // n x c blocks with leading dimension ldc) by the residual form: X diag(p(t))
 // in FP64 plus the divided-difference recurrences on the residuals in FP32

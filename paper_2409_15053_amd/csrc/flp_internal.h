@@ -132,6 +132,13 @@ struct SegEntry {
 };
 // rows per tile of the segmented kernel for block width r and value type
 int seg_rows_per_tile(int r, bool fp32, StepShape sh = StepShape{});
+// the shape the segmented kernel runs for block width r: sh when it is a
+// supported shape with lpr * vec = r, else the default 16-byte shape, else
+// one column per lane on the next power of two >= r lanes (the lanes past
+// column r - 1 leave at once)
+StepShape seg_launch_shape(int r, bool fp32, StepShape sh = StepShape{});
+// the untuned shape of the single-solve kernel for r columns (aligned blocks)
+StepShape step_launch_shape(int r, bool fp32);
 // One launch over nseg segments (tab: device array sorted by tile0).
 hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int total_tiles, hipStream_t s,
                            StepShape sh = StepShape{});

@@ -151,6 +151,8 @@ int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, 
         st.t_check += r->stats.t_check;
         st.t_rr += r->stats.t_rr;
         st.filter_bytes += r->stats.filter_bytes;
+        st.polish_bytes += r->stats.polish_bytes;
+        st.t_polish += r->stats.t_polish;
         st.orth_bytes += r->stats.orth_bytes;
     }
     st.t_mv = bs.t_filter;  // the slices share the segmented launches

@@ -117,7 +117,7 @@ int solve_setup(Solve &S) {
     }
     S.sell = false;
     if (o.format != FLP_FORMAT_CSR)
-        CKR(build_sell(A, S.val32, fp32, B, &S.SA, &S.sval32, s, o.format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad,
+        CKR(build_sell(A, S.val32, fp32, B.sell_off, B.sell_col, B.sell_val, &S.SA, &S.sval32, s, o.format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad,
                        &S.sell));
     S.st.filter_format = S.sell ? FLP_FORMAT_SELL : FLP_FORMAT_CSR;
     S.plan = clenshaw_plan(S.filt.get(), r, fp32 ? (const void *)S.V32 : (const void *)S.Vin, r, S.W, r, S.U[0],
@@ -522,9 +522,13 @@ int solve_finish(Solve &S, flp_result **out) {
                 // recurrences), orthonormalise, Rayleigh-Ritz with A
                 const int c = cur;
                 double pbytes = 0.0;
+                CK(hipStreamSynchronize(s));  // (already idle: the Rayleigh-Ritz above ends on the host)
+                const double tp = now();
                 CKR(polish_apply(pf, A, S.val32, c, X, AX, ldc, lam, Y, s, &pbytes, S.sell ? &S.SA : nullptr,
                                  S.sell ? S.sval32 : nullptr));
-                S.st.filter_bytes += pbytes;
+                CK(hipStreamSynchronize(s));
+                S.st.t_polish += now() - tp;
+                S.st.polish_bytes += pbytes;
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
                 CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
                 CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));

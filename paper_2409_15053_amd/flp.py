@@ -32,7 +32,7 @@ FLP_FORMAT_SELL = 2
 EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
     "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval", "flp_filter_divided",
-    "flp_filter_apply", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
+    "flp_filter_apply", "flp_filter_launch_shape", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_sliced", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_set_allocator", "flp_check_symmetric", "flp_last_error", "flp_version",
     "flp_abi_sizes",
@@ -75,7 +75,8 @@ class FlpStatsC(ctypes.Structure):
                 ("t_total", ctypes.c_double), ("filter_bytes", ctypes.c_double), ("orth_bytes", ctypes.c_double),
                 ("filter_format", ctypes.c_int32), ("filter_group_width", ctypes.c_int32),
                 ("filter_lanes_per_row", ctypes.c_int32), ("filter_cols_per_lane", ctypes.c_int32),
-                ("filter_streaming_loads", ctypes.c_int32)]
+                ("filter_streaming_loads", ctypes.c_int32), ("polish_bytes", ctypes.c_double),
+                ("t_polish", ctypes.c_double)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
@@ -122,7 +123,8 @@ def load(path: str = LIB_PATH):
         "flp_filter_info": (ctypes.c_int, [P, P]),
         "flp_filter_eval": (ctypes.c_int, [P, P, P, I32]),
         "flp_filter_divided": (I32, [P, F64, P, I32]),
-        "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, P, I32, I32, P]),
+        "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, I64, P, I64, I32, I32, I32, P]),
+        "flp_filter_launch_shape": (ctypes.c_int, [I32, I32, I32, ctypes.POINTER(FlpTuneInfoC)]),
         "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, P, ctypes.POINTER(FlpTuneInfoC)]),
         "flp_set_autotune": (None, [I32]),
         "flp_set_filter_shape": (None, [I32, I32, I32, I32]),
@@ -255,12 +257,29 @@ def flp_build_filter(alpha: float, beta: float, degree: int, lmin: float, lmax: 
     return Filter(h)
 
 
-def flp_filter_apply(filt: Filter, A: DeviceCsr, V, W, prec: int = FLP_PREC_FP64, stream=None):
-    """W = p(Ahat) V on the device (V, W: contiguous float64 n x r tensors)."""
-    assert V.is_contiguous() and W.is_contiguous() and V.dtype == W.dtype
+def flp_filter_apply(filt: Filter, A: DeviceCsr, V, W, prec: int = FLP_PREC_FP64, stream=None,
+                     format: int = FLP_FORMAT_CSR):
+    """W = p(Ahat) V on the device.  V, W: float64 n x r tensors (or
+    vectors) whose rows may be strided (stride(1) == 1); their row strides
+    are passed as the leading dimensions.  ``format`` selects the storage
+    the products read A in (FLP_FORMAT_CSR, FLP_FORMAT_SELL, FLP_FORMAT_AUTO)."""
+    assert V.dtype == W.dtype
     r = 1 if V.dim() == 1 else V.shape[1]
-    _check(load().flp_filter_apply(filt.h, ctypes.byref(A.c), V.data_ptr(), W.data_ptr(), r, prec,
-                                   _stream_ptr(stream)))
+    if V.dim() == 1:
+        assert V.is_contiguous() and W.is_contiguous()
+        ldv = ldw = 1
+    else:
+        assert V.stride(1) == 1 and W.stride(1) == 1
+        ldv, ldw = V.stride(0), W.stride(0)
+    _check(load().flp_filter_apply(filt.h, ctypes.byref(A.c), V.data_ptr(), ldv, W.data_ptr(), ldw, r, prec,
+                                   format, _stream_ptr(stream)))
+
+
+def flp_filter_launch_shape(r: int, prec: int = FLP_PREC_FP64, segmented: bool = False) -> dict:
+    """The untuned launch shape of a filter step over r columns (host only)."""
+    info = FlpTuneInfoC()
+    _check(load().flp_filter_launch_shape(r, prec, 1 if segmented else 0, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in FlpTuneInfoC._fields_}
 
 
 def flp_tune_filter(A: DeviceCsr, r: int, prec: int = FLP_PREC_FP64, stream=None) -> dict:

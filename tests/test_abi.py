@@ -168,3 +168,35 @@ def test_filter_divided_difference(m):
         # the limit at z = t is p'(t)
         dp = np.polynomial.chebyshev.chebval(t, np.polynomial.chebyshev.chebder(b))
         assert abs(np.polynomial.chebyshev.chebval(t, c) - dp) <= 1e-9 * max(1.0, abs(dp))
+
+
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER])
+@pytest.mark.parametrize("segmented", [False, True])
+def test_filter_launch_shape_covers_every_column(prec, segmented):
+    """Lane-to-column mapping of the filter kernels for every block width
+    1..32: lane s of a row owns columns [s*vec, s*vec + vec), so the lanes
+    of a row cover all r columns (lanes * vec >= r); with 16-byte-aligned
+    widths the mapping is exact, otherwise one column per lane on the next
+    power of two, whose lanes past column r - 1 leave the kernel (the
+    guard `c0 >= r` of both kernels)."""
+    v16 = 4 if prec == flp.FLP_PREC_FP32_FILTER else 2
+    for r in range(1, 33):
+        sh = flp.flp_filter_launch_shape(r, prec, segmented)
+        lpr, vec = sh["lanes_per_row"], sh["cols_per_lane"]
+        assert sh["group_width"] == r
+        assert 64 % lpr == 0 and sh["rows_per_wave"] * lpr == 64
+        assert lpr * vec >= r, (r, lpr, vec)
+        owned = [c for s_ in range(lpr) for c in range(s_ * vec, s_ * vec + vec) if c < r]
+        assert owned == list(range(r))  # each column exactly once
+        if lpr * vec > r:
+            assert vec == 1 and lpr == 1 << (r - 1).bit_length()
+        if r % v16 == 0 and r // v16 in (1, 2, 4, 8, 16) and vec > 1:
+            assert lpr * vec == r
+    # the paper's block size 3 (Table 2) and other widths with no aligned shape
+    for r in (3, 5, 6, 7, 9, 12, 15):
+        sh = flp.flp_filter_launch_shape(r, prec, segmented)
+        assert sh["lanes_per_row"] * sh["cols_per_lane"] >= r
+    with pytest.raises(flp.FlpError):
+        flp.flp_filter_launch_shape(0, prec, segmented)
+    with pytest.raises(flp.FlpError):
+        flp.flp_filter_launch_shape(33, prec, segmented)

@@ -210,6 +210,55 @@ def test_filter_apply_errors(torch):
     W = torch.zeros((A.n, 40), dtype=torch.float64, device="cuda:0")
     with pytest.raises(flp.FlpError):
         flp.flp_filter_apply(f, dA, torch.zeros_like(W), W)  # r > 32
+    # interleaved blocks of one buffer overlap even though they share no entry
+    B = torch.zeros((A.n, 4), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(flp.FlpError):
+        flp.flp_filter_apply(f, dA, B[:, 0:2], B[:, 2:4])
+    with pytest.raises(flp.FlpError):
+        flp.flp_filter_apply(f, dA, V, torch.zeros_like(V), format=7)  # unknown storage
+    lib = flp.load()
+    Wd = torch.zeros_like(V)
+    # leading dimensions below r are refused at the boundary
+    rc = lib.flp_filter_apply(f.h, flp.ctypes.byref(dA.c), V.data_ptr(), 1, Wd.data_ptr(), 2, 2,
+                              flp.FLP_PREC_FP64, flp.FLP_FORMAT_CSR, None)
+    assert rc == flp.FLP_E_ARG
+
+
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER])
+@pytest.mark.parametrize("r,ldv,ldw,v0,w0", [(3, 7, 5, 2, 1), (8, 20, 12, 4, 2), (16, 16, 24, 0, 8), (5, 5, 9, 0, 3)])
+def test_filter_apply_strided_and_sliced_storage(torch, prec, r, ldv, ldw, v0, w0):
+    """V and W as column ranges of wider blocks (leading dimensions ldv, ldw),
+    the products on A in CSR and in its sliced ELL copy: the two storages
+    give the same bits, the columns of W outside the range are untouched,
+    and the result is within the parity bound of the oracle's forward
+    recurrence."""
+    A = I.laplacian_3d_13pt(19, I.gaussian_wells(19, 3))  # n = 6859: ragged last slice
+    m = 25
+    f, b, V, lmin, lmax = filter_case(A, -2.5, -0.5, m, r, seed=r * 11 + ldv)
+    dA = flp.DeviceCsr.from_host(A)
+    big = np.full((A.n, ldv), 7.0)
+    big[:, v0:v0 + r] = V
+    Vd = dev(torch, big)
+    outs = {}
+    for fmt in (flp.FLP_FORMAT_CSR, flp.FLP_FORMAT_SELL, flp.FLP_FORMAT_AUTO):
+        Wb = torch.full((A.n, ldw), -3.0, dtype=torch.float64, device="cuda:0")
+        flp.flp_filter_apply(f, dA, Vd[:, v0:v0 + r], Wb[:, w0:w0 + r], prec=prec, format=fmt)
+        outs[fmt] = Wb
+    torch.cuda.synchronize()
+    base = outs[flp.FLP_FORMAT_CSR].cpu().numpy()
+    for fmt, Wb in outs.items():
+        got = Wb.cpu().numpy()
+        assert np.array_equal(got, base), fmt
+        assert np.all(got[:, :w0] == -3.0) and np.all(got[:, w0 + r:] == -3.0)
+    assert np.all(Vd.cpu().numpy() == big)
+    want = O.filter_apply(A, lmin, lmax, b, V)
+    k = max_row_nnz(A)
+    if prec == flp.FLP_PREC_FP64:
+        tol = 2 * m * m * (k + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    else:
+        tol = 2 * m * (k + 4) * U32 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    err = np.max(np.abs(base[:, w0:w0 + r] - want))
+    assert err <= tol, (err, tol)
 
 
 @pytest.mark.parametrize("n,k,r", [(1000, 1, 1), (1000, 7, 3), (5003, 48, 8), (20011, 160, 16), (777, 16, 16),
@@ -290,7 +339,9 @@ def test_bounds_enclose_spectrum(torch, case):
 def test_filter_apply_full_size_lap3d7_100(torch, prec):
     """Full-size filter parity at the benchmark's launch configuration:
     7-point Laplacian on 100^3 + U[0,1) potential (n = 1e6), block 8,
-    degree 100.  Runs the column-grouped (cache-resident) FP64 path."""
+    degree 100, on the sliced ELL copy the solver reads by default (the
+    tuned launches the benchmark times) and on CSR: identical bits, within
+    the bound of the oracle."""
     w = I.workload_c2(100)
     A = w["A"]
     lmin, lmax = O.gershgorin(A)
@@ -299,22 +350,30 @@ def test_filter_apply_full_size_lap3d7_100(torch, prec):
     b = f.coeffs()
     V = I.random_block(A.n, 8, seed=123)
     dA = flp.DeviceCsr.from_host(A, with_fp32=(prec == flp.FLP_PREC_FP32_FILTER))
-    W = torch.empty((A.n, 8), dtype=torch.float64, device="cuda:0")
-    flp.flp_filter_apply(f, dA, dev(torch, V), W, prec=prec)
+    Vd = dev(torch, V)
+    outs = []
+    for fmt in (flp.FLP_FORMAT_SELL, flp.FLP_FORMAT_CSR):
+        W = torch.empty((A.n, 8), dtype=torch.float64, device="cuda:0")
+        flp.flp_filter_apply(f, dA, Vd, W, prec=prec, format=fmt)
+        outs.append(W)
     torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    flp.flp_release_workspace()
     want = O.filter_apply(A, lmin, lmax, b, V)
     k = max_row_nnz(A)
     if prec == flp.FLP_PREC_FP64:
         tol = 2 * m * m * (k + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
     else:
         tol = 2 * m * (k + 4) * U32 * np.sum(np.abs(b)) * np.max(np.abs(V))
-    err = np.max(np.abs(W.cpu().numpy() - want))
+    err = np.max(np.abs(outs[0].cpu().numpy() - want))
     assert err <= tol, (err, tol)
 
 
-def test_filter_apply_full_size_lap3d13_120(torch):
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER])
+def test_filter_apply_full_size_lap3d13_120(torch, prec):
     """Full-size filter parity on the 13-point 120^3 Hamiltonian with 16
-    Gaussian wells (n = 1.728e6, nnz = 2.2e7), block 16, FP64."""
+    Gaussian wells (n = 1.728e6, nnz = 2.2e7), block 16, on the sliced ELL
+    copy and on CSR (identical bits), within the bound of the oracle."""
     w = I.workload_c3(120)
     A = w["A"]
     lmin, lmax = O.gershgorin(A)
@@ -323,10 +382,19 @@ def test_filter_apply_full_size_lap3d13_120(torch):
     b = f.coeffs()
     V = I.random_block(A.n, 16, seed=7)
     dA = flp.DeviceCsr.from_host(A)
-    W = torch.empty((A.n, 16), dtype=torch.float64, device="cuda:0")
-    flp.flp_filter_apply(f, dA, dev(torch, V), W)
+    Vd = dev(torch, V)
+    outs = []
+    for fmt in (flp.FLP_FORMAT_SELL, flp.FLP_FORMAT_CSR):
+        W = torch.empty((A.n, 16), dtype=torch.float64, device="cuda:0")
+        flp.flp_filter_apply(f, dA, Vd, W, prec=prec, format=fmt)
+        outs.append(W)
     torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    flp.flp_release_workspace()
     want = O.filter_apply(A, lmin, lmax, b, V)
-    tol = 2 * m * m * (13 + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
-    err = np.max(np.abs(W.cpu().numpy() - want))
+    if prec == flp.FLP_PREC_FP64:
+        tol = 2 * m * m * (13 + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    else:
+        tol = 2 * m * (13 + 4) * U32 * np.sum(np.abs(b)) * np.max(np.abs(V))
+    err = np.max(np.abs(outs[0].cpu().numpy() - want))
     assert err <= tol, (err, tol)

@@ -1,0 +1,106 @@
+"""Block sizes with no 16-byte-aligned filter shape (the paper's r = 3 of
+Table 2, and 5, 6, 12): the segmented filter then runs one column per lane
+on the next power of two of lanes, and the lanes past column r - 1 must
+leave without touching the row-major blocks.  The batched, sliced and
+served forms are checked against the dense definition (exact count,
+eigenvalues within 1e-10 relative, residuals <= 1e-9) and against each
+problem solved alone (same count, eigenvalues within 1e-10 relative), in
+both filter precisions."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import flp_oracle as O
+from paper_2409_15053_amd import flp
+from paper_2409_15053_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [3, 5, 6, 12]
+PRECS = [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible MI355X"
+    flp.load()
+    return t
+
+
+def family(grids, seed0, counts):
+    """3D 7-point Laplacian + U[0,1) potential; low-end intervals holding
+    counts[i] eigenvalues with endpoints at gap midpoints."""
+    out = []
+    for i, (N, cnt) in enumerate(zip(grids, counts)):
+        A = I.laplacian_3d(N, I.uniform_potential(N, seed0 + i))
+        lam = np.linalg.eigvalsh(A.to_dense())
+        out.append((A, lam[0] - 0.5, 0.5 * (lam[cnt - 1] + lam[cnt])))
+    return out
+
+
+def check_dense(r, A, alpha, beta):
+    want, _ = O.dense_eigs_in_interval(A, alpha, beta)
+    assert r["converged"]
+    assert r["count"] == len(want)
+    assert np.max(np.abs(np.sort(r["evals"]) - want) / np.abs(want)) <= 1e-10
+    assert np.max(r["resid"]) <= 1e-9
+
+
+def check_alone(dA, alpha, beta, r, block, seed, prec, **kw):
+    alone = flp.flp_solve(dA, alpha, beta, block=block, seed=seed, prec=prec, want_vectors=False, **kw)
+    assert alone["count"] == r["count"]
+    assert np.max(np.abs(alone["evals"] - r["evals"]) / np.abs(r["evals"])) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("block", BLOCKS)
+def test_batch_odd_block(torch, block, prec):
+    cases = family([8, 10, 11, 12], 6100 + block, [10, 16, 21, 27])
+    dAs = [flp.DeviceCsr.from_host(A, with_fp32=True) for A, *_ in cases]
+    seeds = [31 + i for i in range(len(cases))]
+    print(f"batch block={block} prec={prec}", flush=True)
+    res, st = flp.flp_solve_batch(dAs, [c[1] for c in cases], [c[2] for c in cases], block=block, seeds=seeds,
+                                  prec=prec, want_vectors=False)
+    assert st["block_steps"] > 0
+    for i, (A, alpha, beta) in enumerate(cases):
+        check_dense(res[i], A, alpha, beta)
+        check_alone(dAs[i], alpha, beta, res[i], block, seeds[i], prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("block", BLOCKS)
+def test_sliced_odd_block(torch, block, prec):
+    A = I.laplacian_3d(12, I.uniform_potential(12, 6200 + block))
+    lam = np.linalg.eigvalsh(A.to_dense())
+    alpha, beta = lam[0] - 0.5, 0.5 * (lam[39] + lam[40])
+    dA = flp.DeviceCsr.from_host(A, with_fp32=True)
+    print(f"sliced block={block} prec={prec}", flush=True)
+    res = flp.flp_solve_sliced(dA, alpha, beta, 3, block=block, seed=8, prec=prec, want_vectors=False)
+    check_dense(res, A, alpha, beta)
+    whole = flp.flp_solve(dA, alpha, beta, block=block, seed=8, prec=prec, want_vectors=False)
+    assert whole["count"] == res["count"]
+    assert np.max(np.abs(whole["evals"] - res["evals"]) / np.abs(res["evals"])) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("block", BLOCKS)
+def test_server_odd_block(torch, block, prec):
+    cases = family([9, 10, 11, 12, 9], 6300 + block, [12, 15, 18, 24, 20])
+    dAs = [flp.DeviceCsr.from_host(A, with_fp32=True) for A, *_ in cases]
+    print(f"server block={block} prec={prec}", flush=True)
+    sv = flp.Server(block=block, prec=prec, max_active=3)
+    tickets = []
+    try:
+        for i in range(3):
+            tickets.append(sv.submit(dAs[i], cases[i][1], cases[i][2], seed=50 + i))
+        time.sleep(0.02)
+        for i in range(3, len(cases)):
+            tickets.append(sv.submit(dAs[i], cases[i][1], cases[i][2], seed=50 + i))
+        got = [sv.wait(t) for t in tickets]
+    finally:
+        sv.close()
+    for i, (A, alpha, beta) in enumerate(cases):
+        check_dense(got[i], A, alpha, beta)
+        check_alone(dAs[i], alpha, beta, got[i], block, 50 + i, prec, max_basis=1024)

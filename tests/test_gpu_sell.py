@@ -47,9 +47,9 @@ def test_sell_solve_matches_csr(torch, name, block, prec):
     assert sell["stats"]["iters"] == csr["stats"]["iters"]
     assert np.array_equal(sell["evals"], csr["evals"])
     assert np.array_equal(sell["resid"], csr["resid"])
-    if csr["converged"]:
-        assert sell["count"] == len(want)
-        assert np.max(np.abs(np.sort(sell["evals"]) - want) / np.abs(want)) <= 1e-10
+    assert csr["converged"] and sell["converged"]
+    assert sell["count"] == len(want)
+    assert np.max(np.abs(np.sort(sell["evals"]) - want) / np.abs(want)) <= 1e-10
 
 
 @pytest.mark.parametrize("name,want_fmt", [("13pt15", flp.FLP_FORMAT_SELL), ("2d40", flp.FLP_FORMAT_SELL),
@@ -84,8 +84,8 @@ def test_batch_mixing_storages(torch, prec):
     for a, c, cs in zip(auto, csr, cases):
         assert c["stats"]["filter_format"] == flp.FLP_FORMAT_CSR
         assert np.array_equal(a["evals"], c["evals"]) and np.array_equal(a["resid"], c["resid"])
-        if a["converged"]:
-            assert a["count"] == len(cs[3])
+        assert a["converged"] and c["converged"]
+        assert a["count"] == len(cs[3])
 
 
 def test_sell_rejected_in_batched_paths(torch):
