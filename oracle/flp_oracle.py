@@ -271,30 +271,58 @@ class OracleResult:
     basis_cols: int
     times: dict
     converged: bool
+    repairs: int = 0  # basis columns the block QR replaced (rank-deficient blocks)
 
 
 def _block_qr(W: np.ndarray, Qb: np.ndarray, g: np.random.Generator):
     """W = Q_{j+1} S_j with S_j upper triangular, diag >= 0 (eq. lanczos).
 
-    A column whose diagonal falls below 1e-10 times the block's norm is
-    replaced by a random vector orthogonalised against the basis; its row of
-    S_j is set to zero.
+    Returns (Q_{j+1}, S_j, number of replaced columns).  When the
+    Householder QR leaves a diagonal entry at or below 1e-10 times the
+    block's norm, the block is numerically rank deficient: it is then
+    factorised again one column at a time (Gram-Schmidt, each projection
+    taken twice), and a column whose remainder after projection on the
+    columns before it is at or below that threshold is replaced by a random
+    vector orthogonalised against the basis and those columns, with zero
+    diagonal in S_j.  The columns after it are projected on the replacement
+    too, so W = Q_{j+1} S_j keeps holding up to the dropped remainders
+    (each at most the threshold) and Q_{j+1} stays orthonormal and
+    orthogonal to the basis: the block keeps its width r (the reading of
+    the paper's block Lanczos with a fixed block size).
     """
     nrm = np.linalg.norm(W)
+    thr = 1e-10 * max(nrm, 1e-300)
     Qn, S = np.linalg.qr(W)
     sgn = np.sign(np.diag(S))
     sgn[sgn == 0] = 1.0
     Qn = Qn * sgn
     S = sgn[:, None] * S
-    bad = np.nonzero(np.abs(np.diag(S)) <= 1e-10 * max(nrm, 1e-300))[0]
-    for i in bad:
-        v = g.standard_normal(W.shape[0])
-        others = np.concatenate([Qb, np.delete(Qn, i, axis=1)], axis=1)
+    if np.all(np.abs(np.diag(S)) > thr):
+        return Qn, S, 0
+    n, r = W.shape
+    Qn = np.zeros((n, r))
+    S = np.zeros((r, r))
+    replaced = 0
+    for j in range(r):
+        w = W[:, j].copy()
+        for _ in range(2):
+            h = Qn[:, :j].T @ w
+            w -= Qn[:, :j] @ h
+            S[:j, j] += h
+        d = np.linalg.norm(w)
+        if d > thr:
+            Qn[:, j] = w / d
+            S[j, j] = d
+            continue
+        # dependent column: a random direction orthogonal to everything so far
+        v = g.standard_normal(n)
+        others = np.concatenate([Qb, Qn[:, :j]], axis=1)
         for _ in range(2):
             v -= others @ (others.T @ v)
-        Qn[:, i] = v / np.linalg.norm(v)
-        S[i, :] = 0.0
-    return Qn, S
+        Qn[:, j] = v / np.linalg.norm(v)
+        S[j, j] = 0.0
+        replaced += 1
+    return Qn, S, replaced
 
 
 def assemble_T(D: list, S: list) -> np.ndarray:
@@ -311,14 +339,17 @@ def assemble_T(D: list, S: list) -> np.ndarray:
     return T
 
 
-def lanczos_step(A, lmin, lmax, coeffs, Qk: np.ndarray, r: int, g: np.random.Generator):
+def lanczos_step(A, lmin, lmax, coeffs, Qk: np.ndarray, r: int, g: np.random.Generator,
+                 tally: dict | None = None):
     """One block step of FLP (Section 2.3, eq. lanczos; Section 3.2.2).
 
     Qk (n x k) holds the basis so far; its last r columns are Q_j.
     W = p(A) Q_j; full reorthogonalisation of W against every column of Qk
     (classical Gram-Schmidt, two passes); D_j = symmetric part of the
     Q_j^T p(A) Q_j block of the projection; W = Q_{j+1} S_j.
-    Returns (D_j, S_j, Q_{j+1}, seconds in the filter, seconds in ORTH).
+    Returns (D_j, S_j, Q_{j+1}, seconds in the filter, seconds in ORTH);
+    ``tally["repairs"]`` (when given) counts the columns the block QR
+    replaced.
     """
     t1 = time.perf_counter()
     W = filter_apply(A, lmin, lmax, coeffs, Qk[:, -r:])
@@ -330,7 +361,9 @@ def lanczos_step(A, lmin, lmax, coeffs, Qk: np.ndarray, r: int, g: np.random.Gen
     W = W - Qk @ H2
     Hj = (H1 + H2)[-r:, :]
     Dj = 0.5 * (Hj + Hj.T)
-    Qn, Sj = _block_qr(W, Qk, g)
+    Qn, Sj, replaced = _block_qr(W, Qk, g)
+    if tally is not None:
+        tally["repairs"] = tally.get("repairs", 0) + replaced
     return Dj, Sj, Qn, t_mv, time.perf_counter() - t1
 
 
@@ -409,8 +442,9 @@ def flp_solve(A, alpha: float, beta: float, block: int = 1, degree: int = 0,
     converged = False
     steps = 0
     sel = None
+    tally = {"repairs": 0}
     while steps < max_steps:
-        Dj, Sj, Qn, dt_mv, dt_orth = lanczos_step(A, lmin, lmax, coeffs, basis.view(), r, g)
+        Dj, Sj, Qn, dt_mv, dt_orth = lanczos_step(A, lmin, lmax, coeffs, basis.view(), r, g, tally)
         D.append(Dj)
         S.append(Sj)
         t_mv += dt_mv
@@ -456,7 +490,7 @@ def flp_solve(A, alpha: float, beta: float, block: int = 1, degree: int = 0,
     times["total"] = time.perf_counter() - t0
     return OracleResult(evals=evals, evecs=X, resid=res, lmin=lmin, lmax=lmax, degree=m,
                         iters=steps, mv=r * m * steps, basis_cols=Qb.shape[1], times=times,
-                        converged=converged)
+                        converged=converged, repairs=tally["repairs"])
 
 
 # ------------------------------------------------------------ definition for tiny n

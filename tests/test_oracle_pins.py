@@ -340,3 +340,176 @@ def test_planted_single_pass_gram_schmidt_dropped_block_is_caught():
         return 0.5 * (H + H.T), S, Qn, 0.0, 0.0
     orth, rel = lanczos_relation_errors(wrong)
     assert orth > 1e-8 or rel > 1e-8
+
+
+# ----------------------------------------------------------------- block QR of dependent blocks (eq. lanczos)
+
+def _basis_and_blocks(seed=0, n=300):
+    """An orthonormal basis Qb and blocks orthogonal to it whose columns are
+    numerically dependent: a repeated (scaled) column followed by
+    independent ones, a column inside the span of the others up to 1e-14,
+    and the zero block."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    Qb, _ = np.linalg.qr(g.standard_normal((n, 20)))
+
+    def off_basis(X):
+        for _ in range(2):
+            X = X - Qb @ (Qb.T @ X)
+        return X
+
+    W1 = off_basis(g.standard_normal((n, 4)))
+    W1[:, 1] = 2.0 * W1[:, 0]
+    W2 = off_basis(g.standard_normal((n, 5)))
+    W2[:, 2] = W2[:, 0] - 3.0 * W2[:, 1] + 1e-14 * W2[:, 3]
+    return Qb, [W1, W2, np.zeros((n, 3))]
+
+
+def block_qr_errors(qr_fn, seed=0):
+    """Worst deviations over the dependent blocks: Q^T Q - I, Qb^T Q, the
+    relation W = Q S relative to ||W|| (eq. lanczos), the strict lower
+    triangle of S and a negative diagonal; plus the columns replaced."""
+    Qb, blocks = _basis_and_blocks(seed)
+    worst = dict(orth=0.0, basis=0.0, rel=0.0, tri=0.0, negdiag=0.0, replaced=0)
+    for W in blocks:
+        Qn, S, rep = qr_fn(W.copy(), Qb, np.random.Generator(np.random.PCG64(seed + 1)))
+        r = W.shape[1]
+        worst["orth"] = max(worst["orth"], float(np.max(np.abs(Qn.T @ Qn - np.eye(r)))))
+        worst["basis"] = max(worst["basis"], float(np.max(np.abs(Qb.T @ Qn))))
+        worst["rel"] = max(worst["rel"], float(np.max(np.abs(W - Qn @ S))) / max(np.linalg.norm(W), 1.0))
+        worst["tri"] = max(worst["tri"], float(np.max(np.abs(np.tril(S, -1)))))
+        worst["negdiag"] = max(worst["negdiag"], float(-np.min(np.diag(S))))
+        worst["replaced"] += rep
+    return worst
+
+
+def test_block_qr_repairs_dependent_columns():
+    """The dependent-column repair keeps the block orthonormal, orthogonal
+    to the basis, upper triangular with a non-negative diagonal, and keeps
+    W = Q_{j+1} S_j up to the dropped remainders (1e-10 of ||W||)."""
+    e = block_qr_errors(O._block_qr)
+    assert e["replaced"] == 1 + 1 + 3
+    assert e["orth"] < 1e-13 and e["basis"] < 1e-13
+    assert e["rel"] < 1e-10
+    assert e["tri"] == 0.0 and e["negdiag"] <= 0.0
+
+
+def _planted_zero_row(W, Qb, g):
+    # Householder QR, each dependent q_i swapped for a random vector and its
+    # whole row of S zeroed: the later columns lose their q_i components
+    Qn, S = np.linalg.qr(W)
+    sg = np.sign(np.diag(S))
+    sg[sg == 0] = 1.0
+    Qn, S = Qn * sg, sg[:, None] * S
+    bad = np.nonzero(np.abs(np.diag(S)) <= 1e-10 * max(np.linalg.norm(W), 1e-300))[0]
+    for i in bad:
+        v = g.standard_normal(W.shape[0])
+        others = np.concatenate([Qb, np.delete(Qn, i, axis=1)], axis=1)
+        for _ in range(2):
+            v -= others @ (others.T @ v)
+        Qn[:, i] = v / np.linalg.norm(v)
+        S[i, :] = 0.0
+    return Qn, S, len(bad)
+
+
+def _planted_unorthogonalised_replacement(W, Qb, g):
+    # the column-by-column repair with the random replacement left as drawn
+    n, r = W.shape
+    thr = 1e-10 * max(np.linalg.norm(W), 1e-300)
+    Qn, S, rep = np.zeros((n, r)), np.zeros((r, r)), 0
+    for j in range(r):
+        w = W[:, j].copy()
+        for _ in range(2):
+            h = Qn[:, :j].T @ w
+            w -= Qn[:, :j] @ h
+            S[:j, j] += h
+        d = np.linalg.norm(w)
+        if d > thr:
+            Qn[:, j], S[j, j] = w / d, d
+        else:
+            v = g.standard_normal(n)
+            Qn[:, j], rep = v / np.linalg.norm(v), rep + 1
+    return Qn, S, rep
+
+
+def test_planted_block_qr_repair_mistakes_are_caught():
+    e = block_qr_errors(_planted_zero_row)
+    assert e["rel"] > 1e-3
+    e = block_qr_errors(_planted_unorthogonalised_replacement)
+    assert e["orth"] > 1e-3 or e["basis"] > 1e-3
+
+
+def _eigvec_start(N=20, r=4, col=1, seed=3):
+    """2D Laplacian on an N x N grid and a start block whose column `col` is
+    the exact eigenvector sin(2 pi x/(N+1)) sin(2 pi y/(N+1)) (eigenvalue
+    8 sin^2(pi/(N+1)), symmetric in x and y, so the grid ordering does not
+    matter).  The filter maps that column into the span of the start block:
+    the first filtered block is numerically rank deficient in its column
+    `col`, with independent columns after it."""
+    A = I.laplacian_2d(N)
+    s = np.sin(2 * math.pi * np.arange(1, N + 1) / (N + 1))
+    u = np.outer(s, s).ravel()
+    u /= np.linalg.norm(u)
+    assert np.linalg.norm(A.to_scipy() @ u - 8 * math.sin(math.pi / (N + 1)) ** 2 * u) < 1e-14
+    g = np.random.Generator(np.random.PCG64(seed))
+    start = g.standard_normal((A.n, r))
+    start[:, col] = u
+    return A, start
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.1, 0.3), (0.5, 1.0)])
+def test_solve_through_block_qr_repair(alpha, beta):
+    """A solve that goes through the repair (the eigenvector's own
+    eigenvalue 0.1776 inside the first interval, outside the second): the
+    exact count and eigenvalues against dense eigh."""
+    A, start = _eigvec_start()
+    res = O.flp_solve(A, alpha, beta, block=4, seed=4, start=start)
+    assert res.repairs >= 1
+    assert res.converged
+    want, _ = O.dense_eigs_in_interval(A, alpha, beta)
+    assert len(res.evals) == len(want) > 0
+    assert np.max(np.abs(np.sort(res.evals) - want)) < 1e-12
+    assert np.max(res.resid) < 1e-12
+    X = res.evecs
+    assert np.max(np.abs(X.T @ X - np.eye(len(want)))) < 1e-12
+
+
+def repaired_run_errors():
+    """Block Lanczos steps from _eigvec_start's block: (columns replaced,
+    S_1's repaired row, ||Q^T Q - I||, ||p(Ahat) Q_k - Q_{k+1} T~_k||)."""
+    A, start = _eigvec_start()
+    lmin, lmax = O.gershgorin(A)
+    c, e = O.affine_map(lmin, lmax)
+    coeffs = O.cheb_coeffs((0.1 - c) / e, (0.3 - c) / e, 40)
+    g = np.random.Generator(np.random.PCG64(4))
+    r, steps = 4, 8
+    Q = [O.orthonormal_start(start)]
+    D, S = [], []
+    tally = {"repairs": 0}
+    for _ in range(steps):
+        Dj, Sj, Qn, _, _ = O.lanczos_step(A, lmin, lmax, coeffs, np.concatenate(Q, axis=1), r, g, tally)
+        D.append(Dj)
+        S.append(Sj)
+        Q.append(Qn)
+    Qk = np.concatenate(Q[:-1], axis=1)
+    Qk1 = np.concatenate(Q, axis=1)
+    T = O.assemble_T(D, S)
+    Tt = np.vstack([T, np.hstack([np.zeros((r, (steps - 1) * r)), S[-1]])])
+    PQ = O.filter_apply(A, lmin, lmax, coeffs, Qk)
+    return (tally["repairs"], S[0][1], float(np.max(np.abs(Qk1.T @ Qk1 - np.eye(Qk1.shape[1])))),
+            float(np.max(np.abs(PQ - Qk1 @ Tt))))
+
+
+def test_lanczos_relation_through_block_qr_repair():
+    """eq. lanczos, p(Ahat) Q_k = Q_{k+1} T~_k, and orthonormality hold over
+    a run whose first block was repaired in a middle column."""
+    repairs, row, orth, rel = repaired_run_errors()
+    assert repairs >= 1
+    assert row[1] == 0.0 and np.any(row[2:] != 0.0)  # the repaired row still couples the later columns
+    assert orth < 1e-12
+    assert rel < 1e-12
+
+
+def test_planted_zero_row_repair_breaks_the_lanczos_relation(monkeypatch):
+    monkeypatch.setattr(O, "_block_qr", _planted_zero_row)
+    repairs, row, orth, rel = repaired_run_errors()
+    assert repairs >= 1 and rel > 1e-6
