@@ -136,7 +136,8 @@ typedef struct flp_stats {
                                        batched and serving results): columns per launch, */
     int32_t filter_lanes_per_row;   /* lanes per matrix row, */
     int32_t filter_cols_per_lane;   /* columns per lane and */
-    int32_t filter_streaming_loads; /* nontemporal loads of V and U_{k+2} (1) or not (0) */
+    int32_t filter_streaming_loads; /* nontemporal loads of V and U_{k+2} (1) or not (0) and */
+    int32_t filter_tile_chunk;      /* the tile-to-XCD mapping (flp_tune_info.tile_chunk) */
     double polish_bytes;   /* FP32 filter only: algorithmic bytes of the residual-form polish
                               sweeps (not part of filter_bytes) */
     double t_polish;       /* seconds: those sweeps' device time (part of t_rr, not of t_mv) */
@@ -235,6 +236,8 @@ typedef struct flp_tune_info {
     int32_t candidates;    /* configurations timed (0: default or forced, not timed) */
     int32_t streaming_loads; /* 1: V and U_{k+2} are read with nontemporal loads */
     double us_per_step;    /* measured microseconds of one step over all r columns (0 if not timed) */
+    int32_t tile_chunk;    /* tile-to-XCD mapping: 0 = one contiguous range of row tiles per XCD;
+                              c > 0 = chunks of c consecutive row tiles dealt to the 8 XCDs in turn */
 } flp_tune_info;
 
 /* Autotuner.  The first time a (device, precision, r, size class)
@@ -269,12 +272,13 @@ int flp_filter_launch_shape(int32_t r, int32_t prec, int32_t segmented, flp_tune
 void flp_set_autotune(int32_t on);
 
 /* Forces one configuration for every later filter launch (testing and
- * measurement); lanes_per_row = 0 and group_width = 0 restore tuning.  A
- * shape with no kernel for a given width falls back to the default shape;
- * a group width that does not divide r is ignored; streaming_loads = 1
- * reads V and U_{k+2} with nontemporal loads. */
+ * measurement); lanes_per_row = 0, group_width = 0 and tile_chunk < 0
+ * restore tuning.  A shape with no kernel for a given width falls back to
+ * the default shape (keeping tile_chunk); a group width that does not
+ * divide r is ignored; streaming_loads = 1 reads V and U_{k+2} with
+ * nontemporal loads; tile_chunk as in flp_tune_info (>= 0 forces it). */
 void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
-                          int32_t streaming_loads);
+                          int32_t streaming_loads, int32_t tile_chunk);
 
 /* Y = A X (plain CSR SpMM, Section 3.2.1).  X, Y: DEVICE n x r row-major
  * with leading dimensions ldx, ldy >= r; 1 <= r <= 32; FP64.  Async. */

@@ -154,6 +154,7 @@ int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp
         out->candidates = tn.candidates;
         out->streaming_loads = sh.lpr > 0 ? sh.nt : 0;
         out->us_per_step = tn.candidates > 0 ? tn.us_per_step : 0.0;
+        out->tile_chunk = tn.sh.chunk;
         return FLP_OK;
     } catch (const std::bad_alloc &) {
         return fail(FLP_E_NOMEM, "host allocation failed");
@@ -163,10 +164,10 @@ int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp
 void flp_set_autotune(int32_t on) { set_autotune(on); }
 
 void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
-                          int32_t streaming_loads) {
+                          int32_t streaming_loads, int32_t tile_chunk) {
     force_filter_shape(StepShape{std::max(0, (int)lanes_per_row), std::max(0, (int)cols_per_lane),
-                                 streaming_loads ? 1 : 0},
-                       std::max(0, (int)group_width));
+                                 streaming_loads ? 1 : 0, std::max(0, (int)tile_chunk)},
+                       std::max(0, (int)group_width), tile_chunk >= 0);
 }
 
 int flp_spmm(const flp_csr *A, const double *X, int32_t ldx, double *Y, int32_t ldy, int32_t r, void *stream) {

@@ -21,6 +21,23 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return (x < rem) ? x * (q + 1) + s : rem * (q + 1) + (x - rem) * q + s;
 }
 
+// chunk <= 0: xcd_tile (one contiguous range of tiles per XCD).  chunk > 0:
+// the tiles are cut into chunks of `chunk` consecutive tiles dealt to the
+// XCDs in turn (chunk q on XCD q % 8).  Blocks dispatched together then
+// cover one contiguous stretch of rows on all XCDs at once, so rows far
+// apart in a row's neighbour list (a 3D grid's +-plane neighbours) are
+// gathered while still in the shared Infinity Cache, and rows up to a
+// chunk apart share an XCD's L2.  The last G mod (8 chunk) tiles keep
+// block order.  Bijective on [0, G).
+__device__ __forceinline__ int chunk_tile(int b, int G, int chunk) {
+    if (chunk <= 0) return xcd_tile(b, G);
+    const int span = NXCD * chunk;
+    const int full = (G / span) * span;
+    if (b >= full) return b;
+    const int x = b % NXCD, s = b / NXCD;
+    return (s / chunk) * span + x * chunk + s % chunk;
+}
+
 template <typename T, int VEC>
 struct Vec;
 template <>

@@ -102,9 +102,9 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
     int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
     const T *__restrict__ val, int r, const T *__restrict__ X, int ldx, const T *__restrict__ V,
     int ldv, const T *__restrict__ Y, int ldy, Tout *__restrict__ out, int ldo, T alpha, T beta,
-    T gamma, T delta) {
+    T gamma, T delta, int chunk) {
     constexpr int RPB = 256 / LPR;  // rows per block
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, chunk);
     const int row = tile * RPB + threadIdx.x / LPR;
     const int sub = threadIdx.x % LPR;
     const int c0 = sub * VEC;
@@ -152,15 +152,16 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
 template <typename T, typename Tout, int LPR, int VEC, bool NT>
 hipError_t cheb_launch(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r,
                        const T *X, int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out,
-                       int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s, bool sell) {
+                       int ldo, T alpha, T beta, T gamma, T delta, hipStream_t s, bool sell, int chunk) {
     constexpr int RPB = 256 / LPR;
     int grid = (n + RPB - 1) / RPB;
     if (sell)
         hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT, true>), dim3(grid), dim3(256), 0, s, n, rowptr,
-                           colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
+                           colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, chunk);
     else
         hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT, false>), dim3(grid), dim3(256), 0, s, n,
-                           rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta);
+                           rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta,
+                           chunk);
     return hipGetLastError();
 }
 
@@ -253,10 +254,14 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
     bool aligned16 = (ldx % V16 == 0) && (!V || ldv % V16 == 0) && (!Y || ldy % V16 == 0) &&
                      (ldo % V16 == 0) && (sizeof(Tout) == sizeof(T)) && al(X) && al(V) && al(Y) && al(out);
 #define FLP_CHEB_NT(LPR, VEC, NT) \
-    return cheb_launch<T, Tout, LPR, VEC, NT>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s, sell)
+    return cheb_launch<T, Tout, LPR, VEC, NT>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s, sell, sh.chunk)
 #define FLP_CHEB(LPR, VEC) FLP_CHEB_NT(LPR, VEC, false)
     if (aligned16 && r % V16 == 0) {
-        if (!step_shape_ok(r, F32, sh)) sh = default_step_shape(r, F32);
+        if (!step_shape_ok(r, F32, sh)) {
+            const int chunk = sh.chunk;
+            sh = default_step_shape(r, F32);
+            sh.chunk = chunk;
+        }
         const int lpr = sh.lpr, vec = sh.vec;
         const bool nt = sh.nt != 0;
 #define FLP_TRY(L, VV) \
@@ -322,9 +327,10 @@ namespace {
 // exceeds the block width r (the one-column-per-lane shapes for r that is
 // not a power of two), lanes past column r - 1 have no column and leave.
 template <typename T, int LPR, int VEC, bool NT>
-__global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg, int r) {
+__global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg, int r,
+                                                       int chunk) {
     constexpr int RPB = 256 / LPR;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, chunk);
     // The segment holding this tile: the tile offsets ascend, so the
     // segments starting at or before the tile are a prefix; each wave counts
     // it 64 segments at a time with one load per lane and a ballot.  The
@@ -397,8 +403,9 @@ __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restric
 static StepShape seg_shape(int r, bool fp32, StepShape sh) {
     if (step_shape_ok(r, fp32, sh)) return sh;
     StepShape d = default_step_shape(r, fp32);
-    if (d.lpr > 0) return d;
-    return one_column_shape(r);
+    if (d.lpr <= 0) d = one_column_shape(r);
+    d.chunk = sh.chunk;
+    return d;
 }
 
 int seg_rows_per_tile(int r, bool fp32, StepShape sh) { return 256 / seg_shape(r, fp32, sh).lpr; }
@@ -416,7 +423,8 @@ hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int 
     const bool nt = sh.nt != 0;
 #define FLP_SEG_NT(T, LPR, VEC, NT) \
     { \
-        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC, NT>), dim3(total_tiles), dim3(256), 0, s, tab, nseg, r); \
+        hipLaunchKernelGGL((cheb_seg_kernel<T, LPR, VEC, NT>), dim3(total_tiles), dim3(256), 0, s, tab, nseg, r, \
+                           sh.chunk); \
         return hipGetLastError(); \
     }
 #define FLP_SEG(T, LPR, VEC) FLP_SEG_NT(T, LPR, VEC, false)

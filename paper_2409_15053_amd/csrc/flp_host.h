@@ -190,7 +190,8 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
                 const void *V, int ldv, hipStream_t s, FilterTune *out, bool sell = false);
 void set_autotune(int mode);
 int autotune_mode();
-void force_filter_shape(StepShape sh, int gw);
+// chunk: sh.chunk is forced too (else only the shape and width)
+void force_filter_shape(StepShape sh, int gw, bool chunk);
 
 // W = p(Ahat) V (V, W n x r with leading dimensions) through the
 // workspace's Clenshaw buffers.

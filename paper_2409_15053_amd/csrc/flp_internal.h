@@ -82,10 +82,12 @@ inline DMat panel_mat(const double *p, int64_t n, int lpw) {
 // owns vec consecutive columns of the block (lpr * vec = r), so a 256-thread
 // block covers 256 / lpr rows; nt = 1 reads the streamed operands (V and
 // U_{k+2}) with nontemporal loads.  {0, 0, 0} selects the default (16-byte
-// pieces, ordinary loads).  Every shape sums each output element in the same
-// order, so all of them give bit-identical results.
+// pieces, ordinary loads).  chunk: the tile-to-XCD mapping (chunk_tile in
+// flp_device.h; 0 = one contiguous range per XCD).  Every shape sums each
+// output element in the same order, so all of them give bit-identical
+// results.
 struct StepShape {
-    int lpr = 0, vec = 0, nt = 0;
+    int lpr = 0, vec = 0, nt = 0, chunk = 0;
 };
 StepShape default_step_shape(int r, bool fp32);
 std::vector<StepShape> step_shape_candidates(int r, bool fp32);

@@ -608,6 +608,7 @@ int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         S.st.filter_lanes_per_row = used.lpr;
         S.st.filter_cols_per_lane = used.vec;
         S.st.filter_streaming_loads = used.nt;
+        S.st.filter_tile_chunk = tn.sh.chunk;
     }
     std::vector<ClenshawStep> gplan;
     void *stage = nullptr;

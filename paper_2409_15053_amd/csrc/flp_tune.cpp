@@ -34,9 +34,13 @@ namespace flp {
 namespace {
 
 std::atomic<int> g_mode{1};  // 1: tune on first use, 0: fixed defaults
+// tile-to-XCD mappings tried (chunk_tile): one contiguous range per XCD, or
+// chunks of this many tiles dealt to the XCDs in turn
+constexpr int kTileChunks[] = {0, 4, 32};
 std::mutex g_mu;
 StepShape g_force_shape{};
 int g_force_gw = 0;
+bool g_force_chunk = false;
 
 using Key = std::tuple<int, int, int, int64_t, int64_t, int, int>;
 std::map<Key, FilterTune> &cache() {
@@ -73,10 +77,11 @@ int ring(const flp_csr *A, const float *val32, bool fp32, int gw, StepShape sh, 
 void set_autotune(int mode) { g_mode.store(mode ? 1 : 0); }
 int autotune_mode() { return g_mode.load(); }
 
-void force_filter_shape(StepShape sh, int gw) {
+void force_filter_shape(StepShape sh, int gw, bool chunk) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_force_shape = sh;
     g_force_gw = gw;
+    g_force_chunk = chunk;
 }
 
 int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
@@ -87,10 +92,15 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     def.sh = default_step_shape(def.gw, fp32);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        if (g_force_shape.lpr > 0 || g_force_gw > 0) {
+        if (g_force_shape.lpr > 0 || g_force_gw > 0 || g_force_chunk) {
             FilterTune f = def;
             if (g_force_gw > 0 && r % g_force_gw == 0 && (allow_groups || g_force_gw == r)) f.gw = g_force_gw;
-            f.sh = step_shape_ok(f.gw, fp32, g_force_shape) ? g_force_shape : default_step_shape(f.gw, fp32);
+            if (step_shape_ok(f.gw, fp32, g_force_shape)) {
+                f.sh = g_force_shape;
+            } else {
+                f.sh = default_step_shape(f.gw, fp32);
+                f.sh.chunk = g_force_shape.chunk;
+            }
             *out = f;
             return FLP_OK;
         }
@@ -136,7 +146,13 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     int tried = 0;
     for (int gw = r; gw >= 1; gw /= 2) {
         if (r % gw != 0 || (gw != r && !allow_groups)) continue;
-        for (StepShape sh : step_shape_candidates(gw, fp32)) {
+        std::vector<StepShape> cands;
+        for (StepShape sh : step_shape_candidates(gw, fp32))
+            for (int ch : kTileChunks) {
+                sh.chunk = ch;
+                cands.push_back(sh);
+            }
+        for (StepShape sh : cands) {
             // V: the caller's block (gw == r) or a contiguous n x gw group,
             // taken from the unused half of the first buffer
             const void *Vg = gw == r ? V : (const void *)((const char *)U[0] + es * (size_t)n * gw);

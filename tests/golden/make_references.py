@@ -1,0 +1,133 @@
+"""Oracle references for the larger workloads (CPU oracle only).
+
+    python tests/golden/make_references.py c3    # 13-point 120^3 + 16 wells, ~300 eigenvalues
+    python tests/golden/make_references.py c4    # the 64 problems of the batched workload
+    python tests/golden/make_references.py c5    # the first 32 requests of the serving stream
+
+Every eigenvalue written here comes from ``oracle.flp_oracle.flp_solve``
+(FP64, forward-recurrence filter, two-pass Gram-Schmidt, LAPACK for the
+projected problems); nothing is taken from the HIP library.  Each solve
+must report convergence and every residual must be <= 1e-12.  The
+oracle's convergence checks run at the spacing the library uses for the
+same block size (min(30, round(90 / r)) block steps), which only changes
+when the oracle stops, not what it returns.
+
+c3: the interval is placed between the Weyl estimates of 20 and 320
+eigenvalues (semiclassical count of the wells potential), widened by a
+margin, solved once; each endpoint is then moved to the midpoint of the
+widest gap among the ten eigenvalues around it, so no eigenvalue sits
+near an endpoint, and the eigenvalues between the two midpoints are kept.
+
+c4 and c5: the problems' own intervals (inputs.batch_family,
+inputs.build_serve_problem); the distance from each endpoint to the
+nearest eigenvalue found inside is recorded.
+
+The oracle's wall time per solve and the host's thread count are stored
+with each entry (a record of the oracle on this host, not a target).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import flp_oracle as O  # noqa: E402
+from paper_2409_15053_amd import inputs as I  # noqa: E402
+
+
+def cadence(r):
+    return min(30, max(1, (90 + r // 2) // r))
+
+
+def checked_solve(A, alpha, beta, block, degree, seed):
+    t0 = time.perf_counter()
+    res = O.flp_solve(A, alpha, beta, block=block, degree=degree, seed=seed, check_every=cadence(block))
+    sec = time.perf_counter() - t0
+    assert res.converged, "oracle did not converge"
+    assert len(res.evals) == 0 or float(np.max(res.resid)) <= 1e-12, float(np.max(res.resid))
+    return res, sec
+
+
+def weyl_level(V, t):
+    a, b = float(V.min()), float(V.min()) + 20.0
+    for _ in range(100):
+        mid = 0.5 * (a + b)
+        a, b = (mid, b) if I.weyl_count(V, mid) < t else (a, mid)
+    return 0.5 * (a + b)
+
+
+def make_c3():
+    N = 120
+    w = I.workload_c3(N)
+    A = w["A"]
+    V = I.gaussian_wells(N, I.BASE_SEED + 3)
+    a_w, b_w = weyl_level(V, 20.5), weyl_level(V, 320.5)
+    margin = 0.04 * (b_w - a_w)
+    t0 = time.perf_counter()
+    res, sec = checked_solve(A, a_w - margin, b_w + margin, 16, 100, w["seed"])
+    ev = np.sort(res.evals)
+    print(f"c3 wide window [{a_w - margin:.6f}, {b_w + margin:.6f}]: {len(ev)} eigenvalues, iters {res.iters}, "
+          f"{sec:.0f} s", flush=True)
+
+    def gap_mid(level):
+        i = int(np.searchsorted(ev, level))
+        idx = np.arange(max(i - 5, 0), min(i + 5, len(ev) - 1))
+        gaps = ev[idx + 1] - ev[idx]
+        k = int(idx[np.argmax(gaps)])
+        return 0.5 * (ev[k] + ev[k + 1]), float(gaps.max())
+
+    alpha, ga = gap_mid(a_w)
+    beta, gb = gap_mid(b_w)
+    keep = ev[(ev >= alpha) & (ev <= beta)]
+    out = dict(workload=w["name"], n=A.n, nnz=A.nnz, block=16, degree=100, seed=w["seed"], alpha=alpha,
+               beta=beta, count=int(len(keep)), gap_at_alpha=ga, gap_at_beta=gb, evals=keep.tolist(),
+               lmin_oracle=res.lmin, lmax_oracle=res.lmax, oracle_iters=res.iters,
+               oracle_basis_cols=res.basis_cols, oracle_seconds=sec, oracle_threads=O.num_threads(),
+               weyl_window=[a_w, b_w],
+               made_by="tests/golden/make_references.py c3 (CPU oracle only)")
+    path = os.path.join(HERE, "c3_lap3d13_120_wells16.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"wrote {path}: count {len(keep)} in [{alpha:.9f}, {beta:.9f}] ({time.perf_counter() - t0:.0f} s)",
+          flush=True)
+
+
+def make_family(kind):
+    entries = []
+    if kind == "c4":
+        fam = I.batch_family(64)
+        probs = [(I.build_batch_matrix(f), f["alpha"], f["beta"]) for f in fam]
+        block, degrees = 8, [0] * len(fam)
+        path = os.path.join(HERE, "c4_batch64.json")
+    else:
+        fam = I.serve_family(32)
+        probs = [I.build_serve_problem(f) for f in fam]
+        block, degrees = 16, [f["degree"] for f in fam]
+        path = os.path.join(HERE, "c5_serve32.json")
+    t0 = time.perf_counter()
+    for i, (f, (A, alpha, beta)) in enumerate(zip(fam, probs)):
+        res, sec = checked_solve(A, alpha, beta, block, degrees[i], 7000 + i)
+        ev = np.sort(res.evals)
+        entries.append(dict(name=f["name"], N=f["N"], n=A.n, nnz=A.nnz, alpha=alpha, beta=beta, count=int(len(ev)),
+                            evals=ev.tolist(), beta_minus_top=float(beta - ev[-1]) if len(ev) else None,
+                            bottom_minus_alpha=float(ev[0] - alpha) if len(ev) else None,
+                            oracle_iters=res.iters, oracle_seconds=sec))
+        print(f"{kind} {i + 1}/{len(fam)}: g={f['N']} count={len(ev)} iters={res.iters} {sec:.1f} s "
+              f"(total {time.perf_counter() - t0:.0f} s)", flush=True)
+    out = dict(block=block, problems=entries, oracle_threads=O.num_threads(),
+               oracle_seconds_total=float(sum(e["oracle_seconds"] for e in entries)),
+               made_by=f"tests/golden/make_references.py {kind} (CPU oracle only)")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+    print(f"wrote {path} ({time.perf_counter() - t0:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1:] or ["c4", "c5", "c3"]
+    for k in what:
+        make_c3() if k == "c3" else make_family(k)

@@ -107,7 +107,8 @@ def test_tuned_segmented_shape_matches_default(torch):
             flp.flp_set_autotune(False)
             r0, _ = flp.flp_solve_batch(dAs, *args, block=8, seeds=[4, 5, 6], prec=prec)
             flp.flp_set_autotune(True)
-            flp.flp_set_filter_shape(1, 8, 0, True)  # a non-default shape for every launch
+            # a non-default shape and tile-to-XCD mapping for every launch
+            flp.flp_set_filter_shape(1, 8, 0, True, tile_chunk=3)
             r1, _ = flp.flp_solve_batch(dAs, *args, block=8, seeds=[4, 5, 6], prec=prec)
             flp.flp_set_filter_shape(0, 0, 0)
             r2, _ = flp.flp_solve_batch(dAs, *args, block=8, seeds=[4, 5, 6], prec=prec)

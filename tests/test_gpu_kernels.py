@@ -145,12 +145,13 @@ def test_filter_apply_ragged_large_grid(torch):
 
 
 SHAPE_CASES = {
-    # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams)
-    (8, flp.FLP_PREC_FP64): [(4, 2, 8, 0), (2, 4, 8, 1), (1, 8, 8, 0), (2, 2, 4, 1), (1, 4, 4, 0), (1, 2, 2, 1)],
-    (16, flp.FLP_PREC_FP64): [(8, 2, 16, 1), (4, 4, 16, 0), (2, 8, 16, 1), (4, 2, 8, 0), (2, 4, 8, 1),
-                              (1, 8, 8, 0)],
-    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1), (1, 8, 8, 0), (1, 4, 4, 1)],
-    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0), (2, 8, 16, 1), (2, 4, 8, 1), (1, 8, 8, 0)],
+    # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams, tile chunk)
+    (8, flp.FLP_PREC_FP64): [(4, 2, 8, 0, 0), (2, 4, 8, 1, 4), (1, 8, 8, 0, 32), (2, 2, 4, 1, 1), (1, 4, 4, 0, 7),
+                             (1, 2, 2, 1, 0)],
+    (16, flp.FLP_PREC_FP64): [(8, 2, 16, 1, 0), (4, 4, 16, 0, 4), (2, 8, 16, 1, 32), (4, 2, 8, 0, 5),
+                              (2, 4, 8, 1, 0), (1, 8, 8, 0, 1)],
+    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1, 0), (1, 8, 8, 0, 4), (1, 4, 4, 1, 32)],
+    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0, 0), (2, 8, 16, 1, 4), (2, 4, 8, 1, 3), (1, 8, 8, 0, 32)],
 }
 
 
@@ -158,7 +159,8 @@ SHAPE_CASES = {
 def test_filter_launch_shapes_bit_identical(torch, r, prec):
     """Every launch configuration the autotuner may pick (rows per
     wavefront, columns per lane, column-group width, ordinary or nontemporal
-    loads of the streamed operands) sums each output element
+    loads of the streamed operands, tile-to-XCD mapping, including chunk
+    sizes that leave a ragged tail of tiles) sums each output element
     in the same order: all of them give the same bits, and that result is
     within the parity bound of the oracle."""
     A = I.laplacian_3d_13pt(23, I.gaussian_wells(23, 7))  # n = 12167: ragged last tile
@@ -171,11 +173,12 @@ def test_filter_launch_shapes_bit_identical(torch, r, prec):
         flp.flp_set_autotune(False)
         W0 = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
         flp.flp_filter_apply(f, dA, Vd, W0, prec=prec)
-        for lpr, vec, gw, nt in SHAPE_CASES[(r, prec)]:
-            flp.flp_set_filter_shape(lpr, vec, gw, bool(nt))
-            W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
-            flp.flp_filter_apply(f, dA, Vd, W, prec=prec)
-            outs.append(((lpr, vec, gw, nt), W))
+        for lpr, vec, gw, nt, ch in SHAPE_CASES[(r, prec)]:
+            for fmt in (flp.FLP_FORMAT_CSR, flp.FLP_FORMAT_SELL):
+                flp.flp_set_filter_shape(lpr, vec, gw, bool(nt), tile_chunk=ch)
+                W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+                flp.flp_filter_apply(f, dA, Vd, W, prec=prec, format=fmt)
+                outs.append(((lpr, vec, gw, nt, ch, fmt), W))
         flp.flp_set_filter_shape(0, 0, 0)
         flp.flp_set_autotune(True)
         info = flp.flp_tune_filter(dA, r, prec)
