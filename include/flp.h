@@ -113,6 +113,21 @@ typedef struct flp_opts {
                              indices and values), also in the batched and serving forms;
                              flp_solve_sliced keeps CSR (its slices share A) and refuses SELL
                              with FLP_E_ARG. */
+    const double *warm;   /* flp_solve only: DEVICE n x warm_count column-major (the layout of
+                             flp_result.evecs), or NULL.  Warm start for a sequence of related
+                             problems (the self-consistent-field loops of Section 1: each matrix
+                             a small change of the previous one): the previous eigenvectors
+                             and warm_count / 4 (at least 2 block) random guard columns are
+                             refined by subspace iteration with the filter (each sweep
+                             X <- p(Ahat) X in FP64 accuracy by the residual form, orthonormalise,
+                             Rayleigh-Ritz with A) instead of a Lanczos run.  It stops when every
+                             Ritz pair inside [alpha, beta] meets tol, their count did not change
+                             since the previous sweep, and at least half the guard columns have
+                             settled on Ritz values whose filter value is below the candidate
+                             threshold tau (the block reaches past the interval's transition
+                             band); otherwise, after 8 sweeps, the call falls back to the cold
+                             solve.  stats.warm_status says which ran. */
+    int32_t warm_count;   /* columns of warm (0: cold start) */
 } flp_opts;
 
 typedef struct flp_stats {
@@ -141,6 +156,10 @@ typedef struct flp_stats {
     double polish_bytes;   /* FP32 filter only: algorithmic bytes of the residual-form polish
                               sweeps (not part of filter_bytes) */
     double t_polish;       /* seconds: those sweeps' device time (part of t_rr, not of t_mv) */
+    int32_t warm_status;   /* 0: cold solve; 1: the warm start's result; 2: the warm start could
+                              not certify its result and the cold solve ran */
+    int32_t warm_sweeps;   /* subspace iteration sweeps of the warm start (polish_sweeps counts
+                              them too when it was used) */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */
@@ -362,6 +381,12 @@ typedef struct flp_batch_stats {
     double t_orth;            /* seconds: the segmented Gram-Schmidt and block QR launches
                                  (part of t_orth_check) */
     double orth_bytes;        /* algorithmic bytes of those launches (basis read twice per pass) */
+    /* serving only (0 in batched results): */
+    int32_t peak_active;      /* most requests in the active set at once */
+    int32_t admission_waits;  /* times the next queued request waited for device memory */
+    int32_t finish_waits;     /* times a converged request waited for its finish-phase memory */
+    double mem_budget;        /* the admission budget in bytes */
+    double peak_mem_reserved; /* most device bytes reserved at once (admission + finish phase) */
 } flp_batch_stats;
 
 /* Every eigenpair in [alpha[i], beta[i]] of each A[i], for count independent
@@ -388,11 +413,17 @@ int flp_solve_batch(int32_t count, const flp_csr *const *A, const double *alpha,
 /* ------------------------------------------------------------------ serving
  *
  * A server runs a worker thread that owns the device: requests submitted
- * from any thread are admitted while engine slots and device memory allow
- * (each request's footprint -- Lanczos basis of max_basis columns,
- * recurrence vectors, FP32 copies -- is reserved against mem_budget), join
- * the active set at the next block-step boundary, share its segmented
- * filter launches, and leave it when they converge (continuous batching).
+ * from any thread are admitted, in submission order, while engine slots and
+ * device memory allow, join the active set at the next block-step boundary,
+ * share its segmented filter launches, and leave it when they converge
+ * (continuous batching).  Device memory is reserved against mem_budget in
+ * two parts: at admission, the request's solve buffers (Lanczos basis of
+ * max_basis columns, recurrence and block vectors, FP32 and sliced ELL
+ * copies; flp_server_footprint); when it converges, its finish phase (the
+ * Ritz blocks of the candidate vectors, the result's eigenvectors), before
+ * a finisher thread starts it.  A request waits while its part does not fit;
+ * one that would run alone is always let through.  Everything is returned
+ * when the request completes.
  * While a server runs, other flp_* calls must not use the same device. */
 typedef struct flp_server flp_server;
 
@@ -429,6 +460,10 @@ int flp_server_wait(flp_server *sv, uint64_t ticket, flp_result **out);
 int flp_server_cancel(flp_server *sv, uint64_t ticket);
 /* Engine statistics so far (solves = requests submitted). */
 int flp_server_stats(flp_server *sv, flp_batch_stats *out);
+/* Device bytes a request for A with options opts (NULL: defaults; block,
+ * precision and the basis cap as flp_server_submit sets them) reserves at
+ * admission.  Host only.  Errors: FLP_E_ARG. */
+int flp_server_footprint(const flp_server *sv, const flp_csr *A, const flp_opts *opts, double *bytes);
 /* Finish every queued request, stop the worker, free unretrieved results. */
 int flp_server_destroy(flp_server *sv);
 

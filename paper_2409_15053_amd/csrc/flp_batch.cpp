@@ -131,11 +131,23 @@ void Engine::finisher_main(int w) {
         Job *j = nullptr;
         {
             std::unique_lock<std::mutex> lk(fmu);
-            fcv.wait(lk, [&] { return fstop || !fq.empty(); });
-            if (fq.empty()) return;
-            j = fq.front();
-            fq.pop_front();
-            ++fbusy;
+            for (;;) {
+                fcv.wait(lk, [&] { return fstop || !fq.empty(); });
+                if (fq.empty()) return;
+                Job *cand = fq.front();
+                // the finish phase's memory is granted before the job starts
+                // (in queue order); a refusal waits for another job to finish
+                if (!reserve_finish || reserve_finish(cand, finish_bytes(*cand->S), fbusy == 0)) {
+                    j = cand;
+                    fq.pop_front();
+                    ++fbusy;
+                    break;
+                }
+                // refused only while another job is being finished: its
+                // completion wakes this wait
+                const uint64_t seen = fdone_count;
+                fdone.wait(lk, [&] { return fdone_count != seen; });
+            }
         }
         const double t0 = now();
         j->S->s = fs[w % kFinisherStreams];
@@ -156,8 +168,10 @@ void Engine::finisher_main(int w) {
         {
             std::lock_guard<std::mutex> lk(fmu);
             --fbusy;
+            ++fdone_count;
         }
         fdone.notify_all();
+        fcv.notify_all();
     }
 }
 
@@ -501,6 +515,7 @@ int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, co
                         jp->code = check_csr(S.A);
                         if (jp->code == FLP_OK) {
                             jp->B = std::make_unique<SolveBufs>();
+                            jp->B->own_ritz = true;
                             S.B = jp->B.get();
                             jp->code = solve_setup(S);
                         }

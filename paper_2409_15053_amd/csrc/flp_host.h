@@ -188,6 +188,9 @@ struct FilterTune {
 // (scratch, overwritten); V: n x r input block (read only, ld ldv).
 int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
                 const void *V, int ldv, hipStream_t s, FilterTune *out, bool sell = false);
+// The cached tuning of a CSR filter over all r columns at once (no column
+// groups) for A's size class, or the default shape; never times anything.
+int lookup_filter_tune(const flp_csr *A, int r, bool fp32, FilterTune *out);
 void set_autotune(int mode);
 int autotune_mode();
 // chunk: sh.chunk is forced too (else only the shape and width)
@@ -228,6 +231,10 @@ int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, d
 struct SolveBufs {
     Buf Q, W, Vin, U[3], V32, val32, hdev;
     Buf sell_off, sell_col, sell_val;  // sliced ELL copy of A for the filter (FLP_FORMAT_SELL)
+    // Ritz blocks of the finish (batched and serving solves: freed with the
+    // solve; a single solve uses the calling thread's workspace instead)
+    Buf Y, AY, X, AX;
+    bool own_ritz = false;
     const double *val32_src = nullptr;
     int64_t val32_nnz = 0;
     // earlier, smaller basis allocations: freed with the rest (a device free
@@ -344,6 +351,10 @@ int wait_check(Solve &S);
 int solve_after_filter(Solve &S);
 // Ritz vectors, Rayleigh-Ritz with A, FP32 polish, result
 int solve_finish(Solve &S, flp_result **out);
+// Device bytes solve_finish allocates for a solve that has converged (its
+// Ritz blocks, the result's eigenvectors, the polish's FP32 blocks); the
+// basis the solve already holds is not included.
+size_t finish_bytes(const Solve &S);
 
 // ---------------------------------------------------------------- engine
 // Segment tables of one block step for the active solves: table t lists
@@ -395,6 +406,11 @@ struct Engine {
     // error), from the stepping thread or the finisher thread, after the
     // job's device buffers are released.
     std::function<void(Job *)> on_done;
+    // Optional gate of the finish phase: before a finisher starts a job it
+    // asks for finish_bytes(job) more device memory; `lone` is true when
+    // no other job is being finished (such a request must be granted).  A
+    // refusal is retried when another job completes.
+    std::function<bool(Job *, size_t bytes, bool lone)> reserve_finish;
     Engine() = default;
     Engine(const Engine &) = delete;
     Engine &operator=(const Engine &) = delete;
@@ -438,14 +454,17 @@ struct Engine {
     std::condition_variable fcv, fdone;
     std::deque<Job *> fq;
     int fbusy = 0;
+    uint64_t fdone_count = 0;  // jobs the finishers have completed (wakes gated finishers)
     bool fstop = false;
     double t_finish = 0.0;
     void finisher_main(int w);
     void complete(Job *j);
 };
 
-// drivers
+// drivers (solve_impl: the warm start when opts.warm is given, else or on its
+// fallback solve_cold, the filtered Lanczos run)
 int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out);
+int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out);
 int solve_batch_impl(int count, const flp_csr *const *A, const double *alpha, const double *beta,
                      const flp_opts *opts, int use_graph, flp_result **results, int *codes, flp_batch_stats *bs);
 int solve_sliced_impl(const flp_csr *A, double alpha, double beta, int nslices, const flp_opts &o,

@@ -245,6 +245,8 @@ hipError_t launch_resid_norms(int n, int c, const double *AX, int64_t ldax, cons
                               double *out, hipStream_t s);
 int resid_chunks(int n);
 
+// dst (row-major n x c, ldd) = src (column-major n x c, ld n)
+hipError_t launch_transpose_in(int n, int c, const double *src, double *dst, int64_t ldd, hipStream_t s);
 // dst (column-major n x c, ld n) = src (row-major n x c, lds)
 hipError_t launch_transpose_out(int n, int c, const double *src, int64_t lds, double *dst,
                                 hipStream_t s);

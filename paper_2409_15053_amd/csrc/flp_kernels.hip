@@ -395,6 +395,24 @@ __global__ void transpose_out_kernel(int n, int c, const double *__restrict__ sr
     }
 }
 
+// dst (row-major n x c, ldd) = src (column-major n x c, ld n): the inverse
+// of transpose_out_kernel, tile by tile through LDS.
+__global__ void transpose_in_kernel(int n, int c, const double *__restrict__ src, double *__restrict__ dst,
+                                    int64_t ldd) {
+    __shared__ double t[32][33];
+    int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // bx: rows of dst, by: columns
+    int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    for (int k = ty; k < 32; k += 8) {
+        int j = by + k, i = bx + tx;
+        t[tx][k] = (i < n && j < c) ? src[(int64_t)j * n + i] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        int i = bx + k, j = by + tx;
+        if (i < n && j < c) dst[(int64_t)i * ldd + j] = t[k][tx];
+    }
+}
+
 }  // namespace
 
 int gershgorin_blocks(int n) { return (n + 255) / 256; }
@@ -459,6 +477,13 @@ hipError_t launch_resid_norms(int n, int c, const double *AX, int64_t ldax, cons
     hipLaunchKernelGGL(resid_partial_kernel, dim3(nchunks, (c + 63) / 64), dim3(256), 0, s, n, c, AX, ldax, X, ldx,
                        lam, rpc, part);
     hipLaunchKernelGGL(resid_final_kernel, dim3((c + 255) / 256), dim3(256), 0, s, nchunks, c, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_in(int n, int c, const double *src, double *dst, int64_t ldd, hipStream_t s) {
+    if (n <= 0 || c <= 0) return hipSuccess;
+    dim3 grid((n + 31) / 32, (c + 31) / 32);
+    hipLaunchKernelGGL(transpose_in_kernel, grid, dim3(256), 0, s, n, c, src, dst, ldd);
     return hipGetLastError();
 }
 

@@ -3,10 +3,12 @@
 // Requests are queued by flp_server_submit and admitted by a worker thread
 // while engine slots and device memory allow (each request's footprint --
 // Lanczos basis, recurrence vectors, FP32 copies -- is reserved against a
-// budget).  Admitted requests join the engine's active set at the next block
-// step boundary and leave it when they converge, so requests that arrive
-// while others are on the GPU start without waiting for the batch to drain.
-// Only the worker thread touches the device.
+// budget at admission, and its finish phase's Ritz blocks when it has
+// converged).  Admitted requests join the engine's active set at the next
+// block step boundary and leave it when they converge, so requests that
+// arrive while others are on the GPU start without waiting for the batch to
+// drain.  Only the worker thread steps the solves; the engine's finisher
+// threads run the finish phases.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +35,9 @@ struct flp_server {
     std::map<uint64_t, std::unique_ptr<Job>> jobs;
     uint64_t next_id = 1;
     bool stop = false;
-    size_t mem_in_use = 0, mem_budget = 0;
+    size_t mem_in_use = 0, mem_budget = 0, mem_peak = 0;
+    int32_t peak_active = 0, admission_waits = 0, finish_waits = 0;
+    bool head_waiting = false;  // the queue's head is already counted as waiting
     int device = 0;
     Engine eng;
     flp_batch_stats snapshot{};  // engine statistics, copied under the lock
@@ -69,7 +73,14 @@ void worker_main(flp_server *sv) {
         std::vector<Job *> admit;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty() || !sv->eng.active.empty(); });
+            // wake for work: active requests to step, or a queued request
+            // that fits (or would run alone); a head waiting for memory is
+            // woken by the completion that frees it
+            sv->cv_work.wait(lk, [&] {
+                if (sv->stop || !sv->eng.active.empty()) return true;
+                if (sv->pending.empty()) return false;
+                return sv->mem_in_use == 0 || sv->mem_in_use + sv->pending.front()->footprint <= sv->mem_budget;
+            });
             if (sv->stop && sv->pending.empty() && sv->eng.active.empty()) break;
             // admission: free engine slots and device memory (memory comes
             // back when the finisher releases a solve's buffers)
@@ -77,17 +88,25 @@ void worker_main(flp_server *sv) {
                    (int)(sv->eng.active.size() + admit.size()) < sv->o.max_active) {
                 Job *j = sv->pending.front();
                 if (sv->mem_in_use + j->footprint > sv->mem_budget &&
-                    !(sv->eng.active.empty() && admit.empty() && sv->mem_in_use == 0))
-                    break;  // wait for memory (a lone request is always admitted)
+                    !(sv->eng.active.empty() && admit.empty() && sv->mem_in_use == 0)) {
+                    // wait for memory (a lone request is always admitted)
+                    if (!sv->head_waiting) ++sv->admission_waits;
+                    sv->head_waiting = true;
+                    break;
+                }
+                sv->head_waiting = false;
                 sv->pending.pop_front();
                 sv->mem_in_use += j->footprint;
+                sv->mem_peak = std::max(sv->mem_peak, sv->mem_in_use);
                 admit.push_back(j);
             }
+            sv->peak_active = std::max<int32_t>(sv->peak_active, (int32_t)(sv->eng.active.size() + admit.size()));
         }
         for (Job *j : admit) {
             Solve &S = *j->S;
             S.s = sv->eng.s;
             j->B = std::make_unique<SolveBufs>();
+            j->B->own_ritz = true;  // the finish phase's blocks are this request's (freed with it)
             S.B = j->B.get();
             j->code = solve_setup(S);
             if (j->code == FLP_OK) {
@@ -126,8 +145,28 @@ void worker_main(flp_server *sv) {
             std::lock_guard<std::mutex> lk(sv->mu);
             sv->snapshot = st;
             sv->snapshot.solves = (int32_t)sv->submitted;
+            sv->snapshot.peak_active = sv->peak_active;
+            sv->snapshot.admission_waits = sv->admission_waits;
+            sv->snapshot.finish_waits = sv->finish_waits;
+            sv->snapshot.mem_budget = (double)sv->mem_budget;
+            sv->snapshot.peak_mem_reserved = (double)sv->mem_peak;
         }
     }
+}
+
+// The finish phase's memory of a converged request (finisher thread): granted
+// when it fits the budget beside everything reserved, or when no other
+// request is being finished.
+bool reserve_finish(flp_server *sv, Job *j, size_t bytes, bool lone) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (!lone && sv->mem_in_use + bytes > sv->mem_budget) {
+        ++sv->finish_waits;
+        return false;
+    }
+    sv->mem_in_use += bytes;
+    j->footprint += bytes;
+    sv->mem_peak = std::max(sv->mem_peak, sv->mem_in_use);
+    return true;
 }
 
 // Completion of a request (stepping or finisher thread): memory returns to
@@ -167,6 +206,7 @@ int cancel_request(flp_server *sv, uint64_t ticket) {
         j->t_done = now();
         j->finished = true;
         sv->cv_done.notify_all();
+        sv->cv_work.notify_one();  // the next queued request may fit now
         return FLP_OK;
     }
     j->cancel.store(true);  // the engine or a finisher drops it
@@ -211,6 +251,7 @@ int flp_server_create(const flp_server_opts *opts, flp_server **out) {
         CKR(sv->eng.init(o.block, o.prec, o.use_graph != 0));
         flp_server *p = sv.get();
         p->eng.on_done = [p](Job *j) { on_job_done(p, j); };
+        p->eng.reserve_finish = [p](Job *j, size_t bytes, bool lone) { return reserve_finish(p, j, bytes, lone); };
         p->worker = std::thread(worker_main, p);
         *out = sv.release();
         return FLP_OK;
@@ -283,6 +324,19 @@ int flp_server_wait(flp_server *sv, uint64_t ticket, flp_result **out) {
 int flp_server_cancel(flp_server *sv, uint64_t ticket) {
     if (!sv) return fail(FLP_E_ARG, "NULL argument");
     return cancel_request(sv, ticket);
+}
+
+int flp_server_footprint(const flp_server *sv, const flp_csr *A, const flp_opts *opts, double *bytes) {
+    if (!sv || !bytes) return fail(FLP_E_ARG, "NULL argument");
+    CKR(check_csr(A));
+    flp_opts o;
+    flp_opts_default(&o);
+    if (opts) o = *opts;
+    o.block = sv->o.block;
+    o.prec = sv->o.prec;
+    if (o.max_basis <= 0) o.max_basis = sv->o.max_basis;
+    *bytes = (double)footprint(*A, o);
+    return FLP_OK;
 }
 
 int flp_server_stats(flp_server *sv, flp_batch_stats *out) {

@@ -58,6 +58,7 @@ int solve_setup(Solve &S) {
     if (o.format != FLP_FORMAT_AUTO && o.format != FLP_FORMAT_CSR && o.format != FLP_FORMAT_SELL)
         return fail(FLP_E_ARG, "bad storage format");
     if (S.unfiltered && fp32) return fail(FLP_E_ARG, "unfiltered Lanczos runs in FP64 only");
+    if (o.warm || o.warm_count != 0) return fail(FLP_E_ARG, "a warm start runs through flp_solve only");
     if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
 
     // PREPROC: spectrum bounds
@@ -454,11 +455,15 @@ int solve_finish(Solve &S, flp_result **out) {
         std::vector<double> Wc((size_t)K * ldc, 0.0);
         for (int i = 0; i < K; ++i)
             for (int j = 0; j < c; ++j) Wc[(size_t)i * ldc + j] = Zc[(size_t)i * c + j];
-        CK(ensure_grow(w.Y, sizeof(double) * (size_t)n * ldc));
-        CK(ensure_grow(w.AY, sizeof(double) * (size_t)n * ldc));
-        CK(ensure_grow(w.X, sizeof(double) * (size_t)n * ldc));
-        CK(ensure_grow(w.AX, sizeof(double) * (size_t)n * ldc));
-        double *Y = (double *)w.Y.p, *AY = (double *)w.AY.p, *X = (double *)w.X.p, *AX = (double *)w.AX.p;
+        const bool own = S.B && S.B->own_ritz;
+        Buf &bY = own ? S.B->Y : w.Y, &bAY = own ? S.B->AY : w.AY;
+        Buf &bX = own ? S.B->X : w.X, &bAX = own ? S.B->AX : w.AX;
+        const size_t blk = sizeof(double) * (size_t)n * ldc;
+        CK(own ? ensure(bY, blk) : ensure_grow(bY, blk));
+        CK(own ? ensure(bAY, blk) : ensure_grow(bAY, blk));
+        CK(own ? ensure(bX, blk) : ensure_grow(bX, blk));
+        CK(own ? ensure(bAX, blk) : ensure_grow(bAX, blk));
+        double *Y = (double *)bY.p, *AY = (double *)bAY.p, *X = (double *)bX.p, *AX = (double *)bAX.p;
         double *sdev = nullptr;
         CKR(small_dev((size_t)std::max(K, cap) * ldc * 2 + 4 * (size_t)ldc + 64, &sdev));
         CK(h2d(sdev, Wc.data(), sizeof(double) * Wc.size(), s));
@@ -562,6 +567,18 @@ int solve_finish(Solve &S, flp_result **out) {
     return S.converged ? FLP_OK : FLP_E_NOCONV;
 }
 
+size_t finish_bytes(const Solve &S) {
+    const size_t c = S.cand.empty() ? 0 : S.cand.size() + S.guard.size();
+    if (c == 0) return 0;
+    const bool fp32 = S.o.prec == FLP_PREC_FP32_FILTER;
+    const size_t ldc = ((fp32 ? 2 * c : c) + 1) & ~(size_t)1;
+    const size_t n = (size_t)S.n;
+    size_t b = 4 * n * ldc * sizeof(double);  // Y, AY, X, AX
+    b += n * c * sizeof(double);              // the result's eigenvectors (at most c)
+    if (fp32) b += 4 * n * (size_t)polish_block_width() * sizeof(float);  // polish recurrence and residual
+    return b;
+}
+
 // ------------------------------------------------------------------ single solve
 
 namespace {
@@ -581,7 +598,178 @@ void release_single_bufs() {
     B.val32_nnz = 0;
 }
 
-int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out) {
+// ------------------------------------------------------------------ warm start
+
+namespace {
+
+constexpr int kMaxWarmSweeps = 8;
+constexpr int kWarmFallback = 1;  // solve_warm: not certified, the cold solve runs
+
+// Subspace iteration with the filter from [previous eigenvectors, random
+// guards] (flp_opts.warm): X <- p(Ahat) X by the residual form (FP32
+// recurrences on the FP64 residuals, FP64 accuracy), orthonormalise, and
+// Rayleigh-Ritz with A, until the Ritz pairs inside [alpha, beta] meet the
+// tolerance, their count repeats, and at least half the guard columns sit on
+// Ritz values with |p| < tau (past the transition band).  Returns FLP_OK
+// with *out, kWarmFallback, or an error code.
+int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out) {
+    const double t0 = now();
+    hipStream_t s = (hipStream_t)o.stream;
+    Workspace &w = ws();
+    const int n = A->n, k = o.warm_count;
+    if (!o.warm || k < 1 || k > n) return fail(FLP_E_ARG, "warm start needs 1 <= warm_count <= n and a block");
+    if (o.unfiltered) return fail(FLP_E_ARG, "unfiltered Lanczos takes no warm start");
+    if (!(std::isfinite(alpha) && std::isfinite(beta)) || !(alpha < beta))
+        return fail(FLP_E_ARG, "need finite alpha < beta");
+    if (o.prec != FLP_PREC_FP64 && o.prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
+    if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
+    const int r = std::max(1, o.block);
+    const int g = std::min(n - k, std::max(2 * r, (k + 3) / 4));  // guard columns
+    if (g < 1) return kWarmFallback;                              // no room beside the warm block
+    flp_stats st{};
+    double lmin = o.lmin, lmax = o.lmax;
+    if (!(o.lmin < o.lmax)) {
+        const double tb = now();
+        CKR(estimate_bounds_impl(A, o.k0 > 0 ? o.k0 : kDefaultK0, o.seed, &lmin, &lmax, s));
+        st.t_pre = now() - tb;
+    }
+    flp_filter *pf = nullptr;
+    CKR(make_filter(alpha, beta, o.polish_degree > 0 ? o.polish_degree : o.degree, lmin, lmax,
+                    o.eps > 0 ? o.eps : kDefaultEps, &pf));
+    std::unique_ptr<flp_filter> filt(pf);
+    if (alpha <= lmin && beta >= lmax)
+        return fail(FLP_E_ARG, "[alpha, beta] covers the whole spectrum [lmin, lmax]: the filter is the constant 1");
+    const double tau = 0.5 * std::min(cheb_scalar(filt->b, filt->a1), cheb_scalar(filt->b, filt->b1));
+    const double anorm = std::max(std::fabs(lmin), std::fabs(lmax));
+    const double tol = o.tol > 0 ? o.tol : kDefaultTol;
+    const float *v32 = nullptr;
+    CKR(ensure_val32(A, w.val32, &w.val32_src, &w.val32_nnz, &v32, s));
+    const int c0 = k + g, cap = 2 * c0, ldc = (cap + 1) & ~1;
+    const size_t blk = sizeof(double) * (size_t)n * ldc;
+    CK(ensure_grow(w.Y, blk));
+    CK(ensure_grow(w.AY, blk));
+    CK(ensure_grow(w.X, blk));
+    CK(ensure_grow(w.AX, blk));
+    double *Y = (double *)w.Y.p, *AY = (double *)w.AY.p, *X = (double *)w.X.p, *AX = (double *)w.AX.p;
+    double *sdev = nullptr;
+    CKR(small_dev((size_t)cap * ldc * 2 + 4 * (size_t)ldc + 64, &sdev));
+    const double tr = now();
+    CK(launch_transpose_in(n, k, o.warm, Y, ldc, s));
+    CK(launch_randn(n, g, Y + k, ldc, o.seed, 0x3A21, s));
+    CKR(orthonormalize_cols(n, c0, Y, X, ldc, sdev, s));
+    CKR(orthonormalize_cols(n, c0, Y, X, ldc, sdev, s));
+    std::vector<double> lam, rres;
+    CKR(rayleigh_ritz(A, n, c0, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+    int cur = c0, prev_count = -1, sweeps = 0, separations = 0, i0 = 0, i1 = 0;
+    auto inside = [&]() {
+        i0 = 0;
+        while (i0 < cur && lam[i0] < alpha) ++i0;
+        i1 = i0;
+        while (i1 < cur && lam[i1] <= beta) ++i1;
+        double m = 0.0;
+        for (int j = i0; j < i1; ++j) m = std::max(m, rres[j] / anorm);
+        return m;
+    };
+    bool certified = false;
+    for (;;) {
+        const double worst = inside();
+        // Ritz pairs inside the interval far from converged mix eigenvectors
+        // from both sides of it: split them as the finish phase does
+        std::vector<int> mixed;
+        for (int j = i0; j < i1; ++j)
+            if (rres[j] / anorm > kMixedResid) mixed.push_back(j);
+        if (sweeps > 0 && !mixed.empty() && separations < kMaxSeparations && cur + (int)mixed.size() <= cap) {
+            CK(launch_copy_block(n, cur, 1.0, X, ldc, plain_mat(Y, ldc), 0, nullptr, 0, s));
+            for (size_t t = 0; t < mixed.size(); ++t)
+                CK(launch_copy_block(n, 1, 1.0, AX + mixed[t], ldc, plain_mat(Y, ldc), cur + (int)t, nullptr, 0, s));
+            cur += (int)mixed.size();
+            CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
+            CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
+            CKR(rayleigh_ritz(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+            ++separations;
+            continue;
+        }
+        const int count = i1 - i0;
+        int past_band = 0;  // block Ritz values outside the transition band
+        for (int j = 0; j < cur; ++j)
+            if (std::fabs(cheb_scalar(filt->b, (lam[j] - filt->c) / filt->e)) < tau) ++past_band;
+        if (sweeps >= 2 && worst <= tol && count == prev_count && past_band >= (g + 1) / 2) {
+            certified = true;
+            break;
+        }
+        if (sweeps >= kMaxWarmSweeps) break;
+        prev_count = count;
+        double pbytes = 0.0;
+        CK(hipStreamSynchronize(s));
+        const double tp = now();
+        CKR(polish_apply(filt.get(), A, v32, cur, X, AX, ldc, lam, Y, s, &pbytes));
+        CK(hipStreamSynchronize(s));
+        st.t_polish += now() - tp;
+        st.polish_bytes += pbytes;
+        st.mv += (int64_t)cur * filt->m;
+        CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
+        CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
+        CKR(rayleigh_ritz(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+        ++sweeps;
+    }
+    if (!certified) return kWarmFallback;
+    auto *res = new flp_result;
+    std::memset(res, 0, sizeof(*res));
+    std::unique_ptr<flp_result, void (*)(flp_result *)> guard(res, flp_result_free);
+    res->n = n;
+    res->lmin = lmin;
+    res->lmax = lmax;
+    res->alpha = alpha;
+    res->beta = beta;
+    res->degree = filt->m;
+    res->converged = 1;
+    const int cnt = i1 - i0;
+    res->count = cnt;
+    if (cnt > 0) {
+        res->evals = new double[cnt];
+        res->resid = new double[cnt];
+        for (int j = 0; j < cnt; ++j) {
+            res->evals[j] = lam[i0 + j];
+            res->resid[j] = rres[i0 + j] / anorm;
+        }
+        CK(dev_alloc((void **)&res->evecs, sizeof(double) * (size_t)n * cnt));
+        CK(launch_transpose_out(n, cnt, X + i0, ldc, res->evecs, s));
+        CK(hipStreamSynchronize(s));
+    }
+    st.polish_sweeps = sweeps;
+    st.warm_sweeps = sweeps;
+    st.warm_status = 1;
+    st.basis_cols = cur;
+    st.filter_format = FLP_FORMAT_CSR;
+    st.t_rr = now() - tr;
+    st.t_total = now() - t0;
+    res->stats = st;
+    *out = guard.release();
+    return FLP_OK;
+}
+
+}  // namespace
+
+int solve_impl(const flp_csr *A, double alpha, double beta, const flp_opts &o_in, flp_result **out) {
+    flp_opts o = o_in;
+    int warm_sweeps = 0;
+    const bool warm = o.warm_count > 0 || o.warm != nullptr;
+    if (warm) {
+        const int rc = solve_warm(A, alpha, beta, o, out);
+        if (rc != kWarmFallback) return rc;
+        warm_sweeps = kMaxWarmSweeps;
+        o.warm = nullptr;
+        o.warm_count = 0;
+    }
+    const int rc = solve_cold(A, alpha, beta, o, out);
+    if (warm && *out) {
+        (*out)->stats.warm_status = 2;
+        (*out)->stats.warm_sweeps = warm_sweeps;
+    }
+    return rc;
+}
+
+int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out) {
     Solve S;
     S.A = A;
     S.alpha = alpha;

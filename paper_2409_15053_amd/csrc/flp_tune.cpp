@@ -84,6 +84,23 @@ void force_filter_shape(StepShape sh, int gw, bool chunk) {
     g_force_chunk = chunk;
 }
 
+int lookup_filter_tune(const flp_csr *A, int r, bool fp32, FilterTune *out) {
+    FilterTune def;
+    def.gw = r;
+    def.sh = default_step_shape(r, fp32);
+    *out = def;
+    if (g_mode.load() == 0) return FLP_OK;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    const int n = A->n;
+    const Key key{dev, fp32 ? 1 : 0, r, (int64_t)std::lround(4.0 * std::log2((double)n)),
+                  (int64_t)std::lround(4.0 * (double)A->nnz / n), 0, 0};
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = cache().find(key);
+    if (it != cache().end() && it->second.gw == r) *out = it->second;
+    return FLP_OK;
+}
+
 int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
                 const void *V, int ldv, hipStream_t s, FilterTune *out, bool sell) {
     const int n = A->n;

@@ -37,7 +37,7 @@ EXPORTS = [
     "flp_release_workspace", "flp_set_allocator", "flp_check_symmetric", "flp_last_error", "flp_version",
     "flp_abi_sizes",
     "flp_server_opts_default", "flp_server_create", "flp_server_submit", "flp_server_poll",
-    "flp_server_wait", "flp_server_cancel", "flp_server_stats", "flp_server_destroy",
+    "flp_server_wait", "flp_server_cancel", "flp_server_stats", "flp_server_footprint", "flp_server_destroy",
 ]
 
 
@@ -65,7 +65,8 @@ class FlpOptsC(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("max_basis", ctypes.c_int64), ("k0", ctypes.c_int32),
                 ("start", ctypes.c_void_p), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("sym_tol", ctypes.c_double), ("polish_degree", ctypes.c_int32),
-                ("unfiltered", ctypes.c_int32), ("format", ctypes.c_int32)]
+                ("unfiltered", ctypes.c_int32), ("format", ctypes.c_int32), ("warm", ctypes.c_void_p),
+                ("warm_count", ctypes.c_int32)]
 
 
 class FlpStatsC(ctypes.Structure):
@@ -77,7 +78,7 @@ class FlpStatsC(ctypes.Structure):
                 ("filter_lanes_per_row", ctypes.c_int32), ("filter_cols_per_lane", ctypes.c_int32),
                 ("filter_streaming_loads", ctypes.c_int32), ("filter_tile_chunk", ctypes.c_int32),
                 ("polish_bytes", ctypes.c_double),
-                ("t_polish", ctypes.c_double)]
+                ("t_polish", ctypes.c_double), ("warm_status", ctypes.c_int32), ("warm_sweeps", ctypes.c_int32)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
@@ -85,7 +86,10 @@ class FlpBatchStatsC(ctypes.Structure):
                 ("graph_captures", ctypes.c_int32), ("graph_replays", ctypes.c_int32),
                 ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_filter", ctypes.c_double),
                 ("t_orth_check", ctypes.c_double), ("t_finish", ctypes.c_double),
-                ("filter_bytes", ctypes.c_double), ("t_orth", ctypes.c_double), ("orth_bytes", ctypes.c_double)]
+                ("filter_bytes", ctypes.c_double), ("t_orth", ctypes.c_double), ("orth_bytes", ctypes.c_double),
+                ("peak_active", ctypes.c_int32), ("admission_waits", ctypes.c_int32),
+                ("finish_waits", ctypes.c_int32), ("mem_budget", ctypes.c_double),
+                ("peak_mem_reserved", ctypes.c_double)]
 
 
 class FlpServerOptsC(ctypes.Structure):
@@ -152,6 +156,8 @@ def load(path: str = LIB_PATH):
         "flp_server_poll": (ctypes.c_int, [P, U64, ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
         "flp_server_wait": (ctypes.c_int, [P, U64, ctypes.POINTER(ctypes.POINTER(FlpResultC))]),
         "flp_server_stats": (ctypes.c_int, [P, ctypes.POINTER(FlpBatchStatsC)]),
+        "flp_server_footprint": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), ctypes.POINTER(FlpOptsC),
+                                                ctypes.POINTER(ctypes.c_double)]),
         "flp_server_destroy": (ctypes.c_int, [P]),
         "flp_last_error": (ctypes.c_char_p, []),
         "flp_version": (ctypes.c_char_p, []),
@@ -352,7 +358,7 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
               prec: int = FLP_PREC_FP64, start: np.ndarray | None = None, bounds=None, max_basis: int = 0,
               check_every: int = 0, eps: float = 0.0, k0: int = 0, want_vectors: bool = True,
               stream=None, sym_tol: float = -1.0, polish_degree: int = 0, unfiltered: bool = False,
-              format: int = 0) -> dict:
+              format: int = 0, warm=None) -> dict:
     """Every eigenpair of A in [alpha, beta].  Returns a dict with numpy
     ``evals``/``resid``, a torch ``evecs`` (n x count, float64, on A's
     device) and the solve statistics.  ``sym_tol >= 0`` checks A for
@@ -360,7 +366,9 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
     plain block Lanczos with the mapped matrix in place of the filter (FP64
     only).  ``format`` picks the storage the filter reads A in
     (FLP_FORMAT_AUTO, FLP_FORMAT_CSR or FLP_FORMAT_SELL, a sliced ELL copy);
-    ``stats["filter_format"]`` reports the one used."""
+    ``stats["filter_format"]`` reports the one used.  ``warm``: a float64
+    n x k device tensor with unit column stride or column-major layout
+    (e.g. a previous result's ``evecs``) to warm-start from."""
     import torch
     lib = load()
     o = default_opts()
@@ -386,6 +394,15 @@ def flp_solve(A: DeviceCsr, alpha: float, beta: float, block: int = 1, degree: i
     o.polish_degree = polish_degree
     o.unfiltered = 1 if unfiltered else 0
     o.format = format
+    if warm is not None:
+        # column-major n x k: column j at data_ptr + j * n
+        assert warm.dtype == torch.float64 and warm.shape[0] == A.n
+        if warm.dim() == 1:
+            warm = warm[:, None]
+        if not (warm.stride(0) == 1 and warm.stride(1) == A.n):
+            warm = warm.t().contiguous().t()
+        o.warm = warm.data_ptr()
+        o.warm_count = warm.shape[1]
     res = ctypes.POINTER(FlpResultC)()
     rc = lib.flp_solve(ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(res))
     _check(rc, allow=(FLP_E_NOCONV,))
@@ -562,6 +579,14 @@ class Server:
         res = ctypes.POINTER(FlpResultC)()
         rc = load().flp_server_wait(self.h, ticket, ctypes.byref(res))
         return self._finish(ticket, rc, res, want_vectors)
+
+    def footprint(self, A: DeviceCsr, max_basis: int = 0) -> float:
+        """Device bytes a request for A reserves at admission."""
+        o = _make_opts(1, 0, 0, 0, max_basis, 0, 0.0, 0, None, None)
+        o.stream = None
+        b = ctypes.c_double()
+        _check(load().flp_server_footprint(self.h, ctypes.byref(A.c), ctypes.byref(o), ctypes.byref(b)))
+        return b.value
 
     def stats(self) -> dict:
         st = FlpBatchStatsC()

@@ -119,3 +119,57 @@ def test_server_cancel(torch):
             sv.cancel(123456789)                     # unknown ticket
     finally:
         sv.close()
+
+
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP32_FILTER, flp.FLP_PREC_FP64])
+def test_server_admission_by_memory_footprint(torch, prec):
+    """A device-memory budget that holds the admission footprint of two
+    requests at a time: six requests submitted together are admitted two
+    at a time as earlier ones complete (the queue's head waits for memory),
+    and every result is still exact against the dense definition and the
+    same as the request solved alone.  With the default budget all six are
+    admitted at once."""
+    cases = family([12] * 6, 7100, [12, 16, 20, 24, 14, 18])  # equal sizes: equal footprints
+    dAs = [flp.DeviceCsr.from_host(A, with_fp32=True) for A, *_ in cases]
+    probe = flp.Server(block=8, prec=prec, max_active=8, max_basis=512)
+    try:
+        fps = [probe.footprint(dA) for dA in dAs]
+    finally:
+        probe.close()
+    assert all(f > 0 for f in fps)
+    # the footprint covers at least the basis of max_basis columns
+    assert all(f >= min(512, A.n) * A.n * 8 for f, (A, *_ ) in zip(fps, cases))
+    assert max(fps) == min(fps)
+    budget = 2.5 * fps[0]  # room for two admissions, not three
+    sv = flp.Server(block=8, prec=prec, max_active=8, max_basis=512, mem_budget=budget)
+    try:
+        tickets = [sv.submit(dAs[i], a, b, seed=60 + i) for i, (A, a, b) in enumerate(cases)]
+        got = [sv.wait(t) for t in tickets]
+        st = sv.stats()
+    finally:
+        sv.close()
+    assert st["mem_budget"] == pytest.approx(budget, rel=1e-12)
+    assert st["peak_active"] <= 2
+    assert st["admission_waits"] >= 1
+    assert st["peak_mem_reserved"] > 0
+    for i, (A, alpha, beta) in enumerate(cases):
+        want, _ = O.dense_eigs_in_interval(A, alpha, beta)
+        r = got[i]
+        assert r["count"] == len(want)
+        assert np.max(np.abs(np.sort(r["evals"]) - want) / np.abs(want)) <= 1e-10
+        assert np.max(r["resid"]) <= 1e-9
+        alone = flp.flp_solve(dAs[i], alpha, beta, block=8, seed=60 + i, prec=prec, max_basis=512,
+                              want_vectors=False)
+        assert alone["count"] == r["count"]
+        assert np.max(np.abs(alone["evals"] - r["evals"]) / np.abs(r["evals"])) <= 1e-10
+    # the default budget (70 % of free device memory) admits all of them at once
+    sv = flp.Server(block=8, prec=prec, max_active=8, max_basis=512)
+    try:
+        tickets = [sv.submit(dAs[i], a, b, seed=60 + i) for i, (A, a, b) in enumerate(cases)]
+        got2 = [sv.wait(t) for t in tickets]
+        st2 = sv.stats()
+    finally:
+        sv.close()
+    assert st2["admission_waits"] == 0 and st2["peak_active"] >= 2
+    for r, r2 in zip(got, got2):
+        assert r["count"] == r2["count"]
