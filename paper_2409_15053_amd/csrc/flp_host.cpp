@@ -645,7 +645,8 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
 
 int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int c, const double *X,
                  const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
-                 double *bytes, const flp_csr *sellA, const float *sell32) {
+                 double *bytes, const flp_csr *sellA, const float *sell32, const std::vector<double> *rres,
+                 double lock_abs, int chunk) {
     Workspace &w = ws();
     // the recurrence reads the sliced ELL copy when the solve holds one
     const bool sell = sellA != nullptr;
@@ -654,32 +655,71 @@ int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int 
     const float *mval = sell ? sell32 : val32;
     const int n = A->n, PW = polish_block_width();
     const int mg = std::max(p->m, 1);  // coefficients of the divided differences
+    const double cc = p->c, e = p->e;
+    // locked columns: residual already at or below lock_abs, so the residual
+    // term is dropped and the column is only scaled by p(t_j)
+    std::vector<int> active, locked;
+    for (int j = 0; j < c; ++j) {
+        if (rres && lock_abs > 0.0 && (*rres)[j] <= lock_abs)
+            locked.push_back(j);
+        else
+            active.push_back(j);
+    }
+    const int na = (int)active.size();
+    const int nblk = (na + PW - 1) / PW;
     for (auto &u : w.PU) CK(ensure(u, sizeof(float) * (size_t)n * PW));
     CK(ensure(w.PR, sizeof(float) * (size_t)n * PW));
     const size_t tab_bytes = ((sizeof(float) * (size_t)mg * PW + 255) / 256) * 256;
-    CK(ensure(w.PC, tab_bytes + sizeof(double) * 2 * PW));
+    // per block: coefficient table, Ritz values and p(t_j) (2 PW doubles),
+    // column indices (PW ints); then the locked columns' indices and scales
+    const size_t blk_bytes = tab_bytes + sizeof(double) * 2 * PW + sizeof(int) * PW + 256;
+    const size_t lock_bytes = (sizeof(int) + sizeof(double)) * (size_t)locked.size() + 256;
+    CK(ensure_grow(w.PC, blk_bytes * (size_t)std::max(nblk, 1) + lock_bytes));
     float *U[3] = {(float *)w.PU[0].p, (float *)w.PU[1].p, (float *)w.PU[2].p};
     float *R = (float *)w.PR.p;
-    float *coef = (float *)w.PC.p;
-    double *lp = (double *)((char *)w.PC.p + tab_bytes);  // Ritz values, then p(t_j)
-    const double cc = p->c, e = p->e;
+    char *pc = (char *)w.PC.p;
     const float a2 = (float)(2.0 / e), b2 = (float)(-2.0 * cc / e), a1 = (float)(1.0 / e), b1 = (float)(-cc / e);
-    std::vector<float> tab((size_t)mg * PW);
-    std::vector<double> lph(2 * PW), g;
-    for (int j0 = 0; j0 < c; j0 += PW) {
-        const int wc = std::min(PW, c - j0);
-        std::fill(tab.begin(), tab.end(), 0.0f);
-        std::fill(lph.begin(), lph.end(), 0.0);
+    std::vector<char> host(blk_bytes * (size_t)std::max(nblk, 1) + lock_bytes, 0);
+    std::vector<double> g;
+    for (int bi = 0; bi < nblk; ++bi) {
+        char *hb = host.data() + blk_bytes * bi;
+        float *tab = (float *)hb;
+        double *lph = (double *)(hb + tab_bytes);
+        int *cl = (int *)(hb + tab_bytes + sizeof(double) * 2 * PW);
+        const int wc = std::min(PW, na - bi * PW);
         for (int j = 0; j < wc; ++j) {
-            const double t = (lam[j0 + j] - cc) / e;
+            const int col = active[bi * PW + j];
+            const double t = (lam[col] - cc) / e;
             cheb_divided(p->b, t, g);
             for (int k = 0; k < mg; ++k) tab[(size_t)k * PW + j] = (float)g[k];
-            lph[j] = lam[j0 + j];
+            lph[j] = lam[col];
             lph[PW + j] = cheb_scalar(p->b, t);
+            cl[j] = col;
         }
-        CK(h2d(coef, tab.data(), sizeof(float) * tab.size(), s));
-        CK(h2d(lp, lph.data(), sizeof(double) * lph.size(), s));
-        CK(launch_polish_resid(n, wc, X + j0, AX + j0, ldc, lp, 1.0 / e, R, s));
+    }
+    {
+        char *hl = host.data() + blk_bytes * (size_t)std::max(nblk, 1);
+        int *lc = (int *)hl;
+        double *ls = (double *)(hl + ((sizeof(int) * locked.size() + 7) / 8) * 8);
+        for (size_t t = 0; t < locked.size(); ++t) {
+            lc[t] = locked[t];
+            ls[t] = cheb_scalar(p->b, (lam[locked[t]] - cc) / e);
+        }
+    }
+    CK(h2d(pc, host.data(), host.size(), s));
+    if (!locked.empty()) {
+        char *dl = pc + blk_bytes * (size_t)std::max(nblk, 1);
+        const int *lc = (const int *)dl;
+        const double *ls = (const double *)(dl + ((sizeof(int) * locked.size() + 7) / 8) * 8);
+        CK(launch_polish_locked(n, (int)locked.size(), lc, ls, X, ldc, Y, s));
+    }
+    for (int bi = 0; bi < nblk; ++bi) {
+        char *db = pc + blk_bytes * bi;
+        const float *coef = (const float *)db;
+        const double *lp = (const double *)(db + tab_bytes);
+        const int *cl = (const int *)(db + tab_bytes + sizeof(double) * 2 * PW);
+        const int wc = std::min(PW, na - bi * PW);
+        CK(launch_polish_resid(n, wc, X, AX, ldc, cl, lp, 1.0 / e, R, s));
         // Clenshaw for sum_k g_k T_k(Ahat) r: u_k = g_k r + 2 Ahat u_{k+1} - u_{k+2}
         // (k = mg-1 .. 1), result g_0 r + Ahat u_1 - u_2, plus p(t_j) x_j
         const float *u1 = nullptr, *u2 = nullptr;
@@ -687,18 +727,21 @@ int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int 
         for (int k = mg - 1; k >= 1; --k) {
             float *out = U[next];
             next = (next + 1) % 3;
-            CK(launch_polish_step(n, mrow, mcol, mval, u1, u2, R, coef + (size_t)k * PW, a2, b2, out, s, sell));
+            CK(launch_polish_step(n, mrow, mcol, mval, u1, u2, R, coef + (size_t)k * PW, a2, b2, out, s, sell,
+                                  chunk));
             u2 = u1;
             u1 = out;
         }
-        CK(launch_polish_last(n, mrow, mcol, mval, u1, u2, R, coef, a1, b1, Y + j0, ldc, wc, X + j0, ldc, lp + PW, s,
-                              sell));
+        CK(launch_polish_last(n, mrow, mcol, mval, u1, u2, R, coef, a1, b1, Y, ldc, wc, X, ldc, cl, lp + PW, s, sell,
+                              chunk));
     }
     if (bytes) {
         // per step: the matrix in FP32 once, the gathered block, U_{k+2},
-        // the residual block and the output (FP32); plus the FP64 in/out
+        // the residual block and the output (FP32); plus the FP64 in/out of
+        // every column (X, AX read and Y written for the active ones, X read
+        // and Y written for the locked ones)
         const double step = (double)A->nnz * 8.0 + 4.0 * (n + 1) + 4.0 * (double)n * PW * 4.0;
-        *bytes = step * mg * ((c + PW - 1) / PW) + 8.0 * 4.0 * (double)n * c;
+        *bytes = step * mg * nblk + 8.0 * 3.0 * (double)n * na + 8.0 * 2.0 * (double)n * locked.size();
     }
     return FLP_OK;
 }

@@ -56,6 +56,9 @@ constexpr int kMaxPolish = 5;  // FP64 polish sweeps after an FP32-filter solve
 // solve counts as a mixture of eigenvectors (converged pairs sit near 1e-7)
 constexpr double kMixedResid = 1e-4;
 constexpr int kMaxSeparations = 8;  // Rayleigh-Ritz rounds on span{X, A x} for mixed pairs
+// A polish sweep locks (only scales by p(t)) Ritz columns whose relative
+// residual is already below this fraction of the tolerance
+constexpr double kLockFrac = 0.1;
 constexpr int kSetupThreads = 8;  // host threads for the set-up of a batch's solves
 constexpr int kMaxSpeculative = 2;  // block steps a solve may take past a convergence check in flight
 
@@ -205,11 +208,16 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
 // Y = p(Ahat) X for c Ritz vectors of A (X, AX = A X, Ritz values lam;
 // n x c blocks with leading dimension ldc) by the residual form: X diag(p(t))
 // in FP64 plus the divided-difference recurrences on the residuals in FP32
-// (val32: FP32 copy of A's values).  Returns the algorithmic bytes moved.
+// (val32: FP32 copy of A's values), 32 columns per recurrence.  Columns
+// whose residual norm rres[j] (unscaled, as rayleigh_ritz returns it) is at
+// or below lock_abs are locked: only scaled by p(t_j) (lock_abs <= 0 or
+// rres == NULL: none).  chunk: tile-to-XCD mapping of the recurrence.
+// Returns the algorithmic bytes moved.
 int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int c, const double *X,
                  const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
                  double *bytes,
-                 const flp_csr *sellA = nullptr, const float *sell32 = nullptr);
+                 const flp_csr *sellA = nullptr, const float *sell32 = nullptr,
+                 const std::vector<double> *rres = nullptr, double lock_abs = 0.0, int chunk = 0);
 
 // ---------------------------------------------------------------- dense helpers
 void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, std::vector<int> &bad);
@@ -301,6 +309,7 @@ struct Solve {
     bool converged = false, done = false;
     std::vector<int> cand;
     std::vector<int> guard;  // FP32 filter: Ritz vectors just outside the candidates, polished with them
+    int tile_chunk = 0;       // tile-to-XCD mapping the filter launches use (the polish follows it)
     flp_stats st{};
     double t_start = 0;
     int code = FLP_OK;  // first error

@@ -25,9 +25,11 @@ constexpr int PV = 4;        // columns per lane
 constexpr int PL = PW / PV;  // lanes per row
 constexpr int PRB = 256 / PL;  // rows per 256-thread block
 
-// R32 = (AX - X diag(lam)) * inv_e for the w real columns; zero padding.
+// R32 = (AX - X diag(lam)) * inv_e for the w real columns of the block
+// (block column j is Ritz column cols[j]); zero padding.
 __global__ __launch_bounds__(256) void polish_resid_kernel(int n, int w, const double *__restrict__ X,
                                                            const double *__restrict__ AX, int64_t ldc,
+                                                           const int *__restrict__ cols,
                                                            const double *__restrict__ lam, double inv_e,
                                                            float *__restrict__ R32) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -35,17 +37,38 @@ __global__ __launch_bounds__(256) void polish_resid_kernel(int n, int w, const d
     const int64_t row = idx / PW;
     const int j = (int)(idx % PW);
     float v = 0.0f;
-    if (j < w) v = (float)((AX[row * ldc + j] - lam[j] * X[row * ldc + j]) * inv_e);
+    if (j < w) {
+        const int64_t q = row * ldc + cols[j];
+        v = (float)((AX[q] - lam[j] * X[q]) * inv_e);
+    }
     R32[idx] = v;
+}
+
+// Y[:, cols[j]] = scale[j] X[:, cols[j]] for j < nl: the locked columns of a
+// sweep (their residual is already below the tolerance, so the residual
+// term of p(Ahat) x is dropped and p(Ahat) x = p(t) x).
+__global__ __launch_bounds__(256) void polish_locked_kernel(int n, int nl, const int *__restrict__ cols,
+                                                            const double *__restrict__ scale,
+                                                            const double *__restrict__ X, int64_t ldc,
+                                                            double *__restrict__ Y) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * nl) return;
+    const int64_t row = idx / nl;
+    const int j = (int)(idx % nl);
+    const int64_t q = row * ldc + cols[j];
+    Y[q] = scale[j] * X[q];
 }
 
 // One Clenshaw step of the column-wise polynomials g_j:
 //   out = a (A U1) + b U1 + coef[j] R - U2
 // (U1 == null: the first step, out = coef[j] R; U2 == null: no U2 term).
-// LAST: the final step; it writes Y[:, j] = out_j + ptheta[j] X[:, j] in FP64
-// for the w real columns.  SELL: rowptr / colind / val are the sliced ELL
-// copy (slice offsets; entry k of a row at q0 + k * kSellC); its padding adds
-// exact zeros after the row's nonzeros, which it visits in their CSR order.
+// LAST: the final step; it writes Y[:, cols[j]] = out_j + ptheta[j] X[:, cols[j]]
+// in FP64 for the w real columns.  SELL: rowptr / colind / val are the
+// sliced ELL copy (slice offsets; entry k of a row at q0 + k * kSellC); its
+// padding adds exact zeros after the row's nonzeros, which it visits in
+// their CSR order.  The row's nonzeros go in groups of 8 with every load of
+// a group issued before its products (slots past the row's end re-read its
+// last entry with weight zero); tiles map to XCDs by chunk_tile.
 template <bool LAST, bool SELL>
 __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *__restrict__ rowptr,
                                                           const int32_t *__restrict__ colind,
@@ -54,8 +77,10 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
                                                           const float *__restrict__ coef, float a, float b,
                                                           float *out, double *Y, int64_t ldy, int w,
                                                           const double *__restrict__ X, int64_t ldx,
-                                                          const double *__restrict__ ptheta) {
-    const int row = blockIdx.x * PRB + threadIdx.x / PL;
+                                                          const int *__restrict__ cols,
+                                                          const double *__restrict__ ptheta, int chunk) {
+    constexpr int UNR = 8;
+    const int row = chunk_tile(blockIdx.x, gridDim.x, chunk) * PRB + threadIdx.x / PL;
     if (row >= n) return;
     const int c0 = (threadIdx.x % PL) * PV;
     float acc[PV] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -72,32 +97,23 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
             stride = 1;
             cnt = rowptr[row + 1] - base;
         }
-        int i = 0;
-        for (; i + 4 <= cnt; i += 4) {
-            float v[4];
-            float4 x[4];
+        for (int i = 0; i < cnt; i += UNR) {
+            float v[UNR];
+            float4 x[UNR];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = base + (i + u) * stride;
-                v[u] = val[q];
+            for (int u = 0; u < UNR; ++u) {
+                const int q = base + min(i + u, cnt - 1) * stride;
+                const float vv = val[q];
+                v[u] = (i + u < cnt) ? vv : 0.0f;
                 x[u] = *reinterpret_cast<const float4 *>(U1 + (int64_t)colind[q] * PW + c0);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < UNR; ++u) {
                 acc[0] = fmaf(v[u], x[u].x, acc[0]);
                 acc[1] = fmaf(v[u], x[u].y, acc[1]);
                 acc[2] = fmaf(v[u], x[u].z, acc[2]);
                 acc[3] = fmaf(v[u], x[u].w, acc[3]);
             }
-        }
-        for (; i < cnt; ++i) {
-            const int q = base + i * stride;
-            const float v = val[q];
-            const float4 x = *reinterpret_cast<const float4 *>(U1 + (int64_t)colind[q] * PW + c0);
-            acc[0] = fmaf(v, x.x, acc[0]);
-            acc[1] = fmaf(v, x.y, acc[1]);
-            acc[2] = fmaf(v, x.z, acc[2]);
-            acc[3] = fmaf(v, x.w, acc[3]);
         }
         const float4 s = *reinterpret_cast<const float4 *>(U1 + (int64_t)row * PW + c0);
         u1[0] = s.x;
@@ -124,7 +140,10 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
 #pragma unroll
         for (int j = 0; j < PV; ++j) {
             const int col = c0 + j;
-            if (col < w) Y[(int64_t)row * ldy + col] = (double)o[j] + ptheta[col] * X[(int64_t)row * ldx + col];
+            if (col < w) {
+                const int q = cols[col];
+                Y[(int64_t)row * ldy + q] = (double)o[j] + ptheta[col] * X[(int64_t)row * ldx + q];
+            }
         }
     }
 }
@@ -133,38 +152,49 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
 
 int polish_block_width() { return PW; }
 
-hipError_t launch_polish_resid(int n, int w, const double *X, const double *AX, int64_t ldc, const double *lam,
-                               double inv_e, float *R32, hipStream_t s) {
+hipError_t launch_polish_resid(int n, int w, const double *X, const double *AX, int64_t ldc, const int *cols,
+                               const double *lam, double inv_e, float *R32, hipStream_t s) {
     if (w < 1 || w > PW) return hipErrorInvalidValue;
     const int64_t total = (int64_t)n * PW;
     hipLaunchKernelGGL(polish_resid_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, w, X, AX, ldc,
-                       lam, inv_e, R32);
+                       cols, lam, inv_e, R32);
+    return hipGetLastError();
+}
+
+hipError_t launch_polish_locked(int n, int nl, const int *cols, const double *scale, const double *X, int64_t ldc,
+                                double *Y, hipStream_t s) {
+    if (nl <= 0) return hipSuccess;
+    const int64_t total = (int64_t)n * nl;
+    hipLaunchKernelGGL(polish_locked_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, nl, cols,
+                       scale, X, ldc, Y);
     return hipGetLastError();
 }
 
 hipError_t launch_polish_step(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
-                              float b, float *out, hipStream_t s, bool sell) {
+                              float b, float *out, hipStream_t s, bool sell, int chunk) {
+    const dim3 grid((n + PRB - 1) / PRB);
     if (sell)
-        hipLaunchKernelGGL((polish_step_kernel<false, true>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
-                           colind, val32, U1, U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr);
+        hipLaunchKernelGGL((polish_step_kernel<false, true>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1,
+                           U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr, nullptr, chunk);
     else
-        hipLaunchKernelGGL((polish_step_kernel<false, false>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
-                           colind, val32, U1, U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr);
+        hipLaunchKernelGGL((polish_step_kernel<false, false>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1,
+                           U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr, nullptr, chunk);
     return hipGetLastError();
 }
 
 hipError_t launch_polish_last(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
-                              float b, double *Y, int64_t ldy, int w, const double *X, int64_t ldx,
-                              const double *ptheta, hipStream_t s, bool sell) {
+                              float b, double *Y, int64_t ldy, int w, const double *X, int64_t ldx, const int *cols,
+                              const double *ptheta, hipStream_t s, bool sell, int chunk) {
     if (w < 1 || w > PW) return hipErrorInvalidValue;
+    const dim3 grid((n + PRB - 1) / PRB);
     if (sell)
-        hipLaunchKernelGGL((polish_step_kernel<true, true>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
-                           colind, val32, U1, U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, ptheta);
+        hipLaunchKernelGGL((polish_step_kernel<true, true>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1, U2,
+                           R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, cols, ptheta, chunk);
     else
-        hipLaunchKernelGGL((polish_step_kernel<true, false>), dim3((n + PRB - 1) / PRB), dim3(256), 0, s, n, rowptr,
-                           colind, val32, U1, U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, ptheta);
+        hipLaunchKernelGGL((polish_step_kernel<true, false>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1,
+                           U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, cols, ptheta, chunk);
     return hipGetLastError();
 }
 

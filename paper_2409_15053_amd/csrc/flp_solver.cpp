@@ -530,7 +530,7 @@ int solve_finish(Solve &S, flp_result **out) {
                 CK(hipStreamSynchronize(s));  // (already idle: the Rayleigh-Ritz above ends on the host)
                 const double tp = now();
                 CKR(polish_apply(pf, A, S.val32, c, X, AX, ldc, lam, Y, s, &pbytes, S.sell ? &S.SA : nullptr,
-                                 S.sell ? S.sval32 : nullptr));
+                                 S.sell ? S.sval32 : nullptr, &rres, kLockFrac * tol * anorm, S.tile_chunk));
                 CK(hipStreamSynchronize(s));
                 S.st.t_polish += now() - tp;
                 S.st.polish_bytes += pbytes;
@@ -644,6 +644,8 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     const double tol = o.tol > 0 ? o.tol : kDefaultTol;
     const float *v32 = nullptr;
     CKR(ensure_val32(A, w.val32, &w.val32_src, &w.val32_nnz, &v32, s));
+    FilterTune tn;  // the tile-to-XCD mapping tuned for this matrix size, if any
+    CKR(lookup_filter_tune(A, std::max(1, o.block), false, &tn));
     const int c0 = k + g, cap = 2 * c0, ldc = (cap + 1) & ~1;
     const size_t blk = sizeof(double) * (size_t)n * ldc;
     CK(ensure_grow(w.Y, blk));
@@ -702,7 +704,8 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         double pbytes = 0.0;
         CK(hipStreamSynchronize(s));
         const double tp = now();
-        CKR(polish_apply(filt.get(), A, v32, cur, X, AX, ldc, lam, Y, s, &pbytes));
+        CKR(polish_apply(filt.get(), A, v32, cur, X, AX, ldc, lam, Y, s, &pbytes, nullptr, nullptr, &rres,
+                         kLockFrac * tol * anorm, tn.sh.chunk));
         CK(hipStreamSynchronize(s));
         st.t_polish += now() - tp;
         st.polish_bytes += pbytes;
@@ -797,6 +800,7 @@ int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         S.st.filter_cols_per_lane = used.vec;
         S.st.filter_streaming_loads = used.nt;
         S.st.filter_tile_chunk = tn.sh.chunk;
+        S.tile_chunk = tn.sh.chunk;
     }
     std::vector<ClenshawStep> gplan;
     void *stage = nullptr;
