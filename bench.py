@@ -71,14 +71,19 @@ def parse():
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "sell"],
                     help="storage the single-solve filter reads A in: CSR, a sliced ELL copy, or the "
                          "library's choice")
-    ap.add_argument("--force-shape", default=None, metavar="GW,LPR,VEC,NT",
+    ap.add_argument("--force-shape", default=None, metavar="GW,LPR,VEC,NT[,CHUNK]",
                     help="single-solve filter: use this launch configuration (columns per launch, lanes per "
-                         "row, columns per lane, nontemporal loads 0/1) instead of the tuned one")
+                         "row, columns per lane, nontemporal loads 0/1, optionally the tile-to-XCD mapping: "
+                         "0 one range per XCD, c > 0 chunks of c tiles, c < 0 pencil walk over planes of "
+                         "-c rows) instead of the tuned one")
     ap.add_argument("--unfiltered-compare", action="store_true",
                     help="also run one unfiltered block Lanczos solve of the same problem (FP64) and report "
                          "its basis size and time beside the filtered solve's")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration for HBM traffic)")
+    ap.add_argument("--filter-only", action="store_true",
+                    help="time flp_filter_apply alone (degree --degree, the solve's block width) on the "
+                         "workload's matrix: the filter SpMM's algorithmic GB/s, no eigensolve")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving form: Poisson arrival rate as a fraction of the closed-loop throughput")
     return ap.parse_args()
@@ -254,6 +259,65 @@ def check_cadence(args, r):
     """Block steps between convergence checks: --check-every, else the
     library's rule for block size r (flp_opts.check_every <= 0)."""
     return args.check_every if args.check_every > 0 else min(30, max(1, (90 + r // 2) // r))
+
+
+def bench_filter(args):
+    """The filter alone: flp_filter_apply of a degree --degree filter to a
+    random block of the solve's width on the workload's matrix (the 100^3
+    7-point operator at r = 8, or the 120^3 13-point Hamiltonian at
+    r = 16), in the tuned launch configuration the solves use.  One step is
+    one application (degree Clenshaw steps); its algorithmic bytes are
+    degree x B with B = nnz (w + 4) + 4 (n + 1) + 4 n r w (w = 8 in FP64,
+    4 in FP32), timed with HIP events on the launching stream."""
+    import torch
+    from paper_2409_15053_amd import flp
+    from paper_2409_15053_amd import inputs as I
+    spec = WORKLOADS[args.workload]
+    if spec["kind"] == "c3":
+        A, r, what = I.workload_c3(spec["N"])["A"], 16, f"13-point 4th-order Laplacian {spec['N']}^3 + 16 wells"
+    else:
+        A, r, what = I.workload_c2(spec["N"])["A"], 8, f"7-point Laplacian {spec['N']}^3 + U[0,1)"
+    prec = flp.FLP_PREC_FP32_FILTER if args.prec == "fp32" else flp.FLP_PREC_FP64
+    wv = 4 if prec == flp.FLP_PREC_FP32_FILTER else 8
+    # Gershgorin bounds of the spectrum and an interval in its lowest tenth
+    d = np.abs(A.val)
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    diag = np.zeros(A.n)
+    on = A.colind == rows
+    diag[rows[on]] = A.val[on]
+    rad = np.bincount(rows, weights=d, minlength=A.n) - np.abs(diag)
+    lmin, lmax = float(np.min(diag - rad)), float(np.max(diag + rad))
+    alpha, beta = lmin + 0.01 * (lmax - lmin), lmin + 0.1 * (lmax - lmin)
+    filt = flp.flp_build_filter(alpha, beta, args.degree, lmin, lmax)
+    dA = flp.DeviceCsr.from_host(A, "cuda:0", with_fp32=True)
+    V = torch.from_numpy(I.random_block(A.n, r, I.BASE_SEED + 9)).to("cuda:0")
+    W = torch.empty_like(V)
+    tune = flp.flp_tune_filter(dA, r, prec, format=fmt_code(flp, args))
+    for _ in range(max(1, args.warmup)):
+        flp.flp_filter_apply(filt, dA, V, W, prec=prec, format=fmt_code(flp, args))
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for i in range(args.steps):
+        flp.flp_filter_apply(filt, dA, V, W, prec=prec, format=fmt_code(flp, args), stream=s)
+        print(f"# filter application {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+    e1.record(s)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / args.steps
+    B = A.nnz * (wv + 4) + 4 * (A.n + 1) + 4 * A.n * r * wv
+    gbs = args.degree * B / sec / 1e9
+    launches = args.degree * r // tune["group_width"]
+    out = {"metric": METRIC, "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if wv == 4 else "f64", "data": "synthetic",
+           "config": {"workload": f"filter only: {what}, n={A.n}, nnz={A.nnz}, block {r}, degree {args.degree}",
+                      "n": A.n, "nnz": A.nnz, "block": r, "degree": args.degree, "format": args.format,
+                      "prec": args.prec},
+           "filter": {"GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS, "bytes_per_step_of_r_columns": B,
+                      "avg_step_us": sec / args.degree * 1e6, "launches_per_application": launches,
+                      "avg_launch_us": sec / launches * 1e6, "tuned": tune}}
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):
@@ -614,6 +678,12 @@ def main():
                           "copy_GBps_read_plus_write": 2 * (1 << 30) / sec / 1e9}), flush=True)
         return
     flp.load()
+    if args.force_shape:
+        f = [int(x) for x in args.force_shape.split(",")]
+        flp.flp_set_filter_shape(lanes_per_row=f[1], cols_per_lane=f[2], group_width=f[0], streaming_loads=bool(f[3]),
+                                 tile_chunk=f[4] if len(f) > 4 else flp.FLP_TILE_CHUNK_TUNED)
+    if args.filter_only:
+        return bench_filter(args)
     if WORKLOADS[args.workload]["kind"] == "batch":
         return bench_batch(args)
     if WORKLOADS[args.workload]["kind"] == "serve":
@@ -622,9 +692,6 @@ def main():
         return bench_c3(args)
     w, alpha, beta, ref = load_workload(args.workload)
     A = w["A"]
-    if args.force_shape:
-        gw, lpr, vec, nt = (int(x) for x in args.force_shape.split(","))
-        flp.flp_set_filter_shape(lanes_per_row=lpr, cols_per_lane=vec, group_width=gw, streaming_loads=bool(nt))
     prec = flp.FLP_PREC_FP32_FILTER if args.prec == "fp32" else flp.FLP_PREC_FP64
     dA = flp.DeviceCsr.from_host(A, "cuda:0", with_fp32=(prec == flp.FLP_PREC_FP32_FILTER))
     torch.cuda.synchronize()

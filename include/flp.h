@@ -256,24 +256,41 @@ typedef struct flp_tune_info {
     int32_t streaming_loads; /* 1: V and U_{k+2} are read with nontemporal loads */
     double us_per_step;    /* measured microseconds of one step over all r columns (0 if not timed) */
     int32_t tile_chunk;    /* tile-to-XCD mapping: 0 = one contiguous range of row tiles per XCD;
-                              c > 0 = chunks of c consecutive row tiles dealt to the 8 XCDs in turn */
+                              c > 0 = chunks of c consecutive row tiles dealt to the 8 XCDs in turn;
+                              c < 0 = pencil walk over planes of -c rows: each plane (the rows of one
+                              z-plane of a 3D grid in natural order) is cut into 8 column ranges
+                              and XCD x takes range x plane after plane, so a row's neighbours in
+                              the planes above and below stay in that XCD's L2 */
 } flp_tune_info;
 
-/* Autotuner.  The first time a (device, precision, r, size class)
- * combination is filtered (size class: n to a quarter octave and nonzeros
- * per row to a quarter), every supported launch shape (rows per wavefront,
- * columns per lane, ordinary or nontemporal loads of the streamed operands)
- * and column-group width is timed on the caller's matrix
+/* Host evaluation of the tile-to-XCD traversal the filter kernels use (the
+ * mapping tile_chunk selects): order[b] = the row tile that workgroup b of
+ * a launch of `tiles` workgroups processes, rows_per_tile matrix rows per
+ * tile (for tile_chunk < 0 the plane holds round(-tile_chunk /
+ * rows_per_tile) tiles).  Every mapping is a permutation of [0, tiles).
+ * order: HOST int32[tiles].  Host only; needs no device.  Errors: FLP_E_ARG
+ * (tiles < 0, rows_per_tile < 1, order NULL). */
+int flp_tile_order(int32_t tiles, int32_t tile_chunk, int32_t rows_per_tile, int32_t *order);
+
+/* Autotuner.  The first time a (device, precision, r, storage, size class,
+ * plane length) combination is filtered (size class: n to a quarter octave
+ * and nonzeros per row to a quarter; plane length: the smallest distance
+ * |j - i| >= 1024 from the middle row i to one of its columns j, a 3D
+ * grid's N^2), every supported launch shape (rows per wavefront,
+ * columns per lane, ordinary or nontemporal loads of the streamed operands),
+ * tile-to-XCD mapping (tile_chunk, including the pencil walk over planes of
+ * that length) and column-group width is timed on the caller's matrix
  * over a short ring of filter steps and the fastest is kept for the process
  * (timings taken while other work shares the GPU may pick a slower shape,
  * never a different result); the batched
  * and serving engines tune the shape of their segmented launches on the
  * largest active matrix.  All configurations compute every output element
  * with the same operations in the same order, so results are bit-identical.
- * flp_tune_filter runs (or looks up) that tuning for r columns of A and
- * reports the choice.  A: as for flp_solve (val32 may be NULL).  Synchronises
- * the stream.  Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
-int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp_tune_info *out);
+ * flp_tune_filter runs (or looks up) that tuning for r columns of A read in
+ * storage `format` (as flp_filter_apply's) and reports the choice.  A: as
+ * for flp_solve (val32 may be NULL).  Synchronises the stream.  Errors:
+ * FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
+int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, int32_t format, void *stream, flp_tune_info *out);
 
 /* The launch shape a filter step runs with, before any tuning: for one
  * solve's kernel (segmented = 0) or the batched engine's segmented kernel
@@ -290,12 +307,16 @@ int flp_filter_launch_shape(int32_t r, int32_t prec, int32_t segmented, flp_tune
  * 256 MB Infinity Cache). */
 void flp_set_autotune(int32_t on);
 
+/* tile_chunk value of flp_set_filter_shape that leaves the mapping to the tuner */
+#define FLP_TILE_CHUNK_TUNED INT32_MIN
+
 /* Forces one configuration for every later filter launch (testing and
- * measurement); lanes_per_row = 0, group_width = 0 and tile_chunk < 0
- * restore tuning.  A shape with no kernel for a given width falls back to
- * the default shape (keeping tile_chunk); a group width that does not
- * divide r is ignored; streaming_loads = 1 reads V and U_{k+2} with
- * nontemporal loads; tile_chunk as in flp_tune_info (>= 0 forces it). */
+ * measurement); lanes_per_row = 0, group_width = 0 and tile_chunk =
+ * FLP_TILE_CHUNK_TUNED restore tuning.  A shape with no kernel for a given
+ * width falls back to the default shape (keeping tile_chunk); a group width
+ * that does not divide r is ignored; streaming_loads = 1 reads V and
+ * U_{k+2} with nontemporal loads; tile_chunk as in flp_tune_info (any other
+ * value than FLP_TILE_CHUNK_TUNED forces it). */
 void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
                           int32_t streaming_loads, int32_t tile_chunk);
 

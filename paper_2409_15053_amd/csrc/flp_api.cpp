@@ -126,11 +126,20 @@ int flp_filter_launch_shape(int32_t r, int32_t prec, int32_t segmented, flp_tune
     return FLP_OK;
 }
 
-int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp_tune_info *out) {
+int flp_tile_order(int32_t tiles, int32_t tile_chunk, int32_t rows_per_tile, int32_t *order) {
+    if (tiles < 0 || rows_per_tile < 1 || (tiles > 0 && !order))
+        return fail(FLP_E_ARG, "tiles >= 0, rows_per_tile >= 1 and order non-NULL required");
+    tile_order_host(tiles, tile_chunk, rows_per_tile, order);
+    return FLP_OK;
+}
+
+int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, int32_t format, void *stream, flp_tune_info *out) {
     if (!out) return fail(FLP_E_ARG, "out is NULL");
     CKR(check_csr(A));
     if (r < 1 || r > 32) return fail(FLP_E_ARG, "r must be in [1, 32]");
     if (prec != FLP_PREC_FP64 && prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
+    if (format != FLP_FORMAT_AUTO && format != FLP_FORMAT_CSR && format != FLP_FORMAT_SELL)
+        return fail(FLP_E_ARG, "bad storage format");
     try {
         hipStream_t s = (hipStream_t)stream;
         Workspace &w = ws();
@@ -143,8 +152,12 @@ int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, void *stream, flp
         const float *v32 = nullptr;
         if (fp32) CKR(ensure_val32(A, w.val32, &w.val32_src, &w.val32_nnz, &v32, s));
         void *U[3] = {w.U[0].p, w.U[1].p, w.U[2].p};
+        const flp_csr *fA = A;
+        const float *fv32 = v32;
+        bool sell = false;
+        CKR(workspace_storage(A, v32, fp32, format, s, &fA, &fv32, &sell));
         FilterTune tn;
-        CKR(tune_filter(A, v32, r, fp32, true, U, w.Vg.p, r, s, &tn));
+        CKR(tune_filter(fA, fv32, r, fp32, true, U, w.Vg.p, r, s, &tn, sell));
         CK(hipStreamSynchronize(s));
         StepShape sh = step_shape_ok(tn.gw, fp32, tn.sh) ? tn.sh : default_step_shape(tn.gw, fp32);
         out->group_width = tn.gw;
@@ -165,9 +178,10 @@ void flp_set_autotune(int32_t on) { set_autotune(on); }
 
 void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
                           int32_t streaming_loads, int32_t tile_chunk) {
+    const bool chunk = tile_chunk != FLP_TILE_CHUNK_TUNED;
     force_filter_shape(StepShape{std::max(0, (int)lanes_per_row), std::max(0, (int)cols_per_lane),
-                                 streaming_loads ? 1 : 0, std::max(0, (int)tile_chunk)},
-                       std::max(0, (int)group_width), tile_chunk >= 0);
+                                 streaming_loads ? 1 : 0, chunk ? (int)tile_chunk : 0},
+                       std::max(0, (int)group_width), chunk);
 }
 
 int flp_spmm(const flp_csr *A, const double *X, int32_t ldx, double *Y, int32_t ldy, int32_t r, void *stream) {

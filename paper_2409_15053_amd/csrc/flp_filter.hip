@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void cheb_step_kernel(
     int ldv, const T *__restrict__ Y, int ldy, Tout *__restrict__ out, int ldo, T alpha, T beta,
     T gamma, T delta, int chunk) {
     constexpr int RPB = 256 / LPR;  // rows per block
-    const int tile = chunk_tile(blockIdx.x, gridDim.x, chunk);
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, chunk, RPB);
     const int row = tile * RPB + threadIdx.x / LPR;
     const int sub = threadIdx.x % LPR;
     const int c0 = sub * VEC;
@@ -303,6 +303,10 @@ template hipError_t launch_cheb_step<float, double>(int, const int32_t *, const 
                                                     double *, int, float, float, float, float, hipStream_t,
                                                     StepShape, bool);
 
+void tile_order_host(int tiles, int chunk, int rows_per_tile, int32_t *order) {
+    for (int b = 0; b < tiles; ++b) order[b] = chunk_tile(b, tiles, chunk, rows_per_tile);
+}
+
 hipError_t launch_sell_fill(int n, const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
                             const int32_t *off, int nslices, int32_t *col, double *val64, float *val32,
                             hipStream_t s) {
@@ -330,7 +334,7 @@ template <typename T, int LPR, int VEC, bool NT>
 __global__ __launch_bounds__(256) void cheb_seg_kernel(const SegEntry *__restrict__ tab, int nseg, int r,
                                                        int chunk) {
     constexpr int RPB = 256 / LPR;
-    const int tile = chunk_tile(blockIdx.x, gridDim.x, chunk);
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, chunk > 0 ? chunk : 0, RPB);  // no plane walk across segments
     // The segment holding this tile: the tile offsets ascend, so the
     // segments starting at or before the tile are a prefix; each wave counts
     // it 64 segments at a time with one load per lane and a ballot.  The

@@ -576,6 +576,39 @@ int filter_group_width(int n, int64_t nnz, int r, int prec) {
 
 // W = p(Ahat) V with the workspace's Clenshaw buffers (V, W: n x r with
 // leading dimensions ldv, ldw), filtered in column groups.
+// The storage the calling thread's filter products read A in: A itself, or
+// its sliced ELL copy in the workspace (built once per matrix and precision,
+// then reused) when format asks for it (FLP_FORMAT_AUTO: only if padding
+// adds under kSellMaxPad).
+int workspace_storage(const flp_csr *A, const float *v32, bool fp32, int format, hipStream_t s,
+                      const flp_csr **fA, const float **fv32, bool *sell) {
+    Workspace &w = ws();
+    *fA = A;
+    *fv32 = v32;
+    *sell = false;
+    if (format == FLP_FORMAT_CSR) return FLP_OK;
+    const bool same = w.sell_valid && w.sell_fp32 == fp32 && w.sell_src.n == A->n && w.sell_src.nnz == A->nnz &&
+                      w.sell_src.rowptr == A->rowptr && w.sell_src.colind == A->colind &&
+                      w.sell_src.val == A->val && w.sell_src.val32 == v32;
+    if (!same) {
+        w.sell_valid = false;
+        bool built = false;
+        CKR(build_sell(A, v32, fp32, w.sell_off, w.sell_col, w.sell_val, &w.sell_A, &w.sell_val32, s,
+                       format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad, &built));
+        w.sell_src = *A;
+        w.sell_src.val32 = v32;
+        w.sell_fp32 = fp32;
+        w.sell_built = built;
+        w.sell_valid = true;
+    }
+    if (w.sell_built) {
+        *sell = true;
+        *fA = &w.sell_A;
+        *fv32 = w.sell_val32;
+    }
+    return FLP_OK;
+}
+
 int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, int ldv, double *W, int ldw, int r,
                       int prec, hipStream_t s, int format) {
     Workspace &w = ws();
@@ -594,32 +627,10 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
         vfull = w.V32.p;
         ldfull = r;
     }
-    // the storage the products read: A, or its sliced ELL copy (built once
-    // per matrix and precision, then reused)
     const flp_csr *fA = A;
     const float *fv32 = v32;
     bool sell = false;
-    if (format != FLP_FORMAT_CSR) {
-        const bool same = w.sell_valid && w.sell_fp32 == fp32 && w.sell_src.n == A->n && w.sell_src.nnz == A->nnz &&
-                          w.sell_src.rowptr == A->rowptr && w.sell_src.colind == A->colind &&
-                          w.sell_src.val == A->val && w.sell_src.val32 == v32;
-        if (!same) {
-            w.sell_valid = false;
-            bool built = false;
-            CKR(build_sell(A, v32, fp32, w.sell_off, w.sell_col, w.sell_val, &w.sell_A, &w.sell_val32, s,
-                           format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad, &built));
-            w.sell_src = *A;
-            w.sell_src.val32 = v32;
-            w.sell_fp32 = fp32;
-            w.sell_built = built;
-            w.sell_valid = true;
-        }
-        if (w.sell_built) {
-            sell = true;
-            fA = &w.sell_A;
-            fv32 = w.sell_val32;
-        }
-    }
+    CKR(workspace_storage(A, v32, fp32, format, s, &fA, &fv32, &sell));
     FilterTune tn;
     CKR(tune_filter(fA, fv32, r, fp32, true, U, vfull, ldfull, s, &tn, sell));
     const int gw = tn.gw;

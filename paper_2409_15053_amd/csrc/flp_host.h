@@ -191,9 +191,15 @@ struct FilterTune {
 // (scratch, overwritten); V: n x r input block (read only, ld ldv).
 int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool allow_groups, void *const U[3],
                 const void *V, int ldv, hipStream_t s, FilterTune *out, bool sell = false);
-// The cached tuning of a CSR filter over all r columns at once (no column
-// groups) for A's size class, or the default shape; never times anything.
+// The cached tuning of a filter over r columns for A's size class and plane
+// length (a single solve's first, then the segmented engine's), or the
+// default shape; never times anything.  Callers use its tile mapping.
 int lookup_filter_tune(const flp_csr *A, int r, bool fp32, FilterTune *out);
+// The plane length the tuner's pencil walk uses for A: the smallest
+// distance |j - i| >= 1024 between the middle row i and one of its columns
+// j (a 3D grid's N^2 in natural order), or 0.  sell: A is a sliced ELL copy.
+// Synchronises stream s.
+int plane_rows(const flp_csr *A, bool sell, hipStream_t s, int *out);
 void set_autotune(int mode);
 int autotune_mode();
 // chunk: sh.chunk is forced too (else only the shape and width)
@@ -205,6 +211,10 @@ void force_filter_shape(StepShape sh, int gw, bool chunk);
 // workspace, keyed by A's arrays).
 int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, int ldv, double *W, int ldw, int r,
                       int prec, hipStream_t s, int format = FLP_FORMAT_CSR);
+// The storage the calling thread's filter products read A in for `format`:
+// *fA = A (and *fv32 = v32), or the workspace's sliced ELL copy of A (*sell).
+int workspace_storage(const flp_csr *A, const float *v32, bool fp32, int format, hipStream_t s,
+                      const flp_csr **fA, const float **fv32, bool *sell);
 // Y = p(Ahat) X for c Ritz vectors of A (X, AX = A X, Ritz values lam;
 // n x c blocks with leading dimension ldc) by the residual form: X diag(p(t))
 // in FP64 plus the divided-difference recurrences on the residuals in FP32

@@ -89,6 +89,10 @@ inline DMat panel_mat(const double *p, int64_t n, int lpw) {
 struct StepShape {
     int lpr = 0, vec = 0, nt = 0, chunk = 0;
 };
+// Host evaluation of the tile-to-XCD traversal the filter kernels use:
+// order[b] = the row tile that block b of a `tiles`-block launch processes
+// (chunk as in StepShape::chunk; rows_per_tile rows per tile).
+void tile_order_host(int tiles, int chunk, int rows_per_tile, int32_t *order);
 StepShape default_step_shape(int r, bool fp32);
 std::vector<StepShape> step_shape_candidates(int r, bool fp32);
 bool step_shape_ok(int r, bool fp32, StepShape sh);

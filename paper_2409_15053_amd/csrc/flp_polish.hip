@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
                                                           const int *__restrict__ cols,
                                                           const double *__restrict__ ptheta, int chunk) {
     constexpr int UNR = 8;
-    const int row = chunk_tile(blockIdx.x, gridDim.x, chunk) * PRB + threadIdx.x / PL;
+    const int row = chunk_tile(blockIdx.x, gridDim.x, chunk, PRB) * PRB + threadIdx.x / PL;
     if (row >= n) return;
     const int c0 = (threadIdx.x % PL) * PV;
     float acc[PV] = {0.0f, 0.0f, 0.0f, 0.0f};

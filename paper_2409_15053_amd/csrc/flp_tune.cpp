@@ -13,8 +13,12 @@
 // (the pattern of the real recurrence: gather one buffer, read V and a
 // second buffer, write the third), after one untimed ring; among those within
 // 3 % of the fastest the widest column group is kept.  Results are cached
-// per device, precision, r, grouping allowed and size class (n to a quarter
-// octave, nonzeros per row to a quarter).  Every shape and
+// per device, precision, r, grouping allowed, storage, size class (n to a
+// quarter octave, nonzeros per row to a quarter) and plane length (below).
+// The order in which the row tiles are handed to the XCDs is tuned too
+// (chunk_tile): for a single solve this includes a pencil walk over planes
+// of P rows, P being the nearest neighbour distance of at least 1024 rows in
+// a middle row of the matrix (a 3D grid's N^2).  Every shape and
 // width computes each output element with the same operations in the same
 // order, so tuning never changes results, only speed.
 #include <hip/hip_runtime.h>
@@ -35,14 +39,17 @@ namespace {
 
 std::atomic<int> g_mode{1};  // 1: tune on first use, 0: fixed defaults
 // tile-to-XCD mappings tried (chunk_tile): one contiguous range per XCD, or
-// chunks of this many tiles dealt to the XCDs in turn
+// chunks of this many tiles dealt to the XCDs in turn; a single solve's
+// filter also tries the pencil walk over the matrix's planes (plane_rows)
 constexpr int kTileChunks[] = {0, 4, 32};
+// smallest neighbour distance (in rows) taken for a plane of a grid
+constexpr int kMinPlaneRows = 1024;
 std::mutex g_mu;
 StepShape g_force_shape{};
 int g_force_gw = 0;
 bool g_force_chunk = false;
 
-using Key = std::tuple<int, int, int, int64_t, int64_t, int, int>;
+using Key = std::tuple<int, int, int, int64_t, int64_t, int, int, int>;
 std::map<Key, FilterTune> &cache() {
     static std::map<Key, FilterTune> c;
     return c;
@@ -74,6 +81,40 @@ int ring(const flp_csr *A, const float *val32, bool fp32, int gw, StepShape sh, 
 
 }  // namespace
 
+int plane_rows(const flp_csr *A, bool sell, hipStream_t s, int *out) {
+    *out = 0;
+    const int n = A->n;
+    if (n < 2 * kMinPlaneRows) return FLP_OK;
+    const int row = n / 2;
+    int32_t rp[2] = {0, 0};
+    std::vector<int32_t> cols;
+    if (sell) {  // rowptr holds slice offsets; entry k of the row at off + row % C + k C
+        const int sl = row / kSellC;
+        CK(hipMemcpyAsync(rp, A->rowptr + sl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        const int w = std::min(64, (rp[1] - rp[0]) / kSellC);
+        cols.resize(w);
+        for (int k = 0; k < w; ++k)
+            CK(hipMemcpyAsync(&cols[k], A->colind + rp[0] + row % kSellC + (int64_t)k * kSellC, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+    } else {
+        CK(hipMemcpyAsync(rp, A->rowptr + row, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        const int w = std::min(64, rp[1] - rp[0]);
+        cols.resize(std::max(0, w));
+        if (w > 0)
+            CK(hipMemcpyAsync(cols.data(), A->colind + rp[0], sizeof(int32_t) * w, hipMemcpyDeviceToHost, s));
+    }
+    CK(hipStreamSynchronize(s));
+    int best = 0;
+    for (int32_t c : cols) {
+        const int d = std::abs(c - row);
+        if (d >= kMinPlaneRows && (best == 0 || d < best)) best = d;
+    }
+    *out = best;
+    return FLP_OK;
+}
+
 void set_autotune(int mode) { g_mode.store(mode ? 1 : 0); }
 int autotune_mode() { return g_mode.load(); }
 
@@ -93,11 +134,20 @@ int lookup_filter_tune(const flp_csr *A, int r, bool fp32, FilterTune *out) {
     int dev = 0;
     CK(hipGetDevice(&dev));
     const int n = A->n;
-    const Key key{dev, fp32 ? 1 : 0, r, (int64_t)std::lround(4.0 * std::log2((double)n)),
-                  (int64_t)std::lround(4.0 * (double)A->nnz / n), 0, 0};
+    int plane = 0;
+    CKR(plane_rows(A, false, nullptr, &plane));
+    const int64_t nc = std::lround(4.0 * std::log2((double)n)), zc = std::lround(4.0 * (double)A->nnz / n);
+    // a single solve's tuning (either storage) first, then the segmented engine's
+    const Key keys[] = {Key{dev, fp32 ? 1 : 0, r, nc, zc, 1, 1, plane}, Key{dev, fp32 ? 1 : 0, r, nc, zc, 1, 0, plane},
+                        Key{dev, fp32 ? 1 : 0, r, nc, zc, 0, 1, 0}, Key{dev, fp32 ? 1 : 0, r, nc, zc, 0, 0, 0}};
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = cache().find(key);
-    if (it != cache().end() && it->second.gw == r) *out = it->second;
+    for (const Key &key : keys) {
+        auto it = cache().find(key);
+        if (it != cache().end()) {
+            *out = it->second;
+            return FLP_OK;
+        }
+    }
     return FLP_OK;
 }
 
@@ -134,9 +184,13 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     }
     int dev = 0;
     CK(hipGetDevice(&dev));
-    // size class: n to a quarter octave, nonzeros per row to a quarter
+    // a single solve's filter also tries the pencil walk over the matrix's
+    // planes (the segmented engine's tiles span many matrices)
+    int plane = 0;
+    if (allow_groups) CKR(plane_rows(A, sell, s, &plane));
+    // size class: n to a quarter octave, nonzeros per row to a quarter; plane
     const Key key{dev, fp32 ? 1 : 0, r, (int64_t)std::lround(4.0 * std::log2((double)n)),
-                  (int64_t)std::lround(4.0 * (double)A->nnz / n), allow_groups ? 1 : 0, sell ? 1 : 0};
+                  (int64_t)std::lround(4.0 * (double)A->nnz / n), allow_groups ? 1 : 0, sell ? 1 : 0, plane};
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = cache().find(key);
@@ -164,11 +218,16 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     for (int gw = r; gw >= 1; gw /= 2) {
         if (r % gw != 0 || (gw != r && !allow_groups)) continue;
         std::vector<StepShape> cands;
-        for (StepShape sh : step_shape_candidates(gw, fp32))
+        for (StepShape sh : step_shape_candidates(gw, fp32)) {
             for (int ch : kTileChunks) {
                 sh.chunk = ch;
                 cands.push_back(sh);
             }
+            if (plane > 0) {
+                sh.chunk = -plane;
+                cands.push_back(sh);
+            }
+        }
         for (StepShape sh : cands) {
             // V: the caller's block (gw == r) or a contiguous n x gw group,
             // taken from the unused half of the first buffer

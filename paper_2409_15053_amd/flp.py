@@ -32,7 +32,7 @@ FLP_FORMAT_SELL = 2
 EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
     "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval", "flp_filter_divided",
-    "flp_filter_apply", "flp_filter_launch_shape", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
+    "flp_filter_apply", "flp_filter_launch_shape", "flp_tile_order", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_sliced", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_set_allocator", "flp_check_symmetric", "flp_last_error", "flp_version",
     "flp_abi_sizes",
@@ -130,7 +130,9 @@ def load(path: str = LIB_PATH):
         "flp_filter_divided": (I32, [P, F64, P, I32]),
         "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, I64, P, I64, I32, I32, I32, P]),
         "flp_filter_launch_shape": (ctypes.c_int, [I32, I32, I32, ctypes.POINTER(FlpTuneInfoC)]),
-        "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, P, ctypes.POINTER(FlpTuneInfoC)]),
+        "flp_tile_order": (ctypes.c_int, [I32, I32, I32, P]),
+        "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, I32, P,
+                                           ctypes.POINTER(FlpTuneInfoC)]),
         "flp_set_autotune": (None, [I32]),
         "flp_set_filter_shape": (None, [I32, I32, I32, I32, I32]),
         "flp_spmm": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), P, I32, P, I32, I32, P]),
@@ -289,10 +291,19 @@ def flp_filter_launch_shape(r: int, prec: int = FLP_PREC_FP64, segmented: bool =
     return {f: getattr(info, f) for f, _ in FlpTuneInfoC._fields_}
 
 
-def flp_tune_filter(A: DeviceCsr, r: int, prec: int = FLP_PREC_FP64, stream=None) -> dict:
-    """The filter launch configuration for r columns of A (tuned on first use)."""
+def flp_tile_order(tiles: int, tile_chunk: int, rows_per_tile: int) -> np.ndarray:
+    """Row tile processed by each workgroup of a filter launch (host only)."""
+    out = np.zeros(max(0, tiles), dtype=np.int32)
+    _check(load().flp_tile_order(tiles, tile_chunk, rows_per_tile, _np_ptr(out)))
+    return out
+
+
+def flp_tune_filter(A: DeviceCsr, r: int, prec: int = FLP_PREC_FP64, stream=None,
+                    format: int = FLP_FORMAT_CSR) -> dict:
+    """The filter launch configuration for r columns of A read in storage
+    ``format`` (tuned on first use)."""
     info = FlpTuneInfoC()
-    _check(load().flp_tune_filter(ctypes.byref(A.c), r, prec, _stream_ptr(stream), ctypes.byref(info)))
+    _check(load().flp_tune_filter(ctypes.byref(A.c), r, prec, format, _stream_ptr(stream), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in FlpTuneInfoC._fields_}
 
 
@@ -300,10 +311,14 @@ def flp_set_autotune(on: bool):
     load().flp_set_autotune(1 if on else 0)
 
 
+FLP_TILE_CHUNK_TUNED = -(1 << 31)
+
+
 def flp_set_filter_shape(lanes_per_row: int = 0, cols_per_lane: int = 0, group_width: int = 0,
-                         streaming_loads: bool = False, tile_chunk: int = -1):
-    """Force one filter launch configuration (all zeros and tile_chunk < 0:
-    back to tuning).  tile_chunk >= 0 forces the tile-to-XCD mapping."""
+                         streaming_loads: bool = False, tile_chunk: int = FLP_TILE_CHUNK_TUNED):
+    """Force one filter launch configuration (all zeros and tile_chunk =
+    FLP_TILE_CHUNK_TUNED: back to tuning).  Any other tile_chunk forces the
+    tile-to-XCD mapping (< 0: the pencil walk over planes of -tile_chunk rows)."""
     load().flp_set_filter_shape(lanes_per_row, cols_per_lane, group_width, 1 if streaming_loads else 0,
                                 tile_chunk)
 

@@ -200,3 +200,37 @@ def test_filter_launch_shape_covers_every_column(prec, segmented):
         flp.flp_filter_launch_shape(0, prec, segmented)
     with pytest.raises(flp.FlpError):
         flp.flp_filter_launch_shape(33, prec, segmented)
+
+
+@pytest.mark.parametrize("tiles", [0, 1, 7, 8, 9, 63, 64, 225, 1000, 27000, 27001, 15625, 15626])
+@pytest.mark.parametrize("chunk,rpt", [(0, 64), (4, 64), (32, 32), (-14400, 64), (-10000, 64), (-10000, 32),
+                                       (-28800, 64), (-512, 64), (-1024, 16), (-1 << 20, 64)])
+def test_tile_order_is_a_permutation(tiles, chunk, rpt):
+    """Every tile-to-XCD traversal of the filter kernels hands each row tile
+    to exactly one workgroup (ragged plane counts, planes of fewer than 8
+    tiles, planes longer than the launch, partial last planes)."""
+    order = flp.flp_tile_order(tiles, chunk, rpt)
+    assert np.array_equal(np.sort(order), np.arange(tiles))
+
+
+def test_tile_order_pencil_walk():
+    """The pencil walk over planes of 225 tiles (the 120^3 grid's planes of
+    14 400 rows at 64 rows per tile): workgroup b runs on XCD b % 8, and the
+    workgroups of XCD x, in dispatch order, take the x-th eighth of the
+    walk that goes through pencil 0 (columns 0..27 of every plane) plane
+    after plane, then pencil 1, ..., pencil 7 (columns 196..224), then the
+    tiles past the last full plane."""
+    for G in (27000, 27000 + 100):
+        PT = 225
+        Z = G // PT
+        lo = [p * PT // 8 for p in range(9)]
+        walk = [z * PT + c for p in range(8) for z in range(Z) for c in range(lo[p], lo[p + 1])]
+        walk += list(range(Z * PT, G))
+        order = flp.flp_tile_order(G, -14400, 64)
+        start = 0
+        for x in range(8):
+            cnt = G // 8 + (1 if x < G % 8 else 0)
+            assert np.array_equal(order[x::8], walk[start:start + cnt])
+            start += cnt
+    with pytest.raises(flp.FlpError):
+        flp.flp_tile_order(10, 0, 0)

@@ -145,13 +145,16 @@ def test_filter_apply_ragged_large_grid(torch):
 
 
 SHAPE_CASES = {
-    # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams, tile chunk)
+    # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams, tile chunk);
+    # a negative tile chunk is the pencil walk over planes of that many rows (the 23^3 grid's 529)
     (8, flp.FLP_PREC_FP64): [(4, 2, 8, 0, 0), (2, 4, 8, 1, 4), (1, 8, 8, 0, 32), (2, 2, 4, 1, 1), (1, 4, 4, 0, 7),
-                             (1, 2, 2, 1, 0)],
+                             (1, 2, 2, 1, 0), (4, 2, 8, 1, -529), (2, 2, 4, 0, -1058)],
     (16, flp.FLP_PREC_FP64): [(8, 2, 16, 1, 0), (4, 4, 16, 0, 4), (2, 8, 16, 1, 32), (4, 2, 8, 0, 5),
-                              (2, 4, 8, 1, 0), (1, 8, 8, 0, 1)],
-    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1, 0), (1, 8, 8, 0, 4), (1, 4, 4, 1, 32)],
-    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0, 0), (2, 8, 16, 1, 4), (2, 4, 8, 1, 3), (1, 8, 8, 0, 32)],
+                              (2, 4, 8, 1, 0), (1, 8, 8, 0, 1), (4, 4, 16, 0, -529), (8, 2, 16, 1, -529),
+                              (4, 4, 16, 1, -1058)],
+    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1, 0), (1, 8, 8, 0, 4), (1, 4, 4, 1, 32), (2, 4, 8, 0, -529)],
+    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0, 0), (2, 8, 16, 1, 4), (2, 4, 8, 1, 3), (1, 8, 8, 0, 32),
+                                     (4, 4, 16, 1, -529)],
 }
 
 
@@ -181,7 +184,7 @@ def test_filter_launch_shapes_bit_identical(torch, r, prec):
                 outs.append(((lpr, vec, gw, nt, ch, fmt), W))
         flp.flp_set_filter_shape(0, 0, 0)
         flp.flp_set_autotune(True)
-        info = flp.flp_tune_filter(dA, r, prec)
+        info = flp.flp_tune_filter(dA, r, prec, format=flp.FLP_FORMAT_CSR)
         assert info["candidates"] >= 2 and info["us_per_step"] > 0
         assert r % info["group_width"] == 0
         assert info["lanes_per_row"] * info["cols_per_lane"] == info["group_width"]
