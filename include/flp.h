@@ -117,16 +117,19 @@ typedef struct flp_opts {
                              flp_result.evecs), or NULL.  Warm start for a sequence of related
                              problems (the self-consistent-field loops of Section 1: each matrix
                              a small change of the previous one): the previous eigenvectors
-                             and warm_count / 4 (at least 2 block) random guard columns are
+                             and warm_count / 2 (at least 2 block) random guard columns are
                              refined by subspace iteration with the filter (each sweep
                              X <- p(Ahat) X in FP64 accuracy by the residual form, orthonormalise,
-                             Rayleigh-Ritz with A) instead of a Lanczos run.  It stops when every
-                             Ritz pair inside [alpha, beta] meets tol, their count did not change
-                             since the previous sweep, and at least half the guard columns have
-                             settled on Ritz values whose filter value is below the candidate
-                             threshold tau (the block reaches past the interval's transition
-                             band); otherwise, after 8 sweeps, the call falls back to the cold
-                             solve.  stats.warm_status says which ran. */
+                             Rayleigh-Ritz with A; degree max(polish_degree or degree, 20))
+                             instead of a Lanczos run.  It stops when every Ritz pair inside
+                             [alpha, beta] meets tol, their count did not change since the
+                             previous sweep, and at least two Ritz pairs outside the interval
+                             have settled (residual <= 1e-4 ||A||) on values whose filter value
+                             is below the candidate threshold tau (the block reaches past the
+                             interval's transition band, so no eigenvalue inside is left out).
+                             While no guard gets past the band the guards are doubled, at most
+                             twice; after 16 sweeps the call falls back to the cold solve.
+                             stats.warm_status says which ran. */
     int32_t warm_count;   /* columns of warm (0: cold start) */
 } flp_opts;
 

@@ -602,16 +602,28 @@ void release_single_bufs() {
 
 namespace {
 
-constexpr int kMaxWarmSweeps = 8;
-constexpr int kWarmFallback = 1;  // solve_warm: not certified, the cold solve runs
+constexpr int kMaxWarmSweeps = 16;
+constexpr int kWarmMinDegree = 20;     // lowest filter degree of the warm sweeps
+constexpr int kWarmSettledGuards = 2;  // settled guard pairs past the transition band that certify
+constexpr int kWarmFallback = 1;       // solve_warm: not certified, the cold solve runs
 
 // Subspace iteration with the filter from [previous eigenvectors, random
 // guards] (flp_opts.warm): X <- p(Ahat) X by the residual form (FP32
 // recurrences on the FP64 residuals, FP64 accuracy), orthonormalise, and
-// Rayleigh-Ritz with A, until the Ritz pairs inside [alpha, beta] meet the
-// tolerance, their count repeats, and at least half the guard columns sit on
-// Ritz values with |p| < tau (past the transition band).  Returns FLP_OK
-// with *out, kWarmFallback, or an error code.
+// Rayleigh-Ritz with A.  Subspace iteration captures the eigenvectors in the
+// order of |p(lambda)|, and every eigenvalue inside [alpha, beta] has
+// p >= 2 tau, so once the block holds settled Ritz pairs outside the
+// interval with |p| < tau (past the transition band), no eigenvalue of the
+// interval is left out.  The call certifies its result when the Ritz pairs
+// inside the interval meet the tolerance, their count repeats, and at least
+// kWarmSettledGuards pairs outside it have |p| < tau and a residual below
+// kMixedResid.  Guard columns: half the warm block (at least 2 block); when
+// the pairs inside have nearly converged (1e-6) but no guard has got past
+// the band in three sweeps, the band holds more eigenvalues than guards and
+// as many random guards again are added (up to twice the first width).
+// The filter has degree max(polish_degree or degree, kWarmMinDegree), since
+// the band of a low-degree filter holds too many eigenvalues for the guards.
+// Returns FLP_OK with *out, kWarmFallback, or an error code.
 int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, flp_result **out) {
     const double t0 = now();
     hipStream_t s = (hipStream_t)o.stream;
@@ -624,7 +636,7 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     if (o.prec != FLP_PREC_FP64 && o.prec != FLP_PREC_FP32_FILTER) return fail(FLP_E_ARG, "bad precision");
     if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
     const int r = std::max(1, o.block);
-    const int g = std::min(n - k, std::max(2 * r, (k + 3) / 4));  // guard columns
+    const int g = std::min(n - k, std::max(2 * r, (k + 1) / 2));  // guard columns
     if (g < 1) return kWarmFallback;                              // no room beside the warm block
     flp_stats st{};
     double lmin = o.lmin, lmax = o.lmax;
@@ -637,6 +649,11 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     CKR(make_filter(alpha, beta, o.polish_degree > 0 ? o.polish_degree : o.degree, lmin, lmax,
                     o.eps > 0 ? o.eps : kDefaultEps, &pf));
     std::unique_ptr<flp_filter> filt(pf);
+    if (filt->m < kWarmMinDegree) {
+        flp_filter *pf2 = nullptr;
+        CKR(make_filter(alpha, beta, kWarmMinDegree, lmin, lmax, o.eps > 0 ? o.eps : kDefaultEps, &pf2));
+        filt.reset(pf2);
+    }
     if (alpha <= lmin && beta >= lmax)
         return fail(FLP_E_ARG, "[alpha, beta] covers the whole spectrum [lmin, lmax]: the filter is the constant 1");
     const double tau = 0.5 * std::min(cheb_scalar(filt->b, filt->a1), cheb_scalar(filt->b, filt->b1));
@@ -662,7 +679,7 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     CKR(orthonormalize_cols(n, c0, Y, X, ldc, sdev, s));
     std::vector<double> lam, rres;
     CKR(rayleigh_ritz(A, n, c0, Y, AY, X, AX, ldc, sdev, lam, rres, s));
-    int cur = c0, prev_count = -1, sweeps = 0, separations = 0, i0 = 0, i1 = 0;
+    int cur = c0, prev_count = -1, sweeps = 0, separations = 0, i0 = 0, i1 = 0, last_grow = 0, grown = 0;
     auto inside = [&]() {
         i0 = 0;
         while (i0 < cur && lam[i0] < alpha) ++i0;
@@ -692,14 +709,18 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
             continue;
         }
         const int count = i1 - i0;
-        int past_band = 0;  // block Ritz values outside the transition band
+        int settled = 0;  // settled Ritz pairs outside the interval and past the transition band
         for (int j = 0; j < cur; ++j)
-            if (std::fabs(cheb_scalar(filt->b, (lam[j] - filt->c) / filt->e)) < tau) ++past_band;
-        if (sweeps >= 2 && worst <= tol && count == prev_count && past_band >= (g + 1) / 2) {
+            if ((j < i0 || j >= i1) && rres[j] / anorm <= kMixedResid &&
+                std::fabs(cheb_scalar(filt->b, (lam[j] - filt->c) / filt->e)) < tau)
+                ++settled;
+        if (sweeps >= 2 && worst <= tol && count == prev_count && settled >= kWarmSettledGuards) {
             certified = true;
             break;
         }
         if (sweeps >= kMaxWarmSweeps) break;
+        const bool grow = sweeps >= 3 && sweeps - last_grow >= 3 && settled < kWarmSettledGuards &&
+                          count == prev_count && worst <= 1e-6 && grown < 2 && cur + g <= cap;
         prev_count = count;
         double pbytes = 0.0;
         CK(hipStreamSynchronize(s));
@@ -710,6 +731,12 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         st.t_polish += now() - tp;
         st.polish_bytes += pbytes;
         st.mv += (int64_t)cur * filt->m;
+        if (grow) {  // the band holds more eigenvalues than guards: g more random guards
+            CK(launch_randn(n, g, Y + cur, ldc, o.seed + 1 + grown, 0x3A22, s));
+            cur += g;
+            last_grow = sweeps + 1;
+            ++grown;
+        }
         CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
         CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
         CKR(rayleigh_ritz(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
