@@ -248,6 +248,24 @@ int32_t flp_filter_divided(const flp_filter *p, double t, double *coeffs, int32_
 int flp_filter_apply(const flp_filter *p, const flp_csr *A, const double *V, int64_t ldv, double *W,
                      int64_t ldw, int32_t r, int32_t prec, int32_t format, void *stream);
 
+/* flp_filter_apply without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, allocation-free
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * result as flp_filter_apply with format = FLP_FORMAT_CSR (bit-identical
+ * W), except:
+ * - the Clenshaw ring buffers (and in FP32 the FP32 copy of V) live in a
+ *   fixed 24 MiB device array of the library, one per GPU, held until the
+ *   process ends; n * r must not exceed 1048576 (2^20), else FLP_E_NOMEM
+ *   before anything is launched;
+ * - FLP_PREC_FP32_FILTER needs A->val32 (FLP_E_ARG if NULL);
+ * - no tuning: the default launch shape over all r columns.
+ * Calls on one GPU share that array, so calls that overlap in time on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Nothing needs clearing: every step writes its buffer before the
+ * next one reads it.  Errors: FLP_E_ARG, FLP_E_NOMEM, FLP_E_DEVICE. */
+int flp_filter_apply_noalloc(const flp_filter *p, const flp_csr *A, const double *V, int64_t ldv, double *W,
+                             int64_t ldw, int32_t r, int32_t prec, void *stream);
+
 /* Launch configuration of the filter's sparse-matrix step (the Clenshaw
  * step of Section 2.2 as a CSR SpMM over r columns). */
 typedef struct flp_tune_info {

@@ -32,7 +32,7 @@ FLP_FORMAT_SELL = 2
 EXPORTS = [
     "flp_opts_default", "flp_build_filter", "flp_build_filter_eps", "flp_filter_free",
     "flp_filter_degree", "flp_filter_coeffs", "flp_filter_info", "flp_filter_eval", "flp_filter_divided",
-    "flp_filter_apply", "flp_filter_launch_shape", "flp_tile_order", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
+    "flp_filter_apply", "flp_filter_apply_noalloc", "flp_filter_launch_shape", "flp_tile_order", "flp_tune_filter", "flp_set_autotune", "flp_set_filter_shape", "flp_spmm", "flp_block_orth", "flp_block_qr", "flp_estimate_bounds",
     "flp_solve", "flp_solve_sliced", "flp_solve_batch", "flp_result_free", "flp_result_copy_evecs", "flp_host_sym_eig",
     "flp_release_workspace", "flp_set_allocator", "flp_check_symmetric", "flp_last_error", "flp_version",
     "flp_abi_sizes",
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH):
         "flp_filter_eval": (ctypes.c_int, [P, P, P, I32]),
         "flp_filter_divided": (I32, [P, F64, P, I32]),
         "flp_filter_apply": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, I64, P, I64, I32, I32, I32, P]),
+        "flp_filter_apply_noalloc": (ctypes.c_int, [P, ctypes.POINTER(FlpCsrC), P, I64, P, I64, I32, I32, P]),
         "flp_filter_launch_shape": (ctypes.c_int, [I32, I32, I32, ctypes.POINTER(FlpTuneInfoC)]),
         "flp_tile_order": (ctypes.c_int, [I32, I32, I32, P]),
         "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, I32, P,
@@ -282,6 +283,22 @@ def flp_filter_apply(filt: Filter, A: DeviceCsr, V, W, prec: int = FLP_PREC_FP64
         ldv, ldw = V.stride(0), W.stride(0)
     _check(load().flp_filter_apply(filt.h, ctypes.byref(A.c), V.data_ptr(), ldv, W.data_ptr(), ldw, r, prec,
                                    format, _stream_ptr(stream)))
+
+
+def flp_filter_apply_noalloc(filt: Filter, A: DeviceCsr, V, W, prec: int = FLP_PREC_FP64, stream=None):
+    """W = p(Ahat) V on the device without allocating device memory (CSR
+    storage, the library's fixed scratch array; n * r <= 2^20).  V, W as
+    for flp_filter_apply."""
+    assert V.dtype == W.dtype
+    r = 1 if V.dim() == 1 else V.shape[1]
+    if V.dim() == 1:
+        assert V.is_contiguous() and W.is_contiguous()
+        ldv = ldw = 1
+    else:
+        assert V.stride(1) == 1 and W.stride(1) == 1
+        ldv, ldw = V.stride(0), W.stride(0)
+    _check(load().flp_filter_apply_noalloc(filt.h, ctypes.byref(A.c), V.data_ptr(), ldv, W.data_ptr(), ldw, r,
+                                           prec, _stream_ptr(stream)))
 
 
 def flp_filter_launch_shape(r: int, prec: int = FLP_PREC_FP64, segmented: bool = False) -> dict:
