@@ -71,11 +71,11 @@ def parse():
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "sell"],
                     help="storage the single-solve filter reads A in: CSR, a sliced ELL copy, or the "
                          "library's choice")
-    ap.add_argument("--force-shape", default=None, metavar="GW,LPR,VEC,NT[,CHUNK]",
+    ap.add_argument("--force-shape", default=None, metavar="GW,LPR,VEC,NT[,CHUNK[,WIN]]",
                     help="single-solve filter: use this launch configuration (columns per launch, lanes per "
                          "row, columns per lane, nontemporal loads 0/1, optionally the tile-to-XCD mapping: "
                          "0 one range per XCD, c > 0 chunks of c tiles, c < 0 pencil walk over planes of "
-                         "-c rows) instead of the tuned one")
+                         "-c rows, and the LDS window 0/1) instead of the tuned one")
     ap.add_argument("--unfiltered-compare", action="store_true",
                     help="also run one unfiltered block Lanczos solve of the same problem (FP64) and report "
                          "its basis size and time beside the filtered solve's")
@@ -681,7 +681,8 @@ def main():
     if args.force_shape:
         f = [int(x) for x in args.force_shape.split(",")]
         flp.flp_set_filter_shape(lanes_per_row=f[1], cols_per_lane=f[2], group_width=f[0], streaming_loads=bool(f[3]),
-                                 tile_chunk=f[4] if len(f) > 4 else flp.FLP_TILE_CHUNK_TUNED)
+                                 tile_chunk=f[4] if len(f) > 4 else flp.FLP_TILE_CHUNK_TUNED,
+                                 lds_window=bool(f[5]) if len(f) > 5 else False)
     if args.filter_only:
         return bench_filter(args)
     if WORKLOADS[args.workload]["kind"] == "batch":

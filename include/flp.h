@@ -163,6 +163,8 @@ typedef struct flp_stats {
                               not certify its result and the cold solve ran */
     int32_t warm_sweeps;   /* subspace iteration sweeps of the warm start (polish_sweeps counts
                               them too when it was used) */
+    int32_t filter_lds_window; /* single solve's filter: 1 if each block staged its rows of the
+                                  gathered block in LDS (flp_tune_info.lds_window) */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */
@@ -282,6 +284,10 @@ typedef struct flp_tune_info {
                               z-plane of a 3D grid in natural order) is cut into 8 column ranges
                               and XCD x takes range x plane after plane, so a row's neighbours in
                               the planes above and below stay in that XCD's L2 */
+    int32_t lds_window;    /* 1: each workgroup first copies the rows of the gathered block that it
+                              and the 8 rows on either side own into LDS and reads the columns that
+                              fall there from LDS (the near-diagonal entries of a banded or stencil
+                              matrix), the rest from global memory; same sums */
 } flp_tune_info;
 
 /* Host evaluation of the tile-to-XCD traversal the filter kernels use (the
@@ -337,9 +343,11 @@ void flp_set_autotune(int32_t on);
  * width falls back to the default shape (keeping tile_chunk); a group width
  * that does not divide r is ignored; streaming_loads = 1 reads V and
  * U_{k+2} with nontemporal loads; tile_chunk as in flp_tune_info (any other
- * value than FLP_TILE_CHUNK_TUNED forces it). */
+ * value than FLP_TILE_CHUNK_TUNED forces it); lds_window = 1 stages the
+ * gathered rows near each workgroup's own in LDS (flp_tune_info.lds_window;
+ * ignored by shapes that do not cover the block in 16-byte pieces). */
 void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
-                          int32_t streaming_loads, int32_t tile_chunk);
+                          int32_t streaming_loads, int32_t tile_chunk, int32_t lds_window);
 
 /* Y = A X (plain CSR SpMM, Section 3.2.1).  X, Y: DEVICE n x r row-major
  * with leading dimensions ldx, ldy >= r; 1 <= r <= 32; FP64.  Async. */

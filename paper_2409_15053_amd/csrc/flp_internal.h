@@ -88,13 +88,15 @@ inline DMat panel_mat(const double *p, int64_t n, int lpw) {
 // results.
 struct StepShape {
     int lpr = 0, vec = 0, nt = 0, chunk = 0;
+    int win = 0;  // 1: each block stages its rows of the gathered block, +-8 rows, in LDS (aligned shapes)
 };
 // Host evaluation of the tile-to-XCD traversal the filter kernels use:
 // order[b] = the row tile that block b of a `tiles`-block launch processes
 // (chunk as in StepShape::chunk; rows_per_tile rows per tile).
 void tile_order_host(int tiles, int chunk, int rows_per_tile, int32_t *order);
 StepShape default_step_shape(int r, bool fp32);
-std::vector<StepShape> step_shape_candidates(int r, bool fp32);
+// window: also the LDS-window variants (single-solve kernel only)
+std::vector<StepShape> step_shape_candidates(int r, bool fp32, bool window);
 bool step_shape_ok(int r, bool fp32, StepShape sh);
 
 // out = alpha * (A X) + beta * X + gamma * V + delta * Y, row-major blocks of

@@ -827,6 +827,7 @@ int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         S.st.filter_cols_per_lane = used.vec;
         S.st.filter_streaming_loads = used.nt;
         S.st.filter_tile_chunk = tn.sh.chunk;
+        S.st.filter_lds_window = used.win;
         S.tile_chunk = tn.sh.chunk;
     }
     std::vector<ClenshawStep> gplan;

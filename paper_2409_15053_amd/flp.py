@@ -56,7 +56,7 @@ class FlpTuneInfoC(ctypes.Structure):
     _fields_ = [("group_width", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("cols_per_lane", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("streaming_loads", ctypes.c_int32),
-                ("us_per_step", ctypes.c_double), ("tile_chunk", ctypes.c_int32)]
+                ("us_per_step", ctypes.c_double), ("tile_chunk", ctypes.c_int32), ("lds_window", ctypes.c_int32)]
 
 
 class FlpOptsC(ctypes.Structure):
@@ -78,7 +78,8 @@ class FlpStatsC(ctypes.Structure):
                 ("filter_lanes_per_row", ctypes.c_int32), ("filter_cols_per_lane", ctypes.c_int32),
                 ("filter_streaming_loads", ctypes.c_int32), ("filter_tile_chunk", ctypes.c_int32),
                 ("polish_bytes", ctypes.c_double),
-                ("t_polish", ctypes.c_double), ("warm_status", ctypes.c_int32), ("warm_sweeps", ctypes.c_int32)]
+                ("t_polish", ctypes.c_double), ("warm_status", ctypes.c_int32), ("warm_sweeps", ctypes.c_int32),
+                ("filter_lds_window", ctypes.c_int32)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
@@ -135,7 +136,7 @@ def load(path: str = LIB_PATH):
         "flp_tune_filter": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), I32, I32, I32, P,
                                            ctypes.POINTER(FlpTuneInfoC)]),
         "flp_set_autotune": (None, [I32]),
-        "flp_set_filter_shape": (None, [I32, I32, I32, I32, I32]),
+        "flp_set_filter_shape": (None, [I32, I32, I32, I32, I32, I32]),
         "flp_spmm": (ctypes.c_int, [ctypes.POINTER(FlpCsrC), P, I32, P, I32, I32, P]),
         "flp_block_orth": (ctypes.c_int, [P, I64, I32, I32, P, I32, P, P]),
         "flp_block_qr": (ctypes.c_int, [P, I32, I32, P, P]),
@@ -332,12 +333,13 @@ FLP_TILE_CHUNK_TUNED = -(1 << 31)
 
 
 def flp_set_filter_shape(lanes_per_row: int = 0, cols_per_lane: int = 0, group_width: int = 0,
-                         streaming_loads: bool = False, tile_chunk: int = FLP_TILE_CHUNK_TUNED):
+                         streaming_loads: bool = False, tile_chunk: int = FLP_TILE_CHUNK_TUNED,
+                         lds_window: bool = False):
     """Force one filter launch configuration (all zeros and tile_chunk =
     FLP_TILE_CHUNK_TUNED: back to tuning).  Any other tile_chunk forces the
     tile-to-XCD mapping (< 0: the pencil walk over planes of -tile_chunk rows)."""
     load().flp_set_filter_shape(lanes_per_row, cols_per_lane, group_width, 1 if streaming_loads else 0,
-                                tile_chunk)
+                                tile_chunk, 1 if lds_window else 0)
 
 
 def flp_spmm(A: DeviceCsr, X, Y, stream=None):

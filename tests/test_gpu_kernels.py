@@ -145,16 +145,22 @@ def test_filter_apply_ragged_large_grid(torch):
 
 
 SHAPE_CASES = {
-    # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams, tile chunk);
-    # a negative tile chunk is the pencil walk over planes of that many rows (the 23^3 grid's 529)
-    (8, flp.FLP_PREC_FP64): [(4, 2, 8, 0, 0), (2, 4, 8, 1, 4), (1, 8, 8, 0, 32), (2, 2, 4, 1, 1), (1, 4, 4, 0, 7),
-                             (1, 2, 2, 1, 0), (4, 2, 8, 1, -529), (2, 2, 4, 0, -1058)],
-    (16, flp.FLP_PREC_FP64): [(8, 2, 16, 1, 0), (4, 4, 16, 0, 4), (2, 8, 16, 1, 32), (4, 2, 8, 0, 5),
-                              (2, 4, 8, 1, 0), (1, 8, 8, 0, 1), (4, 4, 16, 0, -529), (8, 2, 16, 1, -529),
-                              (4, 4, 16, 1, -1058)],
-    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1, 0), (1, 8, 8, 0, 4), (1, 4, 4, 1, 32), (2, 4, 8, 0, -529)],
-    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0, 0), (2, 8, 16, 1, 4), (2, 4, 8, 1, 3), (1, 8, 8, 0, 32),
-                                     (4, 4, 16, 1, -529)],
+    # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams, tile chunk,
+    # LDS window); a negative tile chunk is the pencil walk over planes of that many rows (the 23^3
+    # grid's 529)
+    (8, flp.FLP_PREC_FP64): [(4, 2, 8, 0, 0, 0), (2, 4, 8, 1, 4, 0), (1, 8, 8, 0, 32, 0), (2, 2, 4, 1, 1, 0),
+                             (1, 4, 4, 0, 7, 0), (1, 2, 2, 1, 0, 0), (4, 2, 8, 1, -529, 0), (2, 2, 4, 0, -1058, 0),
+                             (4, 2, 8, 0, 0, 1), (2, 4, 8, 1, 4, 1), (1, 8, 8, 0, -529, 1), (2, 2, 4, 0, 0, 1),
+                             (1, 2, 2, 1, 3, 1)],
+    (16, flp.FLP_PREC_FP64): [(8, 2, 16, 1, 0, 0), (4, 4, 16, 0, 4, 0), (2, 8, 16, 1, 32, 0), (4, 2, 8, 0, 5, 0),
+                              (2, 4, 8, 1, 0, 0), (1, 8, 8, 0, 1, 0), (4, 4, 16, 0, -529, 0),
+                              (8, 2, 16, 1, -529, 0), (4, 4, 16, 1, -1058, 0), (4, 4, 16, 0, 0, 1),
+                              (8, 2, 16, 1, -529, 1), (2, 8, 16, 0, 4, 1), (16, 2, 32, 0, 0, 1)],
+    (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1, 0, 0), (1, 8, 8, 0, 4, 0), (1, 4, 4, 1, 32, 0),
+                                    (2, 4, 8, 0, -529, 0), (2, 4, 8, 0, 0, 1), (1, 8, 8, 1, 4, 1)],
+    (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0, 0, 0), (2, 8, 16, 1, 4, 0), (2, 4, 8, 1, 3, 0),
+                                     (1, 8, 8, 0, 32, 0), (4, 4, 16, 1, -529, 0), (4, 4, 16, 0, 0, 1),
+                                     (2, 8, 16, 1, -529, 1), (1, 4, 4, 0, 0, 1)],
 }
 
 
@@ -176,12 +182,12 @@ def test_filter_launch_shapes_bit_identical(torch, r, prec):
         flp.flp_set_autotune(False)
         W0 = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
         flp.flp_filter_apply(f, dA, Vd, W0, prec=prec)
-        for lpr, vec, gw, nt, ch in SHAPE_CASES[(r, prec)]:
+        for lpr, vec, gw, nt, ch, win in SHAPE_CASES[(r, prec)]:
             for fmt in (flp.FLP_FORMAT_CSR, flp.FLP_FORMAT_SELL):
-                flp.flp_set_filter_shape(lpr, vec, gw, bool(nt), tile_chunk=ch)
+                flp.flp_set_filter_shape(lpr, vec, gw, bool(nt), tile_chunk=ch, lds_window=bool(win))
                 W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
                 flp.flp_filter_apply(f, dA, Vd, W, prec=prec, format=fmt)
-                outs.append(((lpr, vec, gw, nt, ch, fmt), W))
+                outs.append(((lpr, vec, gw, nt, ch, win, fmt), W))
         flp.flp_set_filter_shape(0, 0, 0)
         flp.flp_set_autotune(True)
         info = flp.flp_tune_filter(dA, r, prec, format=flp.FLP_FORMAT_CSR)
