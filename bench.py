@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter summary of the dominant kernel on the benchmark workload
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cheb_step_lap3d7_100_fp64_traffic.md")
-KERNEL_SOURCES = ["paper_2409_15053_amd/csrc/flp_filter.hip", "paper_2409_15053_amd/csrc/flp_device.h"]
+KERNEL_SOURCES = ["paper_2409_15053_amd/csrc/flp_filter.hip", "paper_2409_15053_amd/csrc/flp_gather.h",
+                  "paper_2409_15053_amd/csrc/flp_device.h"]
 METRIC = "filter SpMM GB/s (% HBM roofline); eigenpairs/s; p50/p99 solve latency"
 
 WORKLOADS = {
@@ -114,7 +115,7 @@ def measured_traffic(workload, prec, tuned, fmt):
     if kv.get("kernel_sources_sha256") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
     cfg = (f"gw={tuned['group_width']} lpr={tuned['lanes_per_row']} vec={tuned['cols_per_lane']} "
-           f"nt={tuned['streaming_loads']} fmt={fmt}")
+           f"nt={tuned['streaming_loads']} chunk={tuned['tile_chunk']} win={tuned['lds_window']} fmt={fmt}")
     if cfg not in per_cfg:
         return None, f"launch configuration {cfg} was not among the profiled ones {sorted(per_cfg)}"
     return float(per_cfg[cfg]), TRAFFIC_PROFILE[len(ROOT) + 1:]
@@ -738,7 +739,8 @@ def main():
     tuned = {"group_width": s_last["filter_group_width"], "lanes_per_row": s_last["filter_lanes_per_row"],
              "cols_per_lane": s_last["filter_cols_per_lane"],
              "rows_per_wave": 64 // max(1, s_last["filter_lanes_per_row"]),
-             "streaming_loads": s_last["filter_streaming_loads"]}
+             "streaming_loads": s_last["filter_streaming_loads"], "tile_chunk": s_last["filter_tile_chunk"],
+             "lds_window": s_last["filter_lds_window"]}
     st = [r["stats"] for r in results]
     fbytes = sum(s["filter_bytes"] for s in st)
     t_mv = sum(s["t_mv"] for s in st)

@@ -379,7 +379,10 @@ int Engine::step() {
         CKR(tune_filter(big->sell ? &big->SA : big->A, big->sell ? big->sval32 : big->val32, r, T.fp32, false, U,
                         T.fp32 ? (const void *)big->V32 : (const void *)big->Vin, r, s, &tn, big->sell));
         T.sh = tn.sh;
-        for (Solve *S : act) S->tile_chunk = tn.sh.chunk;
+        for (Solve *S : act) {
+            S->tile_chunk = tn.sh.chunk;
+            S->tile_win = tn.sh.win;
+        }
         CKR(build_tables(act, T, s));
         if (use_graph) {
             std::shared_lock<std::shared_mutex> cl(capture_mutex());  // no device-wide sync meanwhile

@@ -657,7 +657,9 @@ int filter_apply_impl(const flp_filter *p, const flp_csr *A, const double *V, in
 int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int c, const double *X,
                  const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
                  double *bytes, const flp_csr *sellA, const float *sell32, const std::vector<double> *rres,
-                 double lock_abs, int chunk) {
+                 double lock_abs, StepShape tile) {
+    const int chunk = tile.chunk;
+    const bool win = tile.win != 0;
     Workspace &w = ws();
     // the recurrence reads the sliced ELL copy when the solve holds one
     const bool sell = sellA != nullptr;
@@ -739,12 +741,12 @@ int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int 
             float *out = U[next];
             next = (next + 1) % 3;
             CK(launch_polish_step(n, mrow, mcol, mval, u1, u2, R, coef + (size_t)k * PW, a2, b2, out, s, sell,
-                                  chunk));
+                                  chunk, win));
             u2 = u1;
             u1 = out;
         }
         CK(launch_polish_last(n, mrow, mcol, mval, u1, u2, R, coef, a1, b1, Y, ldc, wc, X, ldc, cl, lp + PW, s, sell,
-                              chunk));
+                              chunk, win));
     }
     if (bytes) {
         // per step: the matrix in FP32 once, the gathered block, U_{k+2},

@@ -227,7 +227,7 @@ int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int 
                  const double *AX, int ldc, const std::vector<double> &lam, double *Y, hipStream_t s,
                  double *bytes,
                  const flp_csr *sellA = nullptr, const float *sell32 = nullptr,
-                 const std::vector<double> *rres = nullptr, double lock_abs = 0.0, int chunk = 0);
+                 const std::vector<double> *rres = nullptr, double lock_abs = 0.0, StepShape tile = StepShape{});
 
 // ---------------------------------------------------------------- dense helpers
 void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, std::vector<int> &bad);
@@ -320,6 +320,7 @@ struct Solve {
     std::vector<int> cand;
     std::vector<int> guard;  // FP32 filter: Ritz vectors just outside the candidates, polished with them
     int tile_chunk = 0;       // tile-to-XCD mapping the filter launches use (the polish follows it)
+    int tile_win = 0;         // LDS window of the filter launches (the polish follows it)
     flp_stats st{};
     double t_start = 0;
     int code = FLP_OK;  // first error

@@ -154,7 +154,8 @@ hipError_t launch_cheb_seg(bool fp32, int r, const SegEntry *tab, int nseg, int 
 // Residual-form polish (FP32 recurrences of the divided-difference
 // polynomials on the residual block, 32 columns per block; see flp_polish.hip).
 // Block column j is Ritz column cols[j] (a device array); chunk: the tile-to-
-// XCD mapping (chunk_tile).
+// XCD mapping (chunk_tile); win: stage each block's rows of the recurrence's
+// input (and 8 on each side) in LDS (StepShape::win).
 int polish_block_width();
 hipError_t launch_polish_resid(int n, int w, const double *X, const double *AX, int64_t ldc, const int *cols,
                                const double *lam, double inv_e, float *R32, hipStream_t s);
@@ -162,11 +163,13 @@ hipError_t launch_polish_locked(int n, int nl, const int *cols, const double *sc
                                 double *Y, hipStream_t s);
 hipError_t launch_polish_step(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
-                              float b, float *out, hipStream_t s, bool sell = false, int chunk = 0);
+                              float b, float *out, hipStream_t s, bool sell = false, int chunk = 0,
+                              bool win = false);
 hipError_t launch_polish_last(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
                               float b, double *Y, int64_t ldy, int w, const double *X, int64_t ldx, const int *cols,
-                              const double *ptheta, hipStream_t s, bool sell = false, int chunk = 0);
+                              const double *ptheta, hipStream_t s, bool sell = false, int chunk = 0,
+                              bool win = false);
 
 // One solve's part of a segmented block step (full reorthogonalisation of
 // the filtered block W against the basis Q, then W = Q_{j+1} S_j by

@@ -11,18 +11,19 @@
 // times the filter's slope, so the FP64 sum above keeps the accuracy the
 // FP64 recurrence would give while streaming half the bytes.
 //
-// Blocks are 32 columns wide (zero-padded); a lane owns 4 consecutive
-// columns (one 16-byte piece), 8 lanes share a matrix row.
+// Blocks are 32 columns wide (zero-padded); a lane owns 8 consecutive
+// columns (two 16-byte pieces), 4 lanes share a matrix row.
 #include "flp_internal.h"
 #include "flp_device.h"
+#include "flp_gather.h"
 
 namespace flp {
 
 namespace {
 
 constexpr int PW = 32;       // columns per block
-constexpr int PV = 4;        // columns per lane
-constexpr int PL = PW / PV;  // lanes per row
+constexpr int PV = 8;        // columns per lane (two 16-byte pieces)
+constexpr int PL = PW / PV;  // lanes per row (a DPP quad: the row's index broadcast stays in registers)
 constexpr int PRB = 256 / PL;  // rows per 256-thread block
 
 // R32 = (AX - X diag(lam)) * inv_e for the w real columns of the block
@@ -66,10 +67,11 @@ __global__ __launch_bounds__(256) void polish_locked_kernel(int n, int nl, const
 // in FP64 for the w real columns.  SELL: rowptr / colind / val are the
 // sliced ELL copy (slice offsets; entry k of a row at q0 + k * kSellC); its
 // padding adds exact zeros after the row's nonzeros, which it visits in
-// their CSR order.  The row's nonzeros go in groups of 8 with every load of
-// a group issued before its products (slots past the row's end re-read its
-// last entry with weight zero); tiles map to XCDs by chunk_tile.
-template <bool LAST, bool SELL>
+// their CSR order.  The row sum is gather_row's (each nonzero's index and
+// value read once per row, every X load of a group issued before its
+// products); WIN: the block's rows of U1 and 8 on each side staged in LDS;
+// tiles map to XCDs by chunk_tile.
+template <bool LAST, bool SELL, bool WIN>
 __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *__restrict__ rowptr,
                                                           const int32_t *__restrict__ colind,
                                                           const float *__restrict__ val, const float *U1,
@@ -79,63 +81,36 @@ __global__ __launch_bounds__(256) void polish_step_kernel(int n, const int32_t *
                                                           const double *__restrict__ X, int64_t ldx,
                                                           const int *__restrict__ cols,
                                                           const double *__restrict__ ptheta, int chunk) {
-    constexpr int UNR = 8;
-    const int row = chunk_tile(blockIdx.x, gridDim.x, chunk, PRB) * PRB + threadIdx.x / PL;
+    constexpr int WLD = PW + 4;  // LDS row stride (16 bytes of padding)
+    const int r0 = chunk_tile(blockIdx.x, gridDim.x, chunk, PRB) * PRB;
+    const int row = r0 + threadIdx.x / PL;
+    const int sub = threadIdx.x % PL;
+    const int c0 = sub * PV;
+    XSource<float, PV, WIN> xs{U1, PW, c0, nullptr, 0, WLD, 0u};
+    if constexpr (WIN) {
+        __shared__ float win[(PRB + 2 * kWinHalo) * WLD];
+        FLP_LDS float *lwin = (FLP_LDS float *)win;
+        const int wlo = max(0, r0 - kWinHalo), whi = min(n, r0 + PRB + kWinHalo);
+        if (U1) stage_window<float, PW, WLD, PRB + 2 * kWinHalo>(U1, PW, wlo, whi, lwin);
+        __syncthreads();
+        xs.win = lwin;
+        xs.wlo = wlo;
+        xs.wlen = (unsigned)(whi - wlo);
+    }
     if (row >= n) return;
-    const int c0 = (threadIdx.x % PL) * PV;
-    float acc[PV] = {0.0f, 0.0f, 0.0f, 0.0f};
-    float u1[PV] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float acc[PV], u1[PV], u2[PV], r[PV], o[PV];
+#pragma unroll
+    for (int j = 0; j < PV; ++j) acc[j] = u1[j] = u2[j] = 0.0f;
     if (U1) {
-        int base, stride, cnt;  // entry i of the row at base + i * stride
-        if constexpr (SELL) {
-            const int sl = row / kSellC;
-            base = rowptr[sl] + row % kSellC;
-            stride = kSellC;
-            cnt = (rowptr[sl + 1] - rowptr[sl]) / kSellC;
-        } else {
-            base = rowptr[row];
-            stride = 1;
-            cnt = rowptr[row + 1] - base;
-        }
-        for (int i = 0; i < cnt; i += UNR) {
-            float v[UNR];
-            float4 x[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int q = base + min(i + u, cnt - 1) * stride;
-                const float vv = val[q];
-                v[u] = (i + u < cnt) ? vv : 0.0f;
-                x[u] = *reinterpret_cast<const float4 *>(U1 + (int64_t)colind[q] * PW + c0);
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                acc[0] = fmaf(v[u], x[u].x, acc[0]);
-                acc[1] = fmaf(v[u], x[u].y, acc[1]);
-                acc[2] = fmaf(v[u], x[u].z, acc[2]);
-                acc[3] = fmaf(v[u], x[u].w, acc[3]);
-            }
-        }
-        const float4 s = *reinterpret_cast<const float4 *>(U1 + (int64_t)row * PW + c0);
-        u1[0] = s.x;
-        u1[1] = s.y;
-        u1[2] = s.z;
-        u1[3] = s.w;
+        gather_row<float, PV, PL, SELL, WIN>(row, sub, rowptr, colind, val, xs, acc);
+        xs.load(row, u1);
     }
-    float u2[PV] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (U2) {
-        const float4 s = *reinterpret_cast<const float4 *>(U2 + (int64_t)row * PW + c0);
-        u2[0] = s.x;
-        u2[1] = s.y;
-        u2[2] = s.z;
-        u2[3] = s.w;
-    }
-    const float4 r4 = *reinterpret_cast<const float4 *>(R + (int64_t)row * PW + c0);
-    const float r[PV] = {r4.x, r4.y, r4.z, r4.w};
-    float o[PV];
+    if (U2) load_vec<float, PV>(U2 + (int64_t)row * PW + c0, u2);
+    load_vec<float, PV>(R + (int64_t)row * PW + c0, r);
 #pragma unroll
     for (int j = 0; j < PV; ++j) o[j] = a * acc[j] + b * u1[j] + coef[c0 + j] * r[j] - u2[j];
     if constexpr (!LAST) {
-        *reinterpret_cast<float4 *>(out + (int64_t)row * PW + c0) = make_float4(o[0], o[1], o[2], o[3]);
+        store_vec<float, PV>(out + (int64_t)row * PW + c0, o);
     } else {
 #pragma unroll
         for (int j = 0; j < PV; ++j) {
@@ -172,29 +147,45 @@ hipError_t launch_polish_locked(int n, int nl, const int *cols, const double *sc
 
 hipError_t launch_polish_step(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
-                              float b, float *out, hipStream_t s, bool sell, int chunk) {
+                              float b, float *out, hipStream_t s, bool sell, int chunk, bool win) {
     const dim3 grid((n + PRB - 1) / PRB);
-    if (sell)
-        hipLaunchKernelGGL((polish_step_kernel<false, true>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1,
-                           U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr, nullptr, chunk);
-    else
-        hipLaunchKernelGGL((polish_step_kernel<false, false>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1,
-                           U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr, nullptr, chunk);
+#define FLP_POLISH(SELL, WIN)                                                                                      \
+    hipLaunchKernelGGL((polish_step_kernel<false, SELL, WIN>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1, \
+                       U2, R32, coef, a, b, out, nullptr, 0, 0, nullptr, 0, nullptr, nullptr, chunk)
+    if (sell) {
+        if (win)
+            FLP_POLISH(true, true);
+        else
+            FLP_POLISH(true, false);
+    } else if (win) {
+        FLP_POLISH(false, true);
+    } else {
+        FLP_POLISH(false, false);
+    }
+#undef FLP_POLISH
     return hipGetLastError();
 }
 
 hipError_t launch_polish_last(int n, const int32_t *rowptr, const int32_t *colind, const float *val32,
                               const float *U1, const float *U2, const float *R32, const float *coef, float a,
                               float b, double *Y, int64_t ldy, int w, const double *X, int64_t ldx, const int *cols,
-                              const double *ptheta, hipStream_t s, bool sell, int chunk) {
+                              const double *ptheta, hipStream_t s, bool sell, int chunk, bool win) {
     if (w < 1 || w > PW) return hipErrorInvalidValue;
     const dim3 grid((n + PRB - 1) / PRB);
-    if (sell)
-        hipLaunchKernelGGL((polish_step_kernel<true, true>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1, U2,
-                           R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, cols, ptheta, chunk);
-    else
-        hipLaunchKernelGGL((polish_step_kernel<true, false>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1,
-                           U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, cols, ptheta, chunk);
+#define FLP_POLISH(SELL, WIN)                                                                                     \
+    hipLaunchKernelGGL((polish_step_kernel<true, SELL, WIN>), grid, dim3(256), 0, s, n, rowptr, colind, val32, U1, \
+                       U2, R32, coef, a, b, nullptr, Y, ldy, w, X, ldx, cols, ptheta, chunk)
+    if (sell) {
+        if (win)
+            FLP_POLISH(true, true);
+        else
+            FLP_POLISH(true, false);
+    } else if (win) {
+        FLP_POLISH(false, true);
+    } else {
+        FLP_POLISH(false, false);
+    }
+#undef FLP_POLISH
     return hipGetLastError();
 }
 

@@ -530,7 +530,8 @@ int solve_finish(Solve &S, flp_result **out) {
                 CK(hipStreamSynchronize(s));  // (already idle: the Rayleigh-Ritz above ends on the host)
                 const double tp = now();
                 CKR(polish_apply(pf, A, S.val32, c, X, AX, ldc, lam, Y, s, &pbytes, S.sell ? &S.SA : nullptr,
-                                 S.sell ? S.sval32 : nullptr, &rres, kLockFrac * tol * anorm, S.tile_chunk));
+                                 S.sell ? S.sval32 : nullptr, &rres, kLockFrac * tol * anorm,
+                                 StepShape{0, 0, 0, S.tile_chunk, S.tile_win}));
                 CK(hipStreamSynchronize(s));
                 S.st.t_polish += now() - tp;
                 S.st.polish_bytes += pbytes;
@@ -726,7 +727,7 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         CK(hipStreamSynchronize(s));
         const double tp = now();
         CKR(polish_apply(filt.get(), A, v32, cur, X, AX, ldc, lam, Y, s, &pbytes, nullptr, nullptr, &rres,
-                         kLockFrac * tol * anorm, tn.sh.chunk));
+                         kLockFrac * tol * anorm, tn.sh));
         CK(hipStreamSynchronize(s));
         st.t_polish += now() - tp;
         st.polish_bytes += pbytes;
@@ -829,6 +830,7 @@ int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         S.st.filter_tile_chunk = tn.sh.chunk;
         S.st.filter_lds_window = used.win;
         S.tile_chunk = tn.sh.chunk;
+        S.tile_win = used.win;
     }
     std::vector<ClenshawStep> gplan;
     void *stage = nullptr;

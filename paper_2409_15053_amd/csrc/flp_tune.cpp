@@ -218,7 +218,7 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     for (int gw = r; gw >= 1; gw /= 2) {
         if (r % gw != 0 || (gw != r && !allow_groups)) continue;
         std::vector<StepShape> cands;
-        for (StepShape sh : step_shape_candidates(gw, fp32, allow_groups)) {
+        for (StepShape sh : step_shape_candidates(gw, fp32, true)) {
             for (int ch : kTileChunks) {
                 sh.chunk = ch;
                 cands.push_back(sh);
