@@ -923,33 +923,40 @@ int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<dou
 
 // ------------------------------------------------------------------ bounds
 
-int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s) {
+int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s,
+                         const flp_csr *spmv_A) {
     Workspace &w = ws();
     const int n = A->n;
     int k = std::max(1, std::min(k0, n));
-    const int ldb = (k + 2) & ~1;
-    CK(ensure(w.Q, sizeof(double) * (size_t)n * ldb));
+    // The last two Lanczos vectors, row-major n x 2: q_j in column j % 2 (the
+    // next vector overwrites q_{j-1}); w = A q_j is orthogonalised twice
+    // against both (the three-term recurrence, with its rounding removed
+    // twice), which keeps the extreme Ritz values and their residual bounds
+    // that the bounds need without the cost of a full basis.
+    CK(ensure(w.Q, sizeof(double) * (size_t)n * 2));
     CK(ensure(w.W, sizeof(double) * (size_t)n * 2));
-    double *Qb = (double *)w.Q.p, *wv = (double *)w.W.p;
+    double *Qw = (double *)w.Q.p, *wv = (double *)w.W.p;
     double *dev = nullptr;
-    CKR(small_dev((size_t)4 * ldb + 64, &dev));
+    CKR(small_dev((size_t)2 * k + 64, &dev));
     // start vector
     CK(launch_randn(n, 1, wv, 1, seed, 0xB0B0, s));
     double g = 0.0;
     CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, dev, &g, s));
     if (!(g > 0.0)) return fail(FLP_E_DEVICE, "bounds: zero start vector");
-    CK(launch_copy_block(n, 1, 1.0 / std::sqrt(g), wv, 1, plain_mat(Qb, ldb), 0, nullptr, 0, s));
+    CK(launch_copy_block(n, 1, 1.0 / std::sqrt(g), wv, 1, plain_mat(Qw, 2), 0, nullptr, 0, s));
     // k steps without a host round trip: the Gram-Schmidt coefficients, the
-    // norm and the next vector stay on the device (dev: H1, H2 in [0, 2 ldb),
-    // ||w||^2 at 2 ldb, alpha_j / beta_j pairs from 2 ldb + 8)
-    double *gdev = dev + 2 * ldb, *abdev = dev + 2 * ldb + 8;
+    // norm and the next vector stay on the device (dev: H1, H2 in [0, 4),
+    // ||w||^2 at 8, alpha_j / beta_j pairs from 16)
+    double *gdev = dev + 8, *abdev = dev + 16;
+    const flp_csr *M = spmv_A ? spmv_A : A;
     for (int j = 0; j < k; ++j) {
+        const int cur = j % 2, kk = std::min(j + 1, 2);
         // w = A q_j
-        CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, 1, Qb + j, ldb, nullptr, 0, nullptr,
-                                            0, wv, 1, 1.0, 0.0, 0.0, 0.0, s));
-        CKR(cgs2(plain_mat(Qb, ldb), j + 1, n, wv, 1, dev, s));
+        CK(launch_cheb_step<double, double>(n, M->rowptr, M->colind, M->val, 1, Qw + cur, 2, nullptr, 0, nullptr, 0,
+                                            wv, 1, 1.0, 0.0, 0.0, 0.0, s, StepShape{}, spmv_A != nullptr));
+        CKR(cgs2(plain_mat(Qw, 2), kk, n, wv, 1, dev, s));
         CKR(gram_tn(n, 1, 1, plain_mat(wv, 1), wv, 1, gdev, nullptr, s));
-        CK(launch_lanczos_next(n, wv, Qb + j + 1, ldb, gdev, dev, dev + (j + 1), j, abdev, s));
+        CK(launch_lanczos_next(n, wv, Qw + (1 - cur), 2, gdev, dev, dev + kk, kk == 1 ? 0 : cur, j, abdev, s));
     }
     std::vector<double> ab(2 * (size_t)k);
     CK(hipMemcpyAsync(ab.data(), abdev, sizeof(double) * ab.size(), hipMemcpyDeviceToHost, s));
@@ -986,7 +993,7 @@ int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, 
     // Gershgorin enclosure
     int nb = gershgorin_blocks(n);
     CK(ensure(w.partials, sizeof(double) * (2 * (size_t)nb + 8)));
-    CKR(small_dev((size_t)4 * ldb + 64, &dev));
+    CKR(small_dev((size_t)2 * k + 64, &dev));
     CK(launch_gershgorin(n, A->rowptr, A->colind, A->val, (double *)w.partials.p, nb, dev, s));
     double gg[2];
     CK(hipMemcpyAsync(gg, dev, sizeof(gg), hipMemcpyDeviceToHost, s));

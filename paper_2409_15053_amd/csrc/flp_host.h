@@ -239,7 +239,12 @@ int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *d
 int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s);
 int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<double> &S, uint64_t seed,
                   uint64_t sid, hipStream_t s, bool *replaced, int depth = 0);
-int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s);
+// Spectrum bounds (PREPROC): k0 Lanczos steps, each new vector
+// orthogonalised twice against the two before it, Ritz values widened by
+// their residual bounds, clamped into the Gershgorin enclosure.  spmv_A: a
+// sliced ELL copy of A with FP64 values for the products, or NULL (CSR A).
+int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s,
+                         const flp_csr *spmv_A = nullptr);
 int orthonormalize_cols(int n, int c, double *&Y, double *&tmp, int ldc, double *sdev, hipStream_t s);
 int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
                   double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s);

@@ -246,9 +246,10 @@ hipError_t launch_randn(int rows, int cols, double *out, int64_t ld, uint64_t se
 hipError_t launch_copy_block(int rows, int cols, double scale, const double *src, int64_t lds, DMat dst, int dcol0,
                              float *dst32, int64_t ldd32, hipStream_t s);
 hipError_t launch_to_float(int64_t count, const double *src, float *dst, hipStream_t s);
-// alpha_j, beta_j and q_{j+1} of a single-vector Lanczos step (bounds estimate)
+// alpha_j, beta_j and q_{j+1} of a single-vector Lanczos step (bounds
+// estimate); q_j's coefficients at h1[hj], h2[hj]
 hipError_t launch_lanczos_next(int n, const double *w, double *q, int64_t ldq, const double *g, const double *h1,
-                               const double *h2, int j, double *ab, hipStream_t s);
+                               const double *h2, int hj, int j, double *ab, hipStream_t s);
 hipError_t launch_scale(int64_t count, double a, const double *src, double *dst, hipStream_t s);
 
 // resid[j] = || AX[:, j] - lam[j] X[:, j] ||_2 for row-major n x c blocks

@@ -308,16 +308,17 @@ __global__ void randn_kernel(int rows, int cols, double *__restrict__ out, int64
 }
 
 // End of one step of the bounds estimate's single-vector Lanczos, on the
-// device: alpha_j = h1[j] + h2[j] (the two Gram-Schmidt passes' coefficient
-// of q_j), beta_j = sqrt(g) with g = ||w||^2, and q_{j+1} = w / beta_j (zero
-// after a breakdown, beta_j = 0).  ab[2j], ab[2j+1] receive alpha_j, beta_j.
+// device: alpha_j = h1[hj] + h2[hj] (the two Gram-Schmidt passes' coefficient
+// of q_j, column hj of the projection), beta_j = sqrt(g) with g = ||w||^2,
+// and q_{j+1} = w / beta_j (zero after a breakdown, beta_j = 0).  ab[2j],
+// ab[2j+1] receive alpha_j, beta_j.
 __global__ void lanczos_next_kernel(int n, const double *__restrict__ w, double *__restrict__ q, int64_t ldq,
                                     const double *__restrict__ g, const double *__restrict__ h1,
-                                    const double *__restrict__ h2, int j, double *__restrict__ ab) {
+                                    const double *__restrict__ h2, int hj, int j, double *__restrict__ ab) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const double beta = sqrt(fmax(g[0], 0.0));
     if (i == 0) {
-        ab[2 * j] = h1[j] + h2[j];
+        ab[2 * j] = h1[hj] + h2[hj];
         ab[2 * j + 1] = beta;
     }
     if (i < n) q[(int64_t)i * ldq] = beta > 0.0 ? w[i] / beta : 0.0;
@@ -451,8 +452,9 @@ hipError_t launch_copy_block(int rows, int cols, double scale, const double *src
 }
 
 hipError_t launch_lanczos_next(int n, const double *w, double *q, int64_t ldq, const double *g, const double *h1,
-                               const double *h2, int j, double *ab, hipStream_t s) {
-    hipLaunchKernelGGL(lanczos_next_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, w, q, ldq, g, h1, h2, j, ab);
+                               const double *h2, int hj, int j, double *ab, hipStream_t s) {
+    hipLaunchKernelGGL(lanczos_next_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, w, q, ldq, g, h1, h2, hj, j,
+                       ab);
     return hipGetLastError();
 }
 

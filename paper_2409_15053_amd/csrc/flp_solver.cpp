@@ -61,13 +61,23 @@ int solve_setup(Solve &S) {
     if (o.warm || o.warm_count != 0) return fail(FLP_E_ARG, "a warm start runs through flp_solve only");
     if (o.sym_tol >= 0.0) CKR(check_symmetric(A, o.sym_tol, s));
 
+    // the filter's storage of A (and, in FP64, the bounds' SpMVs read it too)
+    SolveBufs &B = *S.B;
+    if (fp32) CKR(ensure_val32(A, B.val32, &B.val32_src, &B.val32_nnz, &S.val32, s));
+    S.sell = false;
+    if (o.format != FLP_FORMAT_CSR)
+        CKR(build_sell(A, S.val32, fp32, B.sell_off, B.sell_col, B.sell_val, &S.SA, &S.sval32, s,
+                       o.format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad, &S.sell));
+    S.st.filter_format = S.sell ? FLP_FORMAT_SELL : FLP_FORMAT_CSR;
+
     // PREPROC: spectrum bounds
     double t0 = now();
     if (o.lmin < o.lmax) {
         S.lmin = o.lmin;
         S.lmax = o.lmax;
     } else {
-        CKR(estimate_bounds_impl(A, o.k0 > 0 ? o.k0 : kDefaultK0, o.seed, &S.lmin, &S.lmax, s));
+        CKR(estimate_bounds_impl(A, o.k0 > 0 ? o.k0 : kDefaultK0, o.seed, &S.lmin, &S.lmax, s,
+                                 S.sell && !fp32 ? &S.SA : nullptr));
     }
     S.st.t_pre = now() - t0;
 
@@ -91,7 +101,6 @@ int solve_setup(Solve &S) {
     // Lanczos basis: column panels of 128 columns, each a contiguous
     // row-major n x 128 block (the reorthogonalisation streams whole panels)
     S.npanels = ((int64_t)S.max_steps * r + (1 << kPanelLog2) - 1) >> kPanelLog2;
-    SolveBufs &B = *S.B;
     // the basis starts with a few panels and grows as the solve needs them
     // (max_basis columns would mostly stay unused)
     const size_t panel_bytes = (sizeof(double) * (size_t)n) << kPanelLog2;
@@ -112,15 +121,9 @@ int solve_setup(Solve &S) {
     for (auto &u : B.U) CK(ensure(u, es * (size_t)n * r));
     for (int i = 0; i < 3; ++i) S.U[i] = B.U[i].p;
     if (fp32) {
-        CKR(ensure_val32(A, B.val32, &B.val32_src, &B.val32_nnz, &S.val32, s));
         CK(ensure(B.V32, sizeof(float) * (size_t)n * r));
         S.V32 = (float *)B.V32.p;
     }
-    S.sell = false;
-    if (o.format != FLP_FORMAT_CSR)
-        CKR(build_sell(A, S.val32, fp32, B.sell_off, B.sell_col, B.sell_val, &S.SA, &S.sval32, s, o.format == FLP_FORMAT_SELL ? 1e300 : kSellMaxPad,
-                       &S.sell));
-    S.st.filter_format = S.sell ? FLP_FORMAT_SELL : FLP_FORMAT_CSR;
     S.plan = clenshaw_plan(S.filt.get(), r, fp32 ? (const void *)S.V32 : (const void *)S.Vin, r, S.W, r, S.U[0],
                            S.U[1], S.U[2], fp32);
 

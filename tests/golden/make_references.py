@@ -7,8 +7,11 @@
 Every eigenvalue written here comes from ``oracle.flp_oracle.flp_solve``
 (FP64, forward-recurrence filter, two-pass Gram-Schmidt, LAPACK for the
 projected problems); nothing is taken from the HIP library.  Each solve
-must report convergence and every residual must be <= 1e-11 (relative to
-||A||; the eigenvalue error that allows is far below the 1e-10 comparison).
+must report convergence and every residual must be <= 1e-10 (relative to
+||A||).  A Rayleigh-Ritz value with residual rho lies within rho^2 / gap of
+its eigenvalue (gap: the distance to the rest of the spectrum), so for the
+gaps of these spectra the stored eigenvalues are far more accurate than the
+1e-10 relative comparison; each problem's largest residual is stored.
 The oracle's convergence checks run at the spacing the library uses for the
 same block size (min(30, round(90 / r)) block steps), which only changes
 when the oracle stops, not what it returns.
@@ -50,7 +53,7 @@ def checked_solve(A, alpha, beta, block, degree, seed):
     res = O.flp_solve(A, alpha, beta, block=block, degree=degree, seed=seed, check_every=cadence(block))
     sec = time.perf_counter() - t0
     assert res.converged, "oracle did not converge"
-    assert len(res.evals) == 0 or float(np.max(res.resid)) <= 1e-11, float(np.max(res.resid))
+    assert len(res.evals) == 0 or float(np.max(res.resid)) <= 1e-10, float(np.max(res.resid))
     return res, sec
 
 
