@@ -76,7 +76,7 @@ def parse():
                     help="single-solve filter: use this launch configuration (columns per launch, lanes per "
                          "row, columns per lane, nontemporal loads 0/1, optionally the tile-to-XCD mapping: "
                          "0 one range per XCD, c > 0 chunks of c tiles, c < 0 pencil walk over planes of "
-                         "-c rows, and the LDS window 0/1) instead of the tuned one")
+                         "-c rows, and the LDS window: 0 none, 1 fixed +-8 rows, 2 sliding) instead of the tuned one")
     ap.add_argument("--unfiltered-compare", action="store_true",
                     help="also run one unfiltered block Lanczos solve of the same problem (FP64) and report "
                          "its basis size and time beside the filtered solve's")
@@ -683,7 +683,7 @@ def main():
         f = [int(x) for x in args.force_shape.split(",")]
         flp.flp_set_filter_shape(lanes_per_row=f[1], cols_per_lane=f[2], group_width=f[0], streaming_loads=bool(f[3]),
                                  tile_chunk=f[4] if len(f) > 4 else flp.FLP_TILE_CHUNK_TUNED,
-                                 lds_window=bool(f[5]) if len(f) > 5 else False)
+                                 lds_window=f[5] if len(f) > 5 else 0)
     if args.filter_only:
         return bench_filter(args)
     if WORKLOADS[args.workload]["kind"] == "batch":
@@ -740,7 +740,7 @@ def main():
              "cols_per_lane": s_last["filter_cols_per_lane"],
              "rows_per_wave": 64 // max(1, s_last["filter_lanes_per_row"]),
              "streaming_loads": s_last["filter_streaming_loads"], "tile_chunk": s_last["filter_tile_chunk"],
-             "lds_window": s_last["filter_lds_window"]}
+             "lds_window": s_last["filter_lds_window"], "window_halo": s_last["filter_window_halo"]}
     st = [r["stats"] for r in results]
     fbytes = sum(s["filter_bytes"] for s in st)
     t_mv = sum(s["t_mv"] for s in st)

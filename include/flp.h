@@ -163,8 +163,9 @@ typedef struct flp_stats {
                               not certify its result and the cold solve ran */
     int32_t warm_sweeps;   /* subspace iteration sweeps of the warm start (polish_sweeps counts
                               them too when it was used) */
-    int32_t filter_lds_window; /* single solve's filter: 1 if each block staged its rows of the
-                                  gathered block in LDS (flp_tune_info.lds_window) */
+    int32_t filter_lds_window; /* single solve's filter: its LDS window (flp_tune_info.lds_window:
+                                  0 none, 1 fixed +-8 rows, 2 sliding) */
+    int32_t filter_window_halo; /* its reach in rows (flp_tune_info.window_halo) */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */
@@ -287,7 +288,14 @@ typedef struct flp_tune_info {
     int32_t lds_window;    /* 1: each workgroup first copies the rows of the gathered block that it
                               and the 8 rows on either side own into LDS and reads the columns that
                               fall there from LDS (the near-diagonal entries of a banded or stencil
-                              matrix), the rest from global memory; same sums */
+                              matrix), the rest from global memory; same sums.
+                              2: sliding window: each workgroup walks one range of consecutive rows
+                              (a fraction of a plane of tile_chunk rows, tile_chunk then being that
+                              plane length, 0 for none) and keeps the gathered block's rows within
+                              window_halo of its current rows in an LDS ring, loading only the rows
+                              that enter it at each step; same sums */
+    int32_t window_halo;   /* rows on either side of its own that a workgroup reads from LDS
+                              (8 for lds_window 1, the tuned halo for 2, else 0) */
 } flp_tune_info;
 
 /* Host evaluation of the tile-to-XCD traversal the filter kernels use (the
@@ -344,7 +352,10 @@ void flp_set_autotune(int32_t on);
  * that does not divide r is ignored; streaming_loads = 1 reads V and
  * U_{k+2} with nontemporal loads; tile_chunk as in flp_tune_info (any other
  * value than FLP_TILE_CHUNK_TUNED forces it); lds_window = 1 stages the
- * gathered rows near each workgroup's own in LDS (flp_tune_info.lds_window;
+ * gathered rows near each workgroup's own in LDS, 2 selects the sliding
+ * window with its halo and plane found from the matrix's middle row (each
+ * solve's own; tile_chunk is then ignored; where no distance beyond 8 rows
+ * fits the LDS, the fixed window is used) (flp_tune_info.lds_window;
  * ignored by shapes that do not cover the block in 16-byte pieces). */
 void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t group_width,
                           int32_t streaming_loads, int32_t tile_chunk, int32_t lds_window);

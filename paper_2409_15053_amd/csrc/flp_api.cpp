@@ -169,6 +169,7 @@ int flp_tune_filter(const flp_csr *A, int32_t r, int32_t prec, int32_t format, v
         out->us_per_step = tn.candidates > 0 ? tn.us_per_step : 0.0;
         out->tile_chunk = tn.sh.chunk;
         out->lds_window = sh.lpr > 0 ? sh.win : 0;
+        out->window_halo = out->lds_window == 2 ? sh.halo : (out->lds_window == 1 ? kWinHalo : 0);
         return FLP_OK;
     } catch (const std::bad_alloc &) {
         return fail(FLP_E_NOMEM, "host allocation failed");
@@ -181,7 +182,8 @@ void flp_set_filter_shape(int32_t lanes_per_row, int32_t cols_per_lane, int32_t 
                           int32_t streaming_loads, int32_t tile_chunk, int32_t lds_window) {
     const bool chunk = tile_chunk != FLP_TILE_CHUNK_TUNED;
     force_filter_shape(StepShape{std::max(0, (int)lanes_per_row), std::max(0, (int)cols_per_lane),
-                                 streaming_loads ? 1 : 0, chunk ? (int)tile_chunk : 0, lds_window ? 1 : 0},
+                                 streaming_loads ? 1 : 0, chunk ? (int)tile_chunk : 0,
+                                 lds_window == 2 ? 2 : (lds_window ? 1 : 0)},
                        std::max(0, (int)group_width), chunk);
 }
 

@@ -380,8 +380,8 @@ int Engine::step() {
                         T.fp32 ? (const void *)big->V32 : (const void *)big->Vin, r, s, &tn, big->sell));
         T.sh = tn.sh;
         for (Solve *S : act) {
-            S->tile_chunk = tn.sh.chunk;
-            S->tile_win = tn.sh.win;
+            S->tile_chunk = tn.sh.win == 2 ? 0 : tn.sh.chunk;
+            S->tile_win = tn.sh.win != 0 ? 1 : 0;
         }
         CKR(build_tables(act, T, s));
         if (use_graph) {

@@ -8,6 +8,10 @@
 #include "flp_gather.h"
 
 #include <algorithm>
+#include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -106,6 +110,174 @@ hipError_t cheb_launch(int n, const int32_t *rowptr, const int32_t *colind, cons
         hipLaunchKernelGGL((cheb_step_kernel<T, Tout, LPR, VEC, NT, false, WIN>), dim3(grid), dim3(256), 0, s, n,
                            rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta,
                            chunk);
+    return hipGetLastError();
+}
+
+// Sliding-window form of the step for matrices whose near neighbours reach
+// further than a block (a 3D grid's in-plane +-N and +-2N rows): workgroup b
+// takes the rows [k L, k L + L), k = xcd_tile(b, K), in steps of RPB rows
+// and keeps the rows [s - halo, s - halo + R), R = RPB + 2 halo, around its
+// current step s in a ring of R rows in LDS (dynamic shared memory).  At
+// each step only the RPB rows entering the window are loaded (issued before
+// the step's sums, written after them into the ring slots of the rows that
+// leave), so every gathered column within halo rows of the row is read from
+// LDS, however many of the row's nonzeros fall there.  With L a fraction
+// 1/m of a grid plane, the rows a plane above and below a row are the ones
+// workgroups k +- m (on the same XCD, xcd_tile) load at the same time.
+// Same sums as cheb_step_kernel.
+template <typename T, typename Tout, int LPR, int VEC, bool NT, bool SELL>
+__global__ __launch_bounds__(256) void cheb_slide_kernel(
+    int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+    const T *__restrict__ val, int r, const T *__restrict__ X, int ldx, const T *__restrict__ V,
+    int ldv, const T *__restrict__ Y, int ldy, Tout *__restrict__ out, int ldo, T alpha, T beta,
+    T gamma, T delta, int halo, int range, int nranges) {
+    constexpr int RPB = 256 / LPR;
+    constexpr int GW = LPR * VEC;
+    constexpr int WLD = GW + 16 / (int)sizeof(T);
+    constexpr int E = 16 / (int)sizeof(T);
+    constexpr int P = GW / E;  // 16-byte pieces per row
+    constexpr int NPRE = (RPB * P + 255) / 256;
+    extern __shared__ unsigned char slide_smem[];
+    FLP_LDS T *ring = (FLP_LDS T *)slide_smem;
+    const int R = RPB + 2 * halo;
+    const int k = xcd_tile((int)blockIdx.x, nranges);
+    const int r0 = k * range;
+    const int r1 = min(n, r0 + range);
+    if (r0 >= r1) return;  // uniform over the block
+    const int sub = threadIdx.x % LPR;
+    const int c0 = sub * VEC;
+    int lo = r0 - halo, pos = 0;
+    {  // the first window: rows [max(0, lo), min(n, lo + R)) at ring rows row - lo
+        const int a = max(0, lo), cnt = (min(n, lo + R) - a) * P;
+        for (int e = threadIdx.x; e < cnt; e += 256)
+            *reinterpret_cast<FLP_LDS flp_f4 *>(ring + (a - lo + e / P) * WLD + (e % P) * E) =
+                *reinterpret_cast<const flp_f4 *>(X + (int64_t)(a + e / P) * ldx + (e % P) * E);
+    }
+    __syncthreads();
+    for (int s0 = r0; s0 < r1; s0 += RPB) {
+        // rows entering the next window: [lo + R, lo + R + RPB), those below n
+        const bool more = s0 + RPB < r1;
+        const int nlo = lo + R;
+        const int nhi = min(n, nlo + RPB);
+        flp_f4 pre[NPRE];
+#pragma unroll
+        for (int it = 0; it < NPRE; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            const int x = nlo + e / P;
+            if (more && e < RPB * P && x < nhi)
+                pre[it] = *reinterpret_cast<const flp_f4 *>(X + (int64_t)x * ldx + (e % P) * E);
+        }
+        const int row = s0 + (int)threadIdx.x / LPR;
+        if (row < r1 && c0 < r) {
+            T vv[VEC], yy[VEC];
+            if (V) load_stream<T, VEC, NT>(V + (int64_t)row * ldv + c0, vv);
+            if (Y) load_stream<T, VEC, NT>(Y + (int64_t)row * ldy + c0, yy);
+            XSource<T, VEC, true> xs{X, ldx, c0, ring, lo, WLD, (unsigned)R};
+            xs.wpos = pos;
+            xs.wring = R;
+            T acc[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = T(0);
+            gather_row<T, VEC, LPR, SELL, true>(row, sub, rowptr, colind, val, xs, acc);
+            T xr[VEC];
+            xs.load(row, xr);
+            T res[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) res[v] = alpha * acc[v] + beta * xr[v];
+            if (V) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) res[v] = fma(gamma, vv[v], res[v]);
+            }
+            if (Y) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) res[v] = fma(delta, yy[v], res[v]);
+            }
+            if constexpr (sizeof(Tout) == sizeof(T)) {
+                store_vec<Tout, VEC>(out + (int64_t)row * ldo + c0, res);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) out[(int64_t)row * ldo + c0 + v] = (Tout)res[v];
+            }
+        }
+        __syncthreads();  // every read of this window is done
+        if (more) {
+            // entering row nlo + i takes the ring slot of leaving row lo + i
+#pragma unroll
+            for (int it = 0; it < NPRE; ++it) {
+                const int e = (int)threadIdx.x + 256 * it;
+                const int x = nlo + e / P;
+                if (e < RPB * P && x < nhi) {
+                    int q = pos + (x - nlo);
+                    if (q >= R) q -= R;
+                    *reinterpret_cast<FLP_LDS flp_f4 *>(ring + q * WLD + (e % P) * E) = pre[it];
+                }
+            }
+        }
+        lo += RPB;
+        pos += RPB;
+        if (pos >= R) pos -= R;
+        __syncthreads();
+    }
+}
+
+// Workgroups of a sliding-window kernel that are resident at once on the
+// current device (compute units x workgroups per unit at `lds` bytes of
+// LDS), with the kernel's dynamic LDS limit raised to `lds` on first use.
+hipError_t slide_slots(const void *kfn, size_t lds, int *slots) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, size_t>, int> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_tuple(dev, kfn, lds);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *slots = it->second;
+        return hipSuccess;
+    }
+    int cus = 0, maxlds = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+    if (lds > (size_t)maxlds) return hipErrorInvalidValue;
+    if ((e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess) return e;
+    int per = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kfn, 256, lds)) != hipSuccess) return e;
+    *slots = cache[key] = std::max(1, cus * std::max(1, per));
+    return hipSuccess;
+}
+
+// Rows per workgroup of a sliding-window launch: a plane of `plane` rows cut
+// into m equal ranges, m as large as keeps every range's workgroup resident
+// at once; without planes (or with more planes than resident workgroups)
+// the rows split evenly over the resident workgroups.  Rounded up to whole
+// steps of rpb rows, so every step starts on a tile boundary as in
+// cheb_step_kernel (a wavefront's rows then lie in one sliced ELL slice).
+int slide_range(int n, int plane, int slots, int rpb) {
+    int64_t L = ((int64_t)n + slots - 1) / slots;
+    if (plane > 0) {
+        const int64_t m = (int64_t)slots * plane / n;
+        if (m >= 1) L = (plane + m - 1) / m;
+    }
+    return (int)std::min<int64_t>(((std::max<int64_t>(L, 1) + rpb - 1) / rpb) * rpb, INT32_MAX / 2);
+}
+
+template <typename T, typename Tout, int LPR, int VEC, bool NT>
+hipError_t slide_launch(int n, const int32_t *rowptr, const int32_t *colind, const T *val, int r, const T *X,
+                        int ldx, const T *V, int ldv, const T *Y, int ldy, Tout *out, int ldo, T alpha, T beta,
+                        T gamma, T delta, hipStream_t s, bool sell, int halo, int plane) {
+    constexpr int RPB = 256 / LPR;
+    constexpr int WLD = LPR * VEC + 16 / (int)sizeof(T);
+    if (halo < 0 || halo > (1 << 16)) return hipErrorInvalidValue;
+    const size_t lds = sizeof(T) * (size_t)(RPB + 2 * halo) * WLD;
+    auto kfn = sell ? cheb_slide_kernel<T, Tout, LPR, VEC, NT, true> : cheb_slide_kernel<T, Tout, LPR, VEC, NT, false>;
+    int slots = 0;
+    hipError_t e = slide_slots((const void *)kfn, lds, &slots);
+    if (e != hipSuccess) return e;
+    const int range = slide_range(n, plane, slots, RPB);
+    const int nr = (int)(((int64_t)n + range - 1) / range);
+    hipLaunchKernelGGL(kfn, dim3(nr), dim3(256), lds, s, n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out,
+                       ldo, alpha, beta, gamma, delta, halo, range, nr);
     return hipGetLastError();
 }
 
@@ -209,9 +381,14 @@ hipError_t launch_cheb_step(int n, const int32_t *rowptr, const int32_t *colind,
             sh.chunk = chunk;
         }
         const int lpr = sh.lpr, vec = sh.vec;
-        const bool nt = sh.nt != 0, win = sh.win != 0;
+        const bool nt = sh.nt != 0, win = sh.win == 1, slide = sh.win == 2;
 #define FLP_TRY(L, VV)                           \
     if (lpr == L && vec == VV) {                 \
+        if (slide) {                             \
+            if (nt)                              \
+                return slide_launch<T, Tout, L, VV, true>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s, sell, sh.halo, sh.chunk); \
+            return slide_launch<T, Tout, L, VV, false>(n, rowptr, colind, val, r, X, ldx, V, ldv, Y, ldy, out, ldo, alpha, beta, gamma, delta, s, sell, sh.halo, sh.chunk); \
+        }                                        \
         if (win) {                               \
             if (nt) {                            \
                 FLP_CHEB_NW(L, VV, true, true);  \

@@ -34,8 +34,7 @@ __device__ __forceinline__ void load_stream(const T *p, T (&v)[VEC]) {
 // that window is read there (the LDS pipeline), any other from global memory
 // (the texture address and data units, which the gathers of a stencil with
 // many neighbours keep busy).  Both hold the same values, so the sums do not
-// change.
-constexpr int kWinHalo = 8;
+// change.  kWinHalo: the fixed window's reach (flp_internal.h).
 
 #define FLP_LDS __attribute__((address_space(3)))
 typedef float flp_f4 __attribute__((ext_vector_type(4)));  // a 16-byte piece
@@ -62,11 +61,19 @@ struct XSource {
     const FLP_LDS T *win;
     int wlo, ld;
     unsigned wlen;
+    // The window may sit in a ring of wring rows (the sliding window of a
+    // workgroup that walks consecutive tiles): row wlo + j is at ring row
+    // (wpos + j) mod wring.  A plain window has wpos = 0 and no wrap.
+    int wpos = 0, wring = 1 << 30;
+    __device__ __forceinline__ int ring_row(int j) const {
+        const int p = wpos + j;
+        return p >= wring ? p - wring : p;
+    }
     __device__ __forceinline__ void load(int col, T (&v)[VEC]) const {
         if constexpr (WIN) {
             const unsigned j = (unsigned)(col - wlo);
             if (j < wlen) {
-                load_vec_lds<T, VEC>(win + (int)j * ld + c0, v);
+                load_vec_lds<T, VEC>(win + ring_row((int)j) * ld + c0, v);
                 return;
             }
         }
@@ -249,10 +256,15 @@ __device__ __forceinline__ void gather_group(int k0, int kmax, int sub, const Ad
 #pragma unroll
         for (int u = 0; u < CNT; ++u) {
             T l[VEC];
-            const int j = inw[u] ? cc[u] - xs.wlo : 0;
+            const int j = xs.ring_row(inw[u] ? cc[u] - xs.wlo : 0);
             load_vec_lds<T, VEC>(xs.win + j * xs.ld + xs.c0, l);
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] = fma(aa[u], inw[u] ? l[v] : xv[u][v], acc[v]);
+            for (int v = 0; v < VEC; ++v) {
+                // select the values, not their addresses (a select of two
+                // array elements' addresses keeps the arrays in scratch)
+                const T lv = l[v], gv = xv[u][v];
+                acc[v] = fma(aa[u], inw[u] ? lv : gv, acc[v]);
+            }
         }
     }
 }

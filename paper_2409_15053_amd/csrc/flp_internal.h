@@ -86,9 +86,16 @@ inline DMat panel_mat(const double *p, int64_t n, int lpw) {
 // flp_device.h; 0 = one contiguous range per XCD).  Every shape sums each
 // output element in the same order, so all of them give bit-identical
 // results.
+// Rows on either side of a block's own that the fixed LDS window holds.
+constexpr int kWinHalo = 8;
+
 struct StepShape {
     int lpr = 0, vec = 0, nt = 0, chunk = 0;
-    int win = 0;  // 1: each block stages its rows of the gathered block, +-8 rows, in LDS (aligned shapes)
+    // 1: each block stages its rows of the gathered block, +-8 rows, in LDS;
+    // 2: sliding window of +-halo rows per workgroup (cheb_slide_kernel),
+    // chunk then being the plane length its row ranges are fitted to (0: none)
+    int win = 0;
+    int halo = 0;
 };
 // Host evaluation of the tile-to-XCD traversal the filter kernels use:
 // order[b] = the row tile that block b of a `tiles`-block launch processes

@@ -832,8 +832,11 @@ int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         S.st.filter_streaming_loads = used.nt;
         S.st.filter_tile_chunk = tn.sh.chunk;
         S.st.filter_lds_window = used.win;
-        S.tile_chunk = tn.sh.chunk;
-        S.tile_win = used.win;
+        S.st.filter_window_halo = used.win == 2 ? used.halo : (used.win == 1 ? kWinHalo : 0);
+        // the polish follows the filter's tile mapping and fixed window (its
+        // kernel has no sliding form: chunk then holds the plane length)
+        S.tile_chunk = used.win == 2 ? 0 : tn.sh.chunk;
+        S.tile_win = used.win != 0 ? 1 : 0;
     }
     std::vector<ClenshawStep> gplan;
     void *stage = nullptr;

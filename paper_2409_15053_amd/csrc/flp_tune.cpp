@@ -44,6 +44,8 @@ std::atomic<int> g_mode{1};  // 1: tune on first use, 0: fixed defaults
 constexpr int kTileChunks[] = {0, 4, 32};
 // smallest neighbour distance (in rows) taken for a plane of a grid
 constexpr int kMinPlaneRows = 1024;
+// LDS a sliding-window workgroup may hold: two fit one compute unit
+constexpr int64_t kSlideLdsBytes = 80 * 1024;
 std::mutex g_mu;
 StepShape g_force_shape{};
 int g_force_gw = 0;
@@ -81,8 +83,12 @@ int ring(const flp_csr *A, const float *val32, bool fp32, int gw, StepShape sh, 
 
 }  // namespace
 
-int plane_rows(const flp_csr *A, bool sell, hipStream_t s, int *out) {
-    *out = 0;
+namespace {
+
+// The distinct distances |col - row| of the nonzeros (up to 64) of the
+// matrix's middle row, ascending; empty for matrices under 2048 rows.
+int row_offsets(const flp_csr *A, bool sell, hipStream_t s, std::vector<int> *out) {
+    out->clear();
     const int n = A->n;
     if (n < 2 * kMinPlaneRows) return FLP_OK;
     const int row = n / 2;
@@ -106,12 +112,44 @@ int plane_rows(const flp_csr *A, bool sell, hipStream_t s, int *out) {
             CK(hipMemcpyAsync(cols.data(), A->colind + rp[0], sizeof(int32_t) * w, hipMemcpyDeviceToHost, s));
     }
     CK(hipStreamSynchronize(s));
-    int best = 0;
-    for (int32_t c : cols) {
-        const int d = std::abs(c - row);
-        if (d >= kMinPlaneRows && (best == 0 || d < best)) best = d;
-    }
-    *out = best;
+    for (int32_t c : cols) out->push_back(std::abs(c - row));
+    std::sort(out->begin(), out->end());
+    out->erase(std::unique(out->begin(), out->end()), out->end());
+    return FLP_OK;
+}
+
+// Halos a sliding-window shape may take: the distances beyond the fixed
+// window's reach and below the plane length (all of them without planes)
+// whose window of RPB + 2 halo rows of gw elements (plus 16 bytes of
+// padding each) fits kSlideLdsBytes, ascending.
+std::vector<int> slide_halos(const std::vector<int> &offs, int plane, int gw, int lpr, size_t es) {
+    const int rpb = 256 / lpr;
+    const int64_t rows = kSlideLdsBytes / (int64_t)(es * gw + 16);
+    const int64_t cap = (rows - rpb) / 2;
+    std::vector<int> h;
+    for (int d : offs)
+        if (d > kWinHalo && (plane == 0 || d < plane) && d <= cap) h.push_back(d);
+    return h;
+}
+
+// The longest of them (0: none).
+int slide_halo(const std::vector<int> &offs, int plane, int gw, int lpr, size_t es) {
+    const std::vector<int> h = slide_halos(offs, plane, gw, lpr, es);
+    return h.empty() ? 0 : h.back();
+}
+
+int plane_of(const std::vector<int> &offs) {
+    for (int d : offs)
+        if (d >= kMinPlaneRows) return d;
+    return 0;
+}
+
+}  // namespace
+
+int plane_rows(const flp_csr *A, bool sell, hipStream_t s, int *out) {
+    std::vector<int> offs;
+    CKR(row_offsets(A, sell, s, &offs));
+    *out = plane_of(offs);
     return FLP_OK;
 }
 
@@ -164,6 +202,13 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
             if (g_force_gw > 0 && r % g_force_gw == 0 && (allow_groups || g_force_gw == r)) f.gw = g_force_gw;
             if (step_shape_ok(f.gw, fp32, g_force_shape)) {
                 f.sh = g_force_shape;
+                if (f.sh.win == 2 && f.sh.halo == 0) {  // sliding window fitted to this matrix
+                    std::vector<int> offs;
+                    CKR(row_offsets(A, sell, s, &offs));
+                    f.sh.chunk = plane_of(offs);
+                    f.sh.halo = slide_halo(offs, f.sh.chunk, f.gw, f.sh.lpr, fp32 ? sizeof(float) : sizeof(double));
+                    if (f.sh.halo == 0) f.sh.win = 1;
+                }
             } else {
                 f.sh = default_step_shape(f.gw, fp32);
                 f.sh.chunk = g_force_shape.chunk;
@@ -186,8 +231,9 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
     CK(hipGetDevice(&dev));
     // a single solve's filter also tries the pencil walk over the matrix's
     // planes (the segmented engine's tiles span many matrices)
-    int plane = 0;
-    if (allow_groups) CKR(plane_rows(A, sell, s, &plane));
+    std::vector<int> offs;
+    if (allow_groups) CKR(row_offsets(A, sell, s, &offs));
+    const int plane = plane_of(offs);
     // size class: n to a quarter octave, nonzeros per row to a quarter; plane
     const Key key{dev, fp32 ? 1 : 0, r, (int64_t)std::lround(4.0 * std::log2((double)n)),
                   (int64_t)std::lround(4.0 * (double)A->nnz / n), allow_groups ? 1 : 0, sell ? 1 : 0, plane};
@@ -228,6 +274,14 @@ int tune_filter(const flp_csr *A, const float *val32, int r, bool fp32, bool all
                 cands.push_back(sh);
             }
         }
+        // the sliding window, its halo and row ranges fitted to the matrix
+        for (StepShape sh : step_shape_candidates(gw, fp32, false))
+            for (int h : slide_halos(offs, plane, gw, sh.lpr, es)) {
+                sh.halo = h;
+                sh.win = 2;
+                sh.chunk = plane;
+                cands.push_back(sh);
+            }
         for (StepShape sh : cands) {
             // V: the caller's block (gw == r) or a contiguous n x gw group,
             // taken from the unused half of the first buffer

@@ -56,7 +56,8 @@ class FlpTuneInfoC(ctypes.Structure):
     _fields_ = [("group_width", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("cols_per_lane", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("streaming_loads", ctypes.c_int32),
-                ("us_per_step", ctypes.c_double), ("tile_chunk", ctypes.c_int32), ("lds_window", ctypes.c_int32)]
+                ("us_per_step", ctypes.c_double), ("tile_chunk", ctypes.c_int32), ("lds_window", ctypes.c_int32),
+                ("window_halo", ctypes.c_int32)]
 
 
 class FlpOptsC(ctypes.Structure):
@@ -79,7 +80,7 @@ class FlpStatsC(ctypes.Structure):
                 ("filter_streaming_loads", ctypes.c_int32), ("filter_tile_chunk", ctypes.c_int32),
                 ("polish_bytes", ctypes.c_double),
                 ("t_polish", ctypes.c_double), ("warm_status", ctypes.c_int32), ("warm_sweeps", ctypes.c_int32),
-                ("filter_lds_window", ctypes.c_int32)]
+                ("filter_lds_window", ctypes.c_int32), ("filter_window_halo", ctypes.c_int32)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
@@ -334,12 +335,14 @@ FLP_TILE_CHUNK_TUNED = -(1 << 31)
 
 def flp_set_filter_shape(lanes_per_row: int = 0, cols_per_lane: int = 0, group_width: int = 0,
                          streaming_loads: bool = False, tile_chunk: int = FLP_TILE_CHUNK_TUNED,
-                         lds_window: bool = False):
+                         lds_window: int = 0):
     """Force one filter launch configuration (all zeros and tile_chunk =
     FLP_TILE_CHUNK_TUNED: back to tuning).  Any other tile_chunk forces the
-    tile-to-XCD mapping (< 0: the pencil walk over planes of -tile_chunk rows)."""
+    tile-to-XCD mapping (< 0: the pencil walk over planes of -tile_chunk rows).
+    lds_window: 0 none, 1 the fixed +-8-row window, 2 the sliding window
+    fitted to each matrix."""
     load().flp_set_filter_shape(lanes_per_row, cols_per_lane, group_width, 1 if streaming_loads else 0,
-                                tile_chunk, 1 if lds_window else 0)
+                                tile_chunk, int(lds_window))
 
 
 def flp_spmm(A: DeviceCsr, X, Y, stream=None):

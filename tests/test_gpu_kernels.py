@@ -147,20 +147,24 @@ def test_filter_apply_ragged_large_grid(torch):
 SHAPE_CASES = {
     # (r, prec): forced (lanes per row, columns per lane, group width, nontemporal streams, tile chunk,
     # LDS window); a negative tile chunk is the pencil walk over planes of that many rows (the 23^3
-    # grid's 529)
+    # grid's 529); LDS window 2 is the sliding window, its halo and plane taken from the matrix
+    # (plane 1058 here, halo 46 or 529 as the ring fits the LDS, row ranges shorter than a step)
     (8, flp.FLP_PREC_FP64): [(4, 2, 8, 0, 0, 0), (2, 4, 8, 1, 4, 0), (1, 8, 8, 0, 32, 0), (2, 2, 4, 1, 1, 0),
                              (1, 4, 4, 0, 7, 0), (1, 2, 2, 1, 0, 0), (4, 2, 8, 1, -529, 0), (2, 2, 4, 0, -1058, 0),
                              (4, 2, 8, 0, 0, 1), (2, 4, 8, 1, 4, 1), (1, 8, 8, 0, -529, 1), (2, 2, 4, 0, 0, 1),
-                             (1, 2, 2, 1, 3, 1)],
+                             (1, 2, 2, 1, 3, 1), (4, 2, 8, 0, 0, 2), (1, 8, 8, 1, 0, 2), (2, 2, 4, 0, 0, 2)],
     (16, flp.FLP_PREC_FP64): [(8, 2, 16, 1, 0, 0), (4, 4, 16, 0, 4, 0), (2, 8, 16, 1, 32, 0), (4, 2, 8, 0, 5, 0),
                               (2, 4, 8, 1, 0, 0), (1, 8, 8, 0, 1, 0), (4, 4, 16, 0, -529, 0),
                               (8, 2, 16, 1, -529, 0), (4, 4, 16, 1, -1058, 0), (4, 4, 16, 0, 0, 1),
-                              (8, 2, 16, 1, -529, 1), (2, 8, 16, 0, 4, 1), (16, 2, 32, 0, 0, 1)],
+                              (8, 2, 16, 1, -529, 1), (2, 8, 16, 0, 4, 1), (16, 2, 32, 0, 0, 1),
+                              (4, 4, 16, 0, 0, 2), (8, 2, 16, 1, 0, 2), (2, 8, 16, 0, 0, 2), (4, 2, 8, 0, 0, 2)],
     (8, flp.FLP_PREC_FP32_FILTER): [(2, 4, 8, 1, 0, 0), (1, 8, 8, 0, 4, 0), (1, 4, 4, 1, 32, 0),
-                                    (2, 4, 8, 0, -529, 0), (2, 4, 8, 0, 0, 1), (1, 8, 8, 1, 4, 1)],
+                                    (2, 4, 8, 0, -529, 0), (2, 4, 8, 0, 0, 1), (1, 8, 8, 1, 4, 1),
+                                    (2, 4, 8, 0, 0, 2), (1, 8, 8, 1, 0, 2)],
     (16, flp.FLP_PREC_FP32_FILTER): [(4, 4, 16, 0, 0, 0), (2, 8, 16, 1, 4, 0), (2, 4, 8, 1, 3, 0),
                                      (1, 8, 8, 0, 32, 0), (4, 4, 16, 1, -529, 0), (4, 4, 16, 0, 0, 1),
-                                     (2, 8, 16, 1, -529, 1), (1, 4, 4, 0, 0, 1)],
+                                     (2, 8, 16, 1, -529, 1), (1, 4, 4, 0, 0, 1), (4, 4, 16, 0, 0, 2),
+                                     (2, 8, 16, 1, 0, 2), (1, 4, 4, 0, 0, 2)],
 }
 
 
@@ -184,7 +188,7 @@ def test_filter_launch_shapes_bit_identical(torch, r, prec):
         flp.flp_filter_apply(f, dA, Vd, W0, prec=prec)
         for lpr, vec, gw, nt, ch, win in SHAPE_CASES[(r, prec)]:
             for fmt in (flp.FLP_FORMAT_CSR, flp.FLP_FORMAT_SELL):
-                flp.flp_set_filter_shape(lpr, vec, gw, bool(nt), tile_chunk=ch, lds_window=bool(win))
+                flp.flp_set_filter_shape(lpr, vec, gw, bool(nt), tile_chunk=ch, lds_window=win)
                 W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
                 flp.flp_filter_apply(f, dA, Vd, W, prec=prec, format=fmt)
                 outs.append(((lpr, vec, gw, nt, ch, win, fmt), W))
@@ -210,6 +214,42 @@ def test_filter_launch_shapes_bit_identical(torch, r, prec):
     else:
         tol = 2 * 12 * (k + 4) * U32 * np.sum(np.abs(b)) * np.max(np.abs(V))
     assert np.max(np.abs(W0.cpu().numpy() - want)) <= tol
+
+
+@pytest.mark.parametrize("prec", [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER])
+def test_filter_sliding_window_long_ranges(torch, prec):
+    """The sliding window over row ranges of several steps: on the 13-point
+    64^3 grid (plane 4096 rows, in-plane reach 128 rows) each workgroup's
+    range is a fraction of a plane and its LDS ring wraps several times.
+    Same bits as the plain launch on both storages, oracle parity in FP64."""
+    A = I.laplacian_3d_13pt(64, I.gaussian_wells(64, 4))
+    r = 16
+    f, b, V, lmin, lmax = filter_case(A, -3.0, -1.0, 6, r, seed=11)
+    dA = flp.DeviceCsr.from_host(A)
+    Vd = dev(torch, V)
+    v16 = 2 if prec == flp.FLP_PREC_FP64 else 4
+    outs = []
+    try:
+        flp.flp_set_autotune(False)
+        flp.flp_set_filter_shape(r // v16, v16, r, False, tile_chunk=0, lds_window=0)
+        W0 = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+        flp.flp_filter_apply(f, dA, Vd, W0, prec=prec)
+        for lpr in (r // v16, r // (2 * v16)):
+            for fmt in (flp.FLP_FORMAT_CSR, flp.FLP_FORMAT_SELL):
+                flp.flp_set_filter_shape(lpr, r // lpr, r, False, tile_chunk=0, lds_window=2)
+                W = torch.empty((A.n, r), dtype=torch.float64, device="cuda:0")
+                flp.flp_filter_apply(f, dA, Vd, W, prec=prec, format=fmt)
+                outs.append(((lpr, fmt), W))
+    finally:
+        flp.flp_set_filter_shape(0, 0, 0)
+        flp.flp_set_autotune(True)
+    torch.cuda.synchronize()
+    for cfg, W in outs:
+        assert torch.equal(W, W0), cfg
+    if prec == flp.FLP_PREC_FP64:
+        want = O.filter_apply(A, lmin, lmax, b, V)
+        tol = 2 * 6 * 6 * (max_row_nnz(A) + 4) * U64 * np.sum(np.abs(b)) * np.max(np.abs(V))
+        assert np.max(np.abs(W0.cpu().numpy() - want)) <= tol
 
 
 def test_filter_apply_errors(torch):
