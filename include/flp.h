@@ -502,8 +502,13 @@ void flp_server_opts_default(flp_server_opts *o);
 int flp_server_create(const flp_server_opts *opts, flp_server **out);
 /* Queue a request: every eigenpair of A in [alpha, beta].  A's device
  * arrays must stay valid until the result has been retrieved.  opts may be
- * NULL; its block and prec are replaced by the server's.  *ticket names the
- * request.  Thread-safe.  Errors: FLP_E_ARG, or the server's device error. */
+ * NULL; its block and prec are replaced by the server's.  The server reads
+ * A on its own streams only after the work queued on opts->stream (the null
+ * stream when opts is NULL or opts->stream is NULL) before this call, so
+ * arrays still being written there (a copy, a conversion to FP32) are
+ * complete when the request starts.  *ticket names the request.
+ * Thread-safe.  Errors: FLP_E_ARG, FLP_E_DEVICE (the event could not be
+ * recorded), or the server's device error. */
 int flp_server_submit(flp_server *sv, const flp_csr *A, double alpha, double beta, const flp_opts *opts,
                       uint64_t *ticket);
 /* FLP_E_PENDING if the request is still queued or running; otherwise its

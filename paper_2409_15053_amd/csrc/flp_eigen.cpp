@@ -139,10 +139,23 @@ void band_to_tridiag(Band &M, int b, std::vector<Rot> &log, double *Zt, int nr) 
 }
 
 // Implicit QR with Wilkinson shift on the tridiagonal (d, e); e[i] couples
-// i and i+1.  On return d holds the eigenvalues (unsorted).
+// i and i+1.  On return d holds the eigenvalues (unsorted).  A matrix whose
+// largest entry lies far from 1 is scaled to it first (the rotations do not
+// depend on the scale): at 1e-200 the squares in the rotations underflow
+// and the iteration would not move.
 bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot> &log, double *Zt, int nr) {
     const int N = (int)d.size();
     if (N <= 1) return true;
+    double amax = 0.0;
+    for (double x : d) amax = std::max(amax, std::fabs(x));
+    for (double x : e) amax = std::max(amax, std::fabs(x));
+    if (!std::isfinite(amax)) return false;
+    if (amax == 0.0) return true;
+    const double scale = (amax < 1e-100 || amax > 1e100) ? 1.0 / amax : 1.0;
+    if (scale != 1.0) {
+        for (double &x : d) x *= scale;
+        for (double &x : e) x *= scale;
+    }
     int hi = N - 1;
     long guard = 0;
     const long max_steps = 60L * N + 100;
@@ -189,6 +202,10 @@ bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, std::vector<Rot>
             log.push_back({k, c, s});
             if (nr) rot_rows(Zt, nr, k, c, s);
         }
+    }
+    if (scale != 1.0) {
+        for (double &x : d) x /= scale;
+        for (double &x : e) x /= scale;
     }
     return true;
 }
@@ -342,12 +359,27 @@ void dense_vectors(const std::vector<Rot> &log, const double *A, const std::vect
     parallel_for(ntiles, nthreads_for((long)(log.size() + (size_t)N * N) * ncols, ntiles), work);
 }
 
+// 1 / (largest |entry|) for a matrix whose entries all lie far from 1 (the
+// squares in the rotations and reflector norms would underflow or
+// overflow), else 1; 0 for non-finite entries.  Eigenvectors do not depend
+// on the scale; eigenvalues are divided by it afterwards.
+double far_scale(const std::vector<double> &v) {
+    double amax = 0.0;
+    for (double x : v) amax = std::max(amax, std::fabs(x));
+    if (!std::isfinite(amax)) return 0.0;
+    return (amax > 0.0 && (amax < 1e-100 || amax > 1e100)) ? 1.0 / amax : 1.0;
+}
+
 // Dense path: eigenvalues ascending in evals, selected columns (indices into
 // the ascending order) of the eigenvector matrix in Zcols (N x ncols).
 int dense_sym_eig(int N, const double *M, double *evals, const int *cols, int ncols, double *Zcols) {
     std::vector<double> A((size_t)N * N);
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) A[(size_t)i * N + j] = 0.5 * (M[(size_t)i * N + j] + M[(size_t)j * N + i]);
+    const double sc = far_scale(A);
+    if (sc == 0.0) return -2;
+    if (sc != 1.0)
+        for (double &x : A) x *= sc;
     std::vector<double> d, e, beta;
     householder_tridiag(N, A.data(), d, e, beta);
     std::vector<Rot> log;
@@ -356,7 +388,7 @@ int dense_sym_eig(int N, const double *M, double *evals, const int *cols, int nc
     std::vector<int> perm(N);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] < d[b]; });
-    for (int i = 0; i < N; ++i) evals[i] = d[perm[i]];
+    for (int i = 0; i < N; ++i) evals[i] = d[perm[i]] / sc;
     if (ncols > 0 && Zcols) {
         std::vector<int> ids(ncols);
         for (int j = 0; j < ncols; ++j) ids[j] = perm[cols[j]];
@@ -382,6 +414,10 @@ int sym_eig_keep(int N, int bw, const double *M, double *evals, const int *rows,
             const int i = j + d;
             Bd.B[(size_t)j * (Bd.w + 1) + d] = 0.5 * (M[(size_t)i * N + j] + M[(size_t)j * N + i]);
         }
+    const double sc = far_scale(Bd.B);
+    if (sc == 0.0) return -2;
+    if (sc != 1.0)
+        for (double &x : Bd.B) x *= sc;
     std::vector<Rot> local;
     std::vector<Rot> &log = keep ? keep->rot : local;
     log.clear();
@@ -400,7 +436,7 @@ int sym_eig_keep(int N, int bw, const double *M, double *evals, const int *rows,
     std::vector<int> perm(N);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] < d[b]; });
-    for (int i = 0; i < N; ++i) evals[i] = d[perm[i]];
+    for (int i = 0; i < N; ++i) evals[i] = d[perm[i]] / sc;
     for (int i = 0; i < nr; ++i)
         for (int j = 0; j < N; ++j) Zrows[(size_t)i * N + j] = Zt[(size_t)perm[j] * nr + i];
     if (keep) {

@@ -406,6 +406,15 @@ struct Job {
     std::string msg;        // error message of a failed request
     bool finished = false;  // result handed back (set under the owner's lock)
     std::atomic<bool> cancel{false};  // cancellation requested (serving)
+    // serving: recorded on the submitter's stream; the engine's stream waits
+    // for it before the request's first launch
+    hipEvent_t ready = nullptr;
+    Job() = default;
+    Job(const Job &) = delete;
+    Job &operator=(const Job &) = delete;
+    ~Job() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
 // Advances a set of active solves in lockstep: per block step, one

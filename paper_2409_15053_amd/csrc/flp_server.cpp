@@ -105,6 +105,18 @@ void worker_main(flp_server *sv) {
         for (Job *j : admit) {
             Solve &S = *j->S;
             S.s = sv->eng.s;
+            if (j->ready) {  // the caller's writes of A come first
+                const hipError_t e = hipStreamWaitEvent(S.s, j->ready, 0);
+                (void)hipEventDestroy(j->ready);
+                j->ready = nullptr;
+                if (e != hipSuccess) {
+                    j->code = fail(FLP_E_DEVICE, "waiting for the request's event failed");
+                    j->msg = last_error_cstr();
+                    j->t_done = now();
+                    sv->eng.on_done(j);
+                    continue;
+                }
+            }
             j->B = std::make_unique<SolveBufs>();
             j->B->own_ritz = true;  // the finish phase's blocks are this request's (freed with it)
             S.B = j->B.get();
@@ -285,6 +297,17 @@ int flp_server_submit(flp_server *sv, const flp_csr *A, double alpha, double bet
             return fail(FLP_E_ARG, "need finite alpha < beta");
         if (S.o.block > A->n) return fail(FLP_E_ARG, "block size exceeds n");
         j->footprint = footprint(*A, S.o);
+        {
+            // the engine reads A after what the caller queued on its stream
+            hipStream_t cs = opts ? (hipStream_t)opts->stream : nullptr;
+            int cur = 0;
+            CK(hipGetDevice(&cur));
+            if (cur != sv->device) CK(hipSetDevice(sv->device));
+            hipError_t e = hipEventCreateWithFlags(&j->ready, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(j->ready, cs);
+            if (cur != sv->device) (void)hipSetDevice(cur);
+            if (e != hipSuccess) return fail(FLP_E_DEVICE, std::string("recording the request's event: ") + hipGetErrorString(e));
+        }
         std::lock_guard<std::mutex> lk(sv->mu);
         if (sv->fatal != FLP_OK) return fail(sv->fatal, "server stopped after a device error: " + sv->fatal_msg);
         j->id = sv->next_id++;

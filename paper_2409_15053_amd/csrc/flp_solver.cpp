@@ -285,6 +285,13 @@ void run_check_body(CheckTask &c) {
     std::vector<int> rows(r);
     for (int i = 0; i < r; ++i) rows[i] = K - r + i;
     std::vector<double> Zl((size_t)r * K);
+    for (double t : c.T)
+        if (!std::isfinite(t)) {
+            c.rc = FLP_E_DEVICE;
+            c.msg = "T_k holds non-finite entries (the filtered block overflowed, or A changed during the solve)";
+            c.secs = now() - t0;
+            return;
+        }
     if (sym_eig_keep(K, r, c.T.data(), theta.data(), rows.data(), r, Zl.data(), &c.eig) != 0) {
         c.rc = FLP_E_DEVICE;
         c.msg = "eigensolver for T_k did not converge";

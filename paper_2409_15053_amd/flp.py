@@ -582,8 +582,11 @@ class Server:
 
     def submit(self, A: DeviceCsr, alpha: float, beta: float, seed: int = 0, degree: int = 0,
                max_basis: int = 0, check_every: int = 0, polish_degree: int = 0) -> int:
+        import torch
         o = _make_opts(1, degree, seed, 0, max_basis, check_every, 0.0, 0, None, None, polish_degree=polish_degree)
-        o.stream = None
+        # the server reads A after the work queued so far on torch's current
+        # stream (where from_host wrote it)
+        o.stream = _stream_ptr(torch.cuda.current_stream(A.val.device))
         t = ctypes.c_uint64()
         _check(load().flp_server_submit(self.h, ctypes.byref(A.c), alpha, beta, ctypes.byref(o), ctypes.byref(t)))
         self._keep[t.value] = A  # the matrix must outlive the request

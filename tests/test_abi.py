@@ -140,6 +140,21 @@ def test_host_eigensolver_degenerate_and_clustered():
     assert np.max(np.abs(M @ Z - Z * ev)) < 1e-13
 
 
+@pytest.mark.parametrize("scale", [1e-200, 1e-120, 1e120, 1e200])
+def test_host_eigensolver_far_scales(scale):
+    # a tridiagonal and a banded matrix whose entries all lie near 1e-200
+    # (or 1e200): the rotations' squares would underflow (overflow) unscaled
+    g = np.random.Generator(np.random.PCG64(int(np.log10(scale)) + 400))
+    for N, bw in [(60, 1), (90, 6)]:
+        M = g.standard_normal((N, N))
+        M = M + M.T
+        i, j = np.indices((N, N))
+        M[np.abs(i - j) > bw] = 0.0
+        ev = flp.flp_host_sym_eig(M * scale, bw, vectors=False)
+        w = np.linalg.eigvalsh(M)
+        assert np.max(np.abs(ev / scale - w)) < 1e-13 * np.max(np.abs(w)) * N ** 0.5
+
+
 def test_opts_defaults_and_new_codes():
     o = flp.default_opts()
     assert o.sym_tol < 0          # the symmetry check is opt-in
