@@ -1070,4 +1070,98 @@ int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, d
     return FLP_OK;
 }
 
+// Rayleigh-Ritz with A on span(Y) for a block whose columns need not be
+// orthonormal (eq. rayleigh, eq. proj on the basis Y C with C^T Y^T Y C = I),
+// in place of orthonormalising Y first: with D = diag(Y^T Y)^(-1/2) and the
+// Cholesky factor D Y^T Y D = R^T R, the symmetric R^-T D Y^T A Y D R^-1 =
+// Z diag(lam) Z^T gives C = D R^-1 Z, X = Y C and AX = (A Y) C.  The
+// column scaling makes D Y^T Y D close to the identity for the blocks the
+// finish phase meets (orthonormal up to rounding, or a filtered block whose
+// columns point along nearly orthogonal eigenvectors with very different
+// norms), so the factorisation loses nothing.  Four n x c x c products
+// instead of the six of two orthonormalisations and a Rayleigh-Ritz.
+// Fails when Y has numerically dependent columns.
+int rayleigh_ritz_gen(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
+                      double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s) {
+    Workspace &w = ws();
+    for (int j0 = 0; j0 < c; j0 += 32) {
+        int cw = std::min(32, c - j0);
+        CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, cw, Y + j0, ldc, nullptr, 0, nullptr,
+                                            0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
+    }
+    std::vector<double> M((size_t)c * c), G((size_t)c * c);
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), Y, ldc, sdev, M.data(), s));
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), AY, ldc, sdev, G.data(), s));
+    std::vector<double> d(c);
+    for (int i = 0; i < c; ++i) {
+        const double m = M[(size_t)i * c + i];
+        if (!(m > 0.0) || !std::isfinite(m)) return fail(FLP_E_DEVICE, "Ritz block has a zero or non-finite column");
+        d[i] = 1.0 / std::sqrt(m);
+    }
+    std::vector<double> Ms((size_t)c * c), Gs((size_t)c * c);
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j) {
+            const size_t ij = (size_t)i * c + j, ji = (size_t)j * c + i;
+            Ms[ij] = d[i] * (0.5 * (M[ij] + M[ji])) * d[j];
+            Gs[ij] = d[i] * (0.5 * (G[ij] + G[ji])) * d[j];
+        }
+    std::vector<double> R, Ri;
+    std::vector<int> bad;
+    cholesky_flag(c, Ms.data(), 1e-24, R, bad);
+    for (int i = 0; i < c; ++i)
+        if (bad[i]) return fail(FLP_E_DEVICE, "Ritz block lost rank");
+    upper_inverse(c, R, Ri);
+    // T = Gs Ri (T[i][j] = sum over k <= j of Gs[i][k] Ri[k][j]), then
+    // H = Ri^T T (H[i][j] = sum over k <= i of Ri[k][i] T[k][j])
+    std::vector<double> T((size_t)c * c, 0.0), H((size_t)c * c, 0.0);
+    for (int i = 0; i < c; ++i)
+        for (int k = 0; k < c; ++k) {
+            const double g = Gs[(size_t)i * c + k];
+            const double *rk = &Ri[(size_t)k * c];
+            double *ti = &T[(size_t)i * c];
+            for (int j = k; j < c; ++j) ti[j] += g * rk[j];
+        }
+    for (int k = 0; k < c; ++k)
+        for (int i = k; i < c; ++i) {
+            const double r = Ri[(size_t)k * c + i];
+            const double *tk = &T[(size_t)k * c];
+            double *hi = &H[(size_t)i * c];
+            for (int j = 0; j < c; ++j) hi[j] += r * tk[j];
+        }
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double v = 0.5 * (H[(size_t)i * c + j] + H[(size_t)j * c + i]);
+            H[(size_t)i * c + j] = H[(size_t)j * c + i] = v;
+        }
+    lam.assign(c, 0.0);
+    std::vector<double> Z((size_t)c * c);
+    std::vector<int> cols(c);
+    for (int i = 0; i < c; ++i) cols[i] = i;
+    if (sym_eig(c, c - 1, H.data(), lam.data(), nullptr, 0, nullptr, cols.data(), c, Z.data()) != 0)
+        return fail(FLP_E_DEVICE, "eigensolver for the Rayleigh-Ritz matrix did not converge");
+    // C = D Ri Z (rows of C padded to ldc)
+    std::vector<double> Cp((size_t)c * ldc, 0.0);
+    for (int i = 0; i < c; ++i) {
+        double *ci = &Cp[(size_t)i * ldc];
+        for (int k = i; k < c; ++k) {
+            const double r = d[i] * Ri[(size_t)i * c + k];
+            const double *zk = &Z[(size_t)k * c];
+            for (int j = 0; j < c; ++j) ci[j] += r * zk[j];
+        }
+    }
+    CK(h2d(sdev, Cp.data(), sizeof(double) * Cp.size(), s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(Y, ldc), sdev, ldc, 0.0, X, ldc, s));
+    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(AY, ldc), sdev, ldc, 0.0, AX, ldc, s));
+    double *lamd = sdev + (size_t)c * ldc;
+    double *rdev = lamd + ldc;
+    CK(h2d(lamd, lam.data(), sizeof(double) * c, s));
+    int nch = resid_chunks(n);
+    CK(ensure(w.resid_part, sizeof(double) * (size_t)nch * c));
+    CK(launch_resid_norms(n, c, AX, ldc, X, ldc, lamd, (double *)w.resid_part.p, nch, rdev, s));
+    res.assign(c, 0.0);
+    CK(hipMemcpyAsync(res.data(), rdev, sizeof(double) * c, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return FLP_OK;
+}
+
 }  // namespace flp

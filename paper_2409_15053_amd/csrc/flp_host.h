@@ -246,6 +246,10 @@ int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<dou
 int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, double *lmax, hipStream_t s,
                          const flp_csr *spmv_A = nullptr);
 int orthonormalize_cols(int n, int c, double *&Y, double *&tmp, int ldc, double *sdev, hipStream_t s);
+// The same for a block Y whose columns need not be orthonormal (Y itself is
+// left as it is): replaces orthonormalising Y and then rayleigh_ritz.
+int rayleigh_ritz_gen(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
+                      double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s);
 int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
                   double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s);
 

@@ -94,11 +94,13 @@ __global__ __launch_bounds__(256) void gemm_tn_fma_kernel(int n, int K, int chun
 
 }  // namespace
 
-// The FMA projection serves B of exactly 8 or 16 columns against a basis
-// of at least 128 columns (thread per column: fewer columns leave most lanes
-// idle, where the MFMA kernel's row-parallel layout does better; measured at
-// n = 1e6, c = 8: 4.2 TB/s at K = 128, 5.3 at 192, 5.8 at 472).
-static bool tn_use_fma(int K, int c) { return (c == 8 || c == 16) && K >= 128; }
+// The FMA projection serves B of exactly 8 columns against a basis of at
+// least 256 columns; the MFMA kernel's row-parallel layout does better below
+// that and at 16 columns, where the thread-per-column kernel's 16 FMAs per
+// loaded element hold it back.  Measured at n = 1e6 (TB/s, FMA / MFMA):
+// c = 8: K = 128 3.5 / 5.4, 256 5.6 / 5.4, 512 6.0 / 5.5, 768 6.1 / 5.6;
+// c = 16: K = 128 2.6 / 5.5, 352 3.8 / 5.0, 768 5.0 / 5.4.
+static bool tn_use_fma(int K, int c) { return c == 8 && K >= 256; }
 
 TnPlan plan_tn(int n, int K, int c) {
     TnPlan p;
@@ -135,12 +137,8 @@ hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A,
                                   double *partials, hipStream_t s) {
     if (tn_use_fma(K, c)) {
         dim3 grid((K + 255) / 256, pl.nchunks);
-        if (c == 8)
-            hipLaunchKernelGGL((gemm_tn_fma_kernel<8, 8>), grid, dim3(256), 0, s, n, K, pl.chunk_rows, A, B, ldb,
-                               partials);
-        else
-            hipLaunchKernelGGL((gemm_tn_fma_kernel<16, 4>), grid, dim3(256), 0, s, n, K, pl.chunk_rows, A, B, ldb,
-                               partials);
+        hipLaunchKernelGGL((gemm_tn_fma_kernel<8, 8>), grid, dim3(256), 0, s, n, K, pl.chunk_rows, A, B, ldb,
+                           partials);
         return hipGetLastError();
     }
     // 16-byte A loads need an even leading dimension and panel stride
@@ -173,10 +171,21 @@ hipError_t launch_gemm_nn(int n, int K, int c, double alpha, DMat A, const doubl
     if (n <= 0 || c <= 0) return hipSuccess;
     bool vec_a = (A.ld % 2 == 0) && (A.ps % 2 == 0) && ((reinterpret_cast<uintptr_t>(A.p) & 15) == 0);
     if (c <= 16) {
-        constexpr int MT = 4, NT = 1;
-        int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);
-        hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks), dim3(256), 0, s, n, K, c, alpha, A, B, ldb, beta,
-                           C, ldc, vec_a);
+        // row tiles per wave: 2 up to a few hundred basis columns, 8 beyond
+        // (more A loads in flight per MFMA chain); at n = 1e6 this streams
+        // Q at 5.0-5.6 TB/s from K = 64 to 768, where 4 tiles gave 4.3-5.1
+        constexpr int NT = 1;
+        if (K >= 320) {
+            constexpr int MT = 8;
+            int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);
+            hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks), dim3(256), 0, s, n, K, c, alpha, A, B, ldb,
+                               beta, C, ldc, vec_a);
+        } else {
+            constexpr int MT = 2;
+            int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);
+            hipLaunchKernelGGL((gemm_nn_kernel<MT, NT>), dim3(rblocks), dim3(256), 0, s, n, K, c, alpha, A, B, ldb,
+                               beta, C, ldc, vec_a);
+        }
     } else {
         constexpr int MT = 2, NT = 4;
         int rblocks = (n + 4 * 16 * MT - 1) / (4 * 16 * MT);

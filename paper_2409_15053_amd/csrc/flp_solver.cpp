@@ -479,9 +479,8 @@ int solve_finish(Solve &S, flp_result **out) {
         CK(h2d(sdev, Wc.data(), sizeof(double) * Wc.size(), s));
         // Ritz vectors of p(A): Y = Q_k W_C
         CK(launch_gemm_nn(n, K, c, 1.0, S.Q, sdev, ldc, 0.0, Y, ldc, s));
-        CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
         std::vector<double> lam, rres;
-        CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+        CKR(rayleigh_ritz_gen(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
         const double alpha = S.alpha, beta = S.beta;
         int cur = c;  // Ritz vectors in the block
         auto worst = [&](int &i0, int &i1) {
@@ -545,9 +544,7 @@ int solve_finish(Solve &S, flp_result **out) {
                 CK(hipStreamSynchronize(s));
                 S.st.t_polish += now() - tp;
                 S.st.polish_bytes += pbytes;
-                CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
-                CKR(orthonormalize_cols(n, c, Y, X, ldc, sdev, s));
-                CKR(rayleigh_ritz(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+                CKR(rayleigh_ritz_gen(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
                 ++S.st.polish_sweeps;
             }
         }
@@ -686,10 +683,8 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
     const double tr = now();
     CK(launch_transpose_in(n, k, o.warm, Y, ldc, s));
     CK(launch_randn(n, g, Y + k, ldc, o.seed, 0x3A21, s));
-    CKR(orthonormalize_cols(n, c0, Y, X, ldc, sdev, s));
-    CKR(orthonormalize_cols(n, c0, Y, X, ldc, sdev, s));
     std::vector<double> lam, rres;
-    CKR(rayleigh_ritz(A, n, c0, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+    CKR(rayleigh_ritz_gen(A, n, c0, Y, AY, X, AX, ldc, sdev, lam, rres, s));
     int cur = c0, prev_count = -1, sweeps = 0, separations = 0, i0 = 0, i1 = 0, last_grow = 0, grown = 0;
     auto inside = [&]() {
         i0 = 0;
@@ -737,7 +732,8 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         CK(hipStreamSynchronize(s));
         const double tp = now();
         CKR(polish_apply(filt.get(), A, v32, cur, X, AX, ldc, lam, Y, s, &pbytes, nullptr, nullptr, &rres,
-                         kLockFrac * tol * anorm, tn.sh));
+                         kLockFrac * tol * anorm,
+                         StepShape{0, 0, 0, tn.sh.win == 2 ? 0 : tn.sh.chunk, tn.sh.win != 0 ? 1 : 0}));
         CK(hipStreamSynchronize(s));
         st.t_polish += now() - tp;
         st.polish_bytes += pbytes;
@@ -748,9 +744,7 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
             last_grow = sweeps + 1;
             ++grown;
         }
-        CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
-        CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
-        CKR(rayleigh_ritz(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+        CKR(rayleigh_ritz_gen(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
         ++sweeps;
     }
     if (!certified) return kWarmFallback;
