@@ -216,13 +216,28 @@ def test_filter_launch_shapes_bit_identical(torch, r, prec):
     assert np.max(np.abs(W0.cpu().numpy() - want)) <= tol
 
 
+def principal(A, m):
+    """The leading m x m block of a CSR matrix (symmetric when A is)."""
+    keep = A.colind < m
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    sel = keep & (rows < m)
+    cnt = np.bincount(rows[sel], minlength=m)
+    rowptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    return I.Csr(m, rowptr, A.colind[sel].astype(np.int32), A.val[sel].copy())
+
+
+@pytest.mark.parametrize("ragged", [False, True])
 @pytest.mark.parametrize("prec", [flp.FLP_PREC_FP64, flp.FLP_PREC_FP32_FILTER])
-def test_filter_sliding_window_long_ranges(torch, prec):
+def test_filter_sliding_window_long_ranges(torch, prec, ragged):
     """The sliding window over row ranges of several steps: on the 13-point
     64^3 grid (plane 4096 rows, in-plane reach 128 rows) each workgroup's
     range is a fraction of a plane and its LDS ring wraps several times.
-    Same bits as the plain launch on both storages, oracle parity in FP64."""
+    Ragged: the leading 61 planes and 1000 rows (a partial last plane and a
+    last range shorter than the others).  Same bits as the plain launch on
+    both storages, oracle parity in FP64."""
     A = I.laplacian_3d_13pt(64, I.gaussian_wells(64, 4))
+    if ragged:
+        A = principal(A, 61 * 4096 + 1000)
     r = 16
     f, b, V, lmin, lmax = filter_case(A, -3.0, -1.0, 6, r, seed=11)
     dA = flp.DeviceCsr.from_host(A)
