@@ -55,8 +55,8 @@ def parse():
     ap.add_argument("--workload", default="lap3d7_100", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--degree", type=int, default=None,
-                    help="filter degree (default: 110 for the 100^3 workload, the fastest of a 100..200 sweep "
-                         "there; 100 for the 120^3 Hamiltonian)")
+                    help="filter degree (default: 100 for the 100^3 workload, the fastest of a 80..140 sweep "
+                         "there at checks every 11 block steps; 100 for the 120^3 Hamiltonian)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="default workload: skip the batched FP32 line measured after the benchmark")
