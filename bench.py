@@ -46,7 +46,9 @@ WORKLOADS = {
     "batch64": dict(golden=None, kind="batch", count=64),
     "batch16": dict(golden=None, kind="batch", count=16),
     "serve": dict(golden=None, kind="serve"),
-    "lap3d13_120": dict(golden=None, kind="c3", N=120, degree=100),
+    # degree 65: the fastest of a 50-160 sweep at checks every 4-8 block
+    # steps for both filter precisions (48 block steps from degree 60 up)
+    "lap3d13_120": dict(golden=None, kind="c3", N=120, degree=65),
 }
 
 
@@ -59,7 +61,8 @@ def parse():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--degree", type=int, default=None,
                     help="filter degree (default: 110 for the 100^3 workload, with checks every 10 block "
-                         "steps the fastest of a 100..120 sweep there; 100 for the 120^3 Hamiltonian)")
+                         "steps the fastest of a 100..120 sweep there; 65 for the 120^3 Hamiltonian, the "
+                         "fastest of a 50..160 sweep)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="default workload: skip the batched FP32 line measured after the benchmark")
