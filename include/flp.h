@@ -166,6 +166,8 @@ typedef struct flp_stats {
     int32_t filter_lds_window; /* single solve's filter: its LDS window (flp_tune_info.lds_window:
                                   0 none, 1 fixed +-8 rows, 2 sliding) */
     int32_t filter_window_halo; /* its reach in rows (flp_tune_info.window_halo) */
+    int32_t separations;        /* FP32 filter: Rayleigh-Ritz rounds on a block grown by A x for Ritz
+                                   pairs mixing eigenvectors from both sides of the interval */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */

@@ -529,6 +529,7 @@ int solve_finish(Solve &S, flp_result **out) {
                     CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
                     CKR(rayleigh_ritz(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
                     ++separations;
+                    ++S.st.separations;
                     continue;
                 }
                 if (worst(i0, i1) <= tol || S.st.polish_sweeps >= kMaxPolish) break;
@@ -712,6 +713,7 @@ int solve_warm(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
             CKR(orthonormalize_cols(n, cur, Y, X, ldc, sdev, s));
             CKR(rayleigh_ritz(A, n, cur, Y, AY, X, AX, ldc, sdev, lam, rres, s));
             ++separations;
+            ++st.separations;
             continue;
         }
         const int count = i1 - i0;

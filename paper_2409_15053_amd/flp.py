@@ -80,7 +80,8 @@ class FlpStatsC(ctypes.Structure):
                 ("filter_streaming_loads", ctypes.c_int32), ("filter_tile_chunk", ctypes.c_int32),
                 ("polish_bytes", ctypes.c_double),
                 ("t_polish", ctypes.c_double), ("warm_status", ctypes.c_int32), ("warm_sweeps", ctypes.c_int32),
-                ("filter_lds_window", ctypes.c_int32), ("filter_window_halo", ctypes.c_int32)]
+                ("filter_lds_window", ctypes.c_int32), ("filter_window_halo", ctypes.c_int32),
+                ("separations", ctypes.c_int32)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
