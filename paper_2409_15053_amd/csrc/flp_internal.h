@@ -264,6 +264,10 @@ hipError_t launch_scale(int64_t count, double a, const double *src, double *dst,
 hipError_t launch_resid_norms(int n, int c, const double *AX, int64_t ldax, const double *X,
                               int64_t ldx, const double *lam, double *part, int nchunks,
                               double *out, hipStream_t s);
+// out[j] = x_j . y_j for the first c columns of X and Y (n rows), summed
+// over resid_chunks(n) row chunks in a fixed order (part: nchunks x c).
+hipError_t launch_col_dots(int n, int c, const double *X, int64_t ldx, const double *Y, int64_t ldy, double *part,
+                           int nchunks, double *out, hipStream_t s);
 int resid_chunks(int n);
 
 // dst (row-major n x c, ldd) = src (column-major n x c, ld n)

@@ -389,6 +389,35 @@ __global__ void resid_final_kernel(int nchunks, int c, const double *__restrict_
     out[j] = sqrt(s);
 }
 
+// Partial sums over chunks of rows of the column dot products x_j . y_j
+// (the layout of resid_partial_kernel), then their sum in chunk order.
+__global__ void coldot_partial_kernel(int n, int c, const double *__restrict__ X, int64_t ldx,
+                                      const double *__restrict__ Y, int64_t ldy, int rows_per_chunk,
+                                      double *__restrict__ part) {
+    __shared__ double red[256];
+    const int chunk = blockIdx.x, j0 = blockIdx.y * 64;
+    const int j = j0 + threadIdx.x % 64, rsub = threadIdx.x / 64;
+    double s = 0.0;
+    if (j < c) {
+        int r0 = chunk * rows_per_chunk, r1 = min(n, r0 + rows_per_chunk);
+        for (int i = r0 + rsub; i < r1; i += 4) s = fma(X[(int64_t)i * ldx + j], Y[(int64_t)i * ldy + j], s);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 64 && j < c) {
+        double t = red[threadIdx.x] + red[threadIdx.x + 64] + red[threadIdx.x + 128] + red[threadIdx.x + 192];
+        part[(size_t)chunk * c + j] = t;
+    }
+}
+
+__global__ void coldot_final_kernel(int nchunks, int c, const double *__restrict__ part, double *__restrict__ out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= c) return;
+    double s = 0.0;
+    for (int q = 0; q < nchunks; ++q) s += part[(size_t)q * c + j];
+    out[j] = s;
+}
+
 __global__ void transpose_out_kernel(int n, int c, const double *__restrict__ src, int64_t lds,
                                      double *__restrict__ dst) {
     __shared__ double t[32][33];
@@ -488,6 +517,16 @@ hipError_t launch_resid_norms(int n, int c, const double *AX, int64_t ldax, cons
     hipLaunchKernelGGL(resid_partial_kernel, dim3(nchunks, (c + 63) / 64), dim3(256), 0, s, n, c, AX, ldax, X, ldx,
                        lam, rpc, part);
     hipLaunchKernelGGL(resid_final_kernel, dim3((c + 255) / 256), dim3(256), 0, s, nchunks, c, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_dots(int n, int c, const double *X, int64_t ldx, const double *Y, int64_t ldy, double *part,
+                           int nchunks, double *out, hipStream_t s) {
+    if (c <= 0) return hipSuccess;
+    int rpc = (n + nchunks - 1) / nchunks;
+    hipLaunchKernelGGL(coldot_partial_kernel, dim3(nchunks, (c + 63) / 64), dim3(256), 0, s, n, c, X, ldx, Y, ldy,
+                       rpc, part);
+    hipLaunchKernelGGL(coldot_final_kernel, dim3((c + 255) / 256), dim3(256), 0, s, nchunks, c, part, out);
     return hipGetLastError();
 }
 

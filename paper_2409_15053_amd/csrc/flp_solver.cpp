@@ -480,7 +480,7 @@ int solve_finish(Solve &S, flp_result **out) {
         // Ritz vectors of p(A): Y = Q_k W_C
         CK(launch_gemm_nn(n, K, c, 1.0, S.Q, sdev, ldc, 0.0, Y, ldc, s));
         std::vector<double> lam, rres;
-        CKR(rayleigh_ritz_gen(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
+        if (!fp32) CKR(rayleigh_ritz_gen(A, n, c, Y, AY, X, AX, ldc, sdev, lam, rres, s));
         const double alpha = S.alpha, beta = S.beta;
         int cur = c;  // Ritz vectors in the block
         auto worst = [&](int &i0, int &i1) {
@@ -504,6 +504,39 @@ int solve_finish(Solve &S, flp_result **out) {
                                 S.o.eps > 0 ? S.o.eps : kDefaultEps, &q));
                 pown.reset(q);
                 pf = q;
+            }
+            {
+                // The first polish sweep starts from the block Y itself: it is
+                // an orthonormal basis of the Ritz space of p(Ahat), and the
+                // residual form needs only A Y and one shift per column (any
+                // shifts give the same p(Ahat) Y; the Rayleigh quotients
+                // y_j^T A y_j keep the FP32 residuals small), so no
+                // Rayleigh-Ritz step precedes it; mixed pairs are separated
+                // after the Rayleigh-Ritz that follows it.
+                for (int j0 = 0; j0 < c; j0 += 32) {
+                    const int cw = std::min(32, c - j0);
+                    CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, cw, Y + j0, ldc, nullptr, 0,
+                                                        nullptr, 0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
+                }
+                const int nch = resid_chunks(n);
+                CK(ensure(w.resid_part, sizeof(double) * (size_t)nch * c));
+                CK(launch_col_dots(n, c, Y, ldc, AY, ldc, (double *)w.resid_part.p, nch, sdev, s));
+                lam.assign(c, 0.0);
+                CK(hipMemcpyAsync(lam.data(), sdev, sizeof(double) * c, hipMemcpyDeviceToHost, s));
+                CK(hipStreamSynchronize(s));
+                double pbytes = 0.0;
+                const double tp = now();
+                CKR(polish_apply(pf, A, S.val32, c, Y, AY, ldc, lam, X, s, &pbytes, S.sell ? &S.SA : nullptr,
+                                 S.sell ? S.sval32 : nullptr, nullptr, 0.0,
+                                 StepShape{0, 0, 0, S.tile_chunk, S.tile_win}));
+                CK(hipStreamSynchronize(s));
+                S.st.t_polish += now() - tp;
+                S.st.polish_bytes += pbytes;
+                // Rayleigh-Ritz with A on the polished block X; its Ritz
+                // vectors land in Y, then X and Y trade places
+                CKR(rayleigh_ritz_gen(A, n, c, X, AY, Y, AX, ldc, sdev, lam, rres, s));
+                std::swap(X, Y);
+                ++S.st.polish_sweeps;
             }
             int separations = 0;
             for (;;) {
