@@ -29,6 +29,7 @@
 #include "flp_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -234,45 +235,108 @@ void parallel_for(int units, int nt, F f) {
     for (auto &t : th) t.join();
 }
 
-// Columns of J_1 J_2 ... J_t selected by ids (unsorted eigen-indices):
-// identity columns, log replayed backwards.  Z is N x ncols row-major.
-void replay_cols(const std::vector<Rot> &log, int N, const int *ids, int ncols, double *Z) {
-    constexpr int TILE = 8;
-    const int ntiles = (ncols + TILE - 1) / TILE;
-    auto work = [&](int t0, int t1) {
-        std::vector<double> tile((size_t)N * TILE);
-        for (int t = t0; t < t1; ++t) {
-            const int c0 = t * TILE, nc = std::min(TILE, ncols - c0);
+// The log replayed backwards on a row-major N x W tile of eigenvector
+// columns, then (dense path, A != nullptr) the Householder reflectors from
+// the last to the first.  Every column sees the same operations in the same
+// order for any W; the width sets how many independent columns share one
+// pass over the log, so that each rotation's dependence on the one before
+// (they share a row) is hidden behind W columns of work.
+template <int W>
+inline __attribute__((always_inline)) void vectors_tile(const Rot *log, size_t nlog, const double *A,
+                                                        const double *beta, int N, double *tile) {
+#pragma clang fp contract(off)
+    for (size_t t = nlog; t-- > 0;) {
+        const double c = log[t].c, s = log[t].s;
+        double *__restrict a = tile + (size_t)log[t].p * W;
+        double *__restrict b = a + W;
+        for (int j = 0; j < W; ++j) {
+            const double u = a[j], v = b[j];
+            a[j] = c * u - s * v;
+            b[j] = s * u + c * v;
+        }
+    }
+    if (!A) return;
+    for (int k = N - 3; k >= 0; --k) {
+        const double bt = beta[k];
+        if (bt == 0.0) continue;
+        const double *v = A + (size_t)k * N + k + 1;
+        double *z = tile + (size_t)(k + 1) * W;
+        const int len = N - k - 1;
+        double acc[W] = {};
+        for (int i = 0; i < len; ++i)
+            for (int j = 0; j < W; ++j) acc[j] += v[i] * z[(size_t)i * W + j];
+        for (int j = 0; j < W; ++j) acc[j] *= bt;
+        for (int i = 0; i < len; ++i)
+            for (int j = 0; j < W; ++j) z[(size_t)i * W + j] -= acc[j] * v[i];
+    }
+}
+
+// The same code built for AVX2 where the CPU has it: 4 doubles per vector
+// operation instead of 2, with no fused multiply-add, so both builds round
+// alike.
+template <int W>
+__attribute__((target("avx2"))) void vectors_tile_avx2(const Rot *log, size_t nlog, const double *A,
+                                                       const double *beta, int N, double *tile) {
+    vectors_tile<W>(log, nlog, A, beta, N, tile);
+}
+template <int W>
+void vectors_tile_base(const Rot *log, size_t nlog, const double *A, const double *beta, int N, double *tile) {
+    vectors_tile<W>(log, nlog, A, beta, N, tile);
+}
+bool cpu_avx2() {
+    static const bool have = __builtin_cpu_supports("avx2");
+    return have;
+}
+
+using TileFn = void (*)(const Rot *, size_t, const double *, const double *, int, double *);
+template <int W>
+TileFn tile_fn() {
+    return cpu_avx2() ? &vectors_tile_avx2<W> : &vectors_tile_base<W>;
+}
+
+// Columns ids (unsorted eigen-indices) of J_1 J_2 ... J_t, or of
+// Q J_1 ... J_t with Q = H_0 H_1 ... H_{N-3} when A holds the reflectors
+// (rows of A, beta[k]): identity columns through vectors_tile, tiles of 32,
+// 16 or 8 columns (the widest that still gives every thread a tile) claimed
+// by the threads in turn.  Z is N x ncols row-major.
+void build_cols(const std::vector<Rot> &log, const double *A, const double *beta, int N, const int *ids, int ncols,
+                double *Z) {
+    const long work = (long)(log.size() + (A ? (size_t)N * N : 0)) * ncols;
+    const int nt = nthreads_for(work, (ncols + 7) / 8);
+    const int W = ncols >= 32 * nt ? 32 : (ncols >= 16 * nt ? 16 : 8);
+    const TileFn fn = W == 32 ? tile_fn<32>() : (W == 16 ? tile_fn<16>() : tile_fn<8>());
+    const int ntiles = (ncols + W - 1) / W;
+    std::atomic<int> next{0};
+    auto work_fn = [&](int, int) {
+        std::vector<double> tile((size_t)N * W);
+        for (;;) {
+            const int t = next.fetch_add(1);
+            if (t >= ntiles) return;
+            const int c0 = t * W, nc = std::min(W, ncols - c0);
             std::fill(tile.begin(), tile.end(), 0.0);
-            for (int j = 0; j < nc; ++j) tile[(size_t)ids[c0 + j] * TILE + j] = 1.0;
-            for (auto it = log.rbegin(); it != log.rend(); ++it) {
-                const Rot &g = *it;
-                double *a = &tile[(size_t)g.p * TILE];
-                double *b = a + TILE;
-                for (int j = 0; j < TILE; ++j) {
-                    const double u = a[j], v = b[j];
-                    a[j] = g.c * u - g.s * v;
-                    b[j] = g.s * u + g.c * v;
-                }
-            }
+            for (int j = 0; j < nc; ++j) tile[(size_t)ids[c0 + j] * W + j] = 1.0;
+            fn(log.data(), log.size(), A, beta, N, tile.data());
             for (int i = 0; i < N; ++i)
-                for (int j = 0; j < nc; ++j) Z[(size_t)i * ncols + c0 + j] = tile[(size_t)i * TILE + j];
+                for (int j = 0; j < nc; ++j) Z[(size_t)i * ncols + c0 + j] = tile[(size_t)i * W + j];
         }
     };
-    parallel_for(ntiles, nthreads_for((long)log.size() * ncols, ntiles), work);
+    parallel_for(std::min(nt, ntiles), std::min(nt, ntiles), work_fn);
+}
+
+void replay_cols(const std::vector<Rot> &log, int N, const int *ids, int ncols, double *Z) {
+    build_cols(log, nullptr, nullptr, N, ids, ncols, Z);
 }
 
 // Householder reduction of a dense symmetric N x N matrix (row-major, full
 // storage, overwritten) to tridiagonal (d, e).  Step k maps row k's entries
 // k+1..N-1 to mu e_1 with H_k = I - beta_k v_k v_k^T (v_k(0) = 1), applied
 // to the trailing block as B -= v w^T + w v^T, w = p - (beta p^T v / 2) v,
-// p = beta B v.  v_k is left in row k, beta_k in beta[k].
-void householder_tridiag(int N, double *A, std::vector<double> &d, std::vector<double> &e,
-                         std::vector<double> &beta) {
-    d.assign(N, 0.0);
-    e.assign(std::max(N - 1, 0), 0.0);
-    beta.assign(std::max(N - 2, 0), 0.0);
-    std::vector<double> p(N), w(N);
+// p = beta B v (B symmetric: p accumulates the rows of B scaled by the
+// entries of v, in row order, so the inner loops run along rows).  v_k is
+// left in row k, beta_k in beta[k].
+inline __attribute__((always_inline)) void householder_body(int N, double *A, double *d, double *e, double *beta,
+                                                            double *p, double *w) {
+#pragma clang fp contract(off)
     for (int k = 0; k + 2 < N; ++k) {
         const int len = N - k - 1;
         double *x = A + (size_t)k * N + k + 1;
@@ -295,24 +359,46 @@ void householder_tridiag(int N, double *A, std::vector<double> &d, std::vector<d
         e[k] = mu;
         beta[k] = bt;
         // p = beta B v over the trailing block B = A[k+1:, k+1:]
+        for (int i = 0; i < len; ++i) p[i] = 0.0;
+        for (int j = 0; j < len; ++j) {
+            const double *__restrict row = A + (size_t)(k + 1 + j) * N + k + 1;
+            double *__restrict pp = p;
+            const double xj = x[j];
+            for (int i = 0; i < len; ++i) pp[i] += row[i] * xj;
+        }
         double pv = 0.0;
         for (int i = 0; i < len; ++i) {
-            const double *row = A + (size_t)(k + 1 + i) * N + k + 1;
-            double t = 0.0;
-            for (int j = 0; j < len; ++j) t += row[j] * x[j];
-            p[i] = bt * t;
+            p[i] *= bt;
             pv += p[i] * x[i];
         }
         const double K = 0.5 * bt * pv;
         for (int i = 0; i < len; ++i) w[i] = p[i] - K * x[i];
         for (int i = 0; i < len; ++i) {
-            double *row = A + (size_t)(k + 1 + i) * N + k + 1;
+            double *__restrict row = A + (size_t)(k + 1 + i) * N + k + 1;  // row k + 1 + i, x is row k
             const double xi = x[i], wi = w[i];
-            for (int j = 0; j < len; ++j) row[j] -= xi * w[j] + wi * x[j];
+            const double *__restrict wr = w;
+            const double *__restrict xr = x;
+            for (int j = 0; j < len; ++j) row[j] -= xi * wr[j] + wi * xr[j];
         }
     }
     for (int k = 0; k < N; ++k) d[k] = A[(size_t)k * N + k];
     if (N >= 2) e[N - 2] = A[(size_t)(N - 2) * N + N - 1];
+}
+__attribute__((target("avx2"))) void householder_avx2(int N, double *A, double *d, double *e, double *beta,
+                                                       double *p, double *w) {
+    householder_body(N, A, d, e, beta, p, w);
+}
+void householder_base(int N, double *A, double *d, double *e, double *beta, double *p, double *w) {
+    householder_body(N, A, d, e, beta, p, w);
+}
+
+void householder_tridiag(int N, double *A, std::vector<double> &d, std::vector<double> &e,
+                         std::vector<double> &beta) {
+    d.assign(N, 0.0);
+    e.assign(std::max(N - 1, 0), 0.0);
+    beta.assign(std::max(N - 2, 0), 0.0);
+    std::vector<double> p(N), w(N);
+    (cpu_avx2() ? householder_avx2 : householder_base)(N, A, d.data(), e.data(), beta.data(), p.data(), w.data());
 }
 
 // Columns ids of Q Z_t, Q = H_0 H_1 ... H_{N-3} (reflectors stored in the
@@ -321,42 +407,7 @@ void householder_tridiag(int N, double *A, std::vector<double> &d, std::vector<d
 // the last to the first.  Z is N x ncols row-major.
 void dense_vectors(const std::vector<Rot> &log, const double *A, const std::vector<double> &beta, int N,
                    const int *ids, int ncols, double *Z) {
-    constexpr int TILE = 8;
-    const int ntiles = (ncols + TILE - 1) / TILE;
-    auto work = [&](int t0, int t1) {
-        std::vector<double> tile((size_t)N * TILE);
-        for (int t = t0; t < t1; ++t) {
-            const int c0 = t * TILE, nc = std::min(TILE, ncols - c0);
-            std::fill(tile.begin(), tile.end(), 0.0);
-            for (int j = 0; j < nc; ++j) tile[(size_t)ids[c0 + j] * TILE + j] = 1.0;
-            for (auto it = log.rbegin(); it != log.rend(); ++it) {
-                const Rot &g = *it;
-                double *a = &tile[(size_t)g.p * TILE];
-                double *b = a + TILE;
-                for (int j = 0; j < TILE; ++j) {
-                    const double u = a[j], v = b[j];
-                    a[j] = g.c * u - g.s * v;
-                    b[j] = g.s * u + g.c * v;
-                }
-            }
-            for (int k = N - 3; k >= 0; --k) {
-                const double bt = beta[k];
-                if (bt == 0.0) continue;
-                const double *v = A + (size_t)k * N + k + 1;
-                double *z = &tile[(size_t)(k + 1) * TILE];
-                const int len = N - k - 1;
-                double acc[TILE] = {};
-                for (int i = 0; i < len; ++i)
-                    for (int j = 0; j < TILE; ++j) acc[j] += v[i] * z[(size_t)i * TILE + j];
-                for (int j = 0; j < TILE; ++j) acc[j] *= bt;
-                for (int i = 0; i < len; ++i)
-                    for (int j = 0; j < TILE; ++j) z[(size_t)i * TILE + j] -= acc[j] * v[i];
-            }
-            for (int i = 0; i < N; ++i)
-                for (int j = 0; j < nc; ++j) Z[(size_t)i * ncols + c0 + j] = tile[(size_t)i * TILE + j];
-        }
-    };
-    parallel_for(ntiles, nthreads_for((long)(log.size() + (size_t)N * N) * ncols, ntiles), work);
+    build_cols(log, A, beta.data(), N, ids, ncols, Z);
 }
 
 // 1 / (largest |entry|) for a matrix whose entries all lie far from 1 (the

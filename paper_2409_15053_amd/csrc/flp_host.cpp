@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <chrono>
 #include <cmath>
@@ -761,40 +762,67 @@ int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int 
 
 // ------------------------------------------------------------------ small dense helpers (host)
 
+namespace {
+// y += a x over len entries: every entry one multiply and one add, in the
+// same order whichever build runs (the AVX2 one, where the CPU has it, has
+// no fused multiply-add), so results do not depend on the machine.
+inline __attribute__((always_inline)) void axpy_body(int len, double a, const double *__restrict x,
+                                                     double *__restrict y) {
+#pragma clang fp contract(off)
+    for (int j = 0; j < len; ++j) y[j] += a * x[j];
+}
+__attribute__((target("avx2"))) void axpy_avx2(int len, double a, const double *x, double *y) {
+    axpy_body(len, a, x, y);
+}
+void axpy_base(int len, double a, const double *x, double *y) { axpy_body(len, a, x, y); }
+}  // namespace
+
+void host_axpy(int len, double a, const double *x, double *y) {
+    static void (*const f)(int, double, const double *, double *) =
+        __builtin_cpu_supports("avx2") ? axpy_avx2 : axpy_base;
+    f(len, a, x, y);
+}
+
 // Upper Cholesky G = R^T R (r x r row-major).  Columns whose pivot falls
 // below thr^2 are flagged bad: their row of R becomes e_i (placeholder) and
-// later columns ignore them.
+// later columns ignore them.  Right-looking: once row i of R is final, its
+// outer product comes off the rows below it (which hold their part of G
+// until their turn), so every entry sees the subtractions of the
+// dot-product form in the same order, along rows.
 void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, std::vector<int> &bad) {
     R.assign((size_t)r * r, 0.0);
     bad.assign(r, 0);
+    for (int i = 0; i < r; ++i)
+        for (int j = i; j < r; ++j) R[(size_t)i * r + j] = G[(size_t)i * r + j];
     for (int i = 0; i < r; ++i) {
-        double d = G[i * r + i];
-        for (int k = 0; k < i; ++k) d -= R[k * r + i] * R[k * r + i];
+        double *ri = &R[(size_t)i * r];
+        const double d = ri[i];
         if (!(d > thr2)) {
             bad[i] = 1;
-            R[i * r + i] = 1.0;
+            ri[i] = 1.0;
+            for (int j = i + 1; j < r; ++j) ri[j] = 0.0;
             continue;
         }
-        double rii = std::sqrt(d);
-        R[i * r + i] = rii;
-        for (int j = i + 1; j < r; ++j) {
-            double t = G[i * r + j];
-            for (int k = 0; k < i; ++k) t -= R[k * r + i] * R[k * r + j];
-            R[i * r + j] = t / rii;
-        }
+        const double rii = std::sqrt(d);
+        ri[i] = rii;
+        for (int j = i + 1; j < r; ++j) ri[j] /= rii;
+        for (int k = i + 1; k < r; ++k) host_axpy(r - k, -ri[k], ri + k, &R[(size_t)k * r + k]);
     }
 }
 
-// inverse of an upper-triangular r x r
+// inverse of an upper-triangular r x r, row by row from the last:
+// Ri[i][j] = -(sum over i < k <= j of R[i][k] Ri[k][j]) / R[i][i], the sum
+// taken in increasing k along the rows of Ri
 void upper_inverse(int r, const std::vector<double> &R, std::vector<double> &Ri) {
     Ri.assign((size_t)r * r, 0.0);
-    for (int j = 0; j < r; ++j) {
-        Ri[j * r + j] = 1.0 / R[j * r + j];
-        for (int i = j - 1; i >= 0; --i) {
-            double t = 0.0;
-            for (int k = i + 1; k <= j; ++k) t += R[i * r + k] * Ri[k * r + j];
-            Ri[i * r + j] = -t / R[i * r + i];
-        }
+    std::vector<double> acc(r);
+    for (int i = r - 1; i >= 0; --i) {
+        const double *ri = &R[(size_t)i * r];
+        std::fill(acc.begin() + i, acc.end(), 0.0);
+        for (int k = i + 1; k < r; ++k) host_axpy(r - k, ri[k], &Ri[(size_t)k * r + k], &acc[k]);
+        double *out = &Ri[(size_t)i * r];
+        out[i] = 1.0 / ri[i];
+        for (int j = i + 1; j < r; ++j) out[j] = -acc[j] / ri[i];
     }
 }
 
@@ -1081,6 +1109,30 @@ int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, d
 // norms), so the factorisation loses nothing.  Four n x c x c products
 // instead of the six of two orthonormalisations and a Rayleigh-Ritz.
 // Fails when Y has numerically dependent columns.
+namespace {
+// f(i) for every i in [0, n), the indices claimed one at a time by up to 16
+// threads when work (an operation count) is large enough to pay for them;
+// f(i) writes only its own output row, so the result does not depend on
+// the thread count.
+template <typename F>
+void rows_parallel(int n, double work, F f) {
+    int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    if (work < 4e6) nt = 1;
+    nt = std::min(nt, n);
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+}  // namespace
+
 int rayleigh_ritz_gen(const flp_csr *A, int n, int c, const double *Y, double *AY, double *X, double *AX, int ldc,
                       double *sdev, std::vector<double> &lam, std::vector<double> &res, hipStream_t s) {
     Workspace &w = ws();
@@ -1112,22 +1164,18 @@ int rayleigh_ritz_gen(const flp_csr *A, int n, int c, const double *Y, double *A
         if (bad[i]) return fail(FLP_E_DEVICE, "Ritz block lost rank");
     upper_inverse(c, R, Ri);
     // T = Gs Ri (T[i][j] = sum over k <= j of Gs[i][k] Ri[k][j]), then
-    // H = Ri^T T (H[i][j] = sum over k <= i of Ri[k][i] T[k][j])
+    // H = Ri^T T (H[i][j] = sum over k <= i of Ri[k][i] T[k][j]); each row
+    // of T and of H is its own task, its sums taken in increasing k
+    const double cube = (double)c * c * c;
     std::vector<double> T((size_t)c * c, 0.0), H((size_t)c * c, 0.0);
-    for (int i = 0; i < c; ++i)
-        for (int k = 0; k < c; ++k) {
-            const double g = Gs[(size_t)i * c + k];
-            const double *rk = &Ri[(size_t)k * c];
-            double *ti = &T[(size_t)i * c];
-            for (int j = k; j < c; ++j) ti[j] += g * rk[j];
-        }
-    for (int k = 0; k < c; ++k)
-        for (int i = k; i < c; ++i) {
-            const double r = Ri[(size_t)k * c + i];
-            const double *tk = &T[(size_t)k * c];
-            double *hi = &H[(size_t)i * c];
-            for (int j = 0; j < c; ++j) hi[j] += r * tk[j];
-        }
+    rows_parallel(c, cube, [&](int i) {
+        double *ti = &T[(size_t)i * c];
+        for (int k = 0; k < c; ++k) host_axpy(c - k, Gs[(size_t)i * c + k], &Ri[(size_t)k * c + k], ti + k);
+    });
+    rows_parallel(c, cube, [&](int i) {
+        double *hi = &H[(size_t)i * c];
+        for (int k = 0; k <= i; ++k) host_axpy(c, Ri[(size_t)k * c + i], &T[(size_t)k * c], hi);
+    });
     for (int i = 0; i < c; ++i)
         for (int j = 0; j < i; ++j) {
             const double v = 0.5 * (H[(size_t)i * c + j] + H[(size_t)j * c + i]);
@@ -1141,14 +1189,10 @@ int rayleigh_ritz_gen(const flp_csr *A, int n, int c, const double *Y, double *A
         return fail(FLP_E_DEVICE, "eigensolver for the Rayleigh-Ritz matrix did not converge");
     // C = D Ri Z (rows of C padded to ldc)
     std::vector<double> Cp((size_t)c * ldc, 0.0);
-    for (int i = 0; i < c; ++i) {
+    rows_parallel(c, cube, [&](int i) {
         double *ci = &Cp[(size_t)i * ldc];
-        for (int k = i; k < c; ++k) {
-            const double r = d[i] * Ri[(size_t)i * c + k];
-            const double *zk = &Z[(size_t)k * c];
-            for (int j = 0; j < c; ++j) ci[j] += r * zk[j];
-        }
-    }
+        for (int k = i; k < c; ++k) host_axpy(c, d[i] * Ri[(size_t)i * c + k], &Z[(size_t)k * c], ci);
+    });
     CK(h2d(sdev, Cp.data(), sizeof(double) * Cp.size(), s));
     CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(Y, ldc), sdev, ldc, 0.0, X, ldc, s));
     CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(AY, ldc), sdev, ldc, 0.0, AX, ldc, s));

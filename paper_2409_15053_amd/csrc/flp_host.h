@@ -230,6 +230,9 @@ int polish_apply(const flp_filter *p, const flp_csr *A, const float *val32, int 
                  const std::vector<double> *rres = nullptr, double lock_abs = 0.0, StepShape tile = StepShape{});
 
 // ---------------------------------------------------------------- dense helpers
+// y += a x over len doubles (host; an AVX2 build where the CPU has one,
+// rounding alike to the plain build)
+void host_axpy(int len, double a, const double *x, double *y);
 void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, std::vector<int> &bad);
 void upper_inverse(int r, const std::vector<double> &R, std::vector<double> &Ri);
 void matmul_upper(int r, const std::vector<double> &A, const std::vector<double> &B, std::vector<double> &C);
