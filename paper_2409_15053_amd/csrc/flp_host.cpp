@@ -868,12 +868,12 @@ int small_dev(size_t elems, double **out) {
 // dev_out: device K x c row-major; host_out (optional) receives a copy
 // (synchronises the stream).
 int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *dev_out,
-            double *host_out, hipStream_t s) {
+            double *host_out, hipStream_t s, bool sym) {
     Buf &pb = ws().partials;
     TnPlan pl = plan_tn(n, K, c);
     CK(ensure(pb, pl.partial_elems * sizeof(double)));
-    CK(launch_gemm_tn_partial(pl, n, K, c, A, B, ldb, (double *)pb.p, s));
-    CK(launch_reduce_partials(pl, K, c, (double *)pb.p, dev_out, c, s));
+    CK(launch_gemm_tn_partial(pl, n, K, c, A, B, ldb, (double *)pb.p, s, sym));
+    CK(launch_reduce_partials(pl, K, c, (double *)pb.p, dev_out, c, s, sym));
     if (host_out) {
         CK(hipMemcpyAsync(host_out, dev_out, sizeof(double) * (size_t)K * c, hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
@@ -1044,7 +1044,7 @@ int estimate_bounds_impl(const flp_csr *A, int k0, uint64_t seed, double *lmin, 
 int orthonormalize_cols(int n, int c, double *&Y, double *&tmp, int ldc, double *sdev, hipStream_t s) {
     std::vector<double> G((size_t)c * c), R, Ri;
     std::vector<int> bad;
-    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), Y, ldc, sdev, G.data(), s));
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), Y, ldc, sdev, G.data(), s, true));
     cholesky_flag(c, G.data(), 1e-300, R, bad);
     for (int i = 0; i < c; ++i)
         if (bad[i]) return fail(FLP_E_DEVICE, "Ritz block lost rank");
@@ -1070,7 +1070,7 @@ int rayleigh_ritz(const flp_csr *A, int n, int c, const double *Y, double *AY, d
                                             0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
     }
     std::vector<double> G((size_t)c * c);
-    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), AY, ldc, sdev, G.data(), s));
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), AY, ldc, sdev, G.data(), s, true));
     std::vector<double> Gs((size_t)c * c);
     for (int i = 0; i < c; ++i)
         for (int j = 0; j < c; ++j) Gs[(size_t)i * c + j] = 0.5 * (G[(size_t)i * c + j] + G[(size_t)j * c + i]);
@@ -1142,8 +1142,8 @@ int rayleigh_ritz_gen(const flp_csr *A, int n, int c, const double *Y, double *A
                                             0, AY + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
     }
     std::vector<double> M((size_t)c * c), G((size_t)c * c);
-    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), Y, ldc, sdev, M.data(), s));
-    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), AY, ldc, sdev, G.data(), s));
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), Y, ldc, sdev, M.data(), s, true));
+    CKR(gram_tn(n, c, c, plain_mat(Y, ldc), AY, ldc, sdev, G.data(), s, true));
     std::vector<double> d(c);
     for (int i = 0; i < c; ++i) {
         const double m = M[(size_t)i * c + i];
@@ -1195,7 +1195,13 @@ int rayleigh_ritz_gen(const flp_csr *A, int n, int c, const double *Y, double *A
     });
     CK(h2d(sdev, Cp.data(), sizeof(double) * Cp.size(), s));
     CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(Y, ldc), sdev, ldc, 0.0, X, ldc, s));
-    CK(launch_gemm_nn(n, c, c, 1.0, plain_mat(AY, ldc), sdev, ldc, 0.0, AX, ldc, s));
+    // AX = A X by the sparse product (a read of A and of X per 32 columns)
+    // rather than AY C (a dense n x c x c product on the FP64 matrix cores)
+    for (int j0 = 0; j0 < c; j0 += 32) {
+        int cw = std::min(32, c - j0);
+        CK(launch_cheb_step<double, double>(n, A->rowptr, A->colind, A->val, cw, X + j0, ldc, nullptr, 0, nullptr,
+                                            0, AX + j0, ldc, 1.0, 0.0, 0.0, 0.0, s));
+    }
     double *lamd = sdev + (size_t)c * ldc;
     double *rdev = lamd + ldc;
     CK(h2d(lamd, lam.data(), sizeof(double) * c, s));

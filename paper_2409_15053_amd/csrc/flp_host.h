@@ -237,8 +237,10 @@ void cholesky_flag(int r, const double *G, double thr2, std::vector<double> &R, 
 void upper_inverse(int r, const std::vector<double> &R, std::vector<double> &Ri);
 void matmul_upper(int r, const std::vector<double> &A, const std::vector<double> &B, std::vector<double> &C);
 
+// sym: K == c and A^T B symmetric (B = A, or B = M A with M symmetric): the
+// blocks below the diagonal are skipped and mirrored.
 int gram_tn(int n, int K, int c, DMat A, const double *B, int64_t ldb, double *dev_out, double *host_out,
-            hipStream_t s);
+            hipStream_t s, bool sym = false);
 int cgs2(DMat Q, int k, int n, double *W, int r, double *hdev, hipStream_t s);
 int block_qr_impl(double *W, int n, int r, const DMat *Q, int k, std::vector<double> &S, uint64_t seed,
                   uint64_t sid, hipStream_t s, bool *replaced, int depth = 0);

@@ -223,11 +223,14 @@ struct TnPlan {
     size_t partial_elems;  // nchunks * K * c
 };
 TnPlan plan_tn(int n, int K, int c);
+// sym (K == c and A^T B symmetric, as B = A or B = M A with M symmetric):
+// only the tile groups on or above the diagonal are computed, and the
+// reduction (with the same flag) mirrors them.
 hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A, const double *B, int64_t ldb,
-                                  double *partials, hipStream_t s);
+                                  double *partials, hipStream_t s, bool sym = false);
 // C (K x c, ldc) = sum over chunks of partials (deterministic order).
 hipError_t launch_reduce_partials(const TnPlan &pl, int K, int c, const double *partials, double *C,
-                                  int ldc, hipStream_t s);
+                                  int ldc, hipStream_t s, bool sym = false);
 
 // C (n x c, ldc) = beta * C + alpha * A (n x K, lda) B (K x c, ldb); B on device.
 hipError_t launch_gemm_nn(int n, int K, int c, double alpha, DMat A, const double *B, int64_t ldb, double beta,

@@ -17,29 +17,39 @@ namespace flp {
 namespace {
 
 template <int NT>
-__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int c, int chunk_rows, DMat A,
+__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(int n, int K, int c, int chunk_rows, int ngroups, DMat A,
                                                               const double *__restrict__ B, int64_t ldb,
-                                                              double *__restrict__ partials, bool aligned) {
+                                                              double *__restrict__ partials, bool aligned, bool sym) {
     __shared__ double red[4][4][WAVE];
     const int ntb = (c + 15) / 16;  // B tiles
-    const int chunk = blockIdx.x;
+    // chunk-major and XCD-aware: the blocks of one row chunk (every tile
+    // group of the output) run together on one XCD, so the chunk's rows of
+    // A and B come from HBM once and from that XCD's L2 for the other groups
+    const int L = xcd_tile(blockIdx.x, gridDim.x);
+    const int chunk = L / ngroups, grp = L % ngroups;
+    const int q0 = (grp / ntb) * NT * 16, tb = grp % ntb;
+    // symmetric result: a group wholly below the diagonal is not computed
+    // (the reduction reads its mirror image); uniform over the block
+    if (sym && q0 > tb * 16 + 15) return;
     const int r0 = chunk * chunk_rows;
-    tn_mfma_block<NT>(r0, min(n, r0 + chunk_rows), K, c, (blockIdx.y / ntb) * NT * 16, blockIdx.y % ntb, A, B, ldb,
-                      aligned, partials + (size_t)chunk * K * c, red);
+    tn_mfma_block<NT>(r0, min(n, r0 + chunk_rows), K, c, q0, tb, A, B, ldb, aligned, partials + (size_t)chunk * K * c,
+                      red);
 }
 
 // Sum of the per-chunk partials in a fixed order (deterministic): each
 // block owns 64 outputs; its 4 thread rows split the chunks and combine
-// through LDS.
+// through LDS.  sym (a square result whose partials exist on and above the
+// diagonal only): entry (i, j) below the diagonal takes the sums of (j, i).
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int nchunks, int total, int c,
                                                               const double *__restrict__ partials,
-                                                              double *__restrict__ C, int ldc) {
+                                                              double *__restrict__ C, int ldc, bool sym) {
     __shared__ double red[4][64];
     const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
     const int o = blockIdx.x * 64 + tx;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (o < total) {
-        const double *p = partials + o;
+        const int i = o / c, j = o % c;
+        const double *p = partials + ((sym && i > j) ? j * c + i : o);
         int q = ty;
         for (; q + 12 < nchunks; q += 16) {
             s0 += p[(size_t)q * total];
@@ -134,7 +144,7 @@ TnPlan plan_tn(int n, int K, int c) {
 }
 
 hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A, const double *B, int64_t ldb,
-                                  double *partials, hipStream_t s) {
+                                  double *partials, hipStream_t s, bool sym) {
     if (tn_use_fma(K, c)) {
         dim3 grid((K + 255) / 256, pl.nchunks);
         hipLaunchKernelGGL((gemm_tn_fma_kernel<8, 8>), grid, dim3(256), 0, s, n, K, pl.chunk_rows, A, B, ldb,
@@ -144,10 +154,11 @@ hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A,
     // 16-byte A loads need an even leading dimension and panel stride
     const bool aligned = !(A.ld & 1) && !(A.ps & 1) && !(reinterpret_cast<uintptr_t>(A.p) & 15);
     const int nt = K <= 32 ? 2 : (K <= 64 ? 4 : 8);
-    dim3 grid(pl.nchunks, ((K + 16 * nt - 1) / (16 * nt)) * ((c + 15) / 16));
+    const int ngroups = ((K + 16 * nt - 1) / (16 * nt)) * ((c + 15) / 16);
+    dim3 grid(pl.nchunks * ngroups);
 #define FLP_TN(NT) \
-    hipLaunchKernelGGL((gemm_tn_partial_kernel<NT>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, A, B, ldb, partials, \
-                       aligned)
+    hipLaunchKernelGGL((gemm_tn_partial_kernel<NT>), grid, dim3(256), 0, s, n, K, c, pl.chunk_rows, ngroups, A, B, ldb, \
+                       partials, aligned, sym && K == c)
     if (nt == 2)
         FLP_TN(2);
     else if (nt == 4)
@@ -159,10 +170,10 @@ hipError_t launch_gemm_tn_partial(const TnPlan &pl, int n, int K, int c, DMat A,
 }
 
 hipError_t launch_reduce_partials(const TnPlan &pl, int K, int c, const double *partials, double *C, int ldc,
-                                  hipStream_t s) {
+                                  hipStream_t s, bool sym) {
     int total = K * c;
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((total + 63) / 64), dim3(256), 0, s, pl.nchunks, total, c,
-                       partials, C, ldc);
+                       partials, C, ldc, sym && K == c);
     return hipGetLastError();
 }
 
