@@ -632,6 +632,7 @@ def bench_c3(args):
                           "polish_GBps": pgb, "polish_frac_hbm": pgb / HBM_PEAK_GBS if pgb else None,
                           "polish_seconds": st["t_polish"], "polish_bytes": st["polish_bytes"],
                           "iters": st["iters"], "polish_sweeps": st["polish_sweeps"],
+                          "candidates": st["candidates"], "guards": st["guards"],
                           "phases_s": {k: st[k] for k in ("t_pre", "t_mv", "t_orth", "t_check", "t_rr",
                                                           "t_polish")},
                           "evals": np.sort(res["evals"])}

@@ -168,6 +168,10 @@ typedef struct flp_stats {
     int32_t filter_window_halo; /* its reach in rows (flp_tune_info.window_halo) */
     int32_t separations;        /* FP32 filter: Rayleigh-Ritz rounds on a block grown by A x for Ritz
                                    pairs mixing eigenvectors from both sides of the interval */
+    int32_t candidates;         /* Ritz pairs of the last check with filter value >= tau (the
+                                   candidates of eq. proj) */
+    int32_t guards;             /* FP32 filter: transition-band Ritz vectors added to them for the
+                                   polish (0 otherwise) */
 } flp_stats;
 
 /* Result of flp_solve; owned by the library until flp_result_free(). */

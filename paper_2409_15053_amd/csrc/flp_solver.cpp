@@ -350,6 +350,15 @@ void run_check_body(CheckTask &c) {
         std::sort(g.begin(), g.end(), [&](int a, int b) { return std::fabs(theta[a]) > std::fabs(theta[b]); });
         const size_t cap = std::max<size_t>(c.cand.size() / 4, 2 * (size_t)r);
         if (g.size() > cap) g.resize(cap);
+        // the polish sweeps the block in fixed-width column blocks, each
+        // costing a full block's traffic: a last block filled by guards
+        // alone is dropped when that keeps at least 3/4 of them and 2r (on
+        // the 120^3 Hamiltonian 349 candidates + 67 guards = 13 blocks of
+        // 32 instead of 87 guards in 14; one sweep still suffices, and the
+        // FP32 solve takes 1.02 s instead of 1.05)
+        const size_t pw = (size_t)polish_block_width();
+        const size_t tail = (c.cand.size() + g.size()) % pw;
+        if (tail != 0 && tail <= g.size() / 4 && g.size() - tail >= 2 * (size_t)r) g.resize(g.size() - tail);
         std::sort(g.begin(), g.end());
         c.guard = g;
     }
@@ -454,6 +463,8 @@ int solve_finish(Solve &S, flp_result **out) {
     S.st.basis_cols = S.kfinal;
     std::vector<int> sel = S.cand;
     sel.insert(sel.end(), S.guard.begin(), S.guard.end());
+    S.st.candidates = (int)S.cand.size();
+    S.st.guards = (int)S.guard.size();
     const int c = S.cand.empty() ? 0 : (int)sel.size();
     if (c > 0) {
         const int K = S.kfinal;

@@ -81,7 +81,7 @@ class FlpStatsC(ctypes.Structure):
                 ("polish_bytes", ctypes.c_double),
                 ("t_polish", ctypes.c_double), ("warm_status", ctypes.c_int32), ("warm_sweeps", ctypes.c_int32),
                 ("filter_lds_window", ctypes.c_int32), ("filter_window_halo", ctypes.c_int32),
-                ("separations", ctypes.c_int32)]
+                ("separations", ctypes.c_int32), ("candidates", ctypes.c_int32), ("guards", ctypes.c_int32)]
 
 
 class FlpBatchStatsC(ctypes.Structure):
