@@ -61,6 +61,7 @@ constexpr int kMaxSeparations = 8;  // Rayleigh-Ritz rounds on span{X, A x} for 
 constexpr double kLockFrac = 0.1;
 constexpr int kSetupThreads = 8;  // host threads for the set-up of a batch's solves
 constexpr int kMaxSpeculative = 2;  // block steps a solve may take past a convergence check in flight
+constexpr int kPaceLaunches = 8;    // filter launches per chunk while a check is in flight (single solve)
 
 int fail(int code, const std::string &msg);
 const char *last_error_cstr();

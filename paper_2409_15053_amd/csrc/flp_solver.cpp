@@ -899,21 +899,45 @@ int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         stage = (char *)S.U[0] + es * (size_t)S.n * gw;  // U buffers hold n x r >= 2 n x gw
         gplan = clenshaw_plan(S.filt.get(), gw, stage, gw, S.W, S.r, S.U[0], S.U[1], S.U[2], fp32);
     }
-    hipEvent_t ev[2];
+    hipEvent_t ev[4];
     for (auto &e : ev) CK(hipEventCreate(&e));
     struct EvGuard {
         hipEvent_t *e;
         ~EvGuard() {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
+            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
         }
     } evg{ev};
     while (!S.done) {
         CK(hipEventRecord(ev[0], S.s));
+        // While a convergence check is still running on the host, the step's
+        // launches go out in chunks, each issued after the chunk before the
+        // previous one has run (the device never waits), and the check is
+        // applied as soon as it is ready: when it decides convergence the
+        // rest of this speculative step is never issued.
+        bool pace = S.check != nullptr;
+        int issued = 0, chunk = 0;
+        bool stop = false;
+        auto after_launch = [&]() -> int {
+            if (!pace || ++issued % kPaceLaunches != 0) return FLP_OK;
+            hipEvent_t e = ev[2 + (chunk & 1)];
+            CK(hipEventRecord(e, S.s));
+            if (chunk > 0) CK(hipEventSynchronize(ev[2 + ((chunk - 1) & 1)]));
+            ++chunk;
+            if (S.check && S.check->ready.load()) {
+                CKR(wait_check(S));
+                stop = S.done;
+                pace = false;  // not converged: the rest of the step goes out at once
+            }
+            return FLP_OK;
+        };
         if (gw == S.r) {
-            for (const auto &st : S.plan) CKR(launch_plan_step(fA, fv32, S.r, st, fp32, S.s, tn.sh, S.sell));
+            for (const auto &st : S.plan) {
+                CKR(launch_plan_step(fA, fv32, S.r, st, fp32, S.s, tn.sh, S.sell));
+                CKR(after_launch());
+                if (stop) break;
+            }
         } else {
-            for (int j0 = 0; j0 < S.r; j0 += gw) {
+            for (int j0 = 0; j0 < S.r && !stop; j0 += gw) {
                 if (fp32)
                     CK(launch_copy_block(S.n, gw, 1.0, S.Vin + j0, S.r, DMat{nullptr, 0, 0, 0}, 0, (float *)stage,
                                          gw, S.s));
@@ -923,6 +947,8 @@ int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
                 for (ClenshawStep st : gplan) {
                     if (st.out == (void *)S.W) st.out = S.W + j0;  // the last step writes the group's columns of W
                     CKR(launch_plan_step(fA, fv32, gw, st, fp32, S.s, tn.sh, S.sell));
+                    CKR(after_launch());
+                    if (stop) break;
                 }
             }
         }
@@ -931,6 +957,13 @@ int solve_cold(const flp_csr *A, double alpha, double beta, const flp_opts &o, f
         float ms = 0;
         CK(hipEventElapsedTime(&ms, ev[0], ev[1]));
         S.st.t_mv += ms * 1e-3;
+        if (stop) {
+            // converged at the check applied above: the part of this step that
+            // ran is discarded (its products and bytes still count)
+            S.st.filter_bytes += filter_step_bytes(S.n, S.A->nnz, gw, S.o.prec) * issued;
+            S.st.mv += (int64_t)gw * issued;
+            break;
+        }
         CKR(solve_after_filter(S));
     }
     return solve_finish(S, out);
