@@ -97,7 +97,11 @@ def test_solve_rejects_bad_csr_without_gpu():
     assert lib.flp_solve(ctypes.byref(A), 0.0, 1.0, None, ctypes.byref(res)) == flp.FLP_E_ARG
 
 
-@pytest.mark.parametrize("N,bw", [(1, 0), (2, 1), (7, 1), (60, 1), (60, 3), (97, 8), (120, 16), (80, 79), (257, 40), (300, 299)])
+# the eigenvector columns are built in tiles of 8, 16 or 32 (the widest
+# that gives every thread one): N = 20 and 24 take 16-column tiles on one
+# thread, 60 and up 32, and the larger ones several threads
+@pytest.mark.parametrize("N,bw", [(1, 0), (2, 1), (7, 1), (20, 3), (24, 23), (60, 1), (60, 3), (97, 8), (120, 16),
+                                  (80, 79), (257, 40), (300, 299), (420, 419)])
 def test_host_banded_eigensolver_against_lapack(N, bw):
     g = np.random.Generator(np.random.PCG64(N * 100 + bw))
     M = g.standard_normal((N, N))
